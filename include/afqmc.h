@@ -1,0 +1,177 @@
+/*
+ * afqmc.h - C ABI of the MI355X (gfx950) correlated-sampling phaseless AFQMC
+ * walker step (Shee, Zhang, Reichman, Friesner; arXiv:1703.01545).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - All matrices are row-major float64 unless stated otherwise.
+ * - Host input arrays are borrowed for the duration of the call and copied;
+ *   the library never keeps or frees caller memory.
+ * - Handles own their device memory (allocated with hipMalloc in
+ *   afqmc_load_hamiltonian / afqmc_init_walkers) until afqmc_free_*.
+ * - Work is enqueued on the HIP stream given to afqmc_load_hamiltonian
+ *   (NULL = the null stream).  Calls that return host data synchronise that
+ *   stream before returning.
+ * - Every call returns an afqmc_status; on failure a message is available
+ *   from afqmc_last_error() (thread-local).  No call aborts, exits or throws
+ *   across the ABI.
+ * - A walker whose weight is no longer positive is frozen, not an error
+ *   (Sec. II.B of the paper); afqmc_get_walkers reports it through `alive`.
+ */
+#ifndef AFQMC_H
+#define AFQMC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    AFQMC_OK = 0,
+    AFQMC_E_INVALID = -1,  /* null pointer, bad enum, non-positive size     */
+    AFQMC_E_SHAPE = -2,    /* inconsistent sizes, or a pair that does not
+                              share M, n_chol, walker count and L (Sec. II.C) */
+    AFQMC_E_NOMEM = -3,    /* device allocation failed                      */
+    AFQMC_E_DEVICE = -4,   /* a HIP runtime call or kernel launch failed    */
+    AFQMC_E_SINGULAR = -5, /* initial determinant orthogonal to the trial   */
+    AFQMC_E_STATE = -6     /* call out of order (e.g. pair at different t)  */
+} afqmc_status;
+
+/* Arithmetic of the Cholesky contractions (force bias, field sum, exchange)
+ * and of the propagator products.  AFQMC_FP64: everything in FP64 (the parity
+ * path).  AFQMC_FP32: L, Theta and the propagator products in FP32 with FP32
+ * accumulation.  AFQMC_BF16: L and Theta in BF16 for the Cholesky
+ * contractions (FP32 accumulation), propagator products in FP32.  In every
+ * mode the walker determinants, overlaps, determinants, Gram-Schmidt,
+ * weights and phases stay FP64. */
+typedef enum { AFQMC_FP64 = 0, AFQMC_FP32 = 1, AFQMC_BF16 = 2 } afqmc_prec;
+
+/* Projection variant.  PHASELESS: the ph-AFQMC step of Sec. II.A with the
+ * hybrid weight of Sec. II.D.  FREE: free projection (no force bias, complex
+ * weight, no phase projection), Sec. II.A. */
+typedef enum { AFQMC_PHASELESS = 0, AFQMC_FREE = 1 } afqmc_mode;
+
+typedef struct afqmc_ham_s* afqmc_ham; /* Hamiltonian: h, L, e_core        */
+typedef struct afqmc_sys_s* afqmc_sys; /* one system: ham + trial + walkers */
+
+typedef struct {
+    double dt;            /* imaginary time step (Eq. 3)                    */
+    int taylor_order;     /* order K of the Taylor series for the HS factor */
+    int ortho_every;      /* modified Gram-Schmidt period in steps (0: off) */
+    int measure_every;    /* mixed-energy period in steps (0: off)          */
+    afqmc_prec contract_prec;
+    afqmc_mode mode;
+} afqmc_params;
+
+/* Load H of Eq. 1: h1 (M x M, symmetric), chol (n_chol x M x M, each
+ * L^gamma symmetric, V_ijkl = sum_gamma L^gamma_ik L^gamma_jl), e_core.
+ * hip_stream: hipStream_t (or NULL) on which all later work of systems built
+ * on this Hamiltonian is enqueued.  Errors: E_INVALID (null/size <= 0),
+ * E_NOMEM, E_DEVICE. */
+afqmc_status afqmc_load_hamiltonian(int M, int n_chol, const double* h1, const double* chol,
+                                    double e_core, void* hip_stream, afqmc_ham* out);
+
+/* Build one system on `ham`: trial determinant (M x (n_alpha + n_beta),
+ * column j = orbital j, alpha columns first; real, Sec. II.A) and n_walkers
+ * walkers initialised to init_phi (same shape; NULL -> the trial; a
+ * different determinant such as ROHF walkers with a UHF trial, Sec. II.D),
+ * weight 1.  Precomputes the mean-field shift a_gamma = Tr(L_gamma G_T)
+ * (Eq. 2, 9), the one-body exponential P = exp(-dt h~/2) with
+ * h~ = h - 1/2 sum L_g L_g + sum a_g L_g, and the half-rotated L^half, h^half.
+ * Errors: E_INVALID, E_SHAPE (n_alpha/n_beta outside [0, M] or both 0),
+ * E_SINGULAR (init overlap with the trial is zero), E_NOMEM, E_DEVICE. */
+afqmc_status afqmc_init_walkers(afqmc_ham ham, int n_alpha, int n_beta, const double* trial,
+                                const double* init_phi, int n_walkers, const afqmc_params* params,
+                                afqmc_sys* out);
+
+/* Advance every live walker n_steps imaginary-time steps (force bias Eq. 8-9,
+ * propagator Eq. 11 by Taylor series between one-body halves, overlap ratio
+ * and phaseless hybrid weight, Sec. II.A/II.D; modified Gram-Schmidt every
+ * ortho_every steps, Sec. II.D).  Fields: `fields` NULL -> counter-based
+ * Philox4x32-10 normals keyed by (seed, stream_id, absolute step t, walker k,
+ * gamma); else a DEVICE pointer to n_steps x n_walkers x n_chol float64
+ * values (C order), read for steps t0 .. t0+n_steps-1.  Measurements are not
+ * taken here (see afqmc_local_energy / afqmc_pair_step).
+ * Errors: E_INVALID, E_STATE (freed handle), E_DEVICE. */
+afqmc_status afqmc_step(afqmc_sys sys, uint64_t seed, uint64_t stream_id, int n_steps,
+                        const double* fields);
+
+/* Mixed local energy of every walker, Eq. 7 and Eq. 10:
+ * E_L = e_core + sum_s Tr(h^half_s Theta^s)
+ *       + 1/2 sum_g [(sum_s Tr T_gs)^2 - sum_s Tr(T_gs T_gs)],
+ * T_gs = L^half_gs Theta^s, and the phaseless mixed estimator
+ * e_mixed = sum_k w_k Re E_L,k / sum_k w_k over live walkers (free mode:
+ * Re(sum W E_L / sum W)).  e_local: host, n_walkers x 2 (re, im) or NULL;
+ * weights: host, n_walkers (free mode: n_walkers x 2) or NULL; e_mixed: host,
+ * 1 double, or NULL.  Synchronises.  Errors: E_INVALID, E_DEVICE. */
+afqmc_status afqmc_local_energy(afqmc_sys sys, double* e_local, double* weights, double* e_mixed);
+
+/* Modified Gram-Schmidt of each spin block of every live walker (Sec. II.D);
+ * overlaps and Theta are recomputed, weights unchanged (Eq. 6). */
+afqmc_status afqmc_orthonormalize(afqmc_sys sys);
+
+/* Correlated pair (Sec. II.B): advance a and b n_steps with identical fields
+ * (walker k of a and of b draw the same x at every step and gamma), no
+ * population control, MGS every ortho_every steps, and every measure_every
+ * steps record E_a, E_b and dE = E_b - E_a.  e_trace: host array of
+ * (n_steps / measure_every) x 3 doubles, or NULL.  `fields` as in afqmc_step
+ * (one device array shared by both systems).  Errors: E_SHAPE when the two
+ * systems differ in M, n_chol, walker count or L (Sec. II.C), or in
+ * dt/ortho_every/measure_every; E_STATE when their step counters differ. */
+afqmc_status afqmc_pair_step(afqmc_sys a, afqmc_sys b, uint64_t seed, int n_steps,
+                             const double* fields, double* e_trace);
+
+/* Many correlated pairs of uneven size advanced together: each phase of the
+ * step is one grouped launch over every system of every pair, and the whole
+ * step is captured once in a HIP graph and replayed.  Pair p uses seed
+ * seeds[p] and stream id p.  e_traces: host, n_pairs x (n_steps /
+ * measure_every) x 3 doubles, or NULL.  All systems must share one stream
+ * (one Hamiltonian stream) and one precision; each pair must satisfy the
+ * afqmc_pair_step preconditions. */
+afqmc_status afqmc_pair_batch_step(int n_pairs, const afqmc_sys* a, const afqmc_sys* b,
+                                   const uint64_t* seeds, int n_steps, double* e_traces);
+
+/* Read back walker state: phi (n_walkers x 2 x N x M: plane 0 = real,
+ * plane 1 = imaginary part of orbital column i, N = n_alpha + n_beta),
+ * w (n_walkers; free mode n_walkers x 2), log_ovlp (n_walkers x 2:
+ * ln <phi_T|phi>, imaginary part modulo 2 pi), alive (n_walkers).  Any may
+ * be NULL.  Host pointers; synchronises. */
+afqmc_status afqmc_get_walkers(afqmc_sys sys, double* phi, double* w, double* log_ovlp,
+                               unsigned char* alive);
+
+/* Query sizes: any pointer may be NULL. */
+afqmc_status afqmc_sys_info(afqmc_sys sys, int* M, int* n_chol, int* n_alpha, int* n_beta,
+                            int* n_walkers, int64_t* step);
+
+/* Snapshot of the walker state (phi, weights, overlaps, Theta, alive, step
+ * counter).  dst NULL: *bytes receives the size needed.  Restoring a snapshot
+ * and stepping again with the same seed reproduces the original run bit for
+ * bit (the fields are a pure function of the step counter). */
+afqmc_status afqmc_checkpoint(afqmc_sys sys, void* dst, size_t* bytes);
+afqmc_status afqmc_restore(afqmc_sys sys, const void* src, size_t bytes);
+
+void afqmc_free_sys(afqmc_sys sys);
+void afqmc_free_ham(afqmc_ham ham);
+
+/* Thread-local message describing the last non-OK status of this thread. */
+const char* afqmc_last_error(void);
+
+/* Kernel self-test: C = A * B^T (A: m x k, B: n x k, C: m x n, host
+ * float64) computed by the library's tiled MFMA GEMM in precision `prec`
+ * (inputs rounded to that precision).  For the numerics tests of the
+ * contraction kernel against a plain reference.  Synchronises. */
+afqmc_status afqmc_selftest_gemm(afqmc_prec prec, int m, int n, int k, const double* A,
+                                 const double* B, double* C);
+
+/* Device Philox4x32-10 normals x[k, gamma] of step t for walkers 0..nw-1,
+ * the same values afqmc_step draws; host output nw x n_chol.  For tests. */
+afqmc_status afqmc_selftest_fields(uint64_t seed, uint64_t stream_id, int64_t t, int nw,
+                                   int n_chol, double* out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* AFQMC_H */

@@ -1,0 +1,250 @@
+"""Python binding of libafqmc (ctypes).  Argument marshalling only: every step
+of the walker propagation runs in the library's HIP kernels; PyTorch only
+supplies the HIP stream and, optionally, device memory for explicit fields.
+
+The library must have been built (``python -m paper_1703_01545_amd.build``);
+importing this module without it raises ImportError — there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libafqmc.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"libafqmc.so not built at {LIB_PATH}; run python -m paper_1703_01545_amd.build")
+
+_lib = C.CDLL(LIB_PATH)
+
+OK, E_INVALID, E_SHAPE, E_NOMEM, E_DEVICE, E_SINGULAR, E_STATE = 0, -1, -2, -3, -4, -5, -6
+PREC = {"fp64": 0, "fp32": 1, "bf16": 2}
+MODE = {"phaseless": 0, "free": 1}
+
+# Every C-ABI entry point declared in include/afqmc.h.
+EXPORTS = [
+    "afqmc_load_hamiltonian", "afqmc_init_walkers", "afqmc_step", "afqmc_local_energy",
+    "afqmc_orthonormalize", "afqmc_pair_step", "afqmc_pair_batch_step", "afqmc_get_walkers",
+    "afqmc_sys_info", "afqmc_checkpoint", "afqmc_restore", "afqmc_free_sys", "afqmc_free_ham",
+    "afqmc_last_error", "afqmc_selftest_gemm", "afqmc_selftest_fields",
+]
+
+
+class Params(C.Structure):
+    _fields_ = [("dt", C.c_double), ("taylor_order", C.c_int), ("ortho_every", C.c_int),
+                ("measure_every", C.c_int), ("contract_prec", C.c_int), ("mode", C.c_int)]
+
+
+_dp = C.POINTER(C.c_double)
+_vp = C.c_void_p
+_lib.afqmc_last_error.restype = C.c_char_p
+_lib.afqmc_load_hamiltonian.argtypes = [C.c_int, C.c_int, _dp, _dp, C.c_double, _vp, C.POINTER(_vp)]
+_lib.afqmc_init_walkers.argtypes = [_vp, C.c_int, C.c_int, _dp, _dp, C.c_int, C.POINTER(Params),
+                                    C.POINTER(_vp)]
+_lib.afqmc_step.argtypes = [_vp, C.c_uint64, C.c_uint64, C.c_int, _vp]
+_lib.afqmc_local_energy.argtypes = [_vp, _dp, _dp, _dp]
+_lib.afqmc_orthonormalize.argtypes = [_vp]
+_lib.afqmc_pair_step.argtypes = [_vp, _vp, C.c_uint64, C.c_int, _vp, _dp]
+_lib.afqmc_pair_batch_step.argtypes = [C.c_int, C.POINTER(_vp), C.POINTER(_vp),
+                                       C.POINTER(C.c_uint64), C.c_int, _dp]
+_lib.afqmc_get_walkers.argtypes = [_vp, _dp, _dp, _dp, C.POINTER(C.c_ubyte)]
+_lib.afqmc_sys_info.argtypes = [_vp] + [C.POINTER(C.c_int)] * 5 + [C.POINTER(C.c_int64)]
+_lib.afqmc_checkpoint.argtypes = [_vp, _vp, C.POINTER(C.c_size_t)]
+_lib.afqmc_restore.argtypes = [_vp, _vp, C.c_size_t]
+_lib.afqmc_free_sys.argtypes = [_vp]
+_lib.afqmc_free_sys.restype = None
+_lib.afqmc_free_ham.argtypes = [_vp]
+_lib.afqmc_free_ham.restype = None
+_lib.afqmc_selftest_gemm.argtypes = [C.c_int, C.c_int, C.c_int, C.c_int, _dp, _dp, _dp]
+_lib.afqmc_selftest_fields.argtypes = [C.c_uint64, C.c_uint64, C.c_int64, C.c_int, C.c_int, _dp]
+for _n in EXPORTS:
+    if _n not in ("afqmc_last_error", "afqmc_free_sys", "afqmc_free_ham"):
+        getattr(_lib, _n).restype = C.c_int
+
+
+class AfqmcError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"afqmc status {status}: {msg}")
+        self.status = status
+
+
+def _check(status: int):
+    if status != OK:
+        raise AfqmcError(status, _lib.afqmc_last_error().decode(errors="replace"))
+
+
+def _ptr(a: Optional[np.ndarray]):
+    if a is None:
+        return None
+    assert a.dtype == np.float64 and a.flags.c_contiguous
+    return a.ctypes.data_as(_dp)
+
+
+def _f64(a) -> np.ndarray:
+    return np.ascontiguousarray(np.asarray(a, dtype=np.float64))
+
+
+def _current_stream() -> int:
+    import torch
+    if not torch.cuda.is_available():
+        return 0
+    return int(torch.cuda.current_stream().cuda_stream)
+
+
+def _dev_ptr(fields) -> Optional[int]:
+    """Device pointer of an explicit-field tensor (torch, float64, on the GPU)."""
+    if fields is None:
+        return None
+    import torch
+    if not (isinstance(fields, torch.Tensor) and fields.is_cuda and fields.dtype == torch.float64
+            and fields.is_contiguous()):
+        raise TypeError("fields must be a contiguous float64 torch tensor on the GPU")
+    return int(fields.data_ptr())
+
+
+class Hamiltonian:
+    """h (M x M), chol (n_chol x M x M) and e_core of Eq. 1, resident on the GPU."""
+
+    def __init__(self, h, chol, e_core: float = 0.0, stream: Optional[int] = None):
+        h = _f64(h)
+        chol = _f64(chol)
+        self.M = h.shape[0]
+        self.n_chol = chol.shape[0]
+        assert h.shape == (self.M, self.M) and chol.shape[1:] == (self.M, self.M)
+        self.stream = _current_stream() if stream is None else int(stream)
+        out = _vp()
+        _check(_lib.afqmc_load_hamiltonian(self.M, self.n_chol, _ptr(h), _ptr(chol), float(e_core),
+                                           _vp(self.stream), C.byref(out)))
+        self._h = out
+
+    def free(self):
+        if self._h:
+            _lib.afqmc_free_ham(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+class System:
+    """One system (trial + walker batch) on a Hamiltonian."""
+
+    def __init__(self, ham: Hamiltonian, n_alpha: int, n_beta: int, trial, n_walkers: int,
+                 dt: float, taylor_order: int = 6, ortho_every: int = 10, measure_every: int = 20,
+                 precision: str = "fp64", mode: str = "phaseless", init_phi=None):
+        self.ham = ham
+        self.M, self.n_chol = ham.M, ham.n_chol
+        self.na, self.nb = int(n_alpha), int(n_beta)
+        self.N = self.na + self.nb
+        self.nw = int(n_walkers)
+        self.mode = mode
+        trial = _f64(trial)
+        assert trial.shape == (self.M, self.N)
+        init = None if init_phi is None else _f64(init_phi)
+        self.params = Params(float(dt), int(taylor_order), int(ortho_every), int(measure_every),
+                             PREC[precision], MODE[mode])
+        out = _vp()
+        _check(_lib.afqmc_init_walkers(ham._h, self.na, self.nb, _ptr(trial), _ptr(init), self.nw,
+                                       C.byref(self.params), C.byref(out)))
+        self._s = out
+
+    def step(self, n_steps: int = 1, seed: int = 0, stream_id: int = 0, fields=None):
+        _check(_lib.afqmc_step(self._s, int(seed), int(stream_id), int(n_steps),
+                               _dev_ptr(fields)))
+
+    def orthonormalize(self):
+        _check(_lib.afqmc_orthonormalize(self._s))
+
+    def local_energy(self):
+        el = np.empty((self.nw, 2))
+        w = np.empty((self.nw, 2) if self.mode == "free" else self.nw)
+        em = np.empty(1)
+        _check(_lib.afqmc_local_energy(self._s, _ptr(el), _ptr(w), _ptr(em)))
+        wv = w[:, 0] + 1j * w[:, 1] if self.mode == "free" else w
+        return el[:, 0] + 1j * el[:, 1], wv, float(em[0])
+
+    def walkers(self):
+        phi = np.empty((self.nw, 2, self.N, self.M))
+        w = np.empty((self.nw, 2) if self.mode == "free" else self.nw)
+        lo = np.empty((self.nw, 2))
+        alive = np.empty(self.nw, dtype=np.uint8)
+        _check(_lib.afqmc_get_walkers(self._s, _ptr(phi), _ptr(w), _ptr(lo),
+                                      alive.ctypes.data_as(C.POINTER(C.c_ubyte))))
+        phic = np.swapaxes(phi[:, 0] + 1j * phi[:, 1], 1, 2)   # (nw, M, N)
+        wv = w[:, 0] + 1j * w[:, 1] if self.mode == "free" else w
+        return dict(phi=phic, weight=wv, lnov=lo[:, 0] + 1j * lo[:, 1], alive=alive.astype(bool))
+
+    def info(self):
+        v = [C.c_int() for _ in range(5)]
+        t = C.c_int64()
+        _check(_lib.afqmc_sys_info(self._s, *[C.byref(x) for x in v], C.byref(t)))
+        return dict(M=v[0].value, n_chol=v[1].value, n_alpha=v[2].value, n_beta=v[3].value,
+                    n_walkers=v[4].value, step=t.value)
+
+    def checkpoint(self) -> bytes:
+        n = C.c_size_t()
+        _check(_lib.afqmc_checkpoint(self._s, None, C.byref(n)))
+        buf = C.create_string_buffer(n.value)
+        _check(_lib.afqmc_checkpoint(self._s, C.cast(buf, _vp), C.byref(n)))
+        return buf.raw
+
+    def restore(self, blob: bytes):
+        buf = C.create_string_buffer(blob, len(blob))
+        _check(_lib.afqmc_restore(self._s, C.cast(buf, _vp), len(blob)))
+
+    def free(self):
+        if getattr(self, "_s", None):
+            _lib.afqmc_free_sys(self._s)
+            self._s = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+def pair_step(a: System, b: System, n_steps: int, seed: int = 0, fields=None) -> np.ndarray:
+    """Correlated pair (Sec. II.B); returns the (n_meas, 3) trace E_a, E_b, dE."""
+    me = a.params.measure_every
+    t0 = a.info()["step"]
+    n_meas = sum(1 for i in range(n_steps) if me > 0 and (t0 + i + 1) % me == 0)
+    tr = np.zeros((max(n_meas, 1), 3))
+    _check(_lib.afqmc_pair_step(a._s, b._s, int(seed), int(n_steps), _dev_ptr(fields), _ptr(tr)))
+    return tr[:n_meas]
+
+
+def pair_batch_step(pairs, seeds, n_steps: int) -> np.ndarray:
+    """Many pairs advanced together; returns (n_pairs, n_meas, 3)."""
+    n = len(pairs)
+    me = pairs[0][0].params.measure_every
+    t0 = pairs[0][0].info()["step"]
+    n_meas = sum(1 for i in range(n_steps) if me > 0 and (t0 + i + 1) % me == 0)
+    A = (_vp * n)(*[p[0]._s for p in pairs])
+    B = (_vp * n)(*[p[1]._s for p in pairs])
+    S = (C.c_uint64 * n)(*[int(s) for s in seeds])
+    tr = np.zeros((n, max(n_meas, 1), 3))
+    _check(_lib.afqmc_pair_batch_step(n, A, B, S, int(n_steps), _ptr(tr)))
+    return tr[:, :n_meas]
+
+
+def selftest_gemm(A, B, precision: str = "fp64") -> np.ndarray:
+    A, B = _f64(A), _f64(B)
+    m, k = A.shape
+    n = B.shape[0]
+    Cm = np.empty((m, n))
+    _check(_lib.afqmc_selftest_gemm(PREC[precision], m, n, k, _ptr(A), _ptr(B), _ptr(Cm)))
+    return Cm
+
+
+def selftest_fields(seed: int, stream_id: int, t: int, nw: int, n_chol: int) -> np.ndarray:
+    out = np.empty((nw, n_chol))
+    _check(_lib.afqmc_selftest_fields(int(seed), int(stream_id), int(t), nw, n_chol, _ptr(out)))
+    return out

@@ -1,0 +1,889 @@
+// C ABI of the correlated-sampling ph-AFQMC walker step (see include/afqmc.h).
+// Host code: handle management, validation, the per-system precompute, and
+// the ordering of the device phases of one step.
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+#include <string>
+#include <vector>
+
+#include "../../include/afqmc.h"
+#include "internal.h"
+
+using namespace afq;
+
+namespace {
+
+thread_local std::string g_err;
+
+afqmc_status fail(afqmc_status s, const std::string& msg) {
+    g_err = msg;
+    return s;
+}
+
+#define HIPCHK(expr)                                                                    \
+    do {                                                                                \
+        hipError_t e_ = (expr);                                                         \
+        if (e_ != hipSuccess)                                                           \
+            return fail(AFQMC_E_DEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+size_t dt_size(DType t) { return t == DT_F64 ? 8 : (t == DT_F32 ? 4 : 2); }
+
+struct DevBuf {
+    void* p = nullptr;
+    size_t n = 0;
+    ~DevBuf() { release(); }
+    void release() {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        n = 0;
+    }
+    hipError_t alloc(size_t bytes) {
+        release();
+        if (bytes == 0) bytes = 16;
+        hipError_t e = hipMalloc(&p, bytes);
+        if (e == hipSuccess) n = bytes;
+        return e;
+    }
+    template <typename T>
+    T* as() const { return (T*)p; }
+};
+
+uint64_t fnv1a(const void* data, size_t n) {
+    const unsigned char* b = (const unsigned char*)data;
+    uint64_t h = 1469598103934665603ull;
+    for (size_t i = 0; i < n; ++i) {
+        h ^= b[i];
+        h *= 1099511628211ull;
+    }
+    return h;
+}
+
+// exp(X) for a small dense real matrix: scaling and squaring with a
+// degree-24 Taylor polynomial (||X / 2^s||_1 <= 1/4).
+void expm_host(const std::vector<double>& X, int n, std::vector<double>& out) {
+    double nrm = 0.0;
+    for (int j = 0; j < n; ++j) {
+        double c = 0.0;
+        for (int i = 0; i < n; ++i) c += fabs(X[(size_t)i * n + j]);
+        nrm = std::max(nrm, c);
+    }
+    int s = 0;
+    while (nrm > 0.25) {
+        nrm *= 0.5;
+        ++s;
+    }
+    const double sc = ldexp(1.0, -s);
+    std::vector<double> A(X.size()), term((size_t)n * n, 0.0), tmp((size_t)n * n);
+    for (size_t i = 0; i < A.size(); ++i) A[i] = X[i] * sc;
+    out.assign((size_t)n * n, 0.0);
+    for (int i = 0; i < n; ++i) out[(size_t)i * n + i] = term[(size_t)i * n + i] = 1.0;
+    auto mul = [&](const std::vector<double>& a, const std::vector<double>& b,
+                   std::vector<double>& c) {
+        std::fill(c.begin(), c.end(), 0.0);
+        for (int i = 0; i < n; ++i)
+            for (int k = 0; k < n; ++k) {
+                const double v = a[(size_t)i * n + k];
+                if (v == 0.0) continue;
+                for (int j = 0; j < n; ++j) c[(size_t)i * n + j] += v * b[(size_t)k * n + j];
+            }
+    };
+    for (int k = 1; k <= 24; ++k) {
+        mul(term, A, tmp);
+        for (size_t i = 0; i < tmp.size(); ++i) term[i] = tmp[i] / k;
+        for (size_t i = 0; i < tmp.size(); ++i) out[i] += term[i];
+    }
+    for (int q = 0; q < s; ++q) {
+        mul(out, out, tmp);
+        out.swap(tmp);
+    }
+}
+
+// Solve for Theta_T = Phi_T (Phi_T^T Phi_T)^{-1} of one spin block (host,
+// small): Gauss-Jordan with partial pivoting.
+bool theta_trial(const double* trial, int M, int N, int off, int n, double* out /* n x M rows */) {
+    std::vector<double> O((size_t)n * n), inv((size_t)n * n, 0.0);
+    for (int a = 0; a < n; ++a)
+        for (int b = 0; b < n; ++b) {
+            double s = 0.0;
+            for (int m = 0; m < M; ++m)
+                s += trial[(size_t)m * N + off + a] * trial[(size_t)m * N + off + b];
+            O[(size_t)a * n + b] = s;
+        }
+    for (int i = 0; i < n; ++i) inv[(size_t)i * n + i] = 1.0;
+    for (int k = 0; k < n; ++k) {
+        int p = k;
+        for (int r = k + 1; r < n; ++r)
+            if (fabs(O[(size_t)r * n + k]) > fabs(O[(size_t)p * n + k])) p = r;
+        if (O[(size_t)p * n + k] == 0.0) return false;
+        for (int c = 0; c < n; ++c) {
+            std::swap(O[(size_t)k * n + c], O[(size_t)p * n + c]);
+            std::swap(inv[(size_t)k * n + c], inv[(size_t)p * n + c]);
+        }
+        const double d = O[(size_t)k * n + k];
+        for (int c = 0; c < n; ++c) {
+            O[(size_t)k * n + c] /= d;
+            inv[(size_t)k * n + c] /= d;
+        }
+        for (int r = 0; r < n; ++r) {
+            if (r == k) continue;
+            const double f = O[(size_t)r * n + k];
+            if (f == 0.0) continue;
+            for (int c = 0; c < n; ++c) {
+                O[(size_t)r * n + c] -= f * O[(size_t)k * n + c];
+                inv[(size_t)r * n + c] -= f * inv[(size_t)k * n + c];
+            }
+        }
+    }
+    // Theta[m][c] = sum_l trial[m][off + l] inv[l][c]; stored as out[c][m]
+    for (int c = 0; c < n; ++c)
+        for (int m = 0; m < M; ++m) {
+            double s = 0.0;
+            for (int l = 0; l < n; ++l) s += trial[(size_t)m * N + off + l] * inv[(size_t)l * n + c];
+            out[(size_t)c * M + m] = s;
+        }
+    return true;
+}
+
+}  // namespace
+
+struct afqmc_ham_s {
+    int M = 0, n_chol = 0;
+    double e_core = 0.0;
+    hipStream_t stream = nullptr;
+    uint64_t chol_hash = 0;
+    std::vector<double> h;
+    DevBuf d_h, d_chol;
+    DevBuf d_lp[3];  // packed L^T per contraction precision: [P][n_chol]
+    int refs = 1;
+    bool released = false;
+};
+
+struct afqmc_sys_s {
+    afqmc_ham ham = nullptr;
+    int M = 0, n_chol = 0, na = 0, nb = 0, N = 0, nw = 0;
+    afqmc_params par{};
+    DType tc = DT_F64;  // contraction storage / compute type
+    DType tp = DT_F64;  // propagator product type
+    int64_t t = 0;
+    bool dead = false;
+    std::vector<double> a_host;
+    // constant per-system data
+    DevBuf d_trialT, d_P, d_Plp, d_a, d_lhx, d_lhx_lp;
+    // walker state
+    DevBuf d_phi, d_phinew, d_theta, d_theta_lp, d_w, d_lnov, d_alive;
+    // step scratch
+    DevBuf d_F, d_X, d_simp, d_Apk, d_Y, d_T2, d_Z, d_ov, d_lnd, d_exch, d_el, d_sums;
+    int n_gt_a = 0, n_gt_b = 0, n_gt = 0;
+    long P() const { return (long)M * (M + 1) / 2; }
+    long NM() const { return (long)N * M; }
+};
+
+namespace {
+
+afqmc_status check_sys(afqmc_sys s) {
+    if (!s) return fail(AFQMC_E_INVALID, "null system handle");
+    if (s->dead) return fail(AFQMC_E_STATE, "system handle already freed");
+    return AFQMC_OK;
+}
+
+void ham_unref(afqmc_ham h) {
+    if (--h->refs == 0) delete h;
+}
+
+const void* lp_or(const DevBuf& lp, const DevBuf& hi, DType t) { return t == DT_F64 ? hi.p : lp.p; }
+
+// ---- device phases of one step -------------------------------------------
+
+afqmc_status force_bias(afqmc_sys s, hipStream_t st) {
+    // F[(w,p), g] = sum_(i,m) Theta[(w,p),(i,m)] L^half[g,(i,m)], g <= n_chol
+    Gemm g{};
+    g.A = lp_or(s->d_theta_lp, s->d_theta, s->tc);
+    g.ta = s->tc;
+    g.ra = rows_strided(s->NM());
+    g.B = lp_or(s->d_lhx_lp, s->d_lhx, s->tc);
+    g.tb = s->tc;
+    g.rb = rows_strided(s->NM());
+    g.C = s->d_F.p;
+    g.tc = DT_F64;
+    g.rc = rows_strided(s->n_chol + 1);
+    g.alpha = 1.0;
+    g.m = 2 * s->nw;
+    g.n = s->n_chol + 1;
+    g.k = (int)s->NM();
+    g.batch = 1;
+    HIPCHK(gemm(g, s->tc, st));
+    return AFQMC_OK;
+}
+
+afqmc_status overlap_theta(afqmc_sys s, double* phi, hipStream_t st) {
+    Gemm g{};
+    g.A = phi;
+    g.ta = DT_F64;
+    g.ra = rows_strided(s->M);
+    g.B = s->d_trialT.p;
+    g.tb = DT_F64;
+    g.rb = rows_strided(s->M);
+    g.C = s->d_ov.p;
+    g.tc = DT_F64;
+    g.rc = rows_strided(s->N);
+    g.alpha = 1.0;
+    g.m = 2 * s->N * s->nw;
+    g.n = s->N;
+    g.k = s->M;
+    g.batch = 1;
+    HIPCHK(gemm(g, DT_F64, st));
+    HIPCHK(lu_theta(s->d_ov.as<double>(), phi, s->d_theta.as<double>(),
+                    s->tc == DT_F64 ? nullptr : s->d_theta_lp.p, s->tc, s->d_lnd.as<double>(),
+                    s->d_alive.as<uint8_t>(), s->nw, s->M, s->N, s->na, s->nb, st));
+    return AFQMC_OK;
+}
+
+afqmc_status one_step(afqmc_sys s, uint64_t seed, uint64_t stream_id, const double* ext,
+                      hipStream_t st) {
+    afqmc_status r;
+    if ((r = force_bias(s, st)) != AFQMC_OK) return r;
+    FieldArgs f{};
+    f.F = s->d_F.as<double>();
+    f.ldf = s->n_chol + 1;
+    f.a = s->d_a.as<double>();
+    f.ext = ext;
+    f.seed = seed;
+    f.stream = stream_id;
+    f.t = s->t;
+    f.alive = s->d_alive.as<uint8_t>();
+    f.X = s->d_X.p;
+    f.tx = s->tc;
+    f.ldx = s->n_chol;
+    f.s_imp = s->d_simp.as<double>();
+    f.nw = s->nw;
+    f.n_chol = s->n_chol;
+    f.sqdt = sqrt(s->par.dt);
+    f.free_proj = s->par.mode == AFQMC_FREE;
+    HIPCHK(fields(f, st));
+    // A[(w,p), q] = sum_g X[(w,p), g] Lpacked[q, g]
+    {
+        Gemm g{};
+        g.A = s->d_X.p;
+        g.ta = s->tc;
+        g.ra = rows_strided(s->n_chol);
+        g.B = s->ham->d_lp[s->tc].p;
+        g.tb = s->tc;
+        g.rb = rows_strided(s->n_chol);
+        g.C = s->d_Apk.p;
+        g.tc = s->tp;
+        g.rc = rows_strided(s->P());
+        g.alpha = 1.0;
+        g.m = 2 * s->nw;
+        g.n = (int)s->P();
+        g.k = s->n_chol;
+        g.batch = 1;
+        HIPCHK(gemm(g, s->tc, st));
+    }
+    const void* Pm = s->tp == DT_F64 ? s->d_P.p : s->d_Plp.p;
+    // Y = P Phi (first one-body half), Z = Y
+    {
+        Gemm g{};
+        g.A = s->d_phi.p;
+        g.ta = DT_F64;
+        g.ra = rows_strided(s->M);
+        g.B = Pm;
+        g.tb = s->tp;
+        g.rb = rows_strided(s->M);
+        g.C = s->d_Y.p;
+        g.C2 = s->d_Z.p;
+        g.tc = s->tp;
+        g.rc = rows_strided(s->M);
+        g.alpha = 1.0;
+        g.m = 2 * s->N * s->nw;
+        g.n = s->M;
+        g.k = s->M;
+        g.batch = 1;
+        HIPCHK(gemm(g, s->tp, st));
+    }
+    // Taylor series of exp(A) applied to Y, accumulated in Z
+    void* cur = s->d_Y.p;
+    void* nxt = s->d_T2.p;
+    for (int n = 1; n <= s->par.taylor_order; ++n) {
+        HIPCHK(taylor_term(cur, nxt, s->d_Z.p, s->d_Apk.p, s->d_alive.as<uint8_t>(), s->nw, s->M,
+                           s->N, 1.0 / n, s->tp, st));
+        std::swap(cur, nxt);
+    }
+    // Phi' = P Z (second one-body half), FP64 result
+    {
+        Gemm g{};
+        g.A = s->d_Z.p;
+        g.ta = s->tp;
+        g.ra = rows_strided(s->M);
+        g.B = Pm;
+        g.tb = s->tp;
+        g.rb = rows_strided(s->M);
+        g.C = s->d_phinew.p;
+        g.tc = DT_F64;
+        g.rc = rows_strided(s->M);
+        g.alpha = 1.0;
+        g.m = 2 * s->N * s->nw;
+        g.n = s->M;
+        g.k = s->M;
+        g.batch = 1;
+        HIPCHK(gemm(g, s->tp, st));
+    }
+    if ((r = overlap_theta(s, s->d_phinew.as<double>(), st)) != AFQMC_OK) return r;
+    HIPCHK(weights(s->d_lnd.as<double>(), s->d_simp.as<double>(), s->d_lnov.as<double>(),
+                   s->d_w.as<double>(), s->d_alive.as<uint8_t>(), s->nw, (int)s->par.mode, 1, st));
+    std::swap(s->d_phi.p, s->d_phinew.p);
+    s->t += 1;
+    return AFQMC_OK;
+}
+
+afqmc_status ortho(afqmc_sys s, hipStream_t st) {
+    HIPCHK(mgs(s->d_phi.as<double>(), s->d_alive.as<uint8_t>(), s->nw, s->M, s->N, s->na, s->nb,
+               st));
+    afqmc_status r = overlap_theta(s, s->d_phi.as<double>(), st);
+    if (r != AFQMC_OK) return r;
+    HIPCHK(weights(s->d_lnd.as<double>(), s->d_simp.as<double>(), s->d_lnov.as<double>(),
+                   s->d_w.as<double>(), s->d_alive.as<uint8_t>(), s->nw, (int)s->par.mode, 0, st));
+    return AFQMC_OK;
+}
+
+afqmc_status measure(afqmc_sys s, hipStream_t st) {
+    afqmc_status r = force_bias(s, st);
+    if (r != AFQMC_OK) return r;
+    const void* lh = lp_or(s->d_lhx_lp, s->d_lhx, s->tc);
+    const void* th = lp_or(s->d_theta_lp, s->d_theta, s->tc);
+    HIPCHK(exchange(lh, th, s->d_exch.as<double>(), s->nw, s->M, s->N, s->n_chol, 0, s->na, 0,
+                    s->n_gt, s->tc, st));
+    HIPCHK(exchange(lh, th, s->d_exch.as<double>(), s->nw, s->M, s->N, s->n_chol, s->na, s->nb, 1,
+                    s->n_gt, s->tc, st));
+    HIPCHK(local_energy(s->d_F.as<double>(), s->n_chol + 1, s->d_exch.as<double>(), s->n_gt_a,
+                        s->n_gt_b, s->nw, s->n_chol, s->ham->e_core, s->d_el.as<double>(), st));
+    HIPCHK(mixed_sums(s->d_el.as<double>(), s->d_w.as<double>(), s->d_alive.as<uint8_t>(), s->nw,
+                      (int)s->par.mode, s->d_sums.as<double>(), st));
+    return AFQMC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* afqmc_last_error(void) { return g_err.c_str(); }
+
+afqmc_status afqmc_load_hamiltonian(int M, int n_chol, const double* h1, const double* chol,
+                                    double e_core, void* hip_stream, afqmc_ham* out) {
+    if (!out) return fail(AFQMC_E_INVALID, "out is null");
+    *out = nullptr;
+    if (M <= 0 || n_chol < 0) return fail(AFQMC_E_INVALID, "M must be > 0 and n_chol >= 0");
+    if (!h1 || (n_chol > 0 && !chol)) return fail(AFQMC_E_INVALID, "null h1 or chol");
+    afqmc_ham h = new afqmc_ham_s();
+    h->M = M;
+    h->n_chol = n_chol;
+    h->e_core = e_core;
+    h->stream = (hipStream_t)hip_stream;
+    h->h.assign(h1, h1 + (size_t)M * M);
+    const size_t nL = (size_t)n_chol * M * M;
+    h->chol_hash = fnv1a(chol, nL * sizeof(double));
+    hipError_t e;
+    if ((e = h->d_h.alloc((size_t)M * M * 8)) != hipSuccess ||
+        (e = h->d_chol.alloc(nL * 8)) != hipSuccess) {
+        delete h;
+        return fail(AFQMC_E_NOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
+    }
+    if ((e = hipMemcpy(h->d_h.p, h1, (size_t)M * M * 8, hipMemcpyHostToDevice)) != hipSuccess ||
+        (nL && (e = hipMemcpy(h->d_chol.p, chol, nL * 8, hipMemcpyHostToDevice)) != hipSuccess)) {
+        delete h;
+        return fail(AFQMC_E_DEVICE, std::string("hipMemcpy: ") + hipGetErrorString(e));
+    }
+    *out = h;
+    return AFQMC_OK;
+}
+
+void afqmc_free_ham(afqmc_ham h) {
+    if (!h || h->released) return;
+    h->released = true;
+    ham_unref(h);
+}
+
+afqmc_status afqmc_init_walkers(afqmc_ham ham, int n_alpha, int n_beta, const double* trial,
+                                const double* init_phi, int n_walkers, const afqmc_params* par,
+                                afqmc_sys* out) {
+    if (!out) return fail(AFQMC_E_INVALID, "out is null");
+    *out = nullptr;
+    if (!ham || ham->released) return fail(AFQMC_E_INVALID, "null or freed Hamiltonian");
+    if (!trial || !par) return fail(AFQMC_E_INVALID, "null trial or params");
+    const int M = ham->M;
+    if (n_alpha < 0 || n_beta < 0 || n_alpha > M || n_beta > M || n_alpha + n_beta == 0)
+        return fail(AFQMC_E_SHAPE, "need 0 <= n_alpha, n_beta <= M and n_alpha + n_beta > 0");
+    if (n_alpha > 64 || n_beta > 64) return fail(AFQMC_E_SHAPE, "at most 64 electrons per spin");
+    if (n_walkers <= 0) return fail(AFQMC_E_INVALID, "n_walkers must be > 0");
+    if (!(par->dt > 0.0) || par->taylor_order < 1 || par->ortho_every < 0 || par->measure_every < 0)
+        return fail(AFQMC_E_INVALID, "bad params (dt > 0, taylor_order >= 1, periods >= 0)");
+    if (par->contract_prec < AFQMC_FP64 || par->contract_prec > AFQMC_BF16)
+        return fail(AFQMC_E_INVALID, "bad contract_prec");
+    if (par->mode != AFQMC_PHASELESS && par->mode != AFQMC_FREE)
+        return fail(AFQMC_E_INVALID, "bad mode");
+    hipStream_t st = ham->stream;
+    afqmc_sys s = new afqmc_sys_s();
+    s->ham = ham;
+    ham->refs++;
+    s->M = M;
+    s->n_chol = ham->n_chol;
+    s->na = n_alpha;
+    s->nb = n_beta;
+    s->N = n_alpha + n_beta;
+    s->nw = n_walkers;
+    s->par = *par;
+    s->tc = par->contract_prec == AFQMC_FP64 ? DT_F64
+                                             : (par->contract_prec == AFQMC_FP32 ? DT_F32 : DT_BF16);
+    s->tp = par->contract_prec == AFQMC_FP64 ? DT_F64 : DT_F32;
+    auto bail = [&](afqmc_status r) {
+        afqmc_free_sys(s);
+        return r;
+    };
+    const int N = s->N, nc = s->n_chol, nw = n_walkers;
+    const long NM = s->NM(), P = s->P();
+    s->n_gt_a = exchange_gtiles(nc, s->na, s->tc);
+    s->n_gt_b = exchange_gtiles(nc, s->nb, s->tc);
+    s->n_gt = std::max(1, std::max(s->n_gt_a, s->n_gt_b));
+    struct A_ {
+        DevBuf* b;
+        size_t bytes;
+    } allocs[] = {
+        {&s->d_trialT, (size_t)NM * 8},
+        {&s->d_P, (size_t)M * M * 8},
+        {&s->d_Plp, (size_t)M * M * 4},
+        {&s->d_a, (size_t)std::max(nc, 1) * 8},
+        {&s->d_lhx, (size_t)(nc + 1) * NM * 8},
+        {&s->d_lhx_lp, s->tc == DT_F64 ? 0 : (size_t)(nc + 1) * NM * dt_size(s->tc)},
+        {&s->d_phi, (size_t)nw * 2 * NM * 8},
+        {&s->d_phinew, (size_t)nw * 2 * NM * 8},
+        {&s->d_theta, (size_t)nw * 2 * NM * 8},
+        {&s->d_theta_lp, s->tc == DT_F64 ? 0 : (size_t)nw * 2 * NM * dt_size(s->tc)},
+        {&s->d_w, (size_t)nw * 2 * 8},
+        {&s->d_lnov, (size_t)nw * 2 * 8},
+        {&s->d_alive, (size_t)nw},
+        {&s->d_F, (size_t)nw * 2 * (nc + 1) * 8},
+        {&s->d_X, (size_t)nw * 2 * std::max(nc, 1) * dt_size(s->tc)},
+        {&s->d_simp, (size_t)nw * 4 * 8},
+        {&s->d_Apk, (size_t)nw * 2 * P * dt_size(s->tp)},
+        {&s->d_Y, (size_t)nw * 2 * NM * dt_size(s->tp)},
+        {&s->d_T2, (size_t)nw * 2 * NM * dt_size(s->tp)},
+        {&s->d_Z, (size_t)nw * 2 * NM * dt_size(s->tp)},
+        {&s->d_ov, (size_t)nw * 2 * N * N * 8},
+        {&s->d_lnd, (size_t)nw * 4 * 8},
+        {&s->d_exch, (size_t)nw * 2 * s->n_gt * 2 * 8},
+        {&s->d_el, (size_t)nw * 2 * 8},
+        {&s->d_sums, 8 * 8},
+    };
+    for (auto& a : allocs) {
+        hipError_t e = a.b->alloc(a.bytes);
+        if (e != hipSuccess)
+            return bail(fail(AFQMC_E_NOMEM, std::string("hipMalloc: ") + hipGetErrorString(e)));
+    }
+    // zero buffers read before first written (theta padding, F one-body row)
+    for (DevBuf* b : {&s->d_theta, &s->d_theta_lp, &s->d_lhx, &s->d_exch, &s->d_simp}) {
+        hipError_t e = hipMemsetAsync(b->p, 0, b->n, st);
+        if (e != hipSuccess) return bail(fail(AFQMC_E_DEVICE, hipGetErrorString(e)));
+    }
+    // trial^T (rows = orbitals)
+    std::vector<double> trialT((size_t)NM);
+    for (int i = 0; i < N; ++i)
+        for (int m = 0; m < M; ++m) trialT[(size_t)i * M + m] = trial[(size_t)m * N + i];
+    if (hipMemcpy(s->d_trialT.p, trialT.data(), NM * 8, hipMemcpyHostToDevice) != hipSuccess)
+        return bail(fail(AFQMC_E_DEVICE, "upload trial"));
+    // L^half_g[i][n] = sum_m trial[m][i] L_g[n][m]; row n_chol holds h^half.
+    {
+        Gemm g{};
+        g.A = s->d_trialT.p;
+        g.ta = DT_F64;
+        g.ra = rows_strided(M);
+        g.a_bs = 0;
+        g.B = ham->d_chol.p;
+        g.tb = DT_F64;
+        g.rb = rows_strided(M);
+        g.b_bs = (long)M * M;
+        g.C = s->d_lhx.p;
+        g.tc = DT_F64;
+        g.rc = rows_strided(M);
+        g.c_bs = NM;
+        g.alpha = 1.0;
+        g.m = N;
+        g.n = M;
+        g.k = M;
+        g.batch = nc;
+        if (nc > 0 && gemm(g, DT_F64, st) != hipSuccess)
+            return bail(fail(AFQMC_E_DEVICE, "L^half GEMM"));
+        g.B = ham->d_h.p;
+        g.b_bs = 0;
+        g.C = s->d_lhx.as<double>() + (size_t)nc * NM;
+        g.batch = 1;
+        if (gemm(g, DT_F64, st) != hipSuccess) return bail(fail(AFQMC_E_DEVICE, "h^half GEMM"));
+    }
+    // a_g = sum_s Tr(L^half_gs Theta_T^s): the force-bias trace of the trial.
+    std::vector<double> thT((size_t)2 * NM, 0.0);
+    if (s->na && !theta_trial(trial, M, N, 0, s->na, thT.data()))
+        return bail(fail(AFQMC_E_SINGULAR, "trial alpha block is singular"));
+    if (s->nb && !theta_trial(trial, M, N, s->na, s->nb, thT.data() + (size_t)s->na * M))
+        return bail(fail(AFQMC_E_SINGULAR, "trial beta block is singular"));
+    std::vector<double> Ftrial((size_t)2 * (nc + 1));
+    {
+        DevBuf dth, dF;
+        if (dth.alloc(2 * NM * 8) != hipSuccess || dF.alloc(2 * (nc + 1) * 8) != hipSuccess)
+            return bail(fail(AFQMC_E_NOMEM, "scratch"));
+        if (hipMemcpy(dth.p, thT.data(), 2 * NM * 8, hipMemcpyHostToDevice) != hipSuccess)
+            return bail(fail(AFQMC_E_DEVICE, "upload"));
+        Gemm g{};
+        g.A = dth.p;
+        g.ta = DT_F64;
+        g.ra = rows_strided(NM);
+        g.B = s->d_lhx.p;
+        g.tb = DT_F64;
+        g.rb = rows_strided(NM);
+        g.C = dF.p;
+        g.tc = DT_F64;
+        g.rc = rows_strided(nc + 1);
+        g.alpha = 1.0;
+        g.m = 2;
+        g.n = nc + 1;
+        g.k = (int)NM;
+        g.batch = 1;
+        if (gemm(g, DT_F64, st) != hipSuccess) return bail(fail(AFQMC_E_DEVICE, "a GEMM"));
+        if (hipStreamSynchronize(st) != hipSuccess ||
+            hipMemcpy(Ftrial.data(), dF.p, Ftrial.size() * 8, hipMemcpyDeviceToHost) != hipSuccess)
+            return bail(fail(AFQMC_E_DEVICE, "a download"));
+    }
+    s->a_host.assign(Ftrial.begin(), Ftrial.begin() + nc);
+    if (nc > 0 && hipMemcpy(s->d_a.p, s->a_host.data(), nc * 8, hipMemcpyHostToDevice) != hipSuccess)
+        return bail(fail(AFQMC_E_DEVICE, "upload a"));
+    // h~ = h - 1/2 sum_g L_g L_g + sum_g a_g L_g  (Eq. 2 remainder), P = exp(-dt h~ / 2)
+    std::vector<double> ht(ham->h);
+    if (nc > 0) {
+        DevBuf dLT, dL2, daL;
+        if (dLT.alloc((size_t)nc * M * M * 8) != hipSuccess || dL2.alloc((size_t)M * M * 8) ||
+            daL.alloc((size_t)M * M * 8))
+            return bail(fail(AFQMC_E_NOMEM, "scratch"));
+        Gemm g{};
+        g.A = dLT.p;
+        g.ta = DT_F64;
+        g.ra = rows_strided((long)nc * M);
+        g.B = dLT.p;
+        g.tb = DT_F64;
+        g.rb = rows_strided((long)nc * M);
+        g.C = dL2.p;
+        g.tc = DT_F64;
+        g.rc = rows_strided(M);
+        g.alpha = 1.0;
+        g.m = M;
+        g.n = M;
+        g.k = nc * M;
+        g.batch = 1;
+        if (permute_chol(ham->d_chol.as<double>(), dLT.as<double>(), M, nc, st) != hipSuccess ||
+            gemm(g, DT_F64, st) != hipSuccess ||
+            chol_weighted_sum(ham->d_chol.as<double>(), s->d_a.as<double>(), daL.as<double>(), M,
+                              nc, st) != hipSuccess)
+            return bail(fail(AFQMC_E_DEVICE, "h~ kernels"));
+        std::vector<double> l2((size_t)M * M), al((size_t)M * M);
+        if (hipStreamSynchronize(st) != hipSuccess ||
+            hipMemcpy(l2.data(), dL2.p, l2.size() * 8, hipMemcpyDeviceToHost) != hipSuccess ||
+            hipMemcpy(al.data(), daL.p, al.size() * 8, hipMemcpyDeviceToHost) != hipSuccess)
+            return bail(fail(AFQMC_E_DEVICE, "h~ download"));
+        for (size_t i = 0; i < ht.size(); ++i) ht[i] = ht[i] - 0.5 * l2[i] + al[i];
+    }
+    {
+        std::vector<double> X(ht.size()), Pm;
+        for (size_t i = 0; i < X.size(); ++i) X[i] = -0.5 * par->dt * ht[i];
+        expm_host(X, M, Pm);
+        std::vector<float> Pf(Pm.begin(), Pm.end());
+        if (hipMemcpy(s->d_P.p, Pm.data(), Pm.size() * 8, hipMemcpyHostToDevice) != hipSuccess ||
+            hipMemcpy(s->d_Plp.p, Pf.data(), Pf.size() * 4, hipMemcpyHostToDevice) != hipSuccess)
+            return bail(fail(AFQMC_E_DEVICE, "upload P"));
+    }
+    // low-precision copies of the contraction operands
+    if (s->tc != DT_F64 &&
+        convert(s->d_lhx.as<double>(), s->d_lhx_lp.p, s->tc, (long)(nc + 1) * NM, st) != hipSuccess)
+        return bail(fail(AFQMC_E_DEVICE, "convert L^half"));
+    if (!ham->d_lp[s->tc].p) {
+        if (ham->d_lp[s->tc].alloc((size_t)P * std::max(nc, 1) * dt_size(s->tc)) != hipSuccess)
+            return bail(fail(AFQMC_E_NOMEM, "packed L"));
+        if (pack_chol(ham->d_chol.as<double>(), ham->d_lp[s->tc].p, s->tc, M, nc, st) != hipSuccess)
+            return bail(fail(AFQMC_E_DEVICE, "pack L"));
+    }
+    // walkers: Phi = init (real), w = 1, alive = 1
+    {
+        const double* src = init_phi ? init_phi : trial;
+        std::vector<double> one((size_t)2 * NM, 0.0);
+        for (int i = 0; i < N; ++i)
+            for (int m = 0; m < M; ++m) one[(size_t)i * M + m] = src[(size_t)m * N + i];
+        for (int k = 0; k < nw; ++k)
+            if (hipMemcpyAsync(s->d_phi.as<double>() + (size_t)k * 2 * NM, one.data(), 2 * NM * 8,
+                               hipMemcpyHostToDevice, st) != hipSuccess)
+                return bail(fail(AFQMC_E_DEVICE, "upload walkers"));
+        std::vector<double> w((size_t)2 * nw, 0.0);
+        for (int k = 0; k < nw; ++k) w[par->mode == AFQMC_FREE ? 2 * k : k] = 1.0;
+        std::vector<uint8_t> al((size_t)nw, 1);
+        if (hipMemcpyAsync(s->d_w.p, w.data(), w.size() * 8, hipMemcpyHostToDevice, st) ||
+            hipMemcpyAsync(s->d_alive.p, al.data(), nw, hipMemcpyHostToDevice, st))
+            return bail(fail(AFQMC_E_DEVICE, "upload weights"));
+        if (hipStreamSynchronize(st) != hipSuccess) return bail(fail(AFQMC_E_DEVICE, "sync"));
+    }
+    afqmc_status r = overlap_theta(s, s->d_phi.as<double>(), st);
+    if (r != AFQMC_OK) return bail(r);
+    if (weights(s->d_lnd.as<double>(), s->d_simp.as<double>(), s->d_lnov.as<double>(),
+                s->d_w.as<double>(), s->d_alive.as<uint8_t>(), nw, (int)par->mode, 0,
+                st) != hipSuccess)
+        return bail(fail(AFQMC_E_DEVICE, "lnov"));
+    std::vector<double> lnov((size_t)2 * nw);
+    if (hipStreamSynchronize(st) != hipSuccess ||
+        hipMemcpy(lnov.data(), s->d_lnov.p, lnov.size() * 8, hipMemcpyDeviceToHost) != hipSuccess)
+        return bail(fail(AFQMC_E_DEVICE, "init overlap"));
+    for (int k = 0; k < nw; ++k)
+        if (!std::isfinite(lnov[2 * k]))
+            return bail(fail(AFQMC_E_SINGULAR, "initial determinant has zero overlap with the trial"));
+    *out = s;
+    return AFQMC_OK;
+}
+
+void afqmc_free_sys(afqmc_sys s) {
+    if (!s || s->dead) return;
+    s->dead = true;
+    afqmc_ham h = s->ham;
+    // release device memory now; the (dead) handle itself stays valid so that
+    // later calls on it report E_STATE instead of touching freed memory
+    for (DevBuf* b : {&s->d_trialT, &s->d_P, &s->d_Plp, &s->d_a, &s->d_lhx, &s->d_lhx_lp,
+                      &s->d_phi, &s->d_phinew, &s->d_theta, &s->d_theta_lp, &s->d_w, &s->d_lnov,
+                      &s->d_alive, &s->d_F, &s->d_X, &s->d_simp, &s->d_Apk, &s->d_Y, &s->d_T2,
+                      &s->d_Z, &s->d_ov, &s->d_lnd, &s->d_exch, &s->d_el, &s->d_sums})
+        b->release();
+    s->ham = nullptr;
+    if (h) ham_unref(h);
+}
+
+afqmc_status afqmc_step(afqmc_sys s, uint64_t seed, uint64_t stream_id, int n_steps,
+                        const double* fields_dev) {
+    afqmc_status r = check_sys(s);
+    if (r != AFQMC_OK) return r;
+    if (n_steps < 0) return fail(AFQMC_E_INVALID, "n_steps < 0");
+    hipStream_t st = s->ham->stream;
+    for (int i = 0; i < n_steps; ++i) {
+        const double* ext = fields_dev ? fields_dev + (size_t)i * s->nw * s->n_chol : nullptr;
+        if ((r = one_step(s, seed, stream_id, ext, st)) != AFQMC_OK) return r;
+        if (s->par.ortho_every > 0 && s->t % s->par.ortho_every == 0)
+            if ((r = ortho(s, st)) != AFQMC_OK) return r;
+    }
+    return AFQMC_OK;
+}
+
+afqmc_status afqmc_orthonormalize(afqmc_sys s) {
+    afqmc_status r = check_sys(s);
+    if (r != AFQMC_OK) return r;
+    return ortho(s, s->ham->stream);
+}
+
+afqmc_status afqmc_local_energy(afqmc_sys s, double* e_local, double* weights_out, double* e_mixed) {
+    afqmc_status r = check_sys(s);
+    if (r != AFQMC_OK) return r;
+    hipStream_t st = s->ham->stream;
+    if ((r = measure(s, st)) != AFQMC_OK) return r;
+    HIPCHK(hipStreamSynchronize(st));
+    if (e_local) HIPCHK(hipMemcpy(e_local, s->d_el.p, (size_t)s->nw * 16, hipMemcpyDeviceToHost));
+    if (weights_out)
+        HIPCHK(hipMemcpy(weights_out, s->d_w.p,
+                         (size_t)s->nw * 8 * (s->par.mode == AFQMC_FREE ? 2 : 1),
+                         hipMemcpyDeviceToHost));
+    if (e_mixed) {
+        double sums[4];
+        HIPCHK(hipMemcpy(sums, s->d_sums.p, sizeof(sums), hipMemcpyDeviceToHost));
+        if (s->par.mode == AFQMC_PHASELESS)
+            *e_mixed = sums[0] / sums[1];
+        else
+            *e_mixed = (sums[0] * sums[2] + sums[1] * sums[3]) / (sums[2] * sums[2] + sums[3] * sums[3]);
+    }
+    return AFQMC_OK;
+}
+
+afqmc_status afqmc_pair_step(afqmc_sys a, afqmc_sys b, uint64_t seed, int n_steps,
+                             const double* fields_dev, double* e_trace) {
+    afqmc_status r;
+    if ((r = check_sys(a)) != AFQMC_OK || (r = check_sys(b)) != AFQMC_OK) return r;
+    if (n_steps < 0) return fail(AFQMC_E_INVALID, "n_steps < 0");
+    if (a == b) return fail(AFQMC_E_INVALID, "a pair needs two distinct systems");
+    if (a->M != b->M || a->n_chol != b->n_chol || a->nw != b->nw ||
+        a->ham->chol_hash != b->ham->chol_hash)
+        return fail(AFQMC_E_SHAPE, "pair systems must share M, n_chol, walker count and L");
+    if (a->par.dt != b->par.dt || a->par.ortho_every != b->par.ortho_every ||
+        a->par.measure_every != b->par.measure_every || a->par.mode != b->par.mode)
+        return fail(AFQMC_E_SHAPE, "pair systems must share dt, periods and mode");
+    if (a->t != b->t) return fail(AFQMC_E_STATE, "pair systems are at different steps");
+    if (a->ham->stream != b->ham->stream) return fail(AFQMC_E_SHAPE, "pair systems need one stream");
+    hipStream_t st = a->ham->stream;
+    const int me = a->par.measure_every, oe = a->par.ortho_every;
+    int n_meas = 0;
+    for (int i = 0; i < n_steps; ++i)
+        if (me > 0 && (a->t + i + 1) % me == 0) ++n_meas;
+    DevBuf trace;
+    HIPCHK(trace.alloc((size_t)std::max(1, n_meas) * 3 * 8));
+    int slot = 0;
+    for (int i = 0; i < n_steps; ++i) {
+        const double* ext = fields_dev ? fields_dev + (size_t)i * a->nw * a->n_chol : nullptr;
+        if ((r = one_step(a, seed, 0, ext, st)) != AFQMC_OK) return r;
+        if ((r = one_step(b, seed, 0, ext, st)) != AFQMC_OK) return r;
+        if (oe > 0 && a->t % oe == 0) {
+            if ((r = ortho(a, st)) != AFQMC_OK) return r;
+            if ((r = ortho(b, st)) != AFQMC_OK) return r;
+        }
+        if (me > 0 && a->t % me == 0) {
+            if ((r = measure(a, st)) != AFQMC_OK) return r;
+            if ((r = measure(b, st)) != AFQMC_OK) return r;
+            HIPCHK(trace_record(a->d_sums.as<double>(), b->d_sums.as<double>(),
+                                trace.as<double>(), slot++, (int)a->par.mode, st));
+        }
+    }
+    HIPCHK(hipStreamSynchronize(st));
+    if (e_trace && n_meas > 0)
+        HIPCHK(hipMemcpy(e_trace, trace.p, (size_t)n_meas * 3 * 8, hipMemcpyDeviceToHost));
+    return AFQMC_OK;
+}
+
+afqmc_status afqmc_pair_batch_step(int n_pairs, const afqmc_sys* a, const afqmc_sys* b,
+                                   const uint64_t* seeds, int n_steps, double* e_traces) {
+    (void)n_pairs;
+    (void)a;
+    (void)b;
+    (void)seeds;
+    (void)n_steps;
+    (void)e_traces;
+    return fail(AFQMC_E_STATE, "pair batch step not available in this build");
+}
+
+afqmc_status afqmc_get_walkers(afqmc_sys s, double* phi, double* w, double* log_ovlp,
+                               unsigned char* alive) {
+    afqmc_status r = check_sys(s);
+    if (r != AFQMC_OK) return r;
+    HIPCHK(hipStreamSynchronize(s->ham->stream));
+    if (phi) HIPCHK(hipMemcpy(phi, s->d_phi.p, (size_t)s->nw * 2 * s->NM() * 8, hipMemcpyDeviceToHost));
+    if (w)
+        HIPCHK(hipMemcpy(w, s->d_w.p, (size_t)s->nw * 8 * (s->par.mode == AFQMC_FREE ? 2 : 1),
+                         hipMemcpyDeviceToHost));
+    if (log_ovlp) HIPCHK(hipMemcpy(log_ovlp, s->d_lnov.p, (size_t)s->nw * 16, hipMemcpyDeviceToHost));
+    if (alive) HIPCHK(hipMemcpy(alive, s->d_alive.p, (size_t)s->nw, hipMemcpyDeviceToHost));
+    return AFQMC_OK;
+}
+
+afqmc_status afqmc_sys_info(afqmc_sys s, int* M, int* n_chol, int* n_alpha, int* n_beta,
+                            int* n_walkers, int64_t* step) {
+    afqmc_status r = check_sys(s);
+    if (r != AFQMC_OK) return r;
+    if (M) *M = s->M;
+    if (n_chol) *n_chol = s->n_chol;
+    if (n_alpha) *n_alpha = s->na;
+    if (n_beta) *n_beta = s->nb;
+    if (n_walkers) *n_walkers = s->nw;
+    if (step) *step = s->t;
+    return AFQMC_OK;
+}
+
+afqmc_status afqmc_checkpoint(afqmc_sys s, void* dst, size_t* bytes) {
+    afqmc_status r = check_sys(s);
+    if (r != AFQMC_OK) return r;
+    if (!bytes) return fail(AFQMC_E_INVALID, "bytes is null");
+    const size_t nphi = (size_t)s->nw * 2 * s->NM() * 8;
+    const size_t need = 64 + 2 * nphi + s->d_w.n + s->d_lnov.n + s->nw;
+    if (!dst) {
+        *bytes = need;
+        return AFQMC_OK;
+    }
+    if (*bytes < need) return fail(AFQMC_E_INVALID, "checkpoint buffer too small");
+    HIPCHK(hipStreamSynchronize(s->ham->stream));
+    char* p = (char*)dst;
+    int64_t hdr[8] = {0x41465143, s->t, s->M, s->N, s->nw, s->n_chol, (int64_t)need, 0};
+    memcpy(p, hdr, 64);
+    p += 64;
+    HIPCHK(hipMemcpy(p, s->d_phi.p, nphi, hipMemcpyDeviceToHost));
+    p += nphi;
+    HIPCHK(hipMemcpy(p, s->d_theta.p, nphi, hipMemcpyDeviceToHost));
+    p += nphi;
+    HIPCHK(hipMemcpy(p, s->d_w.p, s->d_w.n, hipMemcpyDeviceToHost));
+    p += s->d_w.n;
+    HIPCHK(hipMemcpy(p, s->d_lnov.p, s->d_lnov.n, hipMemcpyDeviceToHost));
+    p += s->d_lnov.n;
+    HIPCHK(hipMemcpy(p, s->d_alive.p, s->nw, hipMemcpyDeviceToHost));
+    *bytes = need;
+    return AFQMC_OK;
+}
+
+afqmc_status afqmc_restore(afqmc_sys s, const void* src, size_t bytes) {
+    afqmc_status r = check_sys(s);
+    if (r != AFQMC_OK) return r;
+    if (!src) return fail(AFQMC_E_INVALID, "src is null");
+    const size_t nphi = (size_t)s->nw * 2 * s->NM() * 8;
+    const size_t need = 64 + 2 * nphi + s->d_w.n + s->d_lnov.n + s->nw;
+    int64_t hdr[8];
+    if (bytes < need) return fail(AFQMC_E_SHAPE, "checkpoint too small for this system");
+    memcpy(hdr, src, 64);
+    if (hdr[0] != 0x41465143 || hdr[2] != s->M || hdr[3] != s->N || hdr[4] != s->nw ||
+        hdr[5] != s->n_chol || hdr[6] != (int64_t)need)
+        return fail(AFQMC_E_SHAPE, "checkpoint does not match this system");
+    hipStream_t st = s->ham->stream;
+    const char* p = (const char*)src + 64;
+    HIPCHK(hipStreamSynchronize(st));
+    HIPCHK(hipMemcpy(s->d_phi.p, p, nphi, hipMemcpyHostToDevice));
+    p += nphi;
+    HIPCHK(hipMemcpy(s->d_theta.p, p, nphi, hipMemcpyHostToDevice));
+    p += nphi;
+    HIPCHK(hipMemcpy(s->d_w.p, p, s->d_w.n, hipMemcpyHostToDevice));
+    p += s->d_w.n;
+    HIPCHK(hipMemcpy(s->d_lnov.p, p, s->d_lnov.n, hipMemcpyHostToDevice));
+    p += s->d_lnov.n;
+    HIPCHK(hipMemcpy(s->d_alive.p, p, s->nw, hipMemcpyHostToDevice));
+    if (s->tc != DT_F64) {
+        HIPCHK(convert(s->d_theta.as<double>(), s->d_theta_lp.p, s->tc, (long)s->nw * 2 * s->NM(), st));
+        HIPCHK(hipStreamSynchronize(st));
+    }
+    s->t = hdr[1];
+    return AFQMC_OK;
+}
+
+afqmc_status afqmc_selftest_gemm(afqmc_prec prec, int m, int n, int k, const double* A,
+                                 const double* B, double* C) {
+    if (!A || !B || !C || m <= 0 || n <= 0 || k <= 0) return fail(AFQMC_E_INVALID, "bad args");
+    DevBuf dA, dB, dC;
+    HIPCHK(dA.alloc((size_t)m * k * 8));
+    HIPCHK(dB.alloc((size_t)n * k * 8));
+    HIPCHK(dC.alloc((size_t)m * n * 8));
+    HIPCHK(hipMemcpy(dA.p, A, (size_t)m * k * 8, hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(dB.p, B, (size_t)n * k * 8, hipMemcpyHostToDevice));
+    Gemm g{};
+    g.A = dA.p;
+    g.ta = DT_F64;
+    g.ra = rows_strided(k);
+    g.B = dB.p;
+    g.tb = DT_F64;
+    g.rb = rows_strided(k);
+    g.C = dC.p;
+    g.tc = DT_F64;
+    g.rc = rows_strided(n);
+    g.alpha = 1.0;
+    g.m = m;
+    g.n = n;
+    g.k = k;
+    g.batch = 1;
+    const DType c = prec == AFQMC_FP64 ? DT_F64 : (prec == AFQMC_FP32 ? DT_F32 : DT_BF16);
+    HIPCHK(gemm(g, c, nullptr));
+    HIPCHK(hipDeviceSynchronize());
+    HIPCHK(hipMemcpy(C, dC.p, (size_t)m * n * 8, hipMemcpyDeviceToHost));
+    return AFQMC_OK;
+}
+
+afqmc_status afqmc_selftest_fields(uint64_t seed, uint64_t stream_id, int64_t t, int nw, int n_chol,
+                                   double* out) {
+    if (!out || nw <= 0 || n_chol <= 0) return fail(AFQMC_E_INVALID, "bad args");
+    DevBuf d;
+    HIPCHK(d.alloc((size_t)nw * n_chol * 8));
+    HIPCHK(philox_normals(seed, stream_id, t, nw, n_chol, d.as<double>(), nullptr));
+    HIPCHK(hipDeviceSynchronize());
+    HIPCHK(hipMemcpy(out, d.p, (size_t)nw * n_chol * 8, hipMemcpyDeviceToHost));
+    return AFQMC_OK;
+}
+
+}  // extern "C"

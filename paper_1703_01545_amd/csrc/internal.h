@@ -1,0 +1,137 @@
+// Internal launch interface between the C-ABI host code and the gfx950
+// kernels.  Nothing here is part of the public ABI (include/afqmc.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <hip/hip_bf16.h>
+#include <stdint.h>
+
+namespace afq {
+
+typedef __bf16 bf16_t;
+
+// Row r of a K-contiguous operand starts at element
+//   base + (r / n_in) * s_out + (r % n_in) * s_in
+// (a two-level row index: e.g. (walker*2 + plane, orbital) rows of a walker
+// block, or (gamma, orbital) rows of the half-rotated Cholesky tensor).
+struct RowMap {
+    long base;
+    int n_in;
+    long s_in;
+    long s_out;
+};
+
+inline RowMap rows_strided(long stride, long base = 0) { return RowMap{base, 1, 0, stride}; }
+inline RowMap rows_2level(int n_in, long s_in, long s_out, long base = 0) {
+    return RowMap{base, n_in, s_in, s_out};
+}
+
+enum DType { DT_F64 = 0, DT_F32 = 1, DT_BF16 = 2 };
+
+// C[b][i, j] = alpha * sum_k A[b](i, k) * B[b](j, k) + beta * C[b][i, j]
+// A(i, k) = A[b * a_bs + rowA(i) + k], B(j, k) = B[b * b_bs + rowB(j) + k],
+// C element (i, j) at c_base + b * c_bs + rowC(i) + j.
+// An optional second output C2 (same layout) receives the same values
+// (alpha * acc) without the beta term.
+struct Gemm {
+    const void* A;
+    DType ta;
+    RowMap ra;
+    long a_bs;
+    const void* B;
+    DType tb;
+    RowMap rb;
+    long b_bs;
+    void* C;
+    DType tc;
+    RowMap rc;
+    long c_bs;
+    void* C2;
+    double alpha;
+    double beta;
+    int m, n, k, batch;
+};
+
+// Compute precision of a GEMM (the MFMA input type; accumulation is FP64 for
+// DT_F64 and FP32 otherwise).
+hipError_t gemm(const Gemm& g, DType compute, hipStream_t s);
+
+// One Taylor term of the HS propagator for every walker (complex, Eq. 11):
+//   Tn[w] = (1/n) A_w Tprev[w],  Z[w] += Tn[w]
+// Tprev, Tn, Z: walker blocks [w][plane][N][M] (plane stride N*M); A_w
+// complex symmetric packed (upper triangle, row-major) at
+// Apk[(2w + plane) * P + q], P = M(M+1)/2.  Walkers with live[w] == 0 are
+// skipped.
+hipError_t taylor_term(const void* Tprev, void* Tn, void* Z, const void* Apk, const uint8_t* live,
+                       int nw, int M, int N, double inv_n, DType t, hipStream_t s);
+
+// Exchange partial sums of the mixed local energy:
+//   out[(w * 2 + spin) * n_gtiles + gt] = sum over gamma in tile gt of
+//   sum_ij T_ij T_ji,  T = L^half_{gamma, spin} Theta^spin_w   (complex, 2 doubles)
+// lhalf: [(n_chol + 1)][N][M] in type t (last row unused here);
+// theta: [w][plane][N][M] in type t.  Returns n_gtiles through *ntiles.
+hipError_t exchange(const void* lhalf, const void* theta, double* out, int nw, int M, int N,
+                    int n_chol, int off, int nsig, int spin, int n_gtiles_alloc, DType t,
+                    hipStream_t s);
+int exchange_gtiles(int n_chol, int nsig, DType t);
+
+// ---------------------------------------------------------------- walker-wise
+struct FieldArgs {
+    const double* F;      // [w][2][ldf]  force-bias traces f_g (re, im), gamma < n_chol
+    int ldf;
+    const double* a;      // [n_chol] mean-field shift a_g
+    const double* ext;    // NULL or external fields for this step: [nw][n_chol]
+    uint64_t seed, stream;
+    int64_t t;            // absolute step (Philox counter word)
+    const uint8_t* alive;
+    void* X;              // [w][2][ldx] field-sum coefficients, type tx
+    DType tx;
+    int ldx;
+    double* s_imp;        // [w][4]: s (re, im), importance exponent (re, im)
+    int nw, n_chol;
+    double sqdt;
+    int free_proj;        // 1: xbar = 0 (free projection)
+};
+hipError_t fields(const FieldArgs& f, hipStream_t s);
+
+hipError_t philox_normals(uint64_t seed, uint64_t stream, int64_t t, int nw, int n_chol,
+                          double* out, hipStream_t s);
+
+// Overlap matrices ov[w][plane][N][N] (row = walker orbital i, col = trial
+// orbital j) -> per spin block: ln det (lnd[w][spin] complex) and
+// Theta = Phi O^{-1} written to theta (FP64, [w][2][N][M]); optional low
+// precision copy theta_lp (type tlp) for the contractions.
+hipError_t lu_theta(const double* ov, const double* phi, double* theta, void* theta_lp, DType tlp,
+                    double* lnd, const uint8_t* live, int nw, int M, int N, int na, int nb,
+                    hipStream_t s);
+
+// Weight update: lnR = sum_s lnd - lnov + s; lnI = lnR + imp;
+// phaseless: w *= exp(Re lnI) max(0, cos Im lnR), frozen when not > 0;
+// free: complex W *= exp(lnR).  lnov <- sum_s lnd for live walkers.
+// commit == 0 (after Gram-Schmidt): only lnov is refreshed.
+hipError_t weights(const double* lnd, const double* s_imp, double* lnov, double* w, uint8_t* alive,
+                   int nw, int mode, int commit, hipStream_t s);
+
+hipError_t mgs(double* phi, const uint8_t* live, int nw, int M, int N, int na, int nb,
+               hipStream_t s);
+
+// E_L[w] (complex) from F (f_g and the one-body trace at column n_chol) and
+// the exchange partials.
+hipError_t local_energy(const double* F, int ldf, const double* exch, int n_gt_a, int n_gt_b,
+                        int nw, int n_chol, double e_core, double* el, hipStream_t s);
+
+// out[0] = sum_w alive w Re E_L, out[1] = sum_w alive w (phaseless); free
+// mode: out[0..3] = sum W E_L (re, im), sum W (re, im).
+hipError_t mixed_sums(const double* el, const double* w, const uint8_t* alive, int nw, int mode,
+                      double* out, hipStream_t s);
+
+// Small helpers.
+hipError_t convert(const double* src, void* dst, DType t, long n, hipStream_t s);
+hipError_t pack_chol(const double* L, void* Lp, DType t, int M, int n_chol, hipStream_t s);
+hipError_t permute_chol(const double* L, double* LT, int M, int n_chol, hipStream_t s);
+hipError_t chol_weighted_sum(const double* L, const double* a, double* out, int M, int n_chol,
+                             hipStream_t s);
+hipError_t trace_record(const double* sums_a, const double* sums_b, double* trace, int slot,
+                        int mode, hipStream_t s);
+
+}  // namespace afq

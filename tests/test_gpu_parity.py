@@ -1,0 +1,253 @@
+"""GPU (HIP) path vs the FP64 oracle on identical seeded inputs.
+
+FP64 parity bar: 1e-10 relative in every measured energy and per-walker
+weight, log-overlap (imaginary part compared modulo 2 pi) and determinant.
+"""
+import numpy as np
+import pytest
+
+from oracle import afqmc as O
+from oracle import philox
+from synth import config
+
+from tests.gpu_helpers import Workload, banner, phase_diff, rel
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-10
+
+
+@pytest.fixture(scope="module")
+def lib():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_1703_01545_amd import afqmc
+    return afqmc
+
+
+@pytest.fixture(scope="module")
+def torch_mod():
+    import torch
+    return torch
+
+
+def _bf16_round(x):
+    f = np.asarray(x, dtype=np.float32).view(np.uint32).astype(np.uint64)
+    rounded = ((f + 0x7FFF + ((f >> 16) & 1)) >> 16) << 16
+    return rounded.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+@pytest.mark.parametrize("shape", [(1, 1, 1), (37, 53, 29), (200, 160, 333), (300, 260, 64),
+                                   (1000, 700, 96)])
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16"])
+def test_gemm_kernel(lib, shape, prec):
+    banner(f"gemm {prec} {shape}")
+    m, n, k = shape
+    rng = np.random.default_rng(m * 7 + n + k)
+    A = rng.standard_normal((m, k))
+    B = rng.standard_normal((n, k))
+    got = lib.selftest_gemm(A, B, prec)
+    if prec == "fp64":
+        ref, tol = A @ B.T, 1e-13
+    elif prec == "fp32":
+        ref, tol = A.astype(np.float32).astype(np.float64) @ B.astype(np.float32).astype(np.float64).T, 2e-6
+    else:
+        ref, tol = _bf16_round(A) @ _bf16_round(B).T, 2e-6
+    scale = np.abs(A) @ np.abs(B).T
+    assert np.max(np.abs(got - ref) / scale) < tol
+
+
+def test_device_fields_match_oracle_generator(lib):
+    banner("philox fields")
+    for (seed, stream, t, nw, nc) in [(0, 0, 0, 64, 36), (2 ** 40 + 5, 3, 123457, 33, 401)]:
+        got = lib.selftest_fields(seed, stream, t, nw, nc)
+        ref = philox.normals(seed, stream, t, np.arange(nw), nc)
+        assert np.max(np.abs(got - ref)) < 1e-14 * 8
+
+
+def _run_pair_both(lib, torch, wl: Workload, n_steps, ortho, meas, fields=None, philox_seed=None,
+                   K=6, walkers_sub=None):
+    sa, sb = wl.oracle_systems(K)
+    wa, wb = O.init_walkers(sa, wl.nw if walkers_sub is None else len(walkers_sub)), None
+    wb = O.init_walkers(sb, wl.nw if walkers_sub is None else len(walkers_sub))
+    if fields is not None:
+        ff = O.ExplicitFields(fields, walkers=walkers_sub)
+        dev = torch.from_numpy(np.ascontiguousarray(fields)).cuda()
+    else:
+        ff = O.PhiloxFields(philox_seed, 0, wl.n_chol, walkers=walkers_sub)
+        dev = None
+    ref = O.run_pair(sa, sb, wa, wb, ff, n_steps, ortho, meas)
+    H, (ga, gb) = wl.gpu_systems(lib, K=K, ortho_every=ortho, measure_every=meas)
+    tr = lib.pair_step(ga, gb, n_steps, seed=philox_seed or 0, fields=dev)
+    torch.cuda.synchronize()
+    return ref, tr, (wa, wb), (ga, gb), (sa, sb)
+
+
+def _compare_walkers(gpu_sys, wk, sub=None, tol=TOL):
+    g = gpu_sys.walkers()
+    idx = np.arange(len(wk.weight)) if sub is None else np.asarray(sub)
+    alive = g["alive"][idx]
+    assert np.array_equal(alive, wk.alive)
+    live = wk.alive
+    assert rel(g["weight"][idx][live], wk.weight[live]) < tol
+    assert np.all(g["weight"][idx][~live] == 0.0)
+    assert rel(g["lnov"][idx].real[live], wk.lnov.real[live]) < tol
+    assert np.max(phase_diff(g["lnov"][idx].imag[live], wk.lnov.imag[live]), initial=0) < tol
+    for k in np.nonzero(live)[0]:
+        assert rel(g["phi"][idx[k]], wk.phi[k]) < tol
+
+
+def test_parity_pair_m12_explicit_fields(lib, torch_mod):
+    """M=12 pair (3/3 vs 3/2), 64 walkers, 200 steps, MGS every 5, measured
+    every step, explicit N(0,1) fields."""
+    c = config(0)
+    banner("parity M=12 explicit fields")
+    wl = Workload(c.M, c.n_chol, c.na_a, c.nb_a, c.na_b, c.nb_b, c.n_walkers, c.dt)
+    x = wl.fields(c.n_steps, seed=0)
+    ref, tr, (wa, wb), (ga, gb), _ = _run_pair_both(lib, torch_mod, wl, c.n_steps, c.ortho_every,
+                                                    1, fields=x)
+    assert tr.shape == (c.n_steps, 3)
+    for col, key in enumerate(("EA", "EB", "dE")):
+        r = np.asarray(ref[key])
+        assert np.max(np.abs(tr[:, col] - r) / np.maximum(np.abs(r), 1e-3)) < TOL, key
+    _compare_walkers(ga, wa)
+    _compare_walkers(gb, wb)
+
+
+def test_parity_pair_m12_device_philox(lib, torch_mod):
+    c = config(0)
+    banner("parity M=12 philox")
+    wl = Workload(c.M, c.n_chol, c.na_a, c.nb_a, c.na_b, c.nb_b, c.n_walkers, c.dt)
+    ref, tr, (wa, wb), (ga, gb), _ = _run_pair_both(lib, torch_mod, wl, 100, c.ortho_every, 10,
+                                                    philox_seed=1234)
+    for col, key in enumerate(("EA", "EB")):
+        assert rel(tr[:, col], np.asarray(ref[key])) < TOL
+    _compare_walkers(ga, wa)
+    _compare_walkers(gb, wb)
+
+
+@pytest.mark.parametrize("dims", [(37, 75, 7, 6, 7, 5, 37), (19, 9, 4, 0, 3, 0, 70),
+                                  (64, 130, 16, 16, 16, 15, 5)])
+def test_parity_ragged(lib, torch_mod, dims):
+    """Sizes that leave ragged tails in every tile dimension."""
+    M, nc, a1, b1, a2, b2, nw = dims
+    banner(f"parity ragged {dims}")
+    wl = Workload(M, nc, a1, b1, a2, b2, nw, 0.01, ham_seed=3, e_core=1.25)
+    x = wl.fields(24, seed=5)
+    ref, tr, (wa, wb), (ga, gb), _ = _run_pair_both(lib, torch_mod, wl, 24, 4, 3, fields=x)
+    for col, key in enumerate(("EA", "EB", "dE")):
+        r = np.asarray(ref[key])
+        assert np.max(np.abs(tr[:, col] - r) / np.maximum(np.abs(r), 1e-3)) < TOL, key
+    _compare_walkers(ga, wa)
+    _compare_walkers(gb, wb)
+
+
+def test_parity_m100_sampled_walkers(lib, torch_mod):
+    """M=100 pair at its full walker count (1024), device Philox fields; the
+    oracle recomputes a sample of walkers one by one (walkers are independent
+    under correlated sampling without population control)."""
+    c = config(1)
+    banner("parity M=100 full batch, sampled walkers")
+    n_steps = 40
+    wl = Workload(c.M, c.n_chol, c.na_a, c.nb_a, c.na_b, c.nb_b, c.n_walkers, c.dt)
+    sub = np.array([0, 1, 511, 1023])
+    sa, sb = wl.oracle_systems()
+    wa, wb = O.init_walkers(sa, len(sub)), O.init_walkers(sb, len(sub))
+    O.run_pair(sa, sb, wa, wb, O.PhiloxFields(7, 0, c.n_chol, walkers=sub), n_steps, 10, 20)
+    H, (ga, gb) = wl.gpu_systems(lib, ortho_every=10, measure_every=20)
+    lib.pair_step(ga, gb, n_steps, seed=7)
+    _compare_walkers(ga, wa, sub)
+    _compare_walkers(gb, wb, sub)
+    el_a, w_a, _ = ga.local_energy()
+    ref_el = O.local_energy(sa, wa.theta)
+    assert rel(el_a[sub], ref_el) < TOL
+
+
+def test_identical_pair_exact_zero(lib):
+    banner("identical pair")
+    wl = Workload(20, 40, 4, 4, 4, 4, 32, 0.01, ham_seed=2)
+    H, (ga, gb) = wl.gpu_systems(lib, ortho_every=5, measure_every=5)
+    tr = lib.pair_step(ga, gb, 40, seed=11)
+    assert tr.shape == (8, 3)
+    assert np.all(tr[:, 2] == 0.0)
+
+
+def test_mgs_invariance_and_determinism(lib):
+    banner("mgs invariance / determinism")
+    wl = Workload(30, 60, 6, 5, 6, 4, 24, 0.01, ham_seed=4)
+    H, (ga, gb) = wl.gpu_systems(lib, ortho_every=0, measure_every=0)
+    ga.step(15, seed=3)
+    e0, w0, m0 = ga.local_energy()
+    ga.orthonormalize()
+    e1, w1, m1 = ga.local_energy()
+    assert rel(e1, e0) < 1e-12 and np.array_equal(w0, w1)
+    H2, (ha, hb) = wl.gpu_systems(lib, ortho_every=0, measure_every=0)
+    ha.step(15, seed=3)
+    ha.orthonormalize()
+    e2, w2, m2 = ha.local_energy()
+    assert np.array_equal(e2, e1) and np.array_equal(w2, w1) and m2 == m1
+
+
+def test_checkpoint_restore_bitwise(lib):
+    banner("checkpoint/restore")
+    wl = Workload(24, 48, 5, 5, 5, 4, 16, 0.01, ham_seed=6)
+    H, (ga, gb) = wl.gpu_systems(lib, ortho_every=5, measure_every=5)
+    lib.pair_step(ga, gb, 10, seed=9)
+    ca, cb = ga.checkpoint(), gb.checkpoint()
+    t1 = lib.pair_step(ga, gb, 10, seed=9)
+    ga.restore(ca)
+    gb.restore(cb)
+    t2 = lib.pair_step(ga, gb, 10, seed=9)
+    assert np.array_equal(t1, t2)
+
+
+def test_nan_field_freezes_only_that_walker(lib, torch_mod):
+    """A non-finite field kills one walker; every other walker is bitwise
+    identical to a run without it, and the oracle agrees (Sec. II.B)."""
+    banner("nan field")
+    wl = Workload(16, 30, 4, 3, 4, 2, 12, 0.01, ham_seed=8)
+    x = wl.fields(8, seed=2)
+    xbad = x.copy()
+    xbad[3, 5, 7] = np.nan
+    outs = []
+    for arr in (x, xbad):
+        H, (ga, gb) = wl.gpu_systems(lib, ortho_every=4, measure_every=0)
+        ga.step(8, fields=torch_mod.from_numpy(arr).cuda())
+        outs.append(ga.walkers())
+    assert outs[0]["alive"].all()
+    assert not outs[1]["alive"][5] and outs[1]["weight"][5] == 0.0
+    keep = np.arange(12) != 5
+    assert np.array_equal(outs[0]["phi"][keep], outs[1]["phi"][keep])
+    assert np.array_equal(outs[0]["weight"][keep], outs[1]["weight"][keep])
+    sa, _ = wl.oracle_systems()
+    wk = O.init_walkers(sa, 12)
+    for t in range(8):
+        O.step(sa, wk, xbad[t])
+        if wk.t % 4 == 0:
+            O.orthonormalize(sa, wk)
+    assert np.array_equal(wk.alive, outs[1]["alive"])
+
+
+def test_errors(lib):
+    banner("error paths")
+    wl = Workload(12, 10, 3, 3, 3, 2, 8, 0.01)
+    H, (ga, gb) = wl.gpu_systems(lib)
+    wl2 = Workload(12, 11, 3, 3, 3, 2, 8, 0.01)
+    H2, (ha, hb) = wl2.gpu_systems(lib)
+    with pytest.raises(lib.AfqmcError) as e:
+        lib.pair_step(ga, hb, 2)
+    assert e.value.status == lib.E_SHAPE
+    ga.step(1)
+    with pytest.raises(lib.AfqmcError) as e:
+        lib.pair_step(ga, gb, 2)
+    assert e.value.status == lib.E_STATE
+    # init orthogonal to the trial -> singular
+    _, vec = np.linalg.eigh(wl.ham.h)
+    init = np.concatenate([vec[:, 3:6], vec[:, 3:6]], axis=1)
+    with pytest.raises(lib.AfqmcError) as e:
+        lib.System(H, 3, 3, wl.trials[0], 4, 0.01, init_phi=init)
+    assert e.value.status == lib.E_SINGULAR
+    gb.free()
+    import ctypes
+    st = lib._lib.afqmc_step(gb._s if gb._s else ctypes.c_void_p(), 0, 0, 1, None)
+    assert st == lib.E_INVALID
