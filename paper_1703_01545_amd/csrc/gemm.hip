@@ -14,8 +14,9 @@
 //
 // MFMA fragment layout (v_mfma_{f64,f32}_16x16x4 and v_mfma_f32_16x16x32_bf16):
 // lane l supplies A[l % 16][kb + l / 16] and B^T[l % 16][kb + l / 16]
-// (kb + 8 (l / 16) + e, e < 8, for bf16), and holds accumulator element r of
-// D[4 (l / 16) + r][l % 16].
+// (kb + 8 (l / 16) + e, e < 8, for bf16).  Accumulator element r of lane l
+// is D[4 (l / 16) + r][l % 16] for the FP32-accumulating instructions and
+// D[l / 16 + 4 r][l % 16] for v_mfma_f64_16x16x4.
 #include "internal.h"
 
 namespace afq {
@@ -66,6 +67,16 @@ template <>
 __device__ __forceinline__ double to_c<double, bf16_t>(bf16_t x) { return (double)(float)x; }
 template <>
 __device__ __forceinline__ float to_c<float, bf16_t>(bf16_t x) { return (float)x; }
+
+// Row of accumulator element r held by lane l (see the layout note above).
+template <typename TC>
+__device__ __forceinline__ int acc_row(int lane, int r) {
+    return 4 * (lane >> 4) + r;
+}
+template <>
+__device__ __forceinline__ int acc_row<double>(int lane, int r) {
+    return (lane >> 4) + 4 * r;
+}
 
 __device__ __forceinline__ long rowmap(const RowMap& r, long i) {
     if (r.n_in == 1) return r.base + i * r.s_out;
@@ -223,7 +234,7 @@ __global__ __launch_bounds__(256) void k_gemm(Gemm g) {
     for (int a = 0; a < C::TM; ++a) {
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-            const long i = row0 + wm * C::TM * 16 + a * 16 + 4 * (lane >> 4) + r;
+            const long i = row0 + wm * C::TM * 16 + a * 16 + acc_row<TC>(lane, r);
             if (i >= g.m) continue;
             const long ro = rowmap(g.rc, i);
 #pragma unroll
@@ -366,7 +377,7 @@ __global__ __launch_bounds__(256) void k_taylor(const T* __restrict__ Tp, T* __r
     for (int a = 0; a < TM; ++a)
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-            const int i = row0 + wm * TM * 16 + a * 16 + 4 * (lane >> 4) + r;
+            const int i = row0 + wm * TM * 16 + a * 16 + acc_row<T>(lane, r);
             if (i >= N) continue;
 #pragma unroll
             for (int b = 0; b < TN; ++b) {
@@ -431,7 +442,7 @@ __global__ __launch_bounds__(256) void k_exchange(const TS* __restrict__ lhalf,
     for (int a = 0; a < C::TM; ++a)
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-            const int i = wm * C::TM * 16 + a * 16 + 4 * (lane >> 4) + r;
+            const int i = wm * C::TM * 16 + a * 16 + acc_row<TC>(lane, r);
 #pragma unroll
             for (int b = 0; b < C::TN; ++b) {
                 const int j = wn * C::TN * 16 + b * 16 + (lane & 15);

@@ -46,13 +46,15 @@ def test_gemm_kernel(lib, shape, prec):
     rng = np.random.default_rng(m * 7 + n + k)
     A = rng.standard_normal((m, k))
     B = rng.standard_normal((n, k))
+    # inputs made exactly representable in the compute precision, so the test
+    # checks the MFMA arithmetic and tiling, not the device's tie rounding
+    if prec == "fp32":
+        A, B = A.astype(np.float32).astype(np.float64), B.astype(np.float32).astype(np.float64)
+    elif prec == "bf16":
+        A, B = _bf16_round(A), _bf16_round(B)
     got = lib.selftest_gemm(A, B, prec)
-    if prec == "fp64":
-        ref, tol = A @ B.T, 1e-13
-    elif prec == "fp32":
-        ref, tol = A.astype(np.float32).astype(np.float64) @ B.astype(np.float32).astype(np.float64).T, 2e-6
-    else:
-        ref, tol = _bf16_round(A) @ _bf16_round(B).T, 2e-6
+    ref = A @ B.T
+    tol = 1e-13 if prec == "fp64" else 2e-6
     scale = np.abs(A) @ np.abs(B).T
     assert np.max(np.abs(got - ref) / scale) < tol
 
@@ -241,11 +243,12 @@ def test_errors(lib):
     with pytest.raises(lib.AfqmcError) as e:
         lib.pair_step(ga, gb, 2)
     assert e.value.status == lib.E_STATE
-    # init orthogonal to the trial -> singular
-    _, vec = np.linalg.eigh(wl.ham.h)
-    init = np.concatenate([vec[:, 3:6], vec[:, 3:6]], axis=1)
+    # walkers exactly orthogonal to the trial -> zero overlap -> singular
+    eye = np.eye(12)
+    trial = np.concatenate([eye[:, :3], eye[:, :3]], axis=1)
+    init = np.concatenate([eye[:, 3:6], eye[:, 3:6]], axis=1)
     with pytest.raises(lib.AfqmcError) as e:
-        lib.System(H, 3, 3, wl.trials[0], 4, 0.01, init_phi=init)
+        lib.System(H, 3, 3, trial, 4, 0.01, init_phi=init)
     assert e.value.status == lib.E_SINGULAR
     gb.free()
     import ctypes
