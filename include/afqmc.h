@@ -158,6 +158,19 @@ void afqmc_free_ham(afqmc_ham ham);
 /* Thread-local message describing the last non-OK status of this thread. */
 const char* afqmc_last_error(void);
 
+/* Per-phase kernel timing with HIP events on the system's stream.
+ * afqmc_profile_enable(sys, 1) clears the counters and starts recording a
+ * start/stop event pair around every kernel launch of every later step
+ * (phases: 0 force-bias GEMM, 1 fields, 2 field-sum GEMM, 3 first one-body
+ * half, 4 Taylor term (one launch per term), 5 second one-body half,
+ * 6 overlap GEMM, 7 determinants and Theta, 8 weights, 9 Gram-Schmidt,
+ * 10 exchange, 11 local/mixed energy); 0 stops.  afqmc_profile_read
+ * synchronises and returns the summed milliseconds and the launch count of
+ * one phase.  afqmc_phase_name returns a phase's name, NULL past the last. */
+afqmc_status afqmc_profile_enable(afqmc_sys sys, int enable);
+afqmc_status afqmc_profile_read(afqmc_sys sys, int phase, double* total_ms, int64_t* launches);
+const char* afqmc_phase_name(int phase);
+
 /* Kernel self-test: C = A * B^T (A: m x k, B: n x k, C: m x n, host
  * float64) computed by the library's tiled MFMA GEMM in precision `prec`
  * (inputs rounded to that precision).  For the numerics tests of the

@@ -26,6 +26,12 @@ Conventions (the readings of the paper this oracle takes):
   R = <phi_T|B|phi>/<phi_T|phi> (c-number included).  Phaseless update,
   Sec. II.A: w <- w |I| max(0, cos(Im ln R)).  A walker whose weight is no
   longer positive is frozen for the rest of the run (Sec. II.B).
+* Energy shift (the paper is silent): every weight update carries the
+  constant factor e^{dt e_shift}, e_shift = Re E_L(phi_init) - c0 with
+  c0 = e_core - 1/2 sum_g a_g^2 the constant of H_1.  It is the same for
+  every walker of a system, so it cancels in Eq. 7; it keeps weights O(1)
+  over long runs (without it they grow like e^{-dt (E_L - c0) t} and leave
+  the FP64 range within a few hundred steps).
 * Mixed estimator, Eq. 7 and Eq. 10: E = sum_k w_k Re E_L(phi_k) / sum_k w_k
   over live walkers; E_L = e_core + sum_s Tr(h^half_s Theta^s)
   + 1/2 sum_g [(sum_s Tr T_gs)^2 - sum_s Tr(T_gs T_gs)], T_gs = L^half_gs Theta^s.
@@ -83,9 +89,11 @@ class System:
                 continue
             t = self.trial[:, off:off + n]
             g_t = t @ np.linalg.solve(t.T @ t, t.T)
-            self.a += np.einsum("gij,ji->g", self.chol, g_t)
+            self.a += self.chol.reshape(self.n_chol, self.M * self.M) @ g_t.T.reshape(-1)
         # One-body part after mean-field subtraction (Eq. 2).
-        l2 = np.einsum("gik,gkj->ij", self.chol, self.chol)
+        M_, G_ = self.M, self.n_chol
+        l2 = (np.swapaxes(self.chol, 0, 1).reshape(M_, G_ * M_) @ self.chol.reshape(G_ * M_, M_)
+              if G_ else np.zeros((M_, M_)))
         self.htilde = h - 0.5 * l2 + np.einsum("g,gij->ij", self.a, self.chol)
         self.P = scipy.linalg.expm(-0.5 * self.dt * self.htilde)
         # Half-rotated tensors: L^half_{g s} = Phi_T^{sT} L_g, h^half_s = Phi_T^{sT} h.
@@ -93,7 +101,7 @@ class System:
         self.hhalf = []
         for off, n in self.spins:
             t = self.trial[:, off:off + n]
-            self.lhalf.append(np.einsum("mi,gmn->gin", t, self.chol))
+            self.lhalf.append(np.matmul(t.T[None], self.chol))
             self.hhalf.append(t.T @ h)
 
 
@@ -105,10 +113,11 @@ class Walkers:
     theta: np.ndarray     # (nw, M, N) complex: Phi^s (Phi_T^{sT} Phi^s)^{-1}
     alive: np.ndarray     # (nw,) bool
     t: int = 0            # absolute step counter (feeds the field generator)
+    e_shift: float = 0.0  # constant energy shift of the weight factor
 
     def copy(self) -> "Walkers":
         return Walkers(self.phi.copy(), self.weight.copy(), self.lnov.copy(),
-                       self.theta.copy(), self.alive.copy(), self.t)
+                       self.theta.copy(), self.alive.copy(), self.t, self.e_shift)
 
 
 def overlap(sys: System, phi: np.ndarray):
@@ -138,7 +147,9 @@ def init_walkers(sys: System, nw: int, init_phi: Optional[np.ndarray] = None,
     phi = np.broadcast_to(src.astype(np.complex128), (nw, sys.M, sys.N)).copy()
     lnov, theta = overlap(sys, phi)
     w = np.ones(nw, dtype=np.complex128 if complex_weights else np.float64)
-    return Walkers(phi, w, lnov, theta, np.ones(nw, dtype=bool), 0)
+    e_t = local_energy(sys, theta[:1])[0].real
+    c0 = sys.e_core - 0.5 * float(np.sum(sys.a * sys.a))
+    return Walkers(phi, w, lnov, theta, np.ones(nw, dtype=bool), 0, e_t - c0)
 
 
 def force_bias_f(sys: System, theta: np.ndarray) -> np.ndarray:
@@ -191,17 +202,18 @@ def step(sys: System, wk: Walkers, x: np.ndarray, mode: str = PHASELESS) -> Walk
     """Advance all live walkers one time step with fields x (nw, n_chol)."""
     live = wk.alive
     new_phi, new_lnov, new_theta, lnR, lnI, _ = propagate(sys, wk.phi, wk.lnov, wk.theta, x, mode)
+    shift = sys.dt * wk.e_shift
     if mode == PHASELESS:
-        fac = np.exp(lnI.real) * np.maximum(0.0, np.cos(lnR.imag))
+        fac = np.exp(lnI.real + shift) * np.maximum(0.0, np.cos(lnR.imag))
         w_new = wk.weight * fac
         ok = np.isfinite(w_new) & (w_new > 0.0)
         w_new = np.where(ok, w_new, 0.0)
         still = live & ok
     elif mode == FREE:
-        w_new = wk.weight * np.exp(lnR)
+        w_new = wk.weight * np.exp(lnR + shift)
         still = live.copy()
     elif mode == IS_FREE:
-        w_new = wk.weight * np.exp(lnI)
+        w_new = wk.weight * np.exp(lnI + shift)
         still = live.copy()
     else:
         raise ValueError(mode)

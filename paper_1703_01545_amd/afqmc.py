@@ -30,7 +30,8 @@ EXPORTS = [
     "afqmc_load_hamiltonian", "afqmc_init_walkers", "afqmc_step", "afqmc_local_energy",
     "afqmc_orthonormalize", "afqmc_pair_step", "afqmc_pair_batch_step", "afqmc_get_walkers",
     "afqmc_sys_info", "afqmc_checkpoint", "afqmc_restore", "afqmc_free_sys", "afqmc_free_ham",
-    "afqmc_last_error", "afqmc_selftest_gemm", "afqmc_selftest_fields",
+    "afqmc_last_error", "afqmc_selftest_gemm", "afqmc_selftest_fields", "afqmc_profile_enable",
+    "afqmc_profile_read", "afqmc_phase_name",
 ]
 
 
@@ -61,8 +62,12 @@ _lib.afqmc_free_ham.argtypes = [_vp]
 _lib.afqmc_free_ham.restype = None
 _lib.afqmc_selftest_gemm.argtypes = [C.c_int, C.c_int, C.c_int, C.c_int, _dp, _dp, _dp]
 _lib.afqmc_selftest_fields.argtypes = [C.c_uint64, C.c_uint64, C.c_int64, C.c_int, C.c_int, _dp]
+_lib.afqmc_profile_enable.argtypes = [_vp, C.c_int]
+_lib.afqmc_profile_read.argtypes = [_vp, C.c_int, _dp, C.POINTER(C.c_int64)]
+_lib.afqmc_phase_name.argtypes = [C.c_int]
+_lib.afqmc_phase_name.restype = C.c_char_p
 for _n in EXPORTS:
-    if _n not in ("afqmc_last_error", "afqmc_free_sys", "afqmc_free_ham"):
+    if _n not in ("afqmc_last_error", "afqmc_free_sys", "afqmc_free_ham", "afqmc_phase_name"):
         getattr(_lib, _n).restype = C.c_int
 
 
@@ -187,6 +192,25 @@ class System:
         _check(_lib.afqmc_sys_info(self._s, *[C.byref(x) for x in v], C.byref(t)))
         return dict(M=v[0].value, n_chol=v[1].value, n_alpha=v[2].value, n_beta=v[3].value,
                     n_walkers=v[4].value, step=t.value)
+
+    def profile(self, enable: bool = True):
+        """Start (clearing the counters) or stop per-phase HIP-event timing."""
+        _check(_lib.afqmc_profile_enable(self._s, 1 if enable else 0))
+
+    def profile_read(self):
+        """{phase name: (total ms, launches)} since profiling was enabled."""
+        out = {}
+        i = 0
+        while True:
+            name = _lib.afqmc_phase_name(i)
+            if name is None:
+                break
+            ms = C.c_double()
+            n = C.c_int64()
+            _check(_lib.afqmc_profile_read(self._s, i, C.byref(ms), C.byref(n)))
+            out[name.decode()] = (ms.value, n.value)
+            i += 1
+        return out
 
     def checkpoint(self) -> bytes:
         n = C.c_size_t()

@@ -147,6 +147,79 @@ bool theta_trial(const double* trial, int M, int N, int off, int n, double* out 
     return true;
 }
 
+// Phases of the step, each one kernel launch (the Taylor phase is one
+// launch per term).  Timed with HIP events on the system's stream when
+// profiling is enabled.
+enum Phase {
+    PH_FORCE_BIAS = 0,
+    PH_FIELDS,
+    PH_FIELD_SUM,
+    PH_HALF1,
+    PH_TAYLOR,
+    PH_HALF2,
+    PH_OVERLAP,
+    PH_DET_THETA,
+    PH_WEIGHTS,
+    PH_MGS,
+    PH_EXCHANGE,
+    PH_ENERGY,
+    PH_COUNT
+};
+const char* const kPhaseNames[PH_COUNT] = {
+    "force_bias_gemm", "fields", "field_sum_gemm", "one_body_half_1", "taylor_term",
+    "one_body_half_2", "overlap_gemm", "det_theta", "weights", "mgs", "exchange", "energy"};
+
+struct Profiler {
+    bool on = false;
+    struct Pend {
+        int phase;
+        hipEvent_t a, b;
+    };
+    std::vector<Pend> pend;
+    std::vector<hipEvent_t> pool;
+    double total_ms[PH_COUNT] = {};
+    int64_t launches[PH_COUNT] = {};
+    hipEvent_t get() {
+        if (!pool.empty()) {
+            hipEvent_t e = pool.back();
+            pool.pop_back();
+            return e;
+        }
+        hipEvent_t e = nullptr;
+        if (hipEventCreate(&e) != hipSuccess) return nullptr;
+        return e;
+    }
+    hipError_t resolve(hipStream_t st) {
+        if (pend.empty()) return hipSuccess;
+        hipError_t e = hipStreamSynchronize(st);
+        if (e != hipSuccess) return e;
+        for (auto& p : pend) {
+            float ms = 0.f;
+            if (p.a && p.b && hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
+                total_ms[p.phase] += ms;
+                launches[p.phase] += 1;
+            }
+            if (p.a) pool.push_back(p.a);
+            if (p.b) pool.push_back(p.b);
+        }
+        pend.clear();
+        return hipSuccess;
+    }
+    void reset() {
+        for (int i = 0; i < PH_COUNT; ++i) {
+            total_ms[i] = 0.0;
+            launches[i] = 0;
+        }
+    }
+    ~Profiler() {
+        for (auto& p : pend) {
+            if (p.a) (void)hipEventDestroy(p.a);
+            if (p.b) (void)hipEventDestroy(p.b);
+        }
+        for (auto e : pool) (void)hipEventDestroy(e);
+    }
+};
+
 }  // namespace
 
 struct afqmc_ham_s {
@@ -168,6 +241,7 @@ struct afqmc_sys_s {
     DType tc = DT_F64;  // contraction storage / compute type
     DType tp = DT_F64;  // propagator product type
     int64_t t = 0;
+    double e_shift = 0.0;  // constant energy shift of the weight factor
     bool dead = false;
     std::vector<double> a_host;
     // constant per-system data
@@ -177,6 +251,7 @@ struct afqmc_sys_s {
     // step scratch
     DevBuf d_F, d_X, d_simp, d_Apk, d_Y, d_T2, d_Z, d_ov, d_lnd, d_exch, d_el, d_sums;
     int n_gt_a = 0, n_gt_b = 0, n_gt = 0;
+    Profiler prof;
     long P() const { return (long)M * (M + 1) / 2; }
     long NM() const { return (long)N * M; }
 };
@@ -194,6 +269,27 @@ void ham_unref(afqmc_ham h) {
 }
 
 const void* lp_or(const DevBuf& lp, const DevBuf& hi, DType t) { return t == DT_F64 ? hi.p : lp.p; }
+
+// Brackets one phase with a pair of HIP events when profiling is on.
+struct PhaseTimer {
+    Profiler* p;
+    hipStream_t st;
+    int phase;
+    hipEvent_t a = nullptr;
+    PhaseTimer(afqmc_sys s, int ph, hipStream_t stream) : p(&s->prof), st(stream), phase(ph) {
+        if (p->on) {
+            a = p->get();
+            if (a) (void)hipEventRecord(a, st);
+        }
+    }
+    ~PhaseTimer() {
+        if (p->on && a) {
+            hipEvent_t b = p->get();
+            if (b) (void)hipEventRecord(b, st);
+            p->pend.push_back({phase, a, b});
+        }
+    }
+};
 
 // ---- device phases of one step -------------------------------------------
 
@@ -214,6 +310,7 @@ afqmc_status force_bias(afqmc_sys s, hipStream_t st) {
     g.n = s->n_chol + 1;
     g.k = (int)s->NM();
     g.batch = 1;
+    PhaseTimer pt(s, PH_FORCE_BIAS, st);
     HIPCHK(gemm(g, s->tc, st));
     return AFQMC_OK;
 }
@@ -234,7 +331,11 @@ afqmc_status overlap_theta(afqmc_sys s, double* phi, hipStream_t st) {
     g.n = s->N;
     g.k = s->M;
     g.batch = 1;
-    HIPCHK(gemm(g, DT_F64, st));
+    {
+        PhaseTimer pt(s, PH_OVERLAP, st);
+        HIPCHK(gemm(g, DT_F64, st));
+    }
+    PhaseTimer pt(s, PH_DET_THETA, st);
     HIPCHK(lu_theta(s->d_ov.as<double>(), phi, s->d_theta.as<double>(),
                     s->tc == DT_F64 ? nullptr : s->d_theta_lp.p, s->tc, s->d_lnd.as<double>(),
                     s->d_alive.as<uint8_t>(), s->nw, s->M, s->N, s->na, s->nb, st));
@@ -262,7 +363,10 @@ afqmc_status one_step(afqmc_sys s, uint64_t seed, uint64_t stream_id, const doub
     f.n_chol = s->n_chol;
     f.sqdt = sqrt(s->par.dt);
     f.free_proj = s->par.mode == AFQMC_FREE;
-    HIPCHK(fields(f, st));
+    {
+        PhaseTimer pt(s, PH_FIELDS, st);
+        HIPCHK(fields(f, st));
+    }
     // A[(w,p), q] = sum_g X[(w,p), g] Lpacked[q, g]
     {
         Gemm g{};
@@ -280,6 +384,7 @@ afqmc_status one_step(afqmc_sys s, uint64_t seed, uint64_t stream_id, const doub
         g.n = (int)s->P();
         g.k = s->n_chol;
         g.batch = 1;
+        PhaseTimer pt(s, PH_FIELD_SUM, st);
         HIPCHK(gemm(g, s->tc, st));
     }
     const void* Pm = s->tp == DT_F64 ? s->d_P.p : s->d_Plp.p;
@@ -301,12 +406,14 @@ afqmc_status one_step(afqmc_sys s, uint64_t seed, uint64_t stream_id, const doub
         g.n = s->M;
         g.k = s->M;
         g.batch = 1;
+        PhaseTimer pt(s, PH_HALF1, st);
         HIPCHK(gemm(g, s->tp, st));
     }
     // Taylor series of exp(A) applied to Y, accumulated in Z
     void* cur = s->d_Y.p;
     void* nxt = s->d_T2.p;
     for (int n = 1; n <= s->par.taylor_order; ++n) {
+        PhaseTimer pt(s, PH_TAYLOR, st);
         HIPCHK(taylor_term(cur, nxt, s->d_Z.p, s->d_Apk.p, s->d_alive.as<uint8_t>(), s->nw, s->M,
                            s->N, 1.0 / n, s->tp, st));
         std::swap(cur, nxt);
@@ -328,23 +435,31 @@ afqmc_status one_step(afqmc_sys s, uint64_t seed, uint64_t stream_id, const doub
         g.n = s->M;
         g.k = s->M;
         g.batch = 1;
+        PhaseTimer pt(s, PH_HALF2, st);
         HIPCHK(gemm(g, s->tp, st));
     }
     if ((r = overlap_theta(s, s->d_phinew.as<double>(), st)) != AFQMC_OK) return r;
+    PhaseTimer pt(s, PH_WEIGHTS, st);
     HIPCHK(weights(s->d_lnd.as<double>(), s->d_simp.as<double>(), s->d_lnov.as<double>(),
-                   s->d_w.as<double>(), s->d_alive.as<uint8_t>(), s->nw, (int)s->par.mode, 1, st));
+                   s->d_w.as<double>(), s->d_alive.as<uint8_t>(), s->nw, (int)s->par.mode, 1,
+                   s->par.dt * s->e_shift, st));
     std::swap(s->d_phi.p, s->d_phinew.p);
     s->t += 1;
     return AFQMC_OK;
 }
 
 afqmc_status ortho(afqmc_sys s, hipStream_t st) {
-    HIPCHK(mgs(s->d_phi.as<double>(), s->d_alive.as<uint8_t>(), s->nw, s->M, s->N, s->na, s->nb,
+    {
+        PhaseTimer pt(s, PH_MGS, st);
+        HIPCHK(mgs(s->d_phi.as<double>(), s->d_alive.as<uint8_t>(), s->nw, s->M, s->N, s->na, s->nb,
                st));
+    }
     afqmc_status r = overlap_theta(s, s->d_phi.as<double>(), st);
     if (r != AFQMC_OK) return r;
+    PhaseTimer pt(s, PH_WEIGHTS, st);
     HIPCHK(weights(s->d_lnd.as<double>(), s->d_simp.as<double>(), s->d_lnov.as<double>(),
-                   s->d_w.as<double>(), s->d_alive.as<uint8_t>(), s->nw, (int)s->par.mode, 0, st));
+                   s->d_w.as<double>(), s->d_alive.as<uint8_t>(), s->nw, (int)s->par.mode, 0, 0.0,
+                   st));
     return AFQMC_OK;
 }
 
@@ -353,10 +468,14 @@ afqmc_status measure(afqmc_sys s, hipStream_t st) {
     if (r != AFQMC_OK) return r;
     const void* lh = lp_or(s->d_lhx_lp, s->d_lhx, s->tc);
     const void* th = lp_or(s->d_theta_lp, s->d_theta, s->tc);
-    HIPCHK(exchange(lh, th, s->d_exch.as<double>(), s->nw, s->M, s->N, s->n_chol, 0, s->na, 0,
+    {
+        PhaseTimer pt(s, PH_EXCHANGE, st);
+        HIPCHK(exchange(lh, th, s->d_exch.as<double>(), s->nw, s->M, s->N, s->n_chol, 0, s->na, 0,
                     s->n_gt, s->tc, st));
     HIPCHK(exchange(lh, th, s->d_exch.as<double>(), s->nw, s->M, s->N, s->n_chol, s->na, s->nb, 1,
                     s->n_gt, s->tc, st));
+    }
+    PhaseTimer pt(s, PH_ENERGY, st);
     HIPCHK(local_energy(s->d_F.as<double>(), s->n_chol + 1, s->d_exch.as<double>(), s->n_gt_a,
                         s->n_gt_b, s->nw, s->n_chol, s->ham->e_core, s->d_el.as<double>(), st));
     HIPCHK(mixed_sums(s->d_el.as<double>(), s->d_w.as<double>(), s->d_alive.as<uint8_t>(), s->nw,
@@ -630,7 +749,7 @@ afqmc_status afqmc_init_walkers(afqmc_ham ham, int n_alpha, int n_beta, const do
     afqmc_status r = overlap_theta(s, s->d_phi.as<double>(), st);
     if (r != AFQMC_OK) return bail(r);
     if (weights(s->d_lnd.as<double>(), s->d_simp.as<double>(), s->d_lnov.as<double>(),
-                s->d_w.as<double>(), s->d_alive.as<uint8_t>(), nw, (int)par->mode, 0,
+                s->d_w.as<double>(), s->d_alive.as<uint8_t>(), nw, (int)par->mode, 0, 0.0,
                 st) != hipSuccess)
         return bail(fail(AFQMC_E_DEVICE, "lnov"));
     std::vector<double> lnov((size_t)2 * nw);
@@ -640,6 +759,21 @@ afqmc_status afqmc_init_walkers(afqmc_ham ham, int n_alpha, int n_beta, const do
     for (int k = 0; k < nw; ++k)
         if (!std::isfinite(lnov[2 * k]))
             return bail(fail(AFQMC_E_SINGULAR, "initial determinant has zero overlap with the trial"));
+    // Energy shift: e_shift = Re E_L(initial walker) - c0, c0 = e_core - 1/2 sum a_g^2
+    // (the constant of H_1).  A uniform factor e^{dt e_shift} per step on every
+    // weight of the system: it cancels in the mixed estimator and keeps the
+    // weights O(1) over long runs.
+    {
+        r = measure(s, st);
+        if (r != AFQMC_OK) return bail(r);
+        double el0[2];
+        if (hipStreamSynchronize(st) != hipSuccess ||
+            hipMemcpy(el0, s->d_el.p, sizeof(el0), hipMemcpyDeviceToHost) != hipSuccess)
+            return bail(fail(AFQMC_E_DEVICE, "initial energy"));
+        double c0 = ham->e_core;
+        for (int g = 0; g < nc; ++g) c0 -= 0.5 * s->a_host[g] * s->a_host[g];
+        s->e_shift = el0[0] - c0;
+    }
     *out = s;
     return AFQMC_OK;
 }
@@ -842,6 +976,29 @@ afqmc_status afqmc_restore(afqmc_sys s, const void* src, size_t bytes) {
     }
     s->t = hdr[1];
     return AFQMC_OK;
+}
+
+afqmc_status afqmc_profile_enable(afqmc_sys s, int enable) {
+    afqmc_status r = check_sys(s);
+    if (r != AFQMC_OK) return r;
+    HIPCHK(s->prof.resolve(s->ham->stream));
+    s->prof.reset();
+    s->prof.on = enable != 0;
+    return AFQMC_OK;
+}
+
+afqmc_status afqmc_profile_read(afqmc_sys s, int phase, double* total_ms, int64_t* launches) {
+    afqmc_status r = check_sys(s);
+    if (r != AFQMC_OK) return r;
+    if (phase < 0 || phase >= PH_COUNT) return fail(AFQMC_E_INVALID, "phase out of range");
+    HIPCHK(s->prof.resolve(s->ham->stream));
+    if (total_ms) *total_ms = s->prof.total_ms[phase];
+    if (launches) *launches = s->prof.launches[phase];
+    return AFQMC_OK;
+}
+
+const char* afqmc_phase_name(int phase) {
+    return (phase >= 0 && phase < PH_COUNT) ? kPhaseNames[phase] : nullptr;
 }
 
 afqmc_status afqmc_selftest_gemm(afqmc_prec prec, int m, int n, int k, const double* A,

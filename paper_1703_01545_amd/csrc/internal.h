@@ -106,11 +106,12 @@ hipError_t lu_theta(const double* ov, const double* phi, double* theta, void* th
                     hipStream_t s);
 
 // Weight update: lnR = sum_s lnd - lnov + s; lnI = lnR + imp;
-// phaseless: w *= exp(Re lnI) max(0, cos Im lnR), frozen when not > 0;
-// free: complex W *= exp(lnR).  lnov <- sum_s lnd for live walkers.
+// phaseless: w *= exp(Re lnI + shift) max(0, cos Im lnR), frozen when not
+// > 0; free: complex W *= exp(lnR + shift).  shift = dt * e_shift is the
+// constant energy shift of the system.  lnov <- sum_s lnd for live walkers.
 // commit == 0 (after Gram-Schmidt): only lnov is refreshed.
 hipError_t weights(const double* lnd, const double* s_imp, double* lnov, double* w, uint8_t* alive,
-                   int nw, int mode, int commit, hipStream_t s);
+                   int nw, int mode, int commit, double shift, hipStream_t s);
 
 hipError_t mgs(double* phi, const uint8_t* live, int nw, int M, int N, int na, int nb,
                hipStream_t s);

@@ -288,7 +288,8 @@ __global__ __launch_bounds__(256) void k_lu_theta(const double* __restrict__ ov,
 
 __global__ void k_weights(const double* __restrict__ lnd, const double* __restrict__ s_imp,
                           double* __restrict__ lnov, double* __restrict__ w,
-                          uint8_t* __restrict__ alive, int nw, int mode, int commit) {
+                          uint8_t* __restrict__ alive, int nw, int mode, int commit,
+                          double shift) {
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= nw || !alive[k]) return;
     const double nr = lnd[4 * k + 0] + lnd[4 * k + 2];
@@ -298,13 +299,13 @@ __global__ void k_weights(const double* __restrict__ lnd, const double* __restri
         const double Ri = (ni - lnov[2 * k + 1]) + s_imp[4 * k + 1];
         if (mode == 0) {
             const double Ir = Rr + s_imp[4 * k + 2];
-            const double fac = exp(Ir) * fmax(0.0, cos(Ri));
+            const double fac = exp(Ir + shift) * fmax(0.0, cos(Ri));
             const double wn = w[k] * fac;
             const bool ok = isfinite(wn) && wn > 0.0;
             w[k] = ok ? wn : 0.0;
             if (!ok) alive[k] = 0;
         } else {
-            const double er = exp(Rr);
+            const double er = exp(Rr + shift);
             const double fr = er * cos(Ri), fi = er * sin(Ri);
             const double wr = w[2 * k], wi = w[2 * k + 1];
             w[2 * k] = wr * fr - wi * fi;
@@ -533,10 +534,10 @@ hipError_t lu_theta(const double* ov, const double* phi, double* theta, void* th
 }
 
 hipError_t weights(const double* lnd, const double* s_imp, double* lnov, double* w, uint8_t* alive,
-                   int nw, int mode, int commit, hipStream_t s) {
+                   int nw, int mode, int commit, double shift, hipStream_t s) {
     if (nw <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_weights, dim3(nblk(nw, 256)), dim3(256), 0, s, lnd, s_imp, lnov, w, alive,
-                       nw, mode, commit);
+                       nw, mode, commit, shift);
     return hipGetLastError();
 }
 

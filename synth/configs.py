@@ -6,7 +6,11 @@ matrix h and real symmetric Cholesky vectors L_gamma whose products give the
 two-body matrix elements (Sec. II.A, Eq. 1).  The recipe:
 
 * h = diag(linspace(-2, 1, M)) + sym(G)/sqrt(M), G_ij ~ N(0, 1);
-* L_gamma = sym(G_gamma) * 0.3 * exp(-gamma/10), gamma = 0..n_chol-1;
+* L_gamma = sym(G_gamma) * 0.3 * exp(-gamma/10) * sqrt(12/M), gamma = 0..n_chol-1
+  (the M = 12 recipe with its random parts scaled by 1/sqrt(M), so the
+  spectrum of every L_gamma stays that of the M = 12 case; without the
+  factor the force bias diverges and every walker is frozen within ten steps
+  at M = 200);
 * sym(G) = (G + G^T)/2;
 * draws come from numpy.random.default_rng(seed): h's random part first, then
   the L_gamma in gamma order;
@@ -47,12 +51,15 @@ class Hamiltonian:
 
 
 def make_hamiltonian(M: int, n_chol: int, seed: int = 0, e_core: float = 0.0,
-                     chol_scale: float = 0.3, chol_decay: float = 10.0) -> Hamiltonian:
+                     chol_scale: float = 0.3, chol_decay: float = 10.0,
+                     ref_M: int = 12) -> Hamiltonian:
     rng = np.random.default_rng(seed)
     h = np.diag(np.linspace(-2.0, 1.0, M)) + _sym(rng.standard_normal((M, M))) / np.sqrt(M)
     chol = np.empty((n_chol, M, M))
+    size_scale = np.sqrt(ref_M / M)
     for g in range(n_chol):
-        chol[g] = _sym(rng.standard_normal((M, M))) * chol_scale * np.exp(-g / chol_decay)
+        chol[g] = (_sym(rng.standard_normal((M, M))) * chol_scale * np.exp(-g / chol_decay)
+                   * size_scale)
     return Hamiltonian(h=np.ascontiguousarray(h), chol=chol, e_core=float(e_core))
 
 

@@ -363,7 +363,7 @@ def test_frozen_walker_keeps_others_unchanged():
     ref = O.init_walkers(sys, 6)
     keep = np.array([0, 1, 3, 4, 5])
     sub = O.Walkers(ref.phi[keep].copy(), ref.weight[keep].copy(), ref.lnov[keep].copy(),
-                    ref.theta[keep].copy(), ref.alive[keep].copy(), 0)
+                    ref.theta[keep].copy(), ref.alive[keep].copy(), 0, ref.e_shift)
     f2 = O.PhiloxFields(5, 1, 36, walkers=keep)
     for t in range(12):
         O.step(sys, sub, f2(sub.t, 5))
