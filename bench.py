@@ -27,9 +27,11 @@ if ROOT not in sys.path:
 METRIC = "walker-steps/s at M=200, Nw=2048 (pair); ΔE error vs FP64 oracle (kcal/mol)"
 EH_TO_KCAL = 627.5095
 PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16": 2500.0}
+# split-BF16 contractions issue three BF16 products per algorithmic product
+ISSUE_FACTOR = {"bf16": 3.0}
 
 
-def phase_flops(name, M, nc, na, nb, nw):
+def phase_flops(name, M, nc, na, nb, nw, taylor_order=6):
     """Algorithmic FLOPs of one launch of a phase for one system (real FLOPs;
     a complex multiply-add is 8, real x complex 4)."""
     N = na + nb
@@ -38,9 +40,8 @@ def phase_flops(name, M, nc, na, nb, nw):
     return {
         "force_bias_gemm": 4.0 * nw * nc * N * M,
         "field_sum_gemm": 4.0 * nw * nc * P,
-        "one_body_half_1": 4.0 * N * nw * M * M,
-        "one_body_half_2": 4.0 * N * nw * M * M,
-        "taylor_term": 8.0 * M * M * N * nw,
+        # P T_K(A) P: two real x complex and K complex x complex products
+        "propagate": nw * (2 * 4.0 * N * M * M + taylor_order * 8.0 * N * M * M),
         "overlap_gemm": 4.0 * M * nsq * nw,
         # one launch per spin; the average over the two spin launches
         "exchange": 0.5 * nw * (4.0 * nc * M * nsq + 8.0 * nc * nsq),
@@ -48,10 +49,11 @@ def phase_flops(name, M, nc, na, nb, nw):
 
 
 def phase_dtype(name, prec):
-    tc = prec
-    tp = "fp64" if prec == "fp64" else "fp32"
-    return {"force_bias_gemm": tc, "field_sum_gemm": tc, "exchange": tc, "taylor_term": tp,
-            "one_body_half_1": tp, "one_body_half_2": tp, "overlap_gemm": "fp64"}.get(name)
+    """Matrix-core input type of a phase under a precision plan."""
+    contract = {"fp64": "fp64", "fp32": "fp32", "bf16": "bf16", "bf16_plain": "bf16"}[prec]
+    prop = "fp64" if prec == "fp64" else "fp32"
+    return {"force_bias_gemm": contract, "field_sum_gemm": contract, "exchange": contract,
+            "propagate": prop, "overlap_gemm": "fp64"}.get(name)
 
 
 def cpu_baseline(cfg, n_walkers, n_steps):
@@ -84,7 +86,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=40)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--precision", default="bf16", choices=["bf16", "fp32", "fp64"])
+    ap.add_argument("--precision", default="bf16", choices=["bf16", "fp32", "fp64", "bf16_plain"])
     ap.add_argument("--walkers", type=int, default=None, help="override walkers per system")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")

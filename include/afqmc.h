@@ -40,13 +40,19 @@ typedef enum {
 } afqmc_status;
 
 /* Arithmetic of the Cholesky contractions (force bias, field sum, exchange)
- * and of the propagator products.  AFQMC_FP64: everything in FP64 (the parity
- * path).  AFQMC_FP32: L, Theta and the propagator products in FP32 with FP32
- * accumulation.  AFQMC_BF16: L and Theta in BF16 for the Cholesky
- * contractions (FP32 accumulation), propagator products in FP32.  In every
- * mode the walker determinants, overlaps, determinants, Gram-Schmidt,
- * weights and phases stay FP64. */
-typedef enum { AFQMC_FP64 = 0, AFQMC_FP32 = 1, AFQMC_BF16 = 2 } afqmc_prec;
+ * and of the propagator products.
+ * AFQMC_FP64: everything in FP64 (the parity path).
+ * AFQMC_FP32: L, L^half, Theta and the field coefficients held in FP32, FP32
+ *   MFMA with FP32 accumulation; propagator products in FP32.
+ * AFQMC_BF16: the Cholesky contractions on the BF16 matrix cores with split
+ *   operands (each FP32 operand carried as hi + lo BF16, three products per
+ *   pair, FP32 accumulation; relative error a few 2^-17); propagator
+ *   products (one-body halves and Taylor terms) in FP32.
+ * AFQMC_BF16_PLAIN: L, L^half, Theta and the field coefficients stored as
+ *   single BF16 values, one BF16 product per pair (fastest, least accurate).
+ * In every mode the walker determinants, overlaps, determinants,
+ * Gram-Schmidt, weights and phases stay FP64. */
+typedef enum { AFQMC_FP64 = 0, AFQMC_FP32 = 1, AFQMC_BF16 = 2, AFQMC_BF16_PLAIN = 3 } afqmc_prec;
 
 /* Projection variant.  PHASELESS: the ph-AFQMC step of Sec. II.A with the
  * hybrid weight of Sec. II.D.  FREE: free projection (no force bias, complex
@@ -161,10 +167,10 @@ const char* afqmc_last_error(void);
 /* Per-phase kernel timing with HIP events on the system's stream.
  * afqmc_profile_enable(sys, 1) clears the counters and starts recording a
  * start/stop event pair around every kernel launch of every later step
- * (phases: 0 force-bias GEMM, 1 fields, 2 field-sum GEMM, 3 first one-body
- * half, 4 Taylor term (one launch per term), 5 second one-body half,
- * 6 overlap GEMM, 7 determinants and Theta, 8 weights, 9 Gram-Schmidt,
- * 10 exchange, 11 local/mixed energy); 0 stops.  afqmc_profile_read
+ * (phases: 0 force-bias GEMM, 1 fields, 2 field-sum GEMM, 3 unpacking of
+ * the symmetric A, 4 fused propagation P T_K(A) P, 5 overlap GEMM,
+ * 6 determinants and Theta, 7 weights, 8 Gram-Schmidt, 9 exchange (one
+ * launch per spin), 10 local/mixed energy); 0 stops.  afqmc_profile_read
  * synchronises and returns the summed milliseconds and the launch count of
  * one phase.  afqmc_phase_name returns a phase's name, NULL past the last. */
 afqmc_status afqmc_profile_enable(afqmc_sys sys, int enable);
@@ -177,6 +183,16 @@ const char* afqmc_phase_name(int phase);
  * contraction kernel against a plain reference.  Synchronises. */
 afqmc_status afqmc_selftest_gemm(afqmc_prec prec, int m, int n, int k, const double* A,
                                  const double* B, double* C);
+
+/* Kernel self-test of the fused propagation: out[w] = P T_K(A_w) P phi[w]
+ * (Eq. 3 and Eq. 11, T_K the order-K Taylor polynomial of exp) with the
+ * products in precision `prec` (AFQMC_FP64, else FP32).  phi, out:
+ * nw x 2 x N x M (plane 0 real, plane 1 imaginary of orbital columns); P:
+ * M x M real symmetric; A: nw x 2 x M x M complex symmetric.  Host float64
+ * arrays; synchronises.  For the numerics tests of the propagation kernel. */
+afqmc_status afqmc_selftest_propagate(afqmc_prec prec, int M, int N, int nw, int K,
+                                      const double* phi, const double* P, const double* A,
+                                      double* out);
 
 /* Device Philox4x32-10 normals x[k, gamma] of step t for walkers 0..nw-1,
  * the same values afqmc_step draws; host output nw x n_chol.  For tests. */

@@ -22,7 +22,7 @@ if not os.path.exists(LIB_PATH):
 _lib = C.CDLL(LIB_PATH)
 
 OK, E_INVALID, E_SHAPE, E_NOMEM, E_DEVICE, E_SINGULAR, E_STATE = 0, -1, -2, -3, -4, -5, -6
-PREC = {"fp64": 0, "fp32": 1, "bf16": 2}
+PREC = {"fp64": 0, "fp32": 1, "bf16": 2, "bf16_plain": 3}
 MODE = {"phaseless": 0, "free": 1}
 
 # Every C-ABI entry point declared in include/afqmc.h.
@@ -31,7 +31,7 @@ EXPORTS = [
     "afqmc_orthonormalize", "afqmc_pair_step", "afqmc_pair_batch_step", "afqmc_get_walkers",
     "afqmc_sys_info", "afqmc_checkpoint", "afqmc_restore", "afqmc_free_sys", "afqmc_free_ham",
     "afqmc_last_error", "afqmc_selftest_gemm", "afqmc_selftest_fields", "afqmc_profile_enable",
-    "afqmc_profile_read", "afqmc_phase_name",
+    "afqmc_profile_read", "afqmc_phase_name", "afqmc_selftest_propagate",
 ]
 
 
@@ -62,6 +62,8 @@ _lib.afqmc_free_ham.argtypes = [_vp]
 _lib.afqmc_free_ham.restype = None
 _lib.afqmc_selftest_gemm.argtypes = [C.c_int, C.c_int, C.c_int, C.c_int, _dp, _dp, _dp]
 _lib.afqmc_selftest_fields.argtypes = [C.c_uint64, C.c_uint64, C.c_int64, C.c_int, C.c_int, _dp]
+_lib.afqmc_selftest_propagate.argtypes = [C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, _dp, _dp,
+                                           _dp, _dp]
 _lib.afqmc_profile_enable.argtypes = [_vp, C.c_int]
 _lib.afqmc_profile_read.argtypes = [_vp, C.c_int, _dp, C.POINTER(C.c_int64)]
 _lib.afqmc_phase_name.argtypes = [C.c_int]
@@ -266,6 +268,19 @@ def selftest_gemm(A, B, precision: str = "fp64") -> np.ndarray:
     Cm = np.empty((m, n))
     _check(_lib.afqmc_selftest_gemm(PREC[precision], m, n, k, _ptr(A), _ptr(B), _ptr(Cm)))
     return Cm
+
+
+def selftest_propagate(phi, P, A, K: int, precision: str = "fp64") -> np.ndarray:
+    """phi: (nw, M, N) complex, P: (M, M) real, A: (nw, M, M) complex symmetric ->
+    P T_K(A) P phi computed by the fused propagation kernel."""
+    phi = np.asarray(phi)
+    nw, M, N = phi.shape
+    ph = _f64(np.stack([np.swapaxes(phi.real, 1, 2), np.swapaxes(phi.imag, 1, 2)], axis=1))
+    Ah = _f64(np.stack([A.real, A.imag], axis=1))
+    out = np.empty_like(ph)
+    _check(_lib.afqmc_selftest_propagate(PREC[precision], M, N, nw, int(K), _ptr(ph), _ptr(_f64(P)),
+                                         _ptr(Ah), _ptr(out)))
+    return np.swapaxes(out[:, 0] + 1j * out[:, 1], 1, 2)
 
 
 def selftest_fields(seed: int, stream_id: int, t: int, nw: int, n_chol: int) -> np.ndarray:

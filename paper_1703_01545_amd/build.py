@@ -14,7 +14,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libafqmc.so")
-SOURCES = ["gemm.hip", "walker.hip", "capi.hip"]
+SOURCES = ["gemm.hip", "propagate.hip", "walker.hip", "capi.hip"]
 ARCH = os.environ.get("AFQMC_ARCH", "gfx950")
 
 FLAGS = [
@@ -36,7 +36,7 @@ def _hipcc() -> str:
     return p
 
 
-def build(verbose: bool = False, jobs: int = 3) -> str:
+def build(verbose: bool = False, jobs: int = 4) -> str:
     """Compile every source and link libafqmc.so; always recompiles."""
     os.makedirs(OBJ, exist_ok=True)
     cc = _hipcc()

@@ -154,9 +154,8 @@ enum Phase {
     PH_FORCE_BIAS = 0,
     PH_FIELDS,
     PH_FIELD_SUM,
-    PH_HALF1,
-    PH_TAYLOR,
-    PH_HALF2,
+    PH_UNPACK,
+    PH_PROPAGATE,
     PH_OVERLAP,
     PH_DET_THETA,
     PH_WEIGHTS,
@@ -166,8 +165,8 @@ enum Phase {
     PH_COUNT
 };
 const char* const kPhaseNames[PH_COUNT] = {
-    "force_bias_gemm", "fields", "field_sum_gemm", "one_body_half_1", "taylor_term",
-    "one_body_half_2", "overlap_gemm", "det_theta", "weights", "mgs", "exchange", "energy"};
+    "force_bias_gemm", "fields",       "field_sum_gemm", "unpack_a", "propagate", "overlap_gemm",
+    "det_theta",       "weights",      "mgs",            "exchange", "energy"};
 
 struct Profiler {
     bool on = false;
@@ -229,7 +228,7 @@ struct afqmc_ham_s {
     uint64_t chol_hash = 0;
     std::vector<double> h;
     DevBuf d_h, d_chol;
-    DevBuf d_lp[3];  // packed L^T per contraction precision: [P][n_chol]
+    DevBuf d_lp[4];  // packed L^T per storage type: [P][n_chol]
     int refs = 1;
     bool released = false;
 };
@@ -238,8 +237,9 @@ struct afqmc_sys_s {
     afqmc_ham ham = nullptr;
     int M = 0, n_chol = 0, na = 0, nb = 0, N = 0, nw = 0;
     afqmc_params par{};
-    DType tc = DT_F64;  // contraction storage / compute type
-    DType tp = DT_F64;  // propagator product type
+    DType ts = DT_F64;  // storage type of the contraction operands (L^half, Theta, X, L)
+    DType tc = DT_F64;  // compute type of the contractions (DT_SPLIT: split BF16)
+    DType tp = DT_F64;  // propagator product type (FP64 or FP32)
     int64_t t = 0;
     double e_shift = 0.0;  // constant energy shift of the weight factor
     bool dead = false;
@@ -249,7 +249,7 @@ struct afqmc_sys_s {
     // walker state
     DevBuf d_phi, d_phinew, d_theta, d_theta_lp, d_w, d_lnov, d_alive;
     // step scratch
-    DevBuf d_F, d_X, d_simp, d_Apk, d_Y, d_T2, d_Z, d_ov, d_lnd, d_exch, d_el, d_sums;
+    DevBuf d_F, d_X, d_simp, d_Apk, d_Af, d_ov, d_lnd, d_exch, d_el, d_sums;
     int n_gt_a = 0, n_gt_b = 0, n_gt = 0;
     Profiler prof;
     long P() const { return (long)M * (M + 1) / 2; }
@@ -268,7 +268,7 @@ void ham_unref(afqmc_ham h) {
     if (--h->refs == 0) delete h;
 }
 
-const void* lp_or(const DevBuf& lp, const DevBuf& hi, DType t) { return t == DT_F64 ? hi.p : lp.p; }
+const void* lp_or(const DevBuf& lp, const DevBuf& hi, DType t) { return t == DT_F64 ? hi.p : lp.p; }  // by storage type
 
 // Brackets one phase with a pair of HIP events when profiling is on.
 struct PhaseTimer {
@@ -296,11 +296,11 @@ struct PhaseTimer {
 afqmc_status force_bias(afqmc_sys s, hipStream_t st) {
     // F[(w,p), g] = sum_(i,m) Theta[(w,p),(i,m)] L^half[g,(i,m)], g <= n_chol
     Gemm g{};
-    g.A = lp_or(s->d_theta_lp, s->d_theta, s->tc);
-    g.ta = s->tc;
+    g.A = lp_or(s->d_theta_lp, s->d_theta, s->ts);
+    g.ta = s->ts;
     g.ra = rows_strided(s->NM());
-    g.B = lp_or(s->d_lhx_lp, s->d_lhx, s->tc);
-    g.tb = s->tc;
+    g.B = lp_or(s->d_lhx_lp, s->d_lhx, s->ts);
+    g.tb = s->ts;
     g.rb = rows_strided(s->NM());
     g.C = s->d_F.p;
     g.tc = DT_F64;
@@ -337,7 +337,7 @@ afqmc_status overlap_theta(afqmc_sys s, double* phi, hipStream_t st) {
     }
     PhaseTimer pt(s, PH_DET_THETA, st);
     HIPCHK(lu_theta(s->d_ov.as<double>(), phi, s->d_theta.as<double>(),
-                    s->tc == DT_F64 ? nullptr : s->d_theta_lp.p, s->tc, s->d_lnd.as<double>(),
+                    s->ts == DT_F64 ? nullptr : s->d_theta_lp.p, s->ts, s->d_lnd.as<double>(),
                     s->d_alive.as<uint8_t>(), s->nw, s->M, s->N, s->na, s->nb, st));
     return AFQMC_OK;
 }
@@ -356,7 +356,7 @@ afqmc_status one_step(afqmc_sys s, uint64_t seed, uint64_t stream_id, const doub
     f.t = s->t;
     f.alive = s->d_alive.as<uint8_t>();
     f.X = s->d_X.p;
-    f.tx = s->tc;
+    f.tx = s->ts;
     f.ldx = s->n_chol;
     f.s_imp = s->d_simp.as<double>();
     f.nw = s->nw;
@@ -371,10 +371,10 @@ afqmc_status one_step(afqmc_sys s, uint64_t seed, uint64_t stream_id, const doub
     {
         Gemm g{};
         g.A = s->d_X.p;
-        g.ta = s->tc;
+        g.ta = s->ts;
         g.ra = rows_strided(s->n_chol);
-        g.B = s->ham->d_lp[s->tc].p;
-        g.tb = s->tc;
+        g.B = s->ham->d_lp[s->ts].p;
+        g.tb = s->ts;
         g.rb = rows_strided(s->n_chol);
         g.C = s->d_Apk.p;
         g.tc = s->tp;
@@ -387,56 +387,17 @@ afqmc_status one_step(afqmc_sys s, uint64_t seed, uint64_t stream_id, const doub
         PhaseTimer pt(s, PH_FIELD_SUM, st);
         HIPCHK(gemm(g, s->tc, st));
     }
-    const void* Pm = s->tp == DT_F64 ? s->d_P.p : s->d_Plp.p;
-    // Y = P Phi (first one-body half), Z = Y
     {
-        Gemm g{};
-        g.A = s->d_phi.p;
-        g.ta = DT_F64;
-        g.ra = rows_strided(s->M);
-        g.B = Pm;
-        g.tb = s->tp;
-        g.rb = rows_strided(s->M);
-        g.C = s->d_Y.p;
-        g.C2 = s->d_Z.p;
-        g.tc = s->tp;
-        g.rc = rows_strided(s->M);
-        g.alpha = 1.0;
-        g.m = 2 * s->N * s->nw;
-        g.n = s->M;
-        g.k = s->M;
-        g.batch = 1;
-        PhaseTimer pt(s, PH_HALF1, st);
-        HIPCHK(gemm(g, s->tp, st));
+        PhaseTimer pt(s, PH_UNPACK, st);
+        HIPCHK(unpack_sym(s->d_Apk.p, s->d_Af.p, s->M, 2 * s->nw, s->tp, st));
     }
-    // Taylor series of exp(A) applied to Y, accumulated in Z
-    void* cur = s->d_Y.p;
-    void* nxt = s->d_T2.p;
-    for (int n = 1; n <= s->par.taylor_order; ++n) {
-        PhaseTimer pt(s, PH_TAYLOR, st);
-        HIPCHK(taylor_term(cur, nxt, s->d_Z.p, s->d_Apk.p, s->d_alive.as<uint8_t>(), s->nw, s->M,
-                           s->N, 1.0 / n, s->tp, st));
-        std::swap(cur, nxt);
-    }
-    // Phi' = P Z (second one-body half), FP64 result
+    // Phi' = P T_K(A) P Phi, fused per walker
     {
-        Gemm g{};
-        g.A = s->d_Z.p;
-        g.ta = s->tp;
-        g.ra = rows_strided(s->M);
-        g.B = Pm;
-        g.tb = s->tp;
-        g.rb = rows_strided(s->M);
-        g.C = s->d_phinew.p;
-        g.tc = DT_F64;
-        g.rc = rows_strided(s->M);
-        g.alpha = 1.0;
-        g.m = 2 * s->N * s->nw;
-        g.n = s->M;
-        g.k = s->M;
-        g.batch = 1;
-        PhaseTimer pt(s, PH_HALF2, st);
-        HIPCHK(gemm(g, s->tp, st));
+        const void* Pm = s->tp == DT_F64 ? s->d_P.p : s->d_Plp.p;
+        PhaseTimer pt(s, PH_PROPAGATE, st);
+        HIPCHK(propagate(s->d_phi.as<double>(), s->d_phinew.as<double>(), Pm, s->d_Af.p,
+                         s->d_alive.as<uint8_t>(), s->nw, s->M, s->N, s->par.taylor_order, s->tp,
+                         st));
     }
     if ((r = overlap_theta(s, s->d_phinew.as<double>(), st)) != AFQMC_OK) return r;
     PhaseTimer pt(s, PH_WEIGHTS, st);
@@ -466,14 +427,14 @@ afqmc_status ortho(afqmc_sys s, hipStream_t st) {
 afqmc_status measure(afqmc_sys s, hipStream_t st) {
     afqmc_status r = force_bias(s, st);
     if (r != AFQMC_OK) return r;
-    const void* lh = lp_or(s->d_lhx_lp, s->d_lhx, s->tc);
-    const void* th = lp_or(s->d_theta_lp, s->d_theta, s->tc);
-    {
+    const void* lh = lp_or(s->d_lhx_lp, s->d_lhx, s->ts);
+    const void* th = lp_or(s->d_theta_lp, s->d_theta, s->ts);
+    for (int spin = 0; spin < 2; ++spin) {
+        const int off = spin ? s->na : 0, n = spin ? s->nb : s->na;
+        if (n == 0) continue;
         PhaseTimer pt(s, PH_EXCHANGE, st);
-        HIPCHK(exchange(lh, th, s->d_exch.as<double>(), s->nw, s->M, s->N, s->n_chol, 0, s->na, 0,
-                    s->n_gt, s->tc, st));
-    HIPCHK(exchange(lh, th, s->d_exch.as<double>(), s->nw, s->M, s->N, s->n_chol, s->na, s->nb, 1,
-                    s->n_gt, s->tc, st));
+        HIPCHK(exchange(lh, th, s->d_exch.as<double>(), s->nw, s->M, s->N, s->n_chol, off, n, spin,
+                        s->n_gt, s->tc, st));
     }
     PhaseTimer pt(s, PH_ENERGY, st);
     HIPCHK(local_energy(s->d_F.as<double>(), s->n_chol + 1, s->d_exch.as<double>(), s->n_gt_a,
@@ -535,10 +496,11 @@ afqmc_status afqmc_init_walkers(afqmc_ham ham, int n_alpha, int n_beta, const do
     if (n_alpha < 0 || n_beta < 0 || n_alpha > M || n_beta > M || n_alpha + n_beta == 0)
         return fail(AFQMC_E_SHAPE, "need 0 <= n_alpha, n_beta <= M and n_alpha + n_beta > 0");
     if (n_alpha > 64 || n_beta > 64) return fail(AFQMC_E_SHAPE, "at most 64 electrons per spin");
+    if (M > 256) return fail(AFQMC_E_SHAPE, "the fused propagation supports M <= 256");
     if (n_walkers <= 0) return fail(AFQMC_E_INVALID, "n_walkers must be > 0");
     if (!(par->dt > 0.0) || par->taylor_order < 1 || par->ortho_every < 0 || par->measure_every < 0)
         return fail(AFQMC_E_INVALID, "bad params (dt > 0, taylor_order >= 1, periods >= 0)");
-    if (par->contract_prec < AFQMC_FP64 || par->contract_prec > AFQMC_BF16)
+    if (par->contract_prec < AFQMC_FP64 || par->contract_prec > AFQMC_BF16_PLAIN)
         return fail(AFQMC_E_INVALID, "bad contract_prec");
     if (par->mode != AFQMC_PHASELESS && par->mode != AFQMC_FREE)
         return fail(AFQMC_E_INVALID, "bad mode");
@@ -553,9 +515,12 @@ afqmc_status afqmc_init_walkers(afqmc_ham ham, int n_alpha, int n_beta, const do
     s->N = n_alpha + n_beta;
     s->nw = n_walkers;
     s->par = *par;
-    s->tc = par->contract_prec == AFQMC_FP64 ? DT_F64
-                                             : (par->contract_prec == AFQMC_FP32 ? DT_F32 : DT_BF16);
-    s->tp = par->contract_prec == AFQMC_FP64 ? DT_F64 : DT_F32;
+    switch (par->contract_prec) {
+        case AFQMC_FP64: s->ts = DT_F64; s->tc = DT_F64; s->tp = DT_F64; break;
+        case AFQMC_FP32: s->ts = DT_F32; s->tc = DT_F32; s->tp = DT_F32; break;
+        case AFQMC_BF16: s->ts = DT_F32; s->tc = DT_SPLIT; s->tp = DT_F32; break;
+        default: s->ts = DT_BF16; s->tc = DT_BF16; s->tp = DT_F32; break;
+    }
     auto bail = [&](afqmc_status r) {
         afqmc_free_sys(s);
         return r;
@@ -563,7 +528,7 @@ afqmc_status afqmc_init_walkers(afqmc_ham ham, int n_alpha, int n_beta, const do
     const int N = s->N, nc = s->n_chol, nw = n_walkers;
     const long NM = s->NM(), P = s->P();
     s->n_gt_a = exchange_gtiles(nc, s->na, s->tc);
-    s->n_gt_b = exchange_gtiles(nc, s->nb, s->tc);
+    s->n_gt_b = exchange_gtiles(nc, s->nb, s->tc);  // tiles depend on the compute type
     s->n_gt = std::max(1, std::max(s->n_gt_a, s->n_gt_b));
     struct A_ {
         DevBuf* b;
@@ -574,21 +539,19 @@ afqmc_status afqmc_init_walkers(afqmc_ham ham, int n_alpha, int n_beta, const do
         {&s->d_Plp, (size_t)M * M * 4},
         {&s->d_a, (size_t)std::max(nc, 1) * 8},
         {&s->d_lhx, (size_t)(nc + 1) * NM * 8},
-        {&s->d_lhx_lp, s->tc == DT_F64 ? 0 : (size_t)(nc + 1) * NM * dt_size(s->tc)},
+        {&s->d_lhx_lp, s->ts == DT_F64 ? 0 : (size_t)(nc + 1) * NM * dt_size(s->ts)},
         {&s->d_phi, (size_t)nw * 2 * NM * 8},
         {&s->d_phinew, (size_t)nw * 2 * NM * 8},
         {&s->d_theta, (size_t)nw * 2 * NM * 8},
-        {&s->d_theta_lp, s->tc == DT_F64 ? 0 : (size_t)nw * 2 * NM * dt_size(s->tc)},
+        {&s->d_theta_lp, s->ts == DT_F64 ? 0 : (size_t)nw * 2 * NM * dt_size(s->ts)},
         {&s->d_w, (size_t)nw * 2 * 8},
         {&s->d_lnov, (size_t)nw * 2 * 8},
         {&s->d_alive, (size_t)nw},
         {&s->d_F, (size_t)nw * 2 * (nc + 1) * 8},
-        {&s->d_X, (size_t)nw * 2 * std::max(nc, 1) * dt_size(s->tc)},
+        {&s->d_X, (size_t)nw * 2 * std::max(nc, 1) * dt_size(s->ts)},
         {&s->d_simp, (size_t)nw * 4 * 8},
         {&s->d_Apk, (size_t)nw * 2 * P * dt_size(s->tp)},
-        {&s->d_Y, (size_t)nw * 2 * NM * dt_size(s->tp)},
-        {&s->d_T2, (size_t)nw * 2 * NM * dt_size(s->tp)},
-        {&s->d_Z, (size_t)nw * 2 * NM * dt_size(s->tp)},
+        {&s->d_Af, (size_t)nw * 2 * M * M * dt_size(s->tp)},
         {&s->d_ov, (size_t)nw * 2 * N * N * 8},
         {&s->d_lnd, (size_t)nw * 4 * 8},
         {&s->d_exch, (size_t)nw * 2 * s->n_gt * 2 * 8},
@@ -719,13 +682,13 @@ afqmc_status afqmc_init_walkers(afqmc_ham ham, int n_alpha, int n_beta, const do
             return bail(fail(AFQMC_E_DEVICE, "upload P"));
     }
     // low-precision copies of the contraction operands
-    if (s->tc != DT_F64 &&
-        convert(s->d_lhx.as<double>(), s->d_lhx_lp.p, s->tc, (long)(nc + 1) * NM, st) != hipSuccess)
+    if (s->ts != DT_F64 &&
+        convert(s->d_lhx.as<double>(), s->d_lhx_lp.p, s->ts, (long)(nc + 1) * NM, st) != hipSuccess)
         return bail(fail(AFQMC_E_DEVICE, "convert L^half"));
-    if (!ham->d_lp[s->tc].p) {
-        if (ham->d_lp[s->tc].alloc((size_t)P * std::max(nc, 1) * dt_size(s->tc)) != hipSuccess)
+    if (!ham->d_lp[s->ts].p) {
+        if (ham->d_lp[s->ts].alloc((size_t)P * std::max(nc, 1) * dt_size(s->ts)) != hipSuccess)
             return bail(fail(AFQMC_E_NOMEM, "packed L"));
-        if (pack_chol(ham->d_chol.as<double>(), ham->d_lp[s->tc].p, s->tc, M, nc, st) != hipSuccess)
+        if (pack_chol(ham->d_chol.as<double>(), ham->d_lp[s->ts].p, s->ts, M, nc, st) != hipSuccess)
             return bail(fail(AFQMC_E_DEVICE, "pack L"));
     }
     // walkers: Phi = init (real), w = 1, alive = 1
@@ -786,8 +749,8 @@ void afqmc_free_sys(afqmc_sys s) {
     // later calls on it report E_STATE instead of touching freed memory
     for (DevBuf* b : {&s->d_trialT, &s->d_P, &s->d_Plp, &s->d_a, &s->d_lhx, &s->d_lhx_lp,
                       &s->d_phi, &s->d_phinew, &s->d_theta, &s->d_theta_lp, &s->d_w, &s->d_lnov,
-                      &s->d_alive, &s->d_F, &s->d_X, &s->d_simp, &s->d_Apk, &s->d_Y, &s->d_T2,
-                      &s->d_Z, &s->d_ov, &s->d_lnd, &s->d_exch, &s->d_el, &s->d_sums})
+                      &s->d_alive, &s->d_F, &s->d_X, &s->d_simp, &s->d_Apk, &s->d_Af,
+                      &s->d_ov, &s->d_lnd, &s->d_exch, &s->d_el, &s->d_sums})
         b->release();
     s->ham = nullptr;
     if (h) ham_unref(h);
@@ -970,8 +933,8 @@ afqmc_status afqmc_restore(afqmc_sys s, const void* src, size_t bytes) {
     HIPCHK(hipMemcpy(s->d_lnov.p, p, s->d_lnov.n, hipMemcpyHostToDevice));
     p += s->d_lnov.n;
     HIPCHK(hipMemcpy(s->d_alive.p, p, s->nw, hipMemcpyHostToDevice));
-    if (s->tc != DT_F64) {
-        HIPCHK(convert(s->d_theta.as<double>(), s->d_theta_lp.p, s->tc, (long)s->nw * 2 * s->NM(), st));
+    if (s->ts != DT_F64) {
+        HIPCHK(convert(s->d_theta.as<double>(), s->d_theta_lp.p, s->ts, (long)s->nw * 2 * s->NM(), st));
         HIPCHK(hipStreamSynchronize(st));
     }
     s->t = hdr[1];
@@ -1025,10 +988,42 @@ afqmc_status afqmc_selftest_gemm(afqmc_prec prec, int m, int n, int k, const dou
     g.n = n;
     g.k = k;
     g.batch = 1;
-    const DType c = prec == AFQMC_FP64 ? DT_F64 : (prec == AFQMC_FP32 ? DT_F32 : DT_BF16);
+    const DType c = prec == AFQMC_FP64   ? DT_F64
+                    : prec == AFQMC_FP32 ? DT_F32
+                    : prec == AFQMC_BF16 ? DT_SPLIT
+                                         : DT_BF16;
     HIPCHK(gemm(g, c, nullptr));
     HIPCHK(hipDeviceSynchronize());
     HIPCHK(hipMemcpy(C, dC.p, (size_t)m * n * 8, hipMemcpyDeviceToHost));
+    return AFQMC_OK;
+}
+
+afqmc_status afqmc_selftest_propagate(afqmc_prec prec, int M, int N, int nw, int K,
+                                      const double* phi, const double* P, const double* A,
+                                      double* out) {
+    if (!phi || !P || !A || !out || M <= 0 || N <= 0 || nw <= 0 || K < 0)
+        return fail(AFQMC_E_INVALID, "bad args");
+    if (M > 256) return fail(AFQMC_E_SHAPE, "M <= 256");
+    const DType t = prec == AFQMC_FP64 ? DT_F64 : DT_F32;
+    const size_t nphi = (size_t)nw * 2 * N * M, nA = (size_t)nw * 2 * M * M, nP = (size_t)M * M;
+    DevBuf dphi, dout, dP, dA, dP64, dA64, dlive;
+    HIPCHK(dphi.alloc(nphi * 8));
+    HIPCHK(dout.alloc(nphi * 8));
+    HIPCHK(dP64.alloc(nP * 8));
+    HIPCHK(dA64.alloc(nA * 8));
+    HIPCHK(dP.alloc(nP * dt_size(t)));
+    HIPCHK(dA.alloc(nA * dt_size(t)));
+    HIPCHK(dlive.alloc(nw));
+    HIPCHK(hipMemcpy(dphi.p, phi, nphi * 8, hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(dP64.p, P, nP * 8, hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(dA64.p, A, nA * 8, hipMemcpyHostToDevice));
+    HIPCHK(hipMemset(dlive.p, 1, nw));
+    HIPCHK(convert(dP64.as<double>(), dP.p, t, (long)nP, nullptr));
+    HIPCHK(convert(dA64.as<double>(), dA.p, t, (long)nA, nullptr));
+    HIPCHK(propagate(dphi.as<double>(), dout.as<double>(), dP.p, dA.p, dlive.as<uint8_t>(), nw, M,
+                     N, K, t, nullptr));
+    HIPCHK(hipDeviceSynchronize());
+    HIPCHK(hipMemcpy(out, dout.p, nphi * 8, hipMemcpyDeviceToHost));
     return AFQMC_OK;
 }
 

@@ -26,7 +26,9 @@ inline RowMap rows_2level(int n_in, long s_in, long s_out, long base = 0) {
     return RowMap{base, n_in, s_in, s_out};
 }
 
-enum DType { DT_F64 = 0, DT_F32 = 1, DT_BF16 = 2 };
+// Storage / compute types.  DT_SPLIT is a compute type only: FP32 operands
+// carried as hi + lo BF16 pairs on the BF16 matrix cores.
+enum DType { DT_F64 = 0, DT_F32 = 1, DT_BF16 = 2, DT_SPLIT = 3 };
 
 // C[b][i, j] = alpha * sum_k A[b](i, k) * B[b](j, k) + beta * C[b][i, j]
 // A(i, k) = A[b * a_bs + rowA(i) + k], B(j, k) = B[b * b_bs + rowB(j) + k],
@@ -56,14 +58,18 @@ struct Gemm {
 // DT_F64 and FP32 otherwise).
 hipError_t gemm(const Gemm& g, DType compute, hipStream_t s);
 
-// One Taylor term of the HS propagator for every walker (complex, Eq. 11):
-//   Tn[w] = (1/n) A_w Tprev[w],  Z[w] += Tn[w]
-// Tprev, Tn, Z: walker blocks [w][plane][N][M] (plane stride N*M); A_w
-// complex symmetric packed (upper triangle, row-major) at
-// Apk[(2w + plane) * P + q], P = M(M+1)/2.  Walkers with live[w] == 0 are
-// skipped.
-hipError_t taylor_term(const void* Tprev, void* Tn, void* Z, const void* Apk, const uint8_t* live,
-                       int nw, int M, int N, double inv_n, DType t, hipStream_t s);
+// Packed upper triangle (P = M(M+1)/2 per plane) -> full symmetric M x M,
+// for `planes` consecutive planes (types DT_F64 / DT_F32).
+hipError_t unpack_sym(const void* pk, void* full, int M, int planes, DType t, hipStream_t s);
+
+// Fused propagation of every walker (Eq. 3 and Eq. 11):
+//   Phi_out[w] = P T_K(A_w) P Phi[w],  T_K(A) = sum_{n <= K} A^n / n!
+// phi, phi_out: FP64 walker blocks [w][plane][N][M]; Pm: M x M real
+// symmetric, Af: [w][plane][M][M] complex symmetric, both in type t
+// (DT_F64 or DT_F32, the product precision).  Frozen walkers (live == 0)
+// are copied unchanged.  M <= 256.
+hipError_t propagate(const double* phi, double* phi_out, const void* Pm, const void* Af,
+                     const uint8_t* live, int nw, int M, int N, int K, DType t, hipStream_t s);
 
 // Exchange partial sums of the mixed local energy:
 //   out[(w * 2 + spin) * n_gtiles + gt] = sum over gamma in tile gt of

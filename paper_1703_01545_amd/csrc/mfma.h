@@ -1,0 +1,308 @@
+// Device building blocks shared by the contraction kernels (gfx950):
+// MFMA wrappers, storage conversions, split-BF16 operands, vector loads and
+// the LDS-staged GEMM core.
+//
+// MFMA fragment layout (v_mfma_{f64,f32}_16x16x4 and v_mfma_f32_16x16x32_bf16):
+// lane l supplies A[l % 16][kb + l / 16] and B^T[l % 16][kb + l / 16]
+// (kb + 8 (l / 16) + e, e < 8, for bf16).  Accumulator element r of lane l
+// is D[4 (l / 16) + r][l % 16] for the FP32-accumulating instructions and
+// D[l / 16 + 4 r][l % 16] for v_mfma_f64_16x16x4.
+//
+// Split-BF16 ("x3"): an FP32 value x is carried as hi = bf16(x) and
+// lo = bf16(x - hi); a product a b is evaluated as a_hi b_hi + a_hi b_lo +
+// a_lo b_hi on the BF16 matrix cores with FP32 accumulation (the dropped
+// a_lo b_lo term and the two roundings leave a relative error of a few
+// 2^-17), three MFMAs where FP32 would need eight 16x16x4 instructions.
+#pragma once
+
+#include <type_traits>
+
+#include "internal.h"
+
+namespace afq {
+namespace dev {
+
+typedef double d2 __attribute__((ext_vector_type(2)));
+typedef double d4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+typedef unsigned short us8 __attribute__((ext_vector_type(8)));
+
+// Compute-type tag of the split-BF16 scheme.
+struct Split {};
+
+template <typename TC>
+struct AccT {
+    typedef float s;
+    typedef f4 v;
+};
+template <>
+struct AccT<double> {
+    typedef double s;
+    typedef d4 v;
+};
+
+__device__ __forceinline__ d4 mma1(double a, double b, d4 c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ f4 mma1(float a, float b, f4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ f4 mma8(bf8 a, bf8 b, f4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+
+// Row of accumulator element r held by lane l (see the layout note above).
+template <typename TC>
+__device__ __forceinline__ int acc_row(int lane, int r) {
+    return 4 * (lane >> 4) + r;
+}
+template <>
+__device__ __forceinline__ int acc_row<double>(int lane, int r) {
+    return (lane >> 4) + 4 * r;
+}
+
+__device__ __forceinline__ long rowmap(const RowMap& r, long i) {
+    if (r.n_in == 1) return r.base + i * r.s_out;
+    return r.base + (i / r.n_in) * r.s_out + (i % r.n_in) * r.s_in;
+}
+
+// ---- storage element -> staging value (double for FP64 compute, else float)
+template <typename ST, typename TS>
+__device__ __forceinline__ ST stage(TS x) { return (ST)x; }
+template <>
+__device__ __forceinline__ float stage<float, bf16_t>(bf16_t x) { return (float)x; }
+template <>
+__device__ __forceinline__ double stage<double, bf16_t>(bf16_t x) { return (double)(float)x; }
+
+__device__ __forceinline__ bf16_t to_bf(float x) { return (bf16_t)x; }
+
+template <typename TC>
+struct Info {
+    typedef float ST;                // staging type
+    static constexpr int KM = 32;    // k per MFMA
+    static constexpr int PLANES = 1; // LDS planes per operand (hi/lo for Split)
+    typedef bf16_t LT;               // LDS element type
+};
+template <>
+struct Info<double> {
+    typedef double ST;
+    static constexpr int KM = 4;
+    static constexpr int PLANES = 1;
+    typedef double LT;
+};
+template <>
+struct Info<float> {
+    typedef float ST;
+    static constexpr int KM = 4;
+    static constexpr int PLANES = 1;
+    typedef float LT;
+};
+template <>
+struct Info<Split> {
+    typedef float ST;
+    static constexpr int KM = 32;
+    static constexpr int PLANES = 2;
+    typedef bf16_t LT;
+};
+
+// LDS row pitch in elements: odd word strides for 4/8-byte types, 16-byte
+// aligned rows (+8 elements) for BF16 so fragments load as one 16-byte read.
+template <typename TC, int BK>
+struct Pitch {
+    static constexpr int v = BK + (sizeof(typename Info<TC>::LT) == 2 ? 8 : 1);
+};
+
+// Store one staged value into the LDS plane(s) of compute type TC.
+template <typename TC>
+__device__ __forceinline__ void lds_put(typename Info<TC>::LT* p, long plane, int idx,
+                                        typename Info<TC>::ST v) {
+    if constexpr (std::is_same<TC, Split>::value) {
+        const bf16_t hi = to_bf(v);
+        p[idx] = hi;
+        p[plane + idx] = to_bf(v - (float)hi);
+    } else if constexpr (std::is_same<TC, bf16_t>::value) {
+        p[idx] = to_bf(v);
+    } else {
+        p[idx] = v;
+    }
+}
+
+// Vector width (elements) of one 16-byte global load of storage type TS.
+template <typename TS>
+struct VW {
+    static constexpr int v = 16 / sizeof(TS);
+};
+
+// Load V consecutive elements starting at p[kg] into staging registers;
+// vector load when the whole run is in range and aligned, else per element
+// with k >= K reading as zero.
+template <typename ST, typename TS, int V, bool ALIGNED>
+__device__ __forceinline__ void gload_run(const TS* __restrict__ row, int kg, int K, ST* out) {
+    if (ALIGNED && kg + V <= K) {
+        if constexpr (sizeof(TS) == 8) {
+            const d2 x = *reinterpret_cast<const d2*>(row + kg);
+            out[0] = (ST)x[0];
+            out[1] = (ST)x[1];
+        } else if constexpr (sizeof(TS) == 4) {
+            const f4 x = *reinterpret_cast<const f4*>(row + kg);
+#pragma unroll
+            for (int e = 0; e < 4; ++e) out[e] = (ST)x[e];
+        } else {
+            const bf8 x = *reinterpret_cast<const bf8*>(row + kg);
+#pragma unroll
+            for (int e = 0; e < 8; ++e) out[e] = stage<ST>(x[e]);
+        }
+    } else {
+#pragma unroll
+        for (int e = 0; e < V; ++e) out[e] = (kg + e < K) ? stage<ST>(row[kg + e]) : (ST)0;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// GEMM core.  C[i, j] = sum_k A(i, k) B(j, k), both operands K-contiguous
+// rows resolved once per thread (aoff/boff; -1 = row out of range, reads
+// zero).  BM x BK and BN x BK tiles are staged through LDS with one register
+// prefetch of the next K tile; each of the NT/64 waves accumulates TM x TN
+// MFMA blocks of a (BM/WGM) x (BN/WGN) sub-tile.  V*: elements per global
+// load of each operand (1 = scalar, else one 16-byte vector load).
+template <typename TA, typename TB, typename TC, int BM, int BN, int BK, int WGM, int WGN, int VA,
+          int VB, bool AL>
+struct Core {
+    static constexpr int NT = 64 * WGM * WGN;
+    static constexpr int TM = BM / WGM / 16;
+    static constexpr int TN = BN / WGN / 16;
+    typedef typename Info<TC>::ST ST;
+    typedef typename Info<TC>::LT LT;
+    static constexpr int PK = Pitch<TC, BK>::v;
+    static constexpr int PL = Info<TC>::PLANES;
+    // threads per row and rows per pass for each operand
+    static constexpr int TPRA = BK / VA, RPA = NT / TPRA, LA = BM / RPA;
+    static constexpr int TPRB = BK / VB, RPB = NT / TPRB, LB = BN / RPB;
+    static constexpr int LDS_A = PL * BM * PK, LDS_B = PL * BN * PK;  // elements
+    typedef typename AccT<TC>::v accv;
+    static_assert(BM % (WGM * 16) == 0 && BN % (WGN * 16) == 0, "tile");
+    static_assert(BK % VA == 0 && BK % VB == 0 && NT % TPRA == 0 && NT % TPRB == 0, "loads");
+    static_assert(LA >= 1 && LB >= 1 && BM % RPA == 0 && BN % RPB == 0, "loads");
+    static_assert(BK % Info<TC>::KM == 0, "bk");
+
+    // per-thread rows: r = tid / TPR + j * RP
+    static __device__ __forceinline__ int arow(int j) { return threadIdx.x / TPRA + j * RPA; }
+    static __device__ __forceinline__ int brow(int j) { return threadIdx.x / TPRB + j * RPB; }
+
+    static __device__ __forceinline__ void run(const TA* __restrict__ A, const long* aoff,
+                                               const TB* __restrict__ B, const long* boff, int K,
+                                               LT* As, LT* Bs, accv (&acc)[TM][TN]) {
+        const int tid = threadIdx.x;
+        const int lane = tid & 63;
+        const int wave = tid >> 6;
+        const int wm = wave / WGN, wn = wave % WGN;
+        const int ka = (tid % TPRA) * VA, kb = (tid % TPRB) * VB;
+        ST ra[LA][VA], rb[LB][VB];
+#pragma unroll
+        for (int a = 0; a < TM; ++a)
+#pragma unroll
+            for (int b = 0; b < TN; ++b)
+                for (int e = 0; e < 4; ++e) acc[a][b][e] = 0;
+
+        auto gload = [&](int k0) {
+#pragma unroll
+            for (int j = 0; j < LA; ++j) {
+                if (aoff[j] >= 0)
+                    gload_run<ST, TA, VA, AL>(A + aoff[j], k0 + ka, K, ra[j]);
+                else
+#pragma unroll
+                    for (int e = 0; e < VA; ++e) ra[j][e] = (ST)0;
+            }
+#pragma unroll
+            for (int j = 0; j < LB; ++j) {
+                if (boff[j] >= 0)
+                    gload_run<ST, TB, VB, AL>(B + boff[j], k0 + kb, K, rb[j]);
+                else
+#pragma unroll
+                    for (int e = 0; e < VB; ++e) rb[j][e] = (ST)0;
+            }
+        };
+        auto sstore = [&]() {
+#pragma unroll
+            for (int j = 0; j < LA; ++j)
+#pragma unroll
+                for (int e = 0; e < VA; ++e) lds_put<TC>(As, BM * PK, arow(j) * PK + ka + e, ra[j][e]);
+#pragma unroll
+            for (int j = 0; j < LB; ++j)
+#pragma unroll
+                for (int e = 0; e < VB; ++e) lds_put<TC>(Bs, BN * PK, brow(j) * PK + kb + e, rb[j][e]);
+        };
+
+        gload(0);
+        sstore();
+        __syncthreads();
+        for (int k0 = 0; k0 < K; k0 += BK) {
+            const bool more = k0 + BK < K;
+            if (more) gload(k0 + BK);
+            if constexpr (Info<TC>::KM == 4) {
+#pragma unroll
+                for (int ks = 0; ks < BK; ks += 4) {
+                    LT af[TM], bfr[TN];
+#pragma unroll
+                    for (int a = 0; a < TM; ++a)
+                        af[a] = As[(wm * TM * 16 + a * 16 + (lane & 15)) * PK + ks + (lane >> 4)];
+#pragma unroll
+                    for (int b = 0; b < TN; ++b)
+                        bfr[b] = Bs[(wn * TN * 16 + b * 16 + (lane & 15)) * PK + ks + (lane >> 4)];
+#pragma unroll
+                    for (int a = 0; a < TM; ++a)
+#pragma unroll
+                        for (int b = 0; b < TN; ++b) acc[a][b] = mma1(af[a], bfr[b], acc[a][b]);
+                }
+            } else {
+#pragma unroll
+                for (int ks = 0; ks < BK; ks += 32) {
+                    bf8 ah[TM], bh[TN];
+#pragma unroll
+                    for (int a = 0; a < TM; ++a)
+                        ah[a] = *reinterpret_cast<const bf8*>(
+                            &As[(wm * TM * 16 + a * 16 + (lane & 15)) * PK + ks + 8 * (lane >> 4)]);
+#pragma unroll
+                    for (int b = 0; b < TN; ++b)
+                        bh[b] = *reinterpret_cast<const bf8*>(
+                            &Bs[(wn * TN * 16 + b * 16 + (lane & 15)) * PK + ks + 8 * (lane >> 4)]);
+                    if constexpr (PL == 2) {
+                        bf8 al[TM], bl[TN];
+#pragma unroll
+                        for (int a = 0; a < TM; ++a)
+                            al[a] = *reinterpret_cast<const bf8*>(
+                                &As[BM * PK + (wm * TM * 16 + a * 16 + (lane & 15)) * PK + ks +
+                                    8 * (lane >> 4)]);
+#pragma unroll
+                        for (int b = 0; b < TN; ++b)
+                            bl[b] = *reinterpret_cast<const bf8*>(
+                                &Bs[BN * PK + (wn * TN * 16 + b * 16 + (lane & 15)) * PK + ks +
+                                    8 * (lane >> 4)]);
+#pragma unroll
+                        for (int a = 0; a < TM; ++a)
+#pragma unroll
+                            for (int b = 0; b < TN; ++b) {
+                                acc[a][b] = mma8(al[a], bh[b], acc[a][b]);
+                                acc[a][b] = mma8(ah[a], bl[b], acc[a][b]);
+                                acc[a][b] = mma8(ah[a], bh[b], acc[a][b]);
+                            }
+                    } else {
+#pragma unroll
+                        for (int a = 0; a < TM; ++a)
+#pragma unroll
+                            for (int b = 0; b < TN; ++b) acc[a][b] = mma8(ah[a], bh[b], acc[a][b]);
+                    }
+                }
+            }
+            __syncthreads();
+            if (more) {
+                sstore();
+                __syncthreads();
+            }
+        }
+    }
+};
+
+}  // namespace dev
+}  // namespace afq

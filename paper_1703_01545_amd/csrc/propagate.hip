@@ -1,0 +1,313 @@
+// Fused walker propagation (Eq. 11 between one-body halves, Eq. 3):
+//   Phi' = P T_K(A_w) P Phi,   T_K(A) = sum_{n <= K} A^n / n!,
+// evaluated term by term (term_n = A term_{n-1} / n) for every walker.
+//
+// Each workgroup owns R orbital columns of one walker for the whole
+// propagation: the orbitals never couple (every factor multiplies from the
+// left), so the R x M complex state stays resident in LDS across the
+// 2 + K dense products and only P, A_w and the walker itself stream from
+// HBM/L2.  The running sum Z of the Taylor terms lives in registers.  The
+// products run on the matrix cores (FP32 or FP64 MFMA 16x16x4).
+#include "mfma.h"
+
+namespace afq {
+namespace {
+
+using namespace dev;
+
+// Packed upper triangle (row-major, P = M(M+1)/2 per plane) -> full
+// symmetric M x M, through a 32 x 33 LDS tile so both the direct and the
+// mirrored writes are coalesced.  grid: (row bands of 32, planes).
+template <typename T>
+__global__ __launch_bounds__(256) void k_unpack(const T* __restrict__ pk, T* __restrict__ full,
+                                                int M) {
+    __shared__ T tile[32][33];
+    const long P = (long)M * (M + 1) / 2;
+    const long plane = blockIdx.y;
+    const int ti = blockIdx.x;
+    const T* src = pk + plane * P;
+    T* dst = full + plane * (long)M * M;
+    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // 32 x 8
+    const int nt = (M + 31) / 32;
+    for (int tj = ti; tj < nt; ++tj) {
+        // load rows i in band ti, columns j in band tj with j >= i
+        for (int r = ty; r < 32; r += 8) {
+            const int i = ti * 32 + r, j = tj * 32 + tx;
+            T v = (T)0;
+            if (i < M && j < M && j >= i) v = src[(long)i * (2 * M - i + 1) / 2 + (j - i)];
+            tile[r][tx] = v;
+        }
+        __syncthreads();
+        for (int r = ty; r < 32; r += 8) {
+            const int i = ti * 32 + r, j = tj * 32 + tx;
+            if (i < M && j < M) {
+                // direct element (i, j): upper part from the tile, lower part of a
+                // diagonal tile from its mirror
+                dst[(long)i * M + j] = (j >= i) ? tile[r][tx] : tile[tx][r];
+            }
+            if (tj != ti) {
+                // mirrored element (j', i') with j' = tj*32 + r, i' = ti*32 + tx
+                const int jm = tj * 32 + r, im = ti * 32 + tx;
+                if (jm < M && im < M) dst[(long)jm * M + im] = tile[tx][r];
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// Raw buffer loads: 32-bit byte offsets against a descriptor of the operand
+// (no 64-bit address registers; offsets past the end read as zero).
+constexpr int kBufFlags = 0x00020000;  // gfx9-family raw buffer descriptor word 3
+constexpr int kOutOfRange = 0x40000000;
+
+template <typename T>
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const T* p, long n) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<T*>(p), (short)0, (int)(n * sizeof(T)),
+                                             kBufFlags);
+}
+__device__ __forceinline__ float bload(__amdgpu_buffer_rsrc_t r, int off, float) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
+}
+__device__ __forceinline__ double bload(__amdgpu_buffer_rsrc_t r, int off, double) {
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
+}
+
+// Raw buffer load of 4 consecutive elements of T (float: one dwordx4;
+// double: two dwordx4).  The loaded vector is bit-cast as a whole.
+__device__ __forceinline__ void bload4(__amdgpu_buffer_rsrc_t r, int off, float* v) {
+    const f4 x = __builtin_bit_cast(f4, __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0));
+#pragma unroll
+    for (int e = 0; e < 4; ++e) v[e] = x[e];
+}
+__device__ __forceinline__ void bload4(__amdgpu_buffer_rsrc_t r, int off, double* v) {
+    const d2 x = __builtin_bit_cast(d2, __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0));
+    const d2 y = __builtin_bit_cast(d2, __builtin_amdgcn_raw_buffer_load_b128(r, off + 16, 0, 0));
+    v[0] = x[0];
+    v[1] = x[1];
+    v[2] = y[0];
+    v[3] = y[1];
+}
+
+// One pass: acc[s] = S (16 x Mp, 2 planes in LDS) x B^T for this wave's
+// column blocks cb[s] (skipped when >= MB, a wave-uniform test), B = M x M
+// (rows m, K-contiguous), real (NPB = 1) or complex (NPB = 2, planes M*M
+// apart), read through descriptor rb.
+// Inside each 16-wide K chunk the MFMA k-order is permuted: for sub-step j
+// lane group g = lane / 16 supplies k = k0 + 4 g + j.  Every lane's operand
+// run is then 4 contiguous elements: one LDS read of S and one 16-byte
+// buffer load of B per chunk, straight into registers (each B column block
+// belongs to one wave, so no staging and no barrier inside the pass).  B
+// loads run one chunk ahead.  Columns >= M of B multiply zero columns of S.
+template <typename T, int MAXB, int NPB>
+__device__ __forceinline__ void pass(__amdgpu_buffer_rsrc_t rb, int M, int Mp, int MB,
+                                     const T* S, int SPT, const int* cb,
+                                     typename AccT<T>::v (&acc)[MAXB][2]) {
+    const int lane = threadIdx.x & 63;
+    const int g = lane >> 4, li = lane & 15;
+    const int plane_b = M * M * (int)sizeof(T);
+    const long splane = 16L * SPT;
+    const T* srow_r = S + li * SPT + 4 * g;
+    const T* srow_i = srow_r + splane;
+    int boff[MAXB];
+#pragma unroll
+    for (int s = 0; s < MAXB; ++s) {
+        const int m = cb[s] * 16 + li;
+        boff[s] = m < M ? (m * M + 4 * g) * (int)sizeof(T) : kOutOfRange;
+        acc[s][0] = acc[s][1] = typename AccT<T>::v{0, 0, 0, 0};
+    }
+    T bc[MAXB][NPB][4], bn[MAXB][NPB][4];
+#pragma unroll
+    for (int s = 0; s < MAXB; ++s)
+        if (cb[s] < MB)
+#pragma unroll
+            for (int p = 0; p < NPB; ++p) bload4(rb, boff[s] + p * plane_b, bc[s][p]);
+    for (int k0 = 0; k0 < Mp; k0 += 16) {
+        const bool more = k0 + 16 < Mp;
+        const int kb = (k0 + 16) * (int)sizeof(T);
+#pragma unroll
+        for (int s = 0; s < MAXB; ++s)
+            if (more && cb[s] < MB)
+#pragma unroll
+                for (int p = 0; p < NPB; ++p) bload4(rb, boff[s] + kb + p * plane_b, bn[s][p]);
+        T sr[4], si[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            sr[j] = srow_r[k0 + j];
+            si[j] = srow_i[k0 + j];
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+#pragma unroll
+            for (int s = 0; s < MAXB; ++s) {
+                if (cb[s] >= MB) continue;  // wave-uniform
+                if constexpr (NPB == 1) {
+                    acc[s][0] = mma1(sr[j], bc[s][0][j], acc[s][0]);
+                    acc[s][1] = mma1(si[j], bc[s][0][j], acc[s][1]);
+                } else {
+                    acc[s][0] = mma1(sr[j], bc[s][0][j], acc[s][0]);
+                    acc[s][0] = mma1(-si[j], bc[s][1][j], acc[s][0]);
+                    acc[s][1] = mma1(sr[j], bc[s][1][j], acc[s][1]);
+                    acc[s][1] = mma1(si[j], bc[s][0][j], acc[s][1]);
+                }
+            }
+        }
+#pragma unroll
+        for (int s = 0; s < MAXB; ++s)
+#pragma unroll
+            for (int p = 0; p < NPB; ++p)
+#pragma unroll
+                for (int e = 0; e < 4; ++e) bc[s][p][e] = bn[s][p][e];
+    }
+}
+
+// One workgroup = 16 orbitals (one MFMA row block) of one walker for the
+// whole propagation.  Workgroups are ordered so that the row blocks of a
+// walker run back to back on one XCD and A_w streams through its L2; the
+// assignment of column blocks to waves rotates between workgroups so the
+// waves holding an extra block land on different SIMDs.
+template <typename T, int NWAVE, int MAXB>
+__global__ __launch_bounds__(64 * NWAVE, 2) void k_propagate(
+    const double* __restrict__ phi, double* __restrict__ phi_out, const T* __restrict__ Pm,
+    const T* __restrict__ Af, const uint8_t* __restrict__ live, int nw, int M, int N, int K,
+    int nrb) {
+    typedef typename AccT<T>::v accv;
+    extern __shared__ __attribute__((aligned(16))) char smem_raw[];
+    T* S = reinterpret_cast<T*>(smem_raw);
+    constexpr int NT = 64 * NWAVE;
+    const int Mp = (M + 15) / 16 * 16;
+    const int MB = Mp / 16;
+    const int SPT = Mp + 4;  // 16-byte aligned rows, staggered banks
+    const long splane = 16L * SPT;
+    const long nblk = (long)nw * nrb;
+    const long per = (nblk + 7) / 8;
+    const long L = (long)(blockIdx.x % 8) * per + blockIdx.x / 8;
+    if (L >= nblk) return;
+    const int w = (int)(L / nrb), row0 = (int)(L % nrb) * 16;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const long NM = (long)N * M;
+    const double* src = phi + (long)w * 2 * NM;
+    double* dst = phi_out + (long)w * 2 * NM;
+    const int nrow = min(16, N - row0);
+    if (nrow <= 0) return;
+    if (!live[w]) {  // frozen walker: carried over unchanged
+        for (int e = tid; e < 2 * nrow * M; e += NT) {
+            const int p = e / (nrow * M), rem = e % (nrow * M);
+            const long o = p * NM + (long)(row0 + rem / M) * M + rem % M;
+            dst[o] = src[o];
+        }
+        return;
+    }
+    for (int e = tid; e < 2 * 16 * Mp; e += NT) {
+        const int p = e / (16 * Mp), rem = e % (16 * Mp);
+        const int r = rem / Mp, m = rem % Mp;
+        double v = 0.0;
+        if (r < nrow && m < M) v = src[p * NM + (long)(row0 + r) * M + m];
+        S[p * splane + r * SPT + m] = (T)v;
+    }
+    const int vw = (wave + (int)(L % NWAVE)) % NWAVE;  // rotated wave slot
+    int cb[MAXB];
+#pragma unroll
+    for (int s = 0; s < MAXB; ++s) cb[s] = vw + s * NWAVE;
+    __syncthreads();
+    accv acc[MAXB][2], z[MAXB][2];
+    const long Aplane = (long)M * M;
+    const __amdgpu_buffer_rsrc_t rP = make_rsrc(Pm, Aplane);
+    const __amdgpu_buffer_rsrc_t rA = make_rsrc(Af + (long)w * 2 * Aplane, 2 * Aplane);
+    // write a block of the running state into S; columns >= M stay zero
+    auto put = [&](int s, const accv& vr, const accv& vi) {
+        const int col = cb[s] * 16 + (lane & 15);
+        const bool ok = col < M;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int off = acc_row<T>(lane, r) * SPT + col;
+            S[off] = ok ? vr[r] : (T)0;
+            S[splane + off] = ok ? vi[r] : (T)0;
+        }
+    };
+    // first one-body half
+    pass<T, MAXB, 1>(rP, M, Mp, MB, S, SPT, cb, acc);
+    __syncthreads();
+#pragma unroll
+    for (int s = 0; s < MAXB; ++s) {
+        z[s][0] = acc[s][0];
+        z[s][1] = acc[s][1];
+        if (cb[s] < MB) put(s, acc[s][0], acc[s][1]);
+    }
+    __syncthreads();
+    // Taylor series of exp(A): term_n = A term_{n-1} / n, z = sum of terms
+    for (int n = 1; n <= K; ++n) {
+        pass<T, MAXB, 2>(rA, M, Mp, MB, S, SPT, cb, acc);
+        __syncthreads();
+        const T inv = (T)(1.0 / n);
+#pragma unroll
+        for (int s = 0; s < MAXB; ++s) {
+            acc[s][0] *= inv;
+            acc[s][1] *= inv;
+            z[s][0] += acc[s][0];
+            z[s][1] += acc[s][1];
+            if (cb[s] < MB) {
+                if (n == K)
+                    put(s, z[s][0], z[s][1]);
+                else
+                    put(s, acc[s][0], acc[s][1]);
+            }
+        }
+        __syncthreads();
+    }
+    // second one-body half, FP64 result
+    pass<T, MAXB, 1>(rP, M, Mp, MB, S, SPT, cb, acc);
+#pragma unroll
+    for (int s = 0; s < MAXB; ++s) {
+        const int col = cb[s] * 16 + (lane & 15);
+        if (cb[s] >= MB || col >= M) continue;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int row = acc_row<T>(lane, r);
+            if (row < nrow) {
+                const long o = (long)(row0 + row) * M + col;
+                dst[o] = (double)acc[s][0][r];
+                dst[NM + o] = (double)acc[s][1][r];
+            }
+        }
+    }
+}
+
+template <typename T, int NWAVE, int MAXB>
+hipError_t launch_prop(const double* phi, double* phi_out, const void* Pm, const void* Af,
+                       const uint8_t* live, int nw, int M, int N, int K, hipStream_t s) {
+    const int Mp = (M + 15) / 16 * 16;
+    const size_t shm = 2 * 16 * (size_t)(Mp + 4) * sizeof(T);
+    const int nrb = (N + 15) / 16;
+    const long nblk = (long)nw * nrb;
+    const long grid = ((nblk + 7) / 8) * 8;
+    hipLaunchKernelGGL((k_propagate<T, NWAVE, MAXB>), dim3(grid), dim3(64 * NWAVE), shm, s, phi,
+                       phi_out, (const T*)Pm, (const T*)Af, live, nw, M, N, K, nrb);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t unpack_sym(const void* pk, void* full, int M, int planes, DType t, hipStream_t s) {
+    if (planes <= 0) return hipSuccess;
+    dim3 grid((M + 31) / 32, planes);
+    if (t == DT_F64)
+        hipLaunchKernelGGL(k_unpack<double>, grid, dim3(256), 0, s, (const double*)pk,
+                           (double*)full, M);
+    else if (t == DT_F32)
+        hipLaunchKernelGGL(k_unpack<float>, grid, dim3(256), 0, s, (const float*)pk, (float*)full,
+                           M);
+    else
+        return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+hipError_t propagate(const double* phi, double* phi_out, const void* Pm, const void* Af,
+                     const uint8_t* live, int nw, int M, int N, int K, DType t, hipStream_t s) {
+    if (nw <= 0) return hipSuccess;
+    if (M > 256 || M <= 0 || N <= 0) return hipErrorInvalidValue;
+    if (t == DT_F64) return launch_prop<double, 8, 2>(phi, phi_out, Pm, Af, live, nw, M, N, K, s);
+    if (t == DT_F32) return launch_prop<float, 8, 2>(phi, phi_out, Pm, Af, live, nw, M, N, K, s);
+    return hipErrorInvalidValue;
+}
+
+}  // namespace afq

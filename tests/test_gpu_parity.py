@@ -207,7 +207,7 @@ def test_nan_field_freezes_only_that_walker(lib, torch_mod):
     """A non-finite field kills one walker; every other walker is bitwise
     identical to a run without it, and the oracle agrees (Sec. II.B)."""
     banner("nan field")
-    wl = Workload(16, 30, 4, 3, 4, 2, 12, 0.01, ham_seed=8)
+    wl = Workload(18, 30, 4, 3, 4, 2, 12, 0.01, ham_seed=8)
     x = wl.fields(8, seed=2)
     xbad = x.copy()
     xbad[3, 5, 7] = np.nan
@@ -254,3 +254,28 @@ def test_errors(lib):
     import ctypes
     st = lib._lib.afqmc_step(gb._s if gb._s else ctypes.c_void_p(), 0, 0, 1, None)
     assert st == lib.E_INVALID
+
+
+@pytest.mark.parametrize("dims", [(12, 6, 3), (37, 13, 5), (200, 80, 3), (64, 16, 2), (41, 17, 4)])
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_propagation_kernel(lib, dims, prec):
+    """Fused P T_K(A) P kernel vs the same products in numpy (K = 6)."""
+    M, N, nw = dims
+    banner(f"propagate kernel {prec} {dims}")
+    rng = np.random.default_rng(M + N)
+    phi = rng.standard_normal((nw, M, N)) + 1j * rng.standard_normal((nw, M, N))
+    P = rng.standard_normal((M, M)) * 0.05
+    P = np.eye(M) + 0.5 * (P + P.T)
+    A = (rng.standard_normal((nw, M, M)) + 1j * rng.standard_normal((nw, M, M))) * (0.4 / np.sqrt(M))
+    A = 0.5 * (A + np.swapaxes(A, 1, 2))
+    got = lib.selftest_propagate(phi, P, A, 6, prec)
+    ref = np.empty_like(phi)
+    for k in range(nw):
+        y = P @ phi[k]
+        term, acc = y, y.copy()
+        for n in range(1, 7):
+            term = A[k] @ term / n
+            acc = acc + term
+        ref[k] = P @ acc
+    tol = 1e-12 if prec == "fp64" else 2e-5
+    assert rel(got, ref) < tol
