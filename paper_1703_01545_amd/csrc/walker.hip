@@ -176,9 +176,9 @@ __global__ __launch_bounds__(256) void k_lu_theta(const double* __restrict__ ov,
         Ai[r * ld + n + c] = 0.0;
     }
     __syncthreads();
-    double lr = 0.0, la = 0.0;
+    __shared__ double piv_r[64], piv_i[64];
     int swaps = 0;
-    bool singular = false;
+    const int tx = tid & 63, ty = tid >> 6;  // 64 columns x 4 row groups
     for (int k = 0; k < n; ++k) {
         if (tid < 64) {
             const int r = k + tid;
@@ -212,10 +212,9 @@ __global__ __launch_bounds__(256) void k_lu_theta(const double* __restrict__ ov,
         __syncthreads();
         const double pr = Ar[k * ld + k], pi = Ai[k * ld + k];
         if (tid == 0) {
-            lr += log(hypot(pr, pi));
-            la += atan2(pi, pr);
+            piv_r[k] = pr;
+            piv_i[k] = pi;
         }
-        if (pr == 0.0 && pi == 0.0) singular = true;
         // 1 / pivot
         const double den = pr * pr + pi * pi;
         const double qr = pr / den, qi = -pi / den;
@@ -226,60 +225,79 @@ __global__ __launch_bounds__(256) void k_lu_theta(const double* __restrict__ ov,
             Ai[k * ld + c] = xr * qi + xi * qr;
         }
         __syncthreads();
-        const int ncol = 2 * n - (k + 1);
-        for (int idx = tid; idx < n * ncol; idx += 256) {
-            const int r = idx / ncol, c = k + 1 + idx % ncol;
+        for (int r = ty; r < n; r += 4) {
             if (r == k) continue;
             const double fr = Ar[r * ld + k], fi = Ai[r * ld + k];
-            const double br = Ar[k * ld + c], bi = Ai[k * ld + c];
-            Ar[r * ld + c] -= fr * br - fi * bi;
-            Ai[r * ld + c] -= fr * bi + fi * br;
+            for (int c = k + 1 + tx; c < 2 * n; c += 64) {
+                const double br = Ar[k * ld + c], bi = Ai[k * ld + c];
+                Ar[r * ld + c] -= fr * br - fi * bi;
+                Ai[r * ld + c] -= fr * bi + fi * br;
+            }
         }
         __syncthreads();
     }
-    if (tid == 0) {
-        if (singular) {
-            out_lnd[0] = -INFINITY;
-            out_lnd[1] = 0.0;
-        } else {
-            out_lnd[0] = lr;
-            out_lnd[1] = la + ((swaps & 1) ? M_PI : 0.0);
+    // ln det = sum_k ln(pivot_k) + i pi (swaps mod 2), summed in index order
+    if (tid < 64) {
+        double lr = 0.0, la = 0.0;
+        bool sing = false;
+        if (tid < n) {
+            const double pr = piv_r[tid], pi = piv_i[tid];
+            sing = (pr == 0.0 && pi == 0.0);
+            lr = log(hypot(pr, pi));
+            la = atan2(pi, pr);
+        }
+        lr = wave_sum(lr);
+        la = wave_sum(la);
+        const bool any_sing = __any(sing);
+        if (tid == 0) {
+            if (any_sing) {
+                out_lnd[0] = -INFINITY;
+                out_lnd[1] = 0.0;
+            } else {
+                out_lnd[0] = lr;
+                out_lnd[1] = la + ((swaps & 1) ? M_PI : 0.0);
+            }
         }
     }
     // Theta[m][c] = sum_l Phi[m][l] Inv[l][c]; Inv[l][c] = A[l][n + c].
+    // One basis row m per thread (coalesced Phi loads), CC output columns in
+    // registers, the Inv row broadcast from LDS.
     const double* pr_ = phi + (long)w * 2 * NM;
     const double* pi_ = pr_ + NM;
     double* tr_ = theta + (long)w * 2 * NM;
     double* ti_ = tr_ + NM;
-    constexpr int CC = 8;
-    const int nchunk = (n + CC - 1) / CC;
-    for (int item = tid; item < nchunk * M; item += 256) {
-        const int m = item % M, c0 = (item / M) * CC;
-        double accr[CC], acci[CC];
+    constexpr int CC = 20;
+    for (int c0 = 0; c0 < n; c0 += CC) {
+        for (int m = tid; m < M; m += 256) {
+            double accr[CC], acci[CC];
 #pragma unroll
-        for (int q = 0; q < CC; ++q) accr[q] = acci[q] = 0.0;
-        for (int l = 0; l < n; ++l) {
-            const double xr = pr_[(long)(off + l) * M + m];
-            const double xi = pi_[(long)(off + l) * M + m];
+            for (int q = 0; q < CC; ++q) accr[q] = acci[q] = 0.0;
+#pragma unroll 4
+            for (int l = 0; l < n; ++l) {
+                const double xr = pr_[(long)(off + l) * M + m];
+                const double xi = pi_[(long)(off + l) * M + m];
+                const double* vr_ = Ar + l * ld + n + c0;
+                const double* vi_ = Ai + l * ld + n + c0;
+#pragma unroll
+                for (int q = 0; q < CC; ++q) {
+                    if (c0 + q < n) {
+                        const double vr = vr_[q], vi = vi_[q];
+                        accr[q] += xr * vr - xi * vi;
+                        acci[q] += xr * vi + xi * vr;
+                    }
+                }
+            }
 #pragma unroll
             for (int q = 0; q < CC; ++q) {
                 if (c0 + q < n) {
-                    const double vr = Ar[l * ld + n + c0 + q], vi = Ai[l * ld + n + c0 + q];
-                    accr[q] += xr * vr - xi * vi;
-                    acci[q] += xr * vi + xi * vr;
-                }
-            }
-        }
-#pragma unroll
-        for (int q = 0; q < CC; ++q) {
-            if (c0 + q < n) {
-                const long o = (long)(off + c0 + q) * M + m;
-                tr_[o] = accr[q];
-                ti_[o] = acci[q];
-                if (theta_lp) {
-                    const long base = (long)w * 2 * NM;
-                    put_dt(theta_lp, tlp, base + o, accr[q]);
-                    put_dt(theta_lp, tlp, base + NM + o, acci[q]);
+                    const long o = (long)(off + c0 + q) * M + m;
+                    tr_[o] = accr[q];
+                    ti_[o] = acci[q];
+                    if (theta_lp) {
+                        const long base = (long)w * 2 * NM;
+                        put_dt(theta_lp, tlp, base + o, accr[q]);
+                        put_dt(theta_lp, tlp, base + NM + o, acci[q]);
+                    }
                 }
             }
         }
@@ -318,22 +336,37 @@ __global__ void k_weights(const double* __restrict__ lnd, const double* __restri
 
 // Modified Gram-Schmidt of one spin block per workgroup: for each column j
 // in order, normalise it, then remove its projection q_j^H v_l from every
-// later column l.
+// later column l.  The block is staged in LDS when it fits (STAGE), else it
+// is updated in place in global memory.
+template <bool STAGE>
 __global__ __launch_bounds__(256) void k_mgs(double* __restrict__ phi,
                                              const uint8_t* __restrict__ live, int M, int N,
                                              int na, int nb) {
+    extern __shared__ double stage_buf[];
     const int w = blockIdx.x, spin = blockIdx.y;
     const int off = spin ? na : 0, n = spin ? nb : na;
     if (n == 0 || !live[w]) return;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const long NM = (long)N * M;
-    double* pr = phi + (long)w * 2 * NM + (long)off * M;
-    double* pi = pr + NM;
+    double* gr = phi + (long)w * 2 * NM + (long)off * M;
+    double* gi = gr + NM;
+    double* pr = gr;
+    double* pi = gi;
+    long ldp = M;
+    if (STAGE) {
+        pr = stage_buf;
+        pi = stage_buf + (long)n * M;
+        for (int e = tid; e < n * M; e += 256) {
+            pr[e] = gr[e];
+            pi[e] = gi[e];
+        }
+        __syncthreads();
+    }
     __shared__ double red[4];
     __shared__ double proj[2 * 64];
     for (int j = 0; j < n; ++j) {
-        double* qr = pr + (long)j * M;
-        double* qi = pi + (long)j * M;
+        double* qr = pr + (long)j * ldp;
+        double* qi = pi + (long)j * ldp;
         double s = 0.0;
         for (int m = tid; m < M; m += 256) s += qr[m] * qr[m] + qi[m] * qi[m];
         s = wave_sum(s);
@@ -346,8 +379,8 @@ __global__ __launch_bounds__(256) void k_mgs(double* __restrict__ phi,
         }
         __syncthreads();
         for (int l = j + 1 + wave; l < n; l += 4) {
-            const double* vr = pr + (long)l * M;
-            const double* vi = pi + (long)l * M;
+            const double* vr = pr + (long)l * ldp;
+            const double* vi = pi + (long)l * ldp;
             double a = 0.0, b = 0.0;
             for (int m = lane; m < M; m += 64) {
                 a += qr[m] * vr[m] + qi[m] * vi[m];
@@ -362,14 +395,22 @@ __global__ __launch_bounds__(256) void k_mgs(double* __restrict__ phi,
         }
         __syncthreads();
         const int rest = n - j - 1;
-        for (int idx = tid; idx < rest * M; idx += 256) {
-            const int l = j + 1 + idx / M, m = idx % M;
+        for (int l = j + 1 + (tid >> 6); l < n; l += 4) {
             const double cr = proj[2 * (l - j - 1)], ci = proj[2 * (l - j - 1) + 1];
-            const double xr = qr[m], xi = qi[m];
-            pr[(long)l * M + m] -= cr * xr - ci * xi;
-            pi[(long)l * M + m] -= cr * xi + ci * xr;
+            for (int m = lane; m < M; m += 64) {
+                const double xr = qr[m], xi = qi[m];
+                pr[(long)l * ldp + m] -= cr * xr - ci * xi;
+                pi[(long)l * ldp + m] -= cr * xi + ci * xr;
+            }
         }
+        (void)rest;
         __syncthreads();
+    }
+    if (STAGE) {
+        for (int e = tid; e < n * M; e += 256) {
+            gr[e] = pr[e];
+            gi[e] = pi[e];
+        }
     }
 }
 
@@ -544,7 +585,21 @@ hipError_t weights(const double* lnd, const double* s_imp, double* lnov, double*
 hipError_t mgs(double* phi, const uint8_t* live, int nw, int M, int N, int na, int nb,
                hipStream_t s) {
     if (nw <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_mgs, dim3(nw, 2), dim3(256), 0, s, phi, live, M, N, na, nb);
+    const int nmax = na > nb ? na : nb;
+    const size_t shm = (size_t)2 * nmax * M * sizeof(double);
+    if (shm <= 128 * 1024) {
+        static bool attr = false;
+        if (!attr) {
+            hipError_t e = hipFuncSetAttribute((const void*)k_mgs<true>,
+                                               hipFuncAttributeMaxDynamicSharedMemorySize,
+                                               128 * 1024);
+            if (e != hipSuccess) return e;
+            attr = true;
+        }
+        hipLaunchKernelGGL(k_mgs<true>, dim3(nw, 2), dim3(256), shm, s, phi, live, M, N, na, nb);
+    } else {
+        hipLaunchKernelGGL(k_mgs<false>, dim3(nw, 2), dim3(256), 0, s, phi, live, M, N, na, nb);
+    }
     return hipGetLastError();
 }
 
