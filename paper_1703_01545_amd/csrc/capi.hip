@@ -697,10 +697,12 @@ afqmc_status afqmc_init_walkers(afqmc_ham ham, int n_alpha, int n_beta, const do
         std::vector<double> one((size_t)2 * NM, 0.0);
         for (int i = 0; i < N; ++i)
             for (int m = 0; m < M; ++m) one[(size_t)i * M + m] = src[(size_t)m * N + i];
-        for (int k = 0; k < nw; ++k)
-            if (hipMemcpyAsync(s->d_phi.as<double>() + (size_t)k * 2 * NM, one.data(), 2 * NM * 8,
-                               hipMemcpyHostToDevice, st) != hipSuccess)
-                return bail(fail(AFQMC_E_DEVICE, "upload walkers"));
+        // one walker up, replicated on the device (phinew serves as staging)
+        if (hipMemcpyAsync(s->d_phinew.p, one.data(), 2 * NM * 8, hipMemcpyHostToDevice, st) !=
+                hipSuccess ||
+            broadcast(s->d_phinew.as<double>(), s->d_phi.as<double>(), 2 * NM, nw, st) !=
+                hipSuccess)
+            return bail(fail(AFQMC_E_DEVICE, "upload walkers"));
         std::vector<double> w((size_t)2 * nw, 0.0);
         for (int k = 0; k < nw; ++k) w[par->mode == AFQMC_FREE ? 2 * k : k] = 1.0;
         std::vector<uint8_t> al((size_t)nw, 1);

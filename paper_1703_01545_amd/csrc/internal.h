@@ -133,6 +133,7 @@ hipError_t mixed_sums(const double* el, const double* w, const uint8_t* alive, i
                       double* out, hipStream_t s);
 
 // Small helpers.
+hipError_t broadcast(const double* src, double* dst, long n, int copies, hipStream_t s);
 hipError_t convert(const double* src, void* dst, DType t, long n, hipStream_t s);
 hipError_t pack_chol(const double* L, void* Lp, DType t, int M, int n_chol, hipStream_t s);
 hipError_t permute_chol(const double* L, double* LT, int M, int n_chol, hipStream_t s);

@@ -539,6 +539,14 @@ __global__ void k_wsum(const double* __restrict__ L, const double* __restrict__ 
     out[idx] = s;
 }
 
+// dst[k * n + e] = src[e] for k < copies (initial walker replicated).
+__global__ void k_bcast(const double* __restrict__ src, double* __restrict__ dst, long n,
+                        int copies) {
+    const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n * copies) return;
+    dst[i] = src[i % n];
+}
+
 inline unsigned nblk(long n, int t) { return (unsigned)((n + t - 1) / t); }
 
 }  // namespace
@@ -621,6 +629,12 @@ hipError_t mixed_sums(const double* el, const double* w, const uint8_t* alive, i
 hipError_t trace_record(const double* sa, const double* sb, double* trace, int slot, int mode,
                         hipStream_t s) {
     hipLaunchKernelGGL(k_trace, dim3(1), dim3(64), 0, s, sa, sb, trace, slot, mode);
+    return hipGetLastError();
+}
+
+hipError_t broadcast(const double* src, double* dst, long n, int copies, hipStream_t s) {
+    if (n <= 0 || copies <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_bcast, dim3(nblk(n * copies, 256)), dim3(256), 0, s, src, dst, n, copies);
     return hipGetLastError();
 }
 
