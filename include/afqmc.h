@@ -129,15 +129,39 @@ afqmc_status afqmc_orthonormalize(afqmc_sys sys);
 afqmc_status afqmc_pair_step(afqmc_sys a, afqmc_sys b, uint64_t seed, int n_steps,
                              const double* fields, double* e_trace);
 
-/* Many correlated pairs of uneven size advanced together: each phase of the
- * step is one grouped launch over every system of every pair, and the whole
- * step is captured once in a HIP graph and replayed.  Pair p uses seed
- * seeds[p] and stream id p.  e_traces: host, n_pairs x (n_steps /
- * measure_every) x 3 doubles, or NULL.  All systems must share one stream
- * (one Hamiltonian stream) and one precision; each pair must satisfy the
- * afqmc_pair_step preconditions. */
+/* Many correlated pairs of uneven size advanced together (the pairs of
+ * Sec. II.B, batched).  Pair p (systems a[p], b[p]) runs exactly what
+ * afqmc_pair_step(a[p], b[p], seeds[p], n_steps, NULL, ...) runs, bit for
+ * bit.  The pairs are spread over `lanes` streams (largest first onto the
+ * least-loaded lane; lanes <= 0 picks 4).  One period of
+ * lcm(ortho_every, measure_every) steps (doubled when odd) of every pair is
+ * captured once into a HIP graph with fork/join edges between the lanes and
+ * replayed for each whole period; the Philox step word and the trace slot
+ * are read from device counters, so one graph serves every period.  Steps
+ * before the first period boundary and after the last one are launched
+ * directly.  Every system is autotuned (afqmc_autotune) before capture.
+ * Graphs are cached per (handles, seeds, lanes) until a handle is freed.
+ * flags bit 0: no graph, launch every step directly (same lanes).
+ * e_traces: host, n_pairs x n_meas x 3 doubles (E_a, E_b, dE), n_meas =
+ * number of measurement steps among the n_steps, or NULL.  Errors: as
+ * afqmc_pair_step for each pair; E_STATE when the systems are not all at
+ * the same step; E_SHAPE when they differ in dt, periods or mode, or do not
+ * share one stream; E_INVALID for null arrays or a handle used twice.
+ * Synchronises. */
 afqmc_status afqmc_pair_batch_step(int n_pairs, const afqmc_sys* a, const afqmc_sys* b,
-                                   const uint64_t* seeds, int n_steps, double* e_traces);
+                                   const uint64_t* seeds, int n_steps, int lanes, int flags,
+                                   double* e_traces);
+
+/* Launch-shape autotuner.  Times every candidate launch shape of the
+ * force-bias, field-sum and overlap GEMMs (64 x 64 or 128 x 128 tiles) and
+ * of the fused propagation (waves per workgroup x column blocks per wave) on
+ * this system's own buffers and keeps the fastest per problem shape in a
+ * process-wide table, which every later step of any system of that shape
+ * uses.  All candidates sum in the same order, so tuning never changes a
+ * result bit.  The walker state is left unchanged.  choice (optional, host,
+ * 4 ints): the chosen force-bias tile, field-sum tile, overlap tile
+ * (1: 64 x 64, 2: 128 x 128) and propagation shape index.  Synchronises. */
+afqmc_status afqmc_autotune(afqmc_sys sys, int* choice);
 
 /* Read back walker state: phi (n_walkers x 2 x N x M: plane 0 = real,
  * plane 1 = imaginary part of orbital column i, N = n_alpha + n_beta),
@@ -186,11 +210,14 @@ afqmc_status afqmc_selftest_gemm(afqmc_prec prec, int m, int n, int k, const dou
 
 /* Kernel self-test of the fused propagation: out[w] = P T_K(A_w) P phi[w]
  * (Eq. 3 and Eq. 11, T_K the order-K Taylor polynomial of exp) with the
- * products in precision `prec` (AFQMC_FP64, else FP32).  phi, out:
+ * products in precision `prec` (AFQMC_FP64, else FP32), workgroup shape
+ * `variant` (0: 8 waves x 2 column blocks, 1: 4 x 4, 2: 4 x 2, 3: 2 x 4,
+ * 4: 4 x 1; a shape serves M <= 16 waves blocks; FP64 takes at most 2
+ * blocks per wave; E_SHAPE otherwise).  phi, out:
  * nw x 2 x N x M (plane 0 real, plane 1 imaginary of orbital columns); P:
  * M x M real symmetric; A: nw x 2 x M x M complex symmetric.  Host float64
  * arrays; synchronises.  For the numerics tests of the propagation kernel. */
-afqmc_status afqmc_selftest_propagate(afqmc_prec prec, int M, int N, int nw, int K,
+afqmc_status afqmc_selftest_propagate(afqmc_prec prec, int M, int N, int nw, int K, int variant,
                                       const double* phi, const double* P, const double* A,
                                       double* out);
 

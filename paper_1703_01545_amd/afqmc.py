@@ -31,7 +31,7 @@ EXPORTS = [
     "afqmc_orthonormalize", "afqmc_pair_step", "afqmc_pair_batch_step", "afqmc_get_walkers",
     "afqmc_sys_info", "afqmc_checkpoint", "afqmc_restore", "afqmc_free_sys", "afqmc_free_ham",
     "afqmc_last_error", "afqmc_selftest_gemm", "afqmc_selftest_fields", "afqmc_profile_enable",
-    "afqmc_profile_read", "afqmc_phase_name", "afqmc_selftest_propagate",
+    "afqmc_profile_read", "afqmc_phase_name", "afqmc_selftest_propagate", "afqmc_autotune",
 ]
 
 
@@ -51,7 +51,8 @@ _lib.afqmc_local_energy.argtypes = [_vp, _dp, _dp, _dp]
 _lib.afqmc_orthonormalize.argtypes = [_vp]
 _lib.afqmc_pair_step.argtypes = [_vp, _vp, C.c_uint64, C.c_int, _vp, _dp]
 _lib.afqmc_pair_batch_step.argtypes = [C.c_int, C.POINTER(_vp), C.POINTER(_vp),
-                                       C.POINTER(C.c_uint64), C.c_int, _dp]
+                                       C.POINTER(C.c_uint64), C.c_int, C.c_int, C.c_int, _dp]
+_lib.afqmc_autotune.argtypes = [_vp, C.POINTER(C.c_int)]
 _lib.afqmc_get_walkers.argtypes = [_vp, _dp, _dp, _dp, C.POINTER(C.c_ubyte)]
 _lib.afqmc_sys_info.argtypes = [_vp] + [C.POINTER(C.c_int)] * 5 + [C.POINTER(C.c_int64)]
 _lib.afqmc_checkpoint.argtypes = [_vp, _vp, C.POINTER(C.c_size_t)]
@@ -62,8 +63,8 @@ _lib.afqmc_free_ham.argtypes = [_vp]
 _lib.afqmc_free_ham.restype = None
 _lib.afqmc_selftest_gemm.argtypes = [C.c_int, C.c_int, C.c_int, C.c_int, _dp, _dp, _dp]
 _lib.afqmc_selftest_fields.argtypes = [C.c_uint64, C.c_uint64, C.c_int64, C.c_int, C.c_int, _dp]
-_lib.afqmc_selftest_propagate.argtypes = [C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, _dp, _dp,
-                                           _dp, _dp]
+_lib.afqmc_selftest_propagate.argtypes = [C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int,
+                                           _dp, _dp, _dp, _dp]
 _lib.afqmc_profile_enable.argtypes = [_vp, C.c_int]
 _lib.afqmc_profile_read.argtypes = [_vp, C.c_int, _dp, C.POINTER(C.c_int64)]
 _lib.afqmc_phase_name.argtypes = [C.c_int]
@@ -247,8 +248,9 @@ def pair_step(a: System, b: System, n_steps: int, seed: int = 0, fields=None) ->
     return tr[:n_meas]
 
 
-def pair_batch_step(pairs, seeds, n_steps: int) -> np.ndarray:
-    """Many pairs advanced together; returns (n_pairs, n_meas, 3)."""
+def pair_batch_step(pairs, seeds, n_steps: int, lanes: int = 0, graph: bool = True) -> np.ndarray:
+    """Many pairs advanced together (graph-replayed unless graph=False);
+    returns (n_pairs, n_meas, 3)."""
     n = len(pairs)
     me = pairs[0][0].params.measure_every
     t0 = pairs[0][0].info()["step"]
@@ -257,8 +259,17 @@ def pair_batch_step(pairs, seeds, n_steps: int) -> np.ndarray:
     B = (_vp * n)(*[p[1]._s for p in pairs])
     S = (C.c_uint64 * n)(*[int(s) for s in seeds])
     tr = np.zeros((n, max(n_meas, 1), 3))
-    _check(_lib.afqmc_pair_batch_step(n, A, B, S, int(n_steps), _ptr(tr)))
+    _check(_lib.afqmc_pair_batch_step(n, A, B, S, int(n_steps), int(lanes), 0 if graph else 1,
+                                      _ptr(tr)))
     return tr[:, :n_meas]
+
+
+def autotune(system: System):
+    """Autotune the system's launch shapes; returns (fb tile, field-sum tile,
+    overlap tile, propagation shape)."""
+    ch = (C.c_int * 4)()
+    _check(_lib.afqmc_autotune(system._s, ch))
+    return tuple(ch)
 
 
 def selftest_gemm(A, B, precision: str = "fp64") -> np.ndarray:
@@ -270,7 +281,7 @@ def selftest_gemm(A, B, precision: str = "fp64") -> np.ndarray:
     return Cm
 
 
-def selftest_propagate(phi, P, A, K: int, precision: str = "fp64") -> np.ndarray:
+def selftest_propagate(phi, P, A, K: int, precision: str = "fp64", variant: int = 0) -> np.ndarray:
     """phi: (nw, M, N) complex, P: (M, M) real, A: (nw, M, M) complex symmetric ->
     P T_K(A) P phi computed by the fused propagation kernel."""
     phi = np.asarray(phi)
@@ -278,8 +289,8 @@ def selftest_propagate(phi, P, A, K: int, precision: str = "fp64") -> np.ndarray
     ph = _f64(np.stack([np.swapaxes(phi.real, 1, 2), np.swapaxes(phi.imag, 1, 2)], axis=1))
     Ah = _f64(np.stack([A.real, A.imag], axis=1))
     out = np.empty_like(ph)
-    _check(_lib.afqmc_selftest_propagate(PREC[precision], M, N, nw, int(K), _ptr(ph), _ptr(_f64(P)),
-                                         _ptr(Ah), _ptr(out)))
+    _check(_lib.afqmc_selftest_propagate(PREC[precision], M, N, nw, int(K), int(variant), _ptr(ph),
+                                         _ptr(_f64(P)), _ptr(Ah), _ptr(out)))
     return np.swapaxes(out[:, 0] + 1j * out[:, 1], 1, 2)
 
 

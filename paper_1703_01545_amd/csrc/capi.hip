@@ -1,55 +1,196 @@
 // C ABI of the correlated-sampling ph-AFQMC walker step (see include/afqmc.h).
 // Host code: handle management, validation, the per-system precompute, and
 // the ordering of the device phases of one step.
-#include <math.h>
-#include <string.h>
-
-#include <algorithm>
-#include <string>
-#include <vector>
-
-#include "../../include/afqmc.h"
-#include "internal.h"
+#include "host.h"
 
 using namespace afq;
+using namespace afq::host;
 
-namespace {
+namespace afq {
+namespace host {
 
 thread_local std::string g_err;
 
-afqmc_status fail(afqmc_status s, const std::string& msg) {
-    g_err = msg;
-    return s;
+const char* const kPhaseNames[PH_COUNT] = {
+    "force_bias_gemm", "fields",       "field_sum_gemm", "unpack_a", "propagate", "overlap_gemm",
+    "det_theta",       "weights",      "mgs",            "exchange", "energy"};
+
+
+Gemm force_bias_gemm(afqmc_sys s) {
+    // F[(w,p), g] = sum_(i,m) Theta[(w,p),(i,m)] L^half[g,(i,m)], g <= n_chol
+    Gemm g{};
+    g.A = lp_or(s->d_theta_lp, s->d_theta, s->ts);
+    g.ta = s->ts;
+    g.ra = rows_strided(s->NM());
+    g.B = lp_or(s->d_lhx_lp, s->d_lhx, s->ts);
+    g.tb = s->ts;
+    g.rb = rows_strided(s->NM());
+    g.C = s->d_F.p;
+    g.tc = DT_F64;
+    g.rc = rows_strided(s->n_chol + 1);
+    g.alpha = 1.0;
+    g.m = 2 * s->nw;
+    g.n = s->n_chol + 1;
+    g.k = (int)s->NM();
+    g.batch = 1;
+    g.tile = s->tile_fb;
+    return g;
 }
 
-#define HIPCHK(expr)                                                                    \
-    do {                                                                                \
-        hipError_t e_ = (expr);                                                         \
-        if (e_ != hipSuccess)                                                           \
-            return fail(AFQMC_E_DEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
-    } while (0)
+afqmc_status force_bias(afqmc_sys s, hipStream_t st) {
+    const Gemm g = force_bias_gemm(s);
+    PhaseTimer pt(s, PH_FORCE_BIAS, st);
+    HIPCHK(gemm(g, s->tc, st));
+    return AFQMC_OK;
+}
 
-size_t dt_size(DType t) { return t == DT_F64 ? 8 : (t == DT_F32 ? 4 : 2); }
+Gemm overlap_gemm(afqmc_sys s, const double* phi) {
+    // O[(w,p,i), j] = sum_m Phi[(w,p,i), m] trial[j, m]
+    Gemm g{};
+    g.A = phi;
+    g.ta = DT_F64;
+    g.ra = rows_strided(s->M);
+    g.B = s->d_trialT.p;
+    g.tb = DT_F64;
+    g.rb = rows_strided(s->M);
+    g.C = s->d_ov.p;
+    g.tc = DT_F64;
+    g.rc = rows_strided(s->N);
+    g.alpha = 1.0;
+    g.m = 2 * s->N * s->nw;
+    g.n = s->N;
+    g.k = s->M;
+    g.batch = 1;
+    g.tile = s->tile_ov;
+    return g;
+}
 
-struct DevBuf {
-    void* p = nullptr;
-    size_t n = 0;
-    ~DevBuf() { release(); }
-    void release() {
-        if (p) (void)hipFree(p);
-        p = nullptr;
-        n = 0;
+afqmc_status overlap_theta(afqmc_sys s, double* phi, hipStream_t st) {
+    const Gemm g = overlap_gemm(s, phi);
+    {
+        PhaseTimer pt(s, PH_OVERLAP, st);
+        HIPCHK(gemm(g, DT_F64, st));
     }
-    hipError_t alloc(size_t bytes) {
-        release();
-        if (bytes == 0) bytes = 16;
-        hipError_t e = hipMalloc(&p, bytes);
-        if (e == hipSuccess) n = bytes;
-        return e;
+    PhaseTimer pt(s, PH_DET_THETA, st);
+    HIPCHK(lu_theta(s->d_ov.as<double>(), phi, s->d_theta.as<double>(),
+                    s->ts == DT_F64 ? nullptr : s->d_theta_lp.p, s->ts, s->d_lnd.as<double>(),
+                    s->d_alive.as<uint8_t>(), s->nw, s->M, s->N, s->na, s->nb, st));
+    return AFQMC_OK;
+}
+
+Gemm field_sum_gemm(afqmc_sys s) {
+    // A[(w,p), q] = sum_g X[(w,p), g] Lpacked[q, g]
+    Gemm g{};
+    g.A = s->d_X.p;
+    g.ta = s->ts;
+    g.ra = rows_strided(s->n_chol);
+    g.B = s->ham->d_lp[s->ts].p;
+    g.tb = s->ts;
+    g.rb = rows_strided(s->n_chol);
+    g.C = s->d_Apk.p;
+    g.tc = s->tp;
+    g.rc = rows_strided(s->P());
+    g.alpha = 1.0;
+    g.m = 2 * s->nw;
+    g.n = (int)s->P();
+    g.k = s->n_chol;
+    g.batch = 1;
+    g.tile = s->tile_fs;
+    return g;
+}
+
+afqmc_status one_step(afqmc_sys s, uint64_t seed, uint64_t stream_id, const double* ext,
+                      hipStream_t st) {
+    afqmc_status r;
+    if ((r = force_bias(s, st)) != AFQMC_OK) return r;
+    FieldArgs f{};
+    f.F = s->d_F.as<double>();
+    f.ldf = s->n_chol + 1;
+    f.a = s->d_a.as<double>();
+    f.ext = ext;
+    f.seed = seed;
+    f.stream = stream_id;
+    f.t = s->t_dev ? s->t - s->t_base : s->t;
+    f.t_dev = s->t_dev;
+    f.alive = s->d_alive.as<uint8_t>();
+    f.X = s->d_X.p;
+    f.tx = s->ts;
+    f.ldx = s->n_chol;
+    f.s_imp = s->d_simp.as<double>();
+    f.nw = s->nw;
+    f.n_chol = s->n_chol;
+    f.sqdt = sqrt(s->par.dt);
+    f.free_proj = s->par.mode == AFQMC_FREE;
+    {
+        PhaseTimer pt(s, PH_FIELDS, st);
+        HIPCHK(fields(f, st));
     }
-    template <typename T>
-    T* as() const { return (T*)p; }
-};
+    {
+        const Gemm g = field_sum_gemm(s);
+        PhaseTimer pt(s, PH_FIELD_SUM, st);
+        HIPCHK(gemm(g, s->tc, st));
+    }
+    {
+        PhaseTimer pt(s, PH_UNPACK, st);
+        HIPCHK(unpack_sym(s->d_Apk.p, s->d_Af.p, s->M, 2 * s->nw, s->tp, st));
+    }
+    // Phi' = P T_K(A) P Phi, fused per walker
+    {
+        const void* Pm = s->tp == DT_F64 ? s->d_P.p : s->d_Plp.p;
+        PhaseTimer pt(s, PH_PROPAGATE, st);
+        HIPCHK(propagate(s->d_phi.as<double>(), s->d_phinew.as<double>(), Pm, s->d_Af.p,
+                         s->d_alive.as<uint8_t>(), s->nw, s->M, s->N, s->par.taylor_order, s->tp,
+                         s->prop_var, st));
+    }
+    if ((r = overlap_theta(s, s->d_phinew.as<double>(), st)) != AFQMC_OK) return r;
+    PhaseTimer pt(s, PH_WEIGHTS, st);
+    HIPCHK(weights(s->d_lnd.as<double>(), s->d_simp.as<double>(), s->d_lnov.as<double>(),
+                   s->d_w.as<double>(), s->d_alive.as<uint8_t>(), s->nw, (int)s->par.mode, 1,
+                   s->par.dt * s->e_shift, st));
+    std::swap(s->d_phi.p, s->d_phinew.p);
+    s->t += 1;
+    return AFQMC_OK;
+}
+
+afqmc_status ortho(afqmc_sys s, hipStream_t st) {
+    {
+        PhaseTimer pt(s, PH_MGS, st);
+        HIPCHK(mgs(s->d_phi.as<double>(), s->d_alive.as<uint8_t>(), s->nw, s->M, s->N, s->na, s->nb,
+               st));
+    }
+    afqmc_status r = overlap_theta(s, s->d_phi.as<double>(), st);
+    if (r != AFQMC_OK) return r;
+    PhaseTimer pt(s, PH_WEIGHTS, st);
+    HIPCHK(weights(s->d_lnd.as<double>(), s->d_simp.as<double>(), s->d_lnov.as<double>(),
+                   s->d_w.as<double>(), s->d_alive.as<uint8_t>(), s->nw, (int)s->par.mode, 0, 0.0,
+                   st));
+    return AFQMC_OK;
+}
+
+afqmc_status measure(afqmc_sys s, hipStream_t st) {
+    afqmc_status r = force_bias(s, st);
+    if (r != AFQMC_OK) return r;
+    const void* lh = lp_or(s->d_lhx_lp, s->d_lhx, s->ts);
+    const void* th = lp_or(s->d_theta_lp, s->d_theta, s->ts);
+    for (int spin = 0; spin < 2; ++spin) {
+        const int off = spin ? s->na : 0, n = spin ? s->nb : s->na;
+        if (n == 0) continue;
+        PhaseTimer pt(s, PH_EXCHANGE, st);
+        HIPCHK(exchange(lh, th, s->d_exch.as<double>(), s->nw, s->M, s->N, s->n_chol, off, n, spin,
+                        s->n_gt, s->tc, st));
+    }
+    PhaseTimer pt(s, PH_ENERGY, st);
+    HIPCHK(local_energy(s->d_F.as<double>(), s->n_chol + 1, s->d_exch.as<double>(), s->n_gt_a,
+                        s->n_gt_b, s->nw, s->n_chol, s->ham->e_core, s->d_el.as<double>(), st));
+    HIPCHK(mixed_sums(s->d_el.as<double>(), s->d_w.as<double>(), s->d_alive.as<uint8_t>(), s->nw,
+                      (int)s->par.mode, s->d_sums.as<double>(), st));
+    return AFQMC_OK;
+}
+
+}  // namespace host
+}  // namespace afq
+
+namespace {
 
 uint64_t fnv1a(const void* data, size_t n) {
     const unsigned char* b = (const unsigned char*)data;
@@ -149,300 +290,6 @@ bool theta_trial(const double* trial, int M, int N, int off, int n, double* out 
 
 // Phases of the step, each one kernel launch (the Taylor phase is one
 // launch per term).  Timed with HIP events on the system's stream when
-// profiling is enabled.
-enum Phase {
-    PH_FORCE_BIAS = 0,
-    PH_FIELDS,
-    PH_FIELD_SUM,
-    PH_UNPACK,
-    PH_PROPAGATE,
-    PH_OVERLAP,
-    PH_DET_THETA,
-    PH_WEIGHTS,
-    PH_MGS,
-    PH_EXCHANGE,
-    PH_ENERGY,
-    PH_COUNT
-};
-const char* const kPhaseNames[PH_COUNT] = {
-    "force_bias_gemm", "fields",       "field_sum_gemm", "unpack_a", "propagate", "overlap_gemm",
-    "det_theta",       "weights",      "mgs",            "exchange", "energy"};
-
-struct Profiler {
-    bool on = false;
-    struct Pend {
-        int phase;
-        hipEvent_t a, b;
-    };
-    std::vector<Pend> pend;
-    std::vector<hipEvent_t> pool;
-    double total_ms[PH_COUNT] = {};
-    int64_t launches[PH_COUNT] = {};
-    hipEvent_t get() {
-        if (!pool.empty()) {
-            hipEvent_t e = pool.back();
-            pool.pop_back();
-            return e;
-        }
-        hipEvent_t e = nullptr;
-        if (hipEventCreate(&e) != hipSuccess) return nullptr;
-        return e;
-    }
-    hipError_t resolve(hipStream_t st) {
-        if (pend.empty()) return hipSuccess;
-        hipError_t e = hipStreamSynchronize(st);
-        if (e != hipSuccess) return e;
-        for (auto& p : pend) {
-            float ms = 0.f;
-            if (p.a && p.b && hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
-                total_ms[p.phase] += ms;
-                launches[p.phase] += 1;
-            }
-            if (p.a) pool.push_back(p.a);
-            if (p.b) pool.push_back(p.b);
-        }
-        pend.clear();
-        return hipSuccess;
-    }
-    void reset() {
-        for (int i = 0; i < PH_COUNT; ++i) {
-            total_ms[i] = 0.0;
-            launches[i] = 0;
-        }
-    }
-    ~Profiler() {
-        for (auto& p : pend) {
-            if (p.a) (void)hipEventDestroy(p.a);
-            if (p.b) (void)hipEventDestroy(p.b);
-        }
-        for (auto e : pool) (void)hipEventDestroy(e);
-    }
-};
-
-}  // namespace
-
-struct afqmc_ham_s {
-    int M = 0, n_chol = 0;
-    double e_core = 0.0;
-    hipStream_t stream = nullptr;
-    uint64_t chol_hash = 0;
-    std::vector<double> h;
-    DevBuf d_h, d_chol;
-    DevBuf d_lp[4];  // packed L^T per storage type: [P][n_chol]
-    int refs = 1;
-    bool released = false;
-};
-
-struct afqmc_sys_s {
-    afqmc_ham ham = nullptr;
-    int M = 0, n_chol = 0, na = 0, nb = 0, N = 0, nw = 0;
-    afqmc_params par{};
-    DType ts = DT_F64;  // storage type of the contraction operands (L^half, Theta, X, L)
-    DType tc = DT_F64;  // compute type of the contractions (DT_SPLIT: split BF16)
-    DType tp = DT_F64;  // propagator product type (FP64 or FP32)
-    int64_t t = 0;
-    double e_shift = 0.0;  // constant energy shift of the weight factor
-    bool dead = false;
-    std::vector<double> a_host;
-    // constant per-system data
-    DevBuf d_trialT, d_P, d_Plp, d_a, d_lhx, d_lhx_lp;
-    // walker state
-    DevBuf d_phi, d_phinew, d_theta, d_theta_lp, d_w, d_lnov, d_alive;
-    // step scratch
-    DevBuf d_F, d_X, d_simp, d_Apk, d_Af, d_ov, d_lnd, d_exch, d_el, d_sums;
-    int n_gt_a = 0, n_gt_b = 0, n_gt = 0;
-    Profiler prof;
-    long P() const { return (long)M * (M + 1) / 2; }
-    long NM() const { return (long)N * M; }
-};
-
-namespace {
-
-afqmc_status check_sys(afqmc_sys s) {
-    if (!s) return fail(AFQMC_E_INVALID, "null system handle");
-    if (s->dead) return fail(AFQMC_E_STATE, "system handle already freed");
-    return AFQMC_OK;
-}
-
-void ham_unref(afqmc_ham h) {
-    if (--h->refs == 0) delete h;
-}
-
-const void* lp_or(const DevBuf& lp, const DevBuf& hi, DType t) { return t == DT_F64 ? hi.p : lp.p; }  // by storage type
-
-// Brackets one phase with a pair of HIP events when profiling is on.
-struct PhaseTimer {
-    Profiler* p;
-    hipStream_t st;
-    int phase;
-    hipEvent_t a = nullptr;
-    PhaseTimer(afqmc_sys s, int ph, hipStream_t stream) : p(&s->prof), st(stream), phase(ph) {
-        if (p->on) {
-            a = p->get();
-            if (a) (void)hipEventRecord(a, st);
-        }
-    }
-    ~PhaseTimer() {
-        if (p->on && a) {
-            hipEvent_t b = p->get();
-            if (b) (void)hipEventRecord(b, st);
-            p->pend.push_back({phase, a, b});
-        }
-    }
-};
-
-// ---- device phases of one step -------------------------------------------
-
-afqmc_status force_bias(afqmc_sys s, hipStream_t st) {
-    // F[(w,p), g] = sum_(i,m) Theta[(w,p),(i,m)] L^half[g,(i,m)], g <= n_chol
-    Gemm g{};
-    g.A = lp_or(s->d_theta_lp, s->d_theta, s->ts);
-    g.ta = s->ts;
-    g.ra = rows_strided(s->NM());
-    g.B = lp_or(s->d_lhx_lp, s->d_lhx, s->ts);
-    g.tb = s->ts;
-    g.rb = rows_strided(s->NM());
-    g.C = s->d_F.p;
-    g.tc = DT_F64;
-    g.rc = rows_strided(s->n_chol + 1);
-    g.alpha = 1.0;
-    g.m = 2 * s->nw;
-    g.n = s->n_chol + 1;
-    g.k = (int)s->NM();
-    g.batch = 1;
-    PhaseTimer pt(s, PH_FORCE_BIAS, st);
-    HIPCHK(gemm(g, s->tc, st));
-    return AFQMC_OK;
-}
-
-afqmc_status overlap_theta(afqmc_sys s, double* phi, hipStream_t st) {
-    Gemm g{};
-    g.A = phi;
-    g.ta = DT_F64;
-    g.ra = rows_strided(s->M);
-    g.B = s->d_trialT.p;
-    g.tb = DT_F64;
-    g.rb = rows_strided(s->M);
-    g.C = s->d_ov.p;
-    g.tc = DT_F64;
-    g.rc = rows_strided(s->N);
-    g.alpha = 1.0;
-    g.m = 2 * s->N * s->nw;
-    g.n = s->N;
-    g.k = s->M;
-    g.batch = 1;
-    {
-        PhaseTimer pt(s, PH_OVERLAP, st);
-        HIPCHK(gemm(g, DT_F64, st));
-    }
-    PhaseTimer pt(s, PH_DET_THETA, st);
-    HIPCHK(lu_theta(s->d_ov.as<double>(), phi, s->d_theta.as<double>(),
-                    s->ts == DT_F64 ? nullptr : s->d_theta_lp.p, s->ts, s->d_lnd.as<double>(),
-                    s->d_alive.as<uint8_t>(), s->nw, s->M, s->N, s->na, s->nb, st));
-    return AFQMC_OK;
-}
-
-afqmc_status one_step(afqmc_sys s, uint64_t seed, uint64_t stream_id, const double* ext,
-                      hipStream_t st) {
-    afqmc_status r;
-    if ((r = force_bias(s, st)) != AFQMC_OK) return r;
-    FieldArgs f{};
-    f.F = s->d_F.as<double>();
-    f.ldf = s->n_chol + 1;
-    f.a = s->d_a.as<double>();
-    f.ext = ext;
-    f.seed = seed;
-    f.stream = stream_id;
-    f.t = s->t;
-    f.alive = s->d_alive.as<uint8_t>();
-    f.X = s->d_X.p;
-    f.tx = s->ts;
-    f.ldx = s->n_chol;
-    f.s_imp = s->d_simp.as<double>();
-    f.nw = s->nw;
-    f.n_chol = s->n_chol;
-    f.sqdt = sqrt(s->par.dt);
-    f.free_proj = s->par.mode == AFQMC_FREE;
-    {
-        PhaseTimer pt(s, PH_FIELDS, st);
-        HIPCHK(fields(f, st));
-    }
-    // A[(w,p), q] = sum_g X[(w,p), g] Lpacked[q, g]
-    {
-        Gemm g{};
-        g.A = s->d_X.p;
-        g.ta = s->ts;
-        g.ra = rows_strided(s->n_chol);
-        g.B = s->ham->d_lp[s->ts].p;
-        g.tb = s->ts;
-        g.rb = rows_strided(s->n_chol);
-        g.C = s->d_Apk.p;
-        g.tc = s->tp;
-        g.rc = rows_strided(s->P());
-        g.alpha = 1.0;
-        g.m = 2 * s->nw;
-        g.n = (int)s->P();
-        g.k = s->n_chol;
-        g.batch = 1;
-        PhaseTimer pt(s, PH_FIELD_SUM, st);
-        HIPCHK(gemm(g, s->tc, st));
-    }
-    {
-        PhaseTimer pt(s, PH_UNPACK, st);
-        HIPCHK(unpack_sym(s->d_Apk.p, s->d_Af.p, s->M, 2 * s->nw, s->tp, st));
-    }
-    // Phi' = P T_K(A) P Phi, fused per walker
-    {
-        const void* Pm = s->tp == DT_F64 ? s->d_P.p : s->d_Plp.p;
-        PhaseTimer pt(s, PH_PROPAGATE, st);
-        HIPCHK(propagate(s->d_phi.as<double>(), s->d_phinew.as<double>(), Pm, s->d_Af.p,
-                         s->d_alive.as<uint8_t>(), s->nw, s->M, s->N, s->par.taylor_order, s->tp,
-                         st));
-    }
-    if ((r = overlap_theta(s, s->d_phinew.as<double>(), st)) != AFQMC_OK) return r;
-    PhaseTimer pt(s, PH_WEIGHTS, st);
-    HIPCHK(weights(s->d_lnd.as<double>(), s->d_simp.as<double>(), s->d_lnov.as<double>(),
-                   s->d_w.as<double>(), s->d_alive.as<uint8_t>(), s->nw, (int)s->par.mode, 1,
-                   s->par.dt * s->e_shift, st));
-    std::swap(s->d_phi.p, s->d_phinew.p);
-    s->t += 1;
-    return AFQMC_OK;
-}
-
-afqmc_status ortho(afqmc_sys s, hipStream_t st) {
-    {
-        PhaseTimer pt(s, PH_MGS, st);
-        HIPCHK(mgs(s->d_phi.as<double>(), s->d_alive.as<uint8_t>(), s->nw, s->M, s->N, s->na, s->nb,
-               st));
-    }
-    afqmc_status r = overlap_theta(s, s->d_phi.as<double>(), st);
-    if (r != AFQMC_OK) return r;
-    PhaseTimer pt(s, PH_WEIGHTS, st);
-    HIPCHK(weights(s->d_lnd.as<double>(), s->d_simp.as<double>(), s->d_lnov.as<double>(),
-                   s->d_w.as<double>(), s->d_alive.as<uint8_t>(), s->nw, (int)s->par.mode, 0, 0.0,
-                   st));
-    return AFQMC_OK;
-}
-
-afqmc_status measure(afqmc_sys s, hipStream_t st) {
-    afqmc_status r = force_bias(s, st);
-    if (r != AFQMC_OK) return r;
-    const void* lh = lp_or(s->d_lhx_lp, s->d_lhx, s->ts);
-    const void* th = lp_or(s->d_theta_lp, s->d_theta, s->ts);
-    for (int spin = 0; spin < 2; ++spin) {
-        const int off = spin ? s->na : 0, n = spin ? s->nb : s->na;
-        if (n == 0) continue;
-        PhaseTimer pt(s, PH_EXCHANGE, st);
-        HIPCHK(exchange(lh, th, s->d_exch.as<double>(), s->nw, s->M, s->N, s->n_chol, off, n, spin,
-                        s->n_gt, s->tc, st));
-    }
-    PhaseTimer pt(s, PH_ENERGY, st);
-    HIPCHK(local_energy(s->d_F.as<double>(), s->n_chol + 1, s->d_exch.as<double>(), s->n_gt_a,
-                        s->n_gt_b, s->nw, s->n_chol, s->ham->e_core, s->d_el.as<double>(), st));
-    HIPCHK(mixed_sums(s->d_el.as<double>(), s->d_w.as<double>(), s->d_alive.as<uint8_t>(), s->nw,
-                      (int)s->par.mode, s->d_sums.as<double>(), st));
-    return AFQMC_OK;
-}
 
 }  // namespace
 
@@ -506,6 +353,8 @@ afqmc_status afqmc_init_walkers(afqmc_ham ham, int n_alpha, int n_beta, const do
         return fail(AFQMC_E_INVALID, "bad mode");
     hipStream_t st = ham->stream;
     afqmc_sys s = new afqmc_sys_s();
+    static uint64_t next_id = 0;
+    s->id = ++next_id;
     s->ham = ham;
     ham->refs++;
     s->M = M;
@@ -754,6 +603,7 @@ void afqmc_free_sys(afqmc_sys s) {
                       &s->d_alive, &s->d_F, &s->d_X, &s->d_simp, &s->d_Apk, &s->d_Af,
                       &s->d_ov, &s->d_lnd, &s->d_exch, &s->d_el, &s->d_sums})
         b->release();
+    drop_batch_plans(s->id);
     s->ham = nullptr;
     if (h) ham_unref(h);
 }
@@ -835,24 +685,13 @@ afqmc_status afqmc_pair_step(afqmc_sys a, afqmc_sys b, uint64_t seed, int n_step
             if ((r = measure(a, st)) != AFQMC_OK) return r;
             if ((r = measure(b, st)) != AFQMC_OK) return r;
             HIPCHK(trace_record(a->d_sums.as<double>(), b->d_sums.as<double>(),
-                                trace.as<double>(), slot++, (int)a->par.mode, st));
+                                trace.as<double>(), slot++, nullptr, 0, (int)a->par.mode, st));
         }
     }
     HIPCHK(hipStreamSynchronize(st));
     if (e_trace && n_meas > 0)
         HIPCHK(hipMemcpy(e_trace, trace.p, (size_t)n_meas * 3 * 8, hipMemcpyDeviceToHost));
     return AFQMC_OK;
-}
-
-afqmc_status afqmc_pair_batch_step(int n_pairs, const afqmc_sys* a, const afqmc_sys* b,
-                                   const uint64_t* seeds, int n_steps, double* e_traces) {
-    (void)n_pairs;
-    (void)a;
-    (void)b;
-    (void)seeds;
-    (void)n_steps;
-    (void)e_traces;
-    return fail(AFQMC_E_STATE, "pair batch step not available in this build");
 }
 
 afqmc_status afqmc_get_walkers(afqmc_sys s, double* phi, double* w, double* log_ovlp,
@@ -1000,13 +839,15 @@ afqmc_status afqmc_selftest_gemm(afqmc_prec prec, int m, int n, int k, const dou
     return AFQMC_OK;
 }
 
-afqmc_status afqmc_selftest_propagate(afqmc_prec prec, int M, int N, int nw, int K,
+afqmc_status afqmc_selftest_propagate(afqmc_prec prec, int M, int N, int nw, int K, int variant,
                                       const double* phi, const double* P, const double* A,
                                       double* out) {
     if (!phi || !P || !A || !out || M <= 0 || N <= 0 || nw <= 0 || K < 0)
         return fail(AFQMC_E_INVALID, "bad args");
     if (M > 256) return fail(AFQMC_E_SHAPE, "M <= 256");
     const DType t = prec == AFQMC_FP64 ? DT_F64 : DT_F32;
+    if (!propagate_variant_ok(variant, M, t))
+        return fail(AFQMC_E_SHAPE, "workgroup shape does not serve this M / precision");
     const size_t nphi = (size_t)nw * 2 * N * M, nA = (size_t)nw * 2 * M * M, nP = (size_t)M * M;
     DevBuf dphi, dout, dP, dA, dP64, dA64, dlive;
     HIPCHK(dphi.alloc(nphi * 8));
@@ -1023,7 +864,7 @@ afqmc_status afqmc_selftest_propagate(afqmc_prec prec, int M, int N, int nw, int
     HIPCHK(convert(dP64.as<double>(), dP.p, t, (long)nP, nullptr));
     HIPCHK(convert(dA64.as<double>(), dA.p, t, (long)nA, nullptr));
     HIPCHK(propagate(dphi.as<double>(), dout.as<double>(), dP.p, dA.p, dlive.as<uint8_t>(), nw, M,
-                     N, K, t, nullptr));
+                     N, K, t, variant, nullptr));
     HIPCHK(hipDeviceSynchronize());
     HIPCHK(hipMemcpy(out, dout.p, nphi * 8, hipMemcpyDeviceToHost));
     return AFQMC_OK;

@@ -95,8 +95,8 @@ template <typename TA, typename TB, typename TC, typename TO>
 hipError_t launch_gemm(const Gemm& g, hipStream_t s) {
     const long tiles128 = ((long)(g.m + 127) / 128) * ((g.n + 127) / 128) * g.batch;
     constexpr int BK = Info<TC>::KM == 4 ? 16 : 32;
-    if (g.m >= 96 && g.n >= 96 && tiles128 >= 512)
-        return launch_tile<TA, TB, TC, TO, 128, 128, BK, 2, 2>(g, s);
+    const bool big = g.tile ? g.tile == 2 : (g.m >= 96 && g.n >= 96 && tiles128 >= 512);
+    if (big) return launch_tile<TA, TB, TC, TO, 128, 128, BK, 2, 2>(g, s);
     return launch_tile<TA, TB, TC, TO, 64, 64, BK, 2, 2>(g, s);
 }
 

@@ -52,6 +52,7 @@ struct Gemm {
     double alpha;
     double beta;
     int m, n, k, batch;
+    int tile;  // 0: size heuristic; 1: 64 x 64 tiles; 2: 128 x 128 tiles
 };
 
 // Compute precision of a GEMM (the MFMA input type; accumulation is FP64 for
@@ -67,9 +68,14 @@ hipError_t unpack_sym(const void* pk, void* full, int M, int planes, DType t, hi
 // phi, phi_out: FP64 walker blocks [w][plane][N][M]; Pm: M x M real
 // symmetric, Af: [w][plane][M][M] complex symmetric, both in type t
 // (DT_F64 or DT_F32, the product precision).  Frozen walkers (live == 0)
-// are copied unchanged.  M <= 256.
+// are copied unchanged.  M <= 256.  `variant` selects the workgroup shape
+// (waves per workgroup x column blocks per wave, see kPropShapes); every
+// variant gives bitwise the same result, 0 is the default.
+constexpr int kPropVariants = 5;
+bool propagate_variant_ok(int variant, int M, DType t);
 hipError_t propagate(const double* phi, double* phi_out, const void* Pm, const void* Af,
-                     const uint8_t* live, int nw, int M, int N, int K, DType t, hipStream_t s);
+                     const uint8_t* live, int nw, int M, int N, int K, DType t, int variant,
+                     hipStream_t s);
 
 // Exchange partial sums of the mixed local energy:
 //   out[(w * 2 + spin) * n_gtiles + gt] = sum over gamma in tile gt of
@@ -88,7 +94,8 @@ struct FieldArgs {
     const double* a;      // [n_chol] mean-field shift a_g
     const double* ext;    // NULL or external fields for this step: [nw][n_chol]
     uint64_t seed, stream;
-    int64_t t;            // absolute step (Philox counter word)
+    int64_t t;            // absolute step (Philox counter word), or an offset
+    const int64_t* t_dev; // non-NULL: step = *t_dev + t (device-side step counter)
     const uint8_t* alive;
     void* X;              // [w][2][ldx] field-sum coefficients, type tx
     DType tx;
@@ -139,7 +146,16 @@ hipError_t pack_chol(const double* L, void* Lp, DType t, int M, int n_chol, hipS
 hipError_t permute_chol(const double* L, double* LT, int M, int n_chol, hipStream_t s);
 hipError_t chol_weighted_sum(const double* L, const double* a, double* out, int M, int n_chol,
                              hipStream_t s);
+// trace[slot] = (E_a, E_b, E_b - E_a).  With device counters ctr (non-NULL)
+// the row is written at ((double*)ctr[2])[3 * (pair * ctr[3] + ctr[1] + slot)]
+// instead (trace ignored).
 hipError_t trace_record(const double* sums_a, const double* sums_b, double* trace, int slot,
-                        int mode, hipStream_t s);
+                        const int64_t* ctr, int pair, int mode, hipStream_t s);
+// Device counters of a replayed graph: ctr[0] step, ctr[1] measurement slot,
+// ctr[2] trace address, ctr[3] trace rows per pair.
+hipError_t set_counters(int64_t* ctr, int64_t c0, int64_t c1, int64_t c2, int64_t c3,
+                        hipStream_t s);
+// ctr[0] += d0; ctr[1] += d1.
+hipError_t advance_counters(int64_t* ctr, int64_t d0, int64_t d1, hipStream_t s);
 
 }  // namespace afq

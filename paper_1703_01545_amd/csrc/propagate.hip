@@ -301,12 +301,44 @@ hipError_t unpack_sym(const void* pk, void* full, int M, int planes, DType t, hi
     return hipGetLastError();
 }
 
+// Workgroup shapes (waves, column blocks per wave): a shape serves M up to
+// 16 * waves * blocks.  Fewer waves per workgroup leave no idle waves at
+// small M; more waves shorten each wave's share at large M.
+namespace {
+struct PropShape {
+    int waves, blocks;
+};
+constexpr PropShape kPropShapes[kPropVariants] = {{8, 2}, {4, 4}, {4, 2}, {2, 4}, {4, 1}};
+}  // namespace
+
+bool propagate_variant_ok(int v, int M, DType t) {
+    if (v < 0 || v >= kPropVariants || M <= 0) return false;
+    if (t != DT_F64 && t != DT_F32) return false;
+    const PropShape p = kPropShapes[v];
+    if (t == DT_F64 && p.blocks > 2) return false;  // register budget of the FP64 state
+    return (M + 15) / 16 <= p.waves * p.blocks;
+}
+
 hipError_t propagate(const double* phi, double* phi_out, const void* Pm, const void* Af,
-                     const uint8_t* live, int nw, int M, int N, int K, DType t, hipStream_t s) {
+                     const uint8_t* live, int nw, int M, int N, int K, DType t, int variant,
+                     hipStream_t s) {
     if (nw <= 0) return hipSuccess;
     if (M > 256 || M <= 0 || N <= 0) return hipErrorInvalidValue;
-    if (t == DT_F64) return launch_prop<double, 8, 2>(phi, phi_out, Pm, Af, live, nw, M, N, K, s);
-    if (t == DT_F32) return launch_prop<float, 8, 2>(phi, phi_out, Pm, Af, live, nw, M, N, K, s);
+    if (!propagate_variant_ok(variant, M, t)) return hipErrorInvalidValue;
+#define AFQ_P(V, T_, W_, B_) \
+    if (variant == V) return launch_prop<T_, W_, B_>(phi, phi_out, Pm, Af, live, nw, M, N, K, s);
+    if (t == DT_F64) {
+        AFQ_P(0, double, 8, 2)
+        AFQ_P(2, double, 4, 2)
+        AFQ_P(4, double, 4, 1)
+    } else {
+        AFQ_P(0, float, 8, 2)
+        AFQ_P(1, float, 4, 4)
+        AFQ_P(2, float, 4, 2)
+        AFQ_P(3, float, 2, 4)
+        AFQ_P(4, float, 4, 1)
+    }
+#undef AFQ_P
     return hipErrorInvalidValue;
 }
 

@@ -84,6 +84,7 @@ __global__ __launch_bounds__(256) void k_fields(FieldArgs f) {
     const long xr = (long)w * 2 * f.ldx, xi = xr + f.ldx;
     double cia = 0.0, cra = 0.0, ir = 0.0, ii = 0.0;
     const double sq = f.sqdt;
+    const int64_t tstep = f.t_dev ? *f.t_dev + f.t : f.t;
     for (int b = lane; 4 * b < f.n_chol; b += 64) {
         double z[4];
         if (f.ext) {
@@ -93,7 +94,7 @@ __global__ __launch_bounds__(256) void k_fields(FieldArgs f) {
                 z[e] = g < f.n_chol ? f.ext[(long)w * f.n_chol + g] : 0.0;
             }
         } else {
-            normals4(f.seed, f.stream, f.t, (uint32_t)w, (uint32_t)b, z);
+            normals4(f.seed, f.stream, tstep, (uint32_t)w, (uint32_t)b, z);
         }
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
@@ -478,8 +479,29 @@ __global__ __launch_bounds__(256) void k_mixed(const double* __restrict__ el,
     if (tid < 4) out[tid] = red[tid][0];
 }
 
-__global__ void k_trace(const double* sa, const double* sb, double* trace, int slot, int mode) {
+__global__ void k_set4(int64_t* ctr, int64_t c0, int64_t c1, int64_t c2, int64_t c3) {
+    if (threadIdx.x == 0) {
+        ctr[0] = c0;
+        ctr[1] = c1;
+        ctr[2] = c2;
+        ctr[3] = c3;
+    }
+}
+
+__global__ void k_advance(int64_t* ctr, int64_t d0, int64_t d1) {
+    if (threadIdx.x == 0) {
+        ctr[0] += d0;
+        ctr[1] += d1;
+    }
+}
+
+__global__ void k_trace(const double* sa, const double* sb, double* trace, long slot,
+                        const int64_t* ctr, int pair, int mode) {
     if (threadIdx.x != 0) return;
+    if (ctr) {
+        trace = reinterpret_cast<double*>(static_cast<uintptr_t>(ctr[2]));
+        slot += (long)pair * ctr[3] + ctr[1];
+    }
     double ea, eb;
     if (mode == 0) {
         ea = sa[0] / sa[1];
@@ -572,10 +594,12 @@ hipError_t lu_theta(const double* ov, const double* phi, double* theta, void* th
     if (nw <= 0) return hipSuccess;
     const int nmax = na > nb ? na : nb;
     const size_t shm = (size_t)2 * nmax * (2 * nmax + 1) * sizeof(double);
-    if (shm > 65536) {
+    static size_t allowed = 65536;  // raised once per new size, outside graph capture
+    if (shm > allowed) {
         hipError_t e = hipFuncSetAttribute((const void*)k_lu_theta,
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
         if (e != hipSuccess) return e;
+        allowed = shm;
     }
     hipLaunchKernelGGL(k_lu_theta, dim3(nw, 2), dim3(256), shm, s, ov, phi, theta, theta_lp, tlp,
                        lnd, live, M, N, na, nb);
@@ -626,9 +650,21 @@ hipError_t mixed_sums(const double* el, const double* w, const uint8_t* alive, i
     return hipGetLastError();
 }
 
-hipError_t trace_record(const double* sa, const double* sb, double* trace, int slot, int mode,
+hipError_t trace_record(const double* sa, const double* sb, double* trace, int slot,
+                        const int64_t* ctr, int pair, int mode, hipStream_t s) {
+    hipLaunchKernelGGL(k_trace, dim3(1), dim3(64), 0, s, sa, sb, trace, (long)slot, ctr, pair,
+                       mode);
+    return hipGetLastError();
+}
+
+hipError_t set_counters(int64_t* ctr, int64_t c0, int64_t c1, int64_t c2, int64_t c3,
                         hipStream_t s) {
-    hipLaunchKernelGGL(k_trace, dim3(1), dim3(64), 0, s, sa, sb, trace, slot, mode);
+    hipLaunchKernelGGL(k_set4, dim3(1), dim3(64), 0, s, ctr, c0, c1, c2, c3);
+    return hipGetLastError();
+}
+
+hipError_t advance_counters(int64_t* ctr, int64_t d0, int64_t d1, hipStream_t s) {
+    hipLaunchKernelGGL(k_advance, dim3(1), dim3(64), 0, s, ctr, d0, d1);
     return hipGetLastError();
 }
 

@@ -279,3 +279,31 @@ def test_propagation_kernel(lib, dims, prec):
         ref[k] = P @ acc
     tol = 1e-12 if prec == "fp64" else 2e-5
     assert rel(got, ref) < tol
+
+
+@pytest.mark.parametrize("dims", [(12, 6, 3), (37, 13, 5), (130, 40, 3), (200, 80, 2), (64, 17, 2)])
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_propagation_shapes_bitwise(lib, dims, prec):
+    """Every workgroup shape the autotuner may pick gives bitwise the result
+    of the default shape (same summation order per output element)."""
+    M, N, nw = dims
+    banner(f"propagate shapes {prec} {dims}")
+    rng = np.random.default_rng(7 * M + N)
+    phi = rng.standard_normal((nw, M, N)) + 1j * rng.standard_normal((nw, M, N))
+    P = rng.standard_normal((M, M)) * 0.05
+    P = np.eye(M) + 0.5 * (P + P.T)
+    A = (rng.standard_normal((nw, M, M)) + 1j * rng.standard_normal((nw, M, M))) * (0.4 / np.sqrt(M))
+    A = 0.5 * (A + np.swapaxes(A, 1, 2))
+    base = lib.selftest_propagate(phi, P, A, 6, prec, variant=0)
+    shapes = {0: (8, 2), 1: (4, 4), 2: (4, 2), 3: (2, 4), 4: (4, 1)}
+    ran = 0
+    for v, (waves, blocks) in shapes.items():
+        ok = (M + 15) // 16 <= waves * blocks and not (prec == "fp64" and blocks > 2)
+        if not ok:
+            with pytest.raises(lib.AfqmcError):
+                lib.selftest_propagate(phi, P, A, 6, prec, variant=v)
+            continue
+        got = lib.selftest_propagate(phi, P, A, 6, prec, variant=v)
+        assert np.array_equal(got, base), f"shape {v} differs"
+        ran += 1
+    assert ran >= 1
