@@ -1,13 +1,18 @@
 #!/usr/bin/env python3
 """Throughput benchmark of the correlated-pair ph-AFQMC walker step.
 
-Workload: the M = 200 pair (n_chol = 800, neutral 40/40 vs ion 40/39
-electrons, 2048 walkers per system, dt = 0.005, Taylor order 6, modified
-Gram-Schmidt every 10 steps, mixed energy every 20 steps), Cholesky
-contractions in BF16 with FP32 accumulation, propagator products in FP32,
-determinants / Gram-Schmidt / weights in FP64.  One "step" is one pair-step:
-both systems advanced one dt, with the periodic Gram-Schmidt and energy
-measurement amortised in (steps are a multiple of the measurement period).
+Default workload: the M = 200 pair (n_chol = 800, neutral 40/40 vs ion
+40/39 electrons, 2048 walkers per system, dt = 0.005, Taylor order 6,
+modified Gram-Schmidt every 10 steps, mixed energy every 20 steps), Cholesky
+contractions in split BF16 (hi + lo products) with FP32 accumulation,
+propagator products in FP32, determinants / Gram-Schmidt / weights in FP64.
+One "step" is one pair-step: both systems advanced one dt, with the periodic
+Gram-Schmidt and energy measurement amortised in (steps are a multiple of the
+measurement period).  The timed steps are replayed from a HIP graph; a
+following profiled pass of direct launches gives the per-kernel times.
+
+--workload batch: 64 uneven pairs (M in 40..240, FP32 contractions) stepped
+together from one graph, against the same pairs stepped one at a time.
 
 Prints one JSON line.  value = walker-steps/s (2 systems x walkers x steps /
 wall time of the timed steps, inputs resident in HBM).
@@ -27,8 +32,6 @@ if ROOT not in sys.path:
 METRIC = "walker-steps/s at M=200, Nw=2048 (pair); ΔE error vs FP64 oracle (kcal/mol)"
 EH_TO_KCAL = 627.5095
 PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16": 2500.0}
-# split-BF16 contractions issue three BF16 products per algorithmic product
-ISSUE_FACTOR = {"bf16": 3.0}
 
 
 def phase_flops(name, M, nc, na, nb, nw, taylor_order=6):
@@ -81,42 +84,45 @@ def cpu_baseline(cfg, n_walkers, n_steps):
                       f"{cfg.measure_every}), FP64 numpy, {el:.1f} s"}
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=40)
-    ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--precision", default="bf16", choices=["bf16", "fp32", "fp64", "bf16_plain"])
-    ap.add_argument("--walkers", type=int, default=None, help="override walkers per system")
-    ap.add_argument("--seed", type=int, default=0)
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-walkers", type=int, default=4)
-    ap.add_argument("--cpu-steps", type=int, default=20)
-    ap.add_argument("--no-fp64-check", action="store_true",
-                    help="skip the FP64 rerun that measures the energy-difference error")
-    args = ap.parse_args()
+def _roofline(prof_a, prof_b, steps, cfg, prec):
+    phases = {}
+    for name in prof_a:
+        ms = prof_a[name][0] + prof_b[name][0]
+        n = prof_a[name][1] + prof_b[name][1]
+        phases[name] = {"ms_per_step": ms / steps, "launches": n,
+                        "avg_launch_ms": ms / n if n else 0.0}
+    gemm_phases = [p for p in phases if phase_flops(p, 1, 1, 1, 1, 1) is not None]
+    dom = max(gemm_phases, key=lambda p: phases[p]["ms_per_step"])
+    fl_a = phase_flops(dom, cfg.M, cfg.n_chol, cfg.na_a, cfg.nb_a, cfg.n_walkers)
+    fl_b = phase_flops(dom, cfg.M, cfg.n_chol, cfg.na_b, cfg.nb_b, cfg.n_walkers)
+    n_a, n_b = prof_a[dom][1], prof_b[dom][1]
+    tot_s = (prof_a[dom][0] + prof_b[dom][0]) * 1e-3
+    achieved = (fl_a * n_a + fl_b * n_b) / tot_s / 1e12
+    dtype = phase_dtype(dom, prec)
+    peak = PEAK_TFLOPS[dtype]
+    roof = {"bound": "mfma", "kernel": dom, "kernel_dtype": dtype,
+            "flops_per_launch": (fl_a * n_a + fl_b * n_b) / max(n_a + n_b, 1),
+            "avg_launch_ms": tot_s * 1e3 / max(n_a + n_b, 1),
+            "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
+            "traffic": None}
+    return phases, roof
 
-    if args.gpus != 1:
-        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported by this build "
-              "(walkers and pairs are independent, see the sharding notes).", file=sys.stderr)
-        sys.exit(2)
 
+def bench_pair(args):
     import numpy as np
     import torch
 
     from paper_1703_01545_amd import afqmc as lib
     from synth import config
 
-    assert torch.cuda.is_available(), "bench.py needs a GPU"
-    torch.cuda.set_device(0)
     cfg = config(2)
     if args.walkers:
         cfg = cfg.with_(n_walkers=args.walkers)
     prec = args.precision
     me = cfg.measure_every
-    if args.steps % me or args.warmup % me:
-        print(f"--steps and --warmup must be multiples of the measurement period {me}",
-              file=sys.stderr)
+    if args.steps % me or args.warmup % me or args.profile_steps % me:
+        print(f"--steps, --warmup and --profile-steps must be multiples of the measurement "
+              f"period {me}", file=sys.stderr)
         sys.exit(2)
     ham = cfg.hamiltonian()
     ta, tb = cfg.trial_a(), cfg.trial_b()
@@ -131,46 +137,40 @@ def main():
         b = lib.System(H, cfg.na_b, cfg.nb_b, tb, cfg.n_walkers, cfg.dt, **kw)
         return H, a, b
 
+    def run(a, b, n):
+        # one pair through the graph-replayed batch path (captured on first use)
+        return lib.pair_batch_step([(a, b)], [args.seed], n, lanes=1)[0]
+
     H, ga, gb = make(prec)
     torch.cuda.synchronize()
-    tr_w = lib.pair_step(ga, gb, args.warmup, seed=args.seed)
+    tr_w = run(ga, gb, args.warmup)
     print(f"[bench] warmup done ({args.warmup} steps)", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    tr_t = run(ga, gb, args.steps)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    print(f"[bench] timed {args.steps} graph-replayed steps in {elapsed:.3f} s", file=sys.stderr,
+          flush=True)
+    # per-kernel HIP events on the launch stream over a profiled pass of the
+    # same trajectory (direct launches)
     ga.profile(True)
     gb.profile(True)
     torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    tr_t = lib.pair_step(ga, gb, args.steps, seed=args.seed)
+    t1 = time.perf_counter()
+    tr_p = lib.pair_step(ga, gb, args.profile_steps, seed=args.seed)
     torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
+    el_prof = time.perf_counter() - t1
     prof_a, prof_b = ga.profile_read(), gb.profile_read()
     ga.profile(False)
     gb.profile(False)
-    print(f"[bench] timed {args.steps} steps in {elapsed:.3f} s", file=sys.stderr, flush=True)
     alive = (ga.walkers()["alive"].mean(), gb.walkers()["alive"].mean())
-    trace = np.concatenate([tr_w, tr_t]) if len(tr_w) else tr_t
+    trace = np.concatenate([x for x in (tr_w, tr_t, tr_p) if len(x)])
+    phases, roofline = _roofline(prof_a, prof_b, args.profile_steps, cfg, prec)
+    roofline["measured_over"] = (f"{args.profile_steps} pair-steps of the same run, direct "
+                                 "launches, HIP events around every launch on its stream")
 
     ws = 2 * cfg.n_walkers * args.steps / elapsed
-    phases = {}
-    for name in prof_a:
-        ms = prof_a[name][0] + prof_b[name][0]
-        n = prof_a[name][1] + prof_b[name][1]
-        phases[name] = {"ms_per_step": ms / args.steps, "launches": n,
-                        "avg_launch_ms": ms / n if n else 0.0}
-    gemm_phases = [p for p in phases if phase_flops(p, 1, 1, 1, 1, 1) is not None]
-    dom = max(gemm_phases, key=lambda p: phases[p]["ms_per_step"])
-    fl_a = phase_flops(dom, cfg.M, cfg.n_chol, cfg.na_a, cfg.nb_a, cfg.n_walkers)
-    fl_b = phase_flops(dom, cfg.M, cfg.n_chol, cfg.na_b, cfg.nb_b, cfg.n_walkers)
-    n_a, n_b = prof_a[dom][1], prof_b[dom][1]
-    tot_s = (prof_a[dom][0] + prof_b[dom][0]) * 1e-3
-    achieved = (fl_a * n_a + fl_b * n_b) / tot_s / 1e12
-    dtype = phase_dtype(dom, prec)
-    peak = PEAK_TFLOPS[dtype]
-    roofline = {"bound": "mfma", "kernel": dom, "kernel_dtype": dtype,
-                "flops_per_launch": (fl_a * n_a + fl_b * n_b) / max(n_a + n_b, 1),
-                "avg_launch_ms": tot_s * 1e3 / max(n_a + n_b, 1),
-                "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
-                "traffic": None}
-
     out = {
         "metric": METRIC, "value": ws, "unit": "walker-steps/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": elapsed * 1e3 / args.steps,
@@ -182,21 +182,28 @@ def main():
                    "M": cfg.M, "n_chol": cfg.n_chol, "n_walkers": cfg.n_walkers, "dt": cfg.dt,
                    "taylor_order": cfg.taylor_order, "ortho_every": cfg.ortho_every,
                    "measure_every": me, "contractions": prec,
-                   "walker_arithmetic": "fp64", "parallelism": "single GPU"},
+                   "walker_arithmetic": "fp64", "launch": "HIP graph replay",
+                   "parallelism": "single GPU"},
         "roofline": roofline,
+        "profiled_ms_per_step": el_prof * 1e3 / args.profile_steps,
         "phases_ms_per_step": {k: round(v["ms_per_step"], 4) for k, v in phases.items()},
         "alive_fraction": [float(alive[0]), float(alive[1])],
         "dE_trace_Eh": [float(x) for x in trace[:, 2]],
     }
 
+    n_all = args.warmup + args.steps + args.profile_steps
     if prec != "fp64" and not args.no_fp64_check:
         del ga, gb, H
         H64, fa, fb = make("fp64")
-        tr64 = lib.pair_step(fa, fb, args.warmup + args.steps, seed=args.seed)
+        tr64 = run(fa, fb, n_all)
         err = np.abs(trace[:, 2] - tr64[:, 2])
+        # statistical scale: spread of the measured dE over the run
+        sd = float(np.std(tr64[:, 2])) if len(tr64) > 1 else None
         out["dE_err_vs_fp64_kcal_per_mol"] = {
             "max": float(err.max() * EH_TO_KCAL), "last": float(err[-1] * EH_TO_KCAL),
-            "steps": args.warmup + args.steps,
+            "mean_dE_err": float(abs(trace[:, 2].mean() - tr64[:, 2].mean()) * EH_TO_KCAL),
+            "steps": n_all,
+            "dE_spread_fp64_kcal_per_mol": None if sd is None else sd * EH_TO_KCAL,
             "note": "same fields, GPU FP64 path (itself matched to the FP64 oracle at 1e-10)"}
         out["dE_fp64_trace_Eh"] = [float(x) for x in tr64[:, 2]]
         print("[bench] fp64 check done", file=sys.stderr, flush=True)
@@ -205,6 +212,120 @@ def main():
         print("[bench] timing the FP64 oracle on a sample", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(cfg, args.cpu_walkers, args.cpu_steps)
     print(json.dumps(out), flush=True)
+
+
+def bench_batch(args):
+    """64 uneven correlated pairs in one graph-replayed launch sequence vs the
+    same pairs stepped one pair at a time."""
+    import numpy as np
+    import torch
+
+    from paper_1703_01545_amd import afqmc as lib
+    from synth import pair_batch_configs
+
+    cfgs = pair_batch_configs(n_pairs=args.pairs)
+    prec = "fp32" if args.precision == "bf16" else args.precision
+    me = cfgs[0].measure_every
+    if args.steps % me or args.warmup % me:
+        print(f"--steps and --warmup must be multiples of {me}", file=sys.stderr)
+        sys.exit(2)
+    pairs, hams, seeds = [], [], []
+    t_gen = time.perf_counter()
+    for p, c in enumerate(cfgs):
+        ham = c.hamiltonian()
+        H = lib.Hamiltonian(ham.h, ham.chol, ham.e_core)
+        kw = dict(taylor_order=c.taylor_order, ortho_every=c.ortho_every, measure_every=me,
+                  precision=prec)
+        a = lib.System(H, c.na_a, c.nb_a, c.trial_a(), c.n_walkers, c.dt, **kw)
+        b = lib.System(H, c.na_b, c.nb_b, c.trial_b(), c.n_walkers, c.dt, **kw)
+        del ham
+        hams.append(H)
+        pairs.append((a, b))
+        seeds.append(args.seed + p)
+        if p % 8 == 7:
+            print(f"[bench] {p + 1} pairs set up ({time.perf_counter() - t_gen:.0f} s)",
+                  file=sys.stderr, flush=True)
+    walkers = sum(c.n_walkers for c in cfgs)
+    # standalone: one pair at a time, direct launches
+    torch.cuda.synchronize()
+    solo = []
+    for (a, b), sd in zip(pairs, seeds):
+        t0 = time.perf_counter()
+        lib.pair_step(a, b, args.steps, seed=sd)
+        torch.cuda.synchronize()
+        solo.append(time.perf_counter() - t0)
+    print(f"[bench] standalone pairs: {sum(solo):.2f} s", file=sys.stderr, flush=True)
+    # batch: warm-up (autotune + capture), then timed graph replays
+    lib.pair_batch_step(pairs, seeds, args.warmup, lanes=args.lanes)
+    torch.cuda.synchronize()
+    print("[bench] batch warmup done", file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    tr = lib.pair_batch_step(pairs, seeds, args.steps, lanes=args.lanes)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    print(f"[bench] batch: {el:.2f} s", file=sys.stderr, flush=True)
+    choices = {}
+    for a, b in pairs:
+        for s in (a, b):
+            ch = lib.autotune(s)  # cached: returns the shapes the graph uses
+            key = f"prop{ch[3]}/fb{ch[0]}/fs{ch[1]}/ov{ch[2]}"
+            choices[key] = choices.get(key, 0) + 1
+    ws = 2 * walkers * args.steps / el
+    fl = 0.0
+    for c in cfgs:
+        P = c.M * (c.M + 1) // 2
+        for na, nb in ((c.na_a, c.nb_a), (c.na_b, c.nb_b)):
+            N = na + nb
+            fl += c.n_walkers * (4.0 * c.n_chol * N * c.M + 4.0 * c.n_chol * P
+                                 + (2 * 4.0 + c.taylor_order * 8.0) * N * c.M * c.M)
+    out = {
+        "metric": "aggregate walker-steps/s, 64 uneven correlated pairs (batched)",
+        "value": ws, "unit": "walker-steps/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": el * 1e3 / args.steps, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": prec, "data": "synthetic",
+        "config": {"workload": f"{len(cfgs)} pairs, M in [{min(c.M for c in cfgs)}, "
+                               f"{max(c.M for c in cfgs)}], n_chol = 4M, N_sigma = M//5, "
+                               f"{walkers} walkers per system in total",
+                   "lanes": args.lanes, "launch": "HIP graph replay, autotuned shapes"},
+        "standalone_sum_s": sum(solo), "batch_s": el,
+        "batch_over_standalone": el / sum(solo),
+        "contraction_tflops_per_s": fl * args.steps / el / 1e12,
+        "tuned_shapes": choices,
+        "dE_finite": bool(np.all(np.isfinite(tr[:, :, 2]))),
+    }
+    print(json.dumps(out), flush=True)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--workload", default="pair", choices=["pair", "batch"])
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--profile-steps", type=int, default=20)
+    ap.add_argument("--precision", default="bf16", choices=["bf16", "fp32", "fp64", "bf16_plain"])
+    ap.add_argument("--walkers", type=int, default=None, help="override walkers per system")
+    ap.add_argument("--pairs", type=int, default=64, help="batch workload: number of pairs")
+    ap.add_argument("--lanes", type=int, default=4, help="batch workload: stream lanes")
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-walkers", type=int, default=4)
+    ap.add_argument("--cpu-steps", type=int, default=100)
+    ap.add_argument("--no-fp64-check", action="store_true",
+                    help="skip the FP64 rerun that measures the energy-difference error")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported by this build "
+              "(walkers and pairs are independent, see the sharding notes).", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    if args.workload == "batch":
+        bench_batch(args)
+    else:
+        bench_pair(args)
 
 
 if __name__ == "__main__":
