@@ -13,7 +13,9 @@ afqmc   the walker step: force bias (Eq. 8-9), HS propagator between one-body
         halves (Eq. 3, 4, 11), overlap ratio and phaseless weight (Sec. II.A
         and the hybrid weight of Sec. II.D), mixed local energy (Eq. 7, 10),
         modified Gram-Schmidt (Sec. II.D), correlated pairs (Sec. II.B);
-        free-projection modes and a tangent-linear derivative.
+        free-projection modes.
+tangent forward-mode dE/dlambda of the mixed energy for h -> h + lambda V
+        through a window of steps (the reference for the reverse-mode adjoint).
 philox  Philox4x32-10 counter-based generator plus Box-Muller normals.
 fci     dense determinant-space Hamiltonian for tiny systems (test pins).
 
