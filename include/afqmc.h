@@ -152,6 +152,27 @@ afqmc_status afqmc_pair_batch_step(int n_pairs, const afqmc_sys* a, const afqmc_
                                    const uint64_t* seeds, int n_steps, int lanes, int flags,
                                    double* e_traces);
 
+/* Reverse-mode derivative of the mixed energy (Eq. 7, Eq. 10) with respect to
+ * a one-body perturbation h -> h + lambda V, at lambda = 0 (the system's own
+ * h).  The paper has no derivative; its correlated pairs at +-lambda are the
+ * finite differences this is checked against.
+ * afqmc_adjoint_forward advances the system n_steps exactly as afqmc_step
+ * with device fields (seed, stream id 0) would, keeping a snapshot of the
+ * walkers every checkpoint_every steps, and returns the mixed energy after the
+ * last step (measured there whatever measure_every says).  lambda enters the
+ * one-body halves P of every step of this window and h^half of the final
+ * local energy; the fields are held fixed (pathwise derivative).
+ * afqmc_adjoint_backward recomputes the window one segment at a time from
+ * the snapshots and returns dE/dlambda; the system is left in the state after
+ * the window.  V: host M x M symmetric, row-major, copied.  prec: AFQMC_FP64
+ * or AFQMC_FP32 products in the adjoint's contractions (FP64 storage and
+ * small dense algebra).  Errors: E_STATE (free mode; backward without a
+ * forward), E_SHAPE (a spin block above 48 orbitals), E_INVALID.
+ * Synchronises. */
+afqmc_status afqmc_adjoint_forward(afqmc_sys sys, const double* V, uint64_t seed, int n_steps,
+                                   int checkpoint_every, afqmc_prec prec, double* energy);
+afqmc_status afqmc_adjoint_backward(afqmc_sys sys, double* dE_dlambda);
+
 /* Launch-shape autotuner.  Times every candidate launch shape of the
  * force-bias, field-sum and overlap GEMMs (64 x 64 or 128 x 128 tiles) and
  * of the fused propagation (waves per workgroup x column blocks per wave) on

@@ -32,6 +32,7 @@ EXPORTS = [
     "afqmc_sys_info", "afqmc_checkpoint", "afqmc_restore", "afqmc_free_sys", "afqmc_free_ham",
     "afqmc_last_error", "afqmc_selftest_gemm", "afqmc_selftest_fields", "afqmc_profile_enable",
     "afqmc_profile_read", "afqmc_phase_name", "afqmc_selftest_propagate", "afqmc_autotune",
+    "afqmc_adjoint_forward", "afqmc_adjoint_backward",
 ]
 
 
@@ -53,6 +54,8 @@ _lib.afqmc_pair_step.argtypes = [_vp, _vp, C.c_uint64, C.c_int, _vp, _dp]
 _lib.afqmc_pair_batch_step.argtypes = [C.c_int, C.POINTER(_vp), C.POINTER(_vp),
                                        C.POINTER(C.c_uint64), C.c_int, C.c_int, C.c_int, _dp]
 _lib.afqmc_autotune.argtypes = [_vp, C.POINTER(C.c_int)]
+_lib.afqmc_adjoint_forward.argtypes = [_vp, _dp, C.c_uint64, C.c_int, C.c_int, C.c_int, _dp]
+_lib.afqmc_adjoint_backward.argtypes = [_vp, _dp]
 _lib.afqmc_get_walkers.argtypes = [_vp, _dp, _dp, _dp, C.POINTER(C.c_ubyte)]
 _lib.afqmc_sys_info.argtypes = [_vp] + [C.POINTER(C.c_int)] * 5 + [C.POINTER(C.c_int64)]
 _lib.afqmc_checkpoint.argtypes = [_vp, _vp, C.POINTER(C.c_size_t)]
@@ -214,6 +217,23 @@ class System:
             out[name.decode()] = (ms.value, n.value)
             i += 1
         return out
+
+    def adjoint_forward(self, V, n_steps: int, seed: int = 0, checkpoint_every: int = 10,
+                        precision: str = "fp64") -> float:
+        """Advance n_steps (device fields) keeping snapshots; returns the mixed
+        energy at the end.  See afqmc_adjoint_backward for dE/dlambda."""
+        V = _f64(V)
+        assert V.shape == (self.M, self.M)
+        e = C.c_double()
+        _check(_lib.afqmc_adjoint_forward(self._s, _ptr(V), int(seed), int(n_steps),
+                                          int(checkpoint_every), PREC[precision], C.byref(e)))
+        return e.value
+
+    def adjoint_backward(self) -> float:
+        """dE/dlambda of the last adjoint_forward window for h -> h + lambda V."""
+        d = C.c_double()
+        _check(_lib.afqmc_adjoint_backward(self._s, C.byref(d)))
+        return d.value
 
     def checkpoint(self) -> bytes:
         n = C.c_size_t()

@@ -11,6 +11,48 @@ namespace host {
 
 thread_local std::string g_err;
 
+// exp(X) for a small dense real matrix: scaling and squaring with a
+// degree-13 Taylor polynomial; with ||X / 2^s||_1 <= 1/4 the truncation is
+// below (1/4)^14 / 14! e^(1/4) < 1e-19 relative.
+void expm_host(const std::vector<double>& X, int n, std::vector<double>& out) {
+    double nrm = 0.0;
+    for (int j = 0; j < n; ++j) {
+        double c = 0.0;
+        for (int i = 0; i < n; ++i) c += fabs(X[(size_t)i * n + j]);
+        nrm = std::max(nrm, c);
+    }
+    int s = 0;
+    while (nrm > 0.25) {
+        nrm *= 0.5;
+        ++s;
+    }
+    const double sc = ldexp(1.0, -s);
+    std::vector<double> A(X.size()), term((size_t)n * n, 0.0), tmp((size_t)n * n);
+    for (size_t i = 0; i < A.size(); ++i) A[i] = X[i] * sc;
+    out.assign((size_t)n * n, 0.0);
+    for (int i = 0; i < n; ++i) out[(size_t)i * n + i] = term[(size_t)i * n + i] = 1.0;
+    auto mul = [&](const std::vector<double>& a, const std::vector<double>& b,
+                   std::vector<double>& c) {
+        std::fill(c.begin(), c.end(), 0.0);
+        for (int i = 0; i < n; ++i)
+            for (int k = 0; k < n; ++k) {
+                const double v = a[(size_t)i * n + k];
+                if (v == 0.0) continue;
+                for (int j = 0; j < n; ++j) c[(size_t)i * n + j] += v * b[(size_t)k * n + j];
+            }
+    };
+    for (int k = 1; k <= 13; ++k) {
+        mul(term, A, tmp);
+        for (size_t i = 0; i < tmp.size(); ++i) term[i] = tmp[i] / k;
+        for (size_t i = 0; i < tmp.size(); ++i) out[i] += term[i];
+    }
+    for (int q = 0; q < s; ++q) {
+        mul(out, out, tmp);
+        out.swap(tmp);
+    }
+}
+
+
 const char* const kPhaseNames[PH_COUNT] = {
     "force_bias_gemm", "fields",       "field_sum_gemm", "unpack_a", "propagate", "overlap_gemm",
     "det_theta",       "weights",      "mgs",            "exchange", "energy"};
@@ -209,47 +251,6 @@ uint64_t fnv1a(const void* data, size_t n) {
         h *= 1099511628211ull;
     }
     return h;
-}
-
-// exp(X) for a small dense real matrix: scaling and squaring with a
-// degree-13 Taylor polynomial; with ||X / 2^s||_1 <= 1/4 the truncation is
-// below (1/4)^14 / 14! e^(1/4) < 1e-19 relative.
-void expm_host(const std::vector<double>& X, int n, std::vector<double>& out) {
-    double nrm = 0.0;
-    for (int j = 0; j < n; ++j) {
-        double c = 0.0;
-        for (int i = 0; i < n; ++i) c += fabs(X[(size_t)i * n + j]);
-        nrm = std::max(nrm, c);
-    }
-    int s = 0;
-    while (nrm > 0.25) {
-        nrm *= 0.5;
-        ++s;
-    }
-    const double sc = ldexp(1.0, -s);
-    std::vector<double> A(X.size()), term((size_t)n * n, 0.0), tmp((size_t)n * n);
-    for (size_t i = 0; i < A.size(); ++i) A[i] = X[i] * sc;
-    out.assign((size_t)n * n, 0.0);
-    for (int i = 0; i < n; ++i) out[(size_t)i * n + i] = term[(size_t)i * n + i] = 1.0;
-    auto mul = [&](const std::vector<double>& a, const std::vector<double>& b,
-                   std::vector<double>& c) {
-        std::fill(c.begin(), c.end(), 0.0);
-        for (int i = 0; i < n; ++i)
-            for (int k = 0; k < n; ++k) {
-                const double v = a[(size_t)i * n + k];
-                if (v == 0.0) continue;
-                for (int j = 0; j < n; ++j) c[(size_t)i * n + j] += v * b[(size_t)k * n + j];
-            }
-    };
-    for (int k = 1; k <= 13; ++k) {
-        mul(term, A, tmp);
-        for (size_t i = 0; i < tmp.size(); ++i) term[i] = tmp[i] / k;
-        for (size_t i = 0; i < tmp.size(); ++i) out[i] += term[i];
-    }
-    for (int q = 0; q < s; ++q) {
-        mul(out, out, tmp);
-        out.swap(tmp);
-    }
 }
 
 // Solve for Theta_T = Phi_T (Phi_T^T Phi_T)^{-1} of one spin block (host,
@@ -531,6 +532,7 @@ afqmc_status afqmc_init_walkers(afqmc_ham ham, int n_alpha, int n_beta, const do
             return bail(fail(AFQMC_E_DEVICE, "h~ download"));
         for (size_t i = 0; i < ht.size(); ++i) ht[i] = ht[i] - 0.5 * l2[i] + al[i];
     }
+    s->htilde = ht;
     {
         std::vector<double> X(ht.size()), Pm;
         for (size_t i = 0; i < X.size(); ++i) X[i] = -0.5 * par->dt * ht[i];
@@ -614,6 +616,7 @@ void afqmc_free_sys(afqmc_sys s) {
                       &s->d_ov, &s->d_lnd, &s->d_exch, &s->d_el, &s->d_sums})
         b->release();
     drop_batch_plans(s->id);
+    free_adjoint(s);
     s->ham = nullptr;
     if (h) ham_unref(h);
 }

@@ -119,6 +119,8 @@ struct Profiler {
         for (auto e : pool) (void)hipEventDestroy(e);
     }
 };
+struct AdjState;
+
 }  // namespace host
 }  // namespace afq
 
@@ -145,6 +147,8 @@ struct afqmc_sys_s {
     double e_shift = 0.0;  // constant energy shift of the weight factor
     bool dead = false;
     std::vector<double> a_host;
+    std::vector<double> htilde;  // one-body part after the mean-field subtraction (host copy)
+    afq::host::AdjState* adj = nullptr;  // reverse-mode tape (adjoint.hip)
     // constant per-system data
     afq::host::DevBuf d_trialT, d_P, d_Plp, d_a, d_lhx, d_lhx_lp;
     // walker state
@@ -223,6 +227,10 @@ afqmc_status measure(afqmc_sys s, hipStream_t st);
 afqmc_status autotune(afqmc_sys s, hipStream_t st);
 // Drops every cached batch graph that references system `id`.
 void drop_batch_plans(uint64_t id);
+// Releases the reverse-mode tape of a system.
+void free_adjoint(afqmc_sys s);
+// exp(X) of a small dense real matrix (host).
+void expm_host(const std::vector<double>& X, int n, std::vector<double>& out);
 
 }  // namespace host
 }  // namespace afq

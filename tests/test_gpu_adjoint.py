@@ -1,0 +1,131 @@
+"""Reverse-mode dE/dlambda (h -> h + lambda V) of the HIP path against the
+oracle's tangent-linear derivative (FP64, 1e-9 relative) and against
+correlated finite differences run on the GPU (the same fields at +-eps)."""
+import numpy as np
+import pytest
+
+from oracle import afqmc as O
+from oracle import tangent as T
+from synth import make_hamiltonian, make_trial, perturbation
+
+from tests.gpu_helpers import banner
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def lib():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_1703_01545_amd import afqmc
+    return afqmc
+
+
+def _setup(M, nc, na, nb, hs=0):
+    ham = make_hamiltonian(M, nc, seed=hs, e_core=0.3)
+    return ham, make_trial(ham.h, na, nb)
+
+
+def _oracle(ham, trial, na, nb, dt, nw, V, seed, burn, window, oe):
+    sys0 = O.System(ham.h, ham.chol, ham.e_core, trial, na, nb, dt)
+    fields = O.PhiloxFields(seed, 0, ham.chol.shape[0])
+    wk = O.init_walkers(sys0, nw)
+    for _ in range(burn):
+        O.step(sys0, wk, fields(wk.t, nw))
+        if wk.t % oe == 0:
+            O.orthonormalize(sys0, wk)
+    E, dE, _ = T.window_tangent(sys0, V, wk, fields, window, oe)
+    return E, dE
+
+
+@pytest.mark.parametrize("dims,every", [((12, 36, 3, 3, 16), 10), ((12, 36, 3, 2, 16), 7),
+                                        ((37, 75, 7, 6, 37), 6)])
+def test_adjoint_matches_oracle_tangent(lib, dims, every):
+    M, nc, na, nb, nw = dims
+    dt, oe, seed, burn, window = 0.01, 5, 21, 15, 20
+    banner(f"adjoint vs oracle tangent {dims} every={every}")
+    ham, trial = _setup(M, nc, na, nb)
+    V = perturbation(M, seed=3, scale=0.1)
+    H = lib.Hamiltonian(ham.h, ham.chol, ham.e_core)
+    s = lib.System(H, na, nb, trial, nw, dt, ortho_every=oe, measure_every=0)
+    s.step(burn, seed=seed)
+    E = s.adjoint_forward(V, window, seed=seed, checkpoint_every=every)
+    dE = s.adjoint_backward()
+    E_o, dE_o = _oracle(ham, trial, na, nb, dt, nw, V, seed, burn, window, oe)
+    assert abs(E - E_o) <= 1e-10 * abs(E_o)
+    assert abs(dE - dE_o) <= 1e-9 * abs(dE_o), (dE, dE_o)
+    assert s.info()["step"] == burn + window
+    # a second backward over the same tape gives the same number
+    assert s.adjoint_backward() == dE
+
+
+def test_adjoint_matches_gpu_correlated_fd(lib):
+    M, nc, na, nb, nw = 24, 72, 5, 4, 48
+    dt, oe, seed, burn, window = 0.01, 5, 4, 10, 20
+    banner("adjoint vs GPU correlated FD")
+    ham, trial = _setup(M, nc, na, nb, hs=2)
+    V = perturbation(M, seed=3, scale=0.1)
+    H = lib.Hamiltonian(ham.h, ham.chol, ham.e_core)
+    base = lib.System(H, na, nb, trial, nw, dt, ortho_every=oe, measure_every=0)
+    base.step(burn, seed=seed)
+    snap = base.checkpoint()
+    E = base.adjoint_forward(V, window, seed=seed, checkpoint_every=10)
+    dE = base.adjoint_backward()
+    eps = 1e-4
+    ep = []
+    for lam in (eps, -eps):
+        Hl = lib.Hamiltonian(ham.h + lam * V, ham.chol, ham.e_core)
+        sl = lib.System(Hl, na, nb, trial, nw, dt, ortho_every=oe, measure_every=0)
+        sl.restore(snap)
+        sl.step(window, seed=seed)
+        ep.append(sl.local_energy()[2])
+    fd = (ep[0] - ep[1]) / (2 * eps)
+    assert abs(dE - fd) <= 1e-6 * abs(fd), (dE, fd, E)
+
+
+def test_adjoint_fp32_close_to_fp64(lib):
+    M, nc, na, nb, nw = 24, 72, 5, 4, 48
+    banner("adjoint fp32 vs fp64")
+    ham, trial = _setup(M, nc, na, nb, hs=2)
+    V = perturbation(M, seed=3, scale=0.1)
+    out = []
+    for prec in ("fp64", "fp32"):
+        H = lib.Hamiltonian(ham.h, ham.chol, ham.e_core)
+        s = lib.System(H, na, nb, trial, nw, 0.01, ortho_every=5, measure_every=0, precision=prec)
+        s.step(10, seed=4)
+        s.adjoint_forward(V, 20, seed=4, checkpoint_every=10, precision=prec)
+        out.append(s.adjoint_backward())
+    assert abs(out[1] - out[0]) <= 1e-3 * abs(out[0]), out
+
+
+def test_autograd_function(lib):
+    import torch
+    from paper_1703_01545_amd.autograd import AfqmcEnergy
+    banner("autograd function")
+    M, nc, na, nb, nw = 12, 36, 3, 2, 16
+    ham, trial = _setup(M, nc, na, nb)
+    V = perturbation(M, seed=3, scale=0.1)
+    H = lib.Hamiltonian(ham.h, ham.chol, ham.e_core)
+    s = lib.System(H, na, nb, trial, nw, 0.01, ortho_every=5, measure_every=0)
+    s.step(15, seed=21)
+    lam = torch.zeros((), dtype=torch.float64, requires_grad=True)
+    E = AfqmcEnergy.apply(lam, s, V, 20, 21, 10, "fp64")
+    E.backward()
+    E_o, dE_o = _oracle(ham, trial, na, nb, 0.01, nw, V, 21, 15, 20, 5)
+    assert abs(E.item() - E_o) <= 1e-10 * abs(E_o)
+    assert abs(lam.grad.item() - dE_o) <= 1e-9 * abs(dE_o)
+    with pytest.raises(ValueError):
+        AfqmcEnergy.apply(torch.ones((), dtype=torch.float64, requires_grad=True), s, V, 1)
+
+
+def test_adjoint_errors(lib):
+    banner("adjoint errors")
+    ham, trial = _setup(12, 36, 3, 2)
+    H = lib.Hamiltonian(ham.h, ham.chol, ham.e_core)
+    s = lib.System(H, 3, 2, trial, 8, 0.01, ortho_every=5, measure_every=0)
+    with pytest.raises(lib.AfqmcError) as e:
+        s.adjoint_backward()
+    assert e.value.status == lib.E_STATE
+    with pytest.raises(lib.AfqmcError) as e:
+        s.adjoint_forward(np.zeros((12, 12)), 0)
+    assert e.value.status == lib.E_INVALID
