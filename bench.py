@@ -13,6 +13,8 @@ following profiled pass of direct launches gives the per-kernel times.
 
 --workload batch: 64 uneven pairs (M in 40..240, FP32 contractions) stepped
 together from one graph, against the same pairs stepped one at a time.
+--workload adjoint: dE/dlambda through the last 100 of 500 steps at M = 100
+against correlated finite differences.
 
 Prints one JSON line.  value = walker-steps/s (2 systems x walkers x steps /
 wall time of the timed steps, inputs resident in HBM).
@@ -296,10 +298,79 @@ def bench_batch(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_adjoint(args):
+    """dE/dlambda for h -> h + lambda V at M = 100 (512 walkers): 400 steps at
+    lambda = 0, then the reverse pass through the last 100 steps (snapshots
+    every 10), FP64 and FP32, against correlated finite differences at
+    lambda = +-1e-3 on the same fields (the last 100 steps, and the whole
+    500-step run for the truncation bias of the window)."""
+    import torch
+
+    from paper_1703_01545_amd import afqmc as lib
+    from synth import config, perturbation
+
+    cfg = config(3)
+    ham = cfg.hamiltonian()
+    V = perturbation(cfg.M, seed=3, scale=0.1)
+    trial = cfg.trial_a()
+    burn, window, every, eps = 400, 100, 10, 1e-3
+    kw = dict(taylor_order=cfg.taylor_order, ortho_every=cfg.ortho_every, measure_every=0)
+    res = {}
+    for prec in ("fp64", "fp32"):
+        H = lib.Hamiltonian(ham.h, ham.chol, ham.e_core)
+        s = lib.System(H, cfg.na_a, cfg.nb_a, trial, cfg.n_walkers, cfg.dt, precision=prec, **kw)
+        s.step(burn, seed=args.seed)
+        snap = s.checkpoint()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s.step(window, seed=args.seed)
+        torch.cuda.synchronize()
+        t_fwd = time.perf_counter() - t0
+        s.restore(snap)
+        t0 = time.perf_counter()
+        E = s.adjoint_forward(V, window, seed=args.seed, checkpoint_every=every, precision=prec)
+        t_af = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        dE = s.adjoint_backward()
+        t_ab = time.perf_counter() - t0
+        fd = {}
+        for name, steps_pert in (("window", window), ("full", burn + window)):
+            e = []
+            for lam in (eps, -eps):
+                Hl = lib.Hamiltonian(ham.h + lam * V, ham.chol, ham.e_core)
+                sl = lib.System(Hl, cfg.na_a, cfg.nb_a, trial, cfg.n_walkers, cfg.dt,
+                                precision=prec, **kw)
+                if name == "window":
+                    sl.restore(snap)
+                    sl.step(window, seed=args.seed)
+                else:
+                    sl.step(burn + window, seed=args.seed)
+                e.append(sl.local_energy()[2])
+                del sl, Hl
+            fd[name] = (e[0] - e[1]) / (2 * eps)
+        res[prec] = {"E": E, "dE_dlambda": dE, "fd_window": fd["window"], "fd_full": fd["full"],
+                     "rel_err_vs_fd_window": abs(dE - fd["window"]) / abs(fd["window"]),
+                     "forward_window_s": t_fwd, "adjoint_forward_s": t_af,
+                     "adjoint_backward_s": t_ab,
+                     "adjoint_cost_over_forward": (t_af + t_ab) / t_fwd}
+        print(f"[bench] adjoint {prec}: dE={dE:.10g} fd={fd['window']:.10g}", file=sys.stderr,
+              flush=True)
+    out = {"metric": "dE_mixed/dlambda through the last 100 steps (reverse mode) vs correlated FD",
+           "value": res["fp64"]["dE_dlambda"], "unit": "Eh per unit lambda", "n_gpus": 1,
+           "steps": window, "warmup": burn, "higher_is_better": None, "vs_baseline": None,
+           "dtype": "fp64", "data": "synthetic",
+           "config": {"workload": f"M={cfg.M} n_chol={cfg.n_chol} {cfg.na_a}/{cfg.nb_a} electrons, "
+                                  f"{cfg.n_walkers} walkers, V = sym(N(0,1))/10, window {window} "
+                                  f"of {burn + window} steps, snapshots every {every}",
+                      "fd_step": eps},
+           "results": res}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--workload", default="pair", choices=["pair", "batch"])
+    ap.add_argument("--workload", default="pair", choices=["pair", "batch", "adjoint"])
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--profile-steps", type=int, default=20)
@@ -324,6 +395,8 @@ def main():
     torch.cuda.set_device(0)
     if args.workload == "batch":
         bench_batch(args)
+    elif args.workload == "adjoint":
+        bench_adjoint(args)
     else:
         bench_pair(args)
 
