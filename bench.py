@@ -55,8 +55,9 @@ def phase_flops(name, M, nc, na, nb, nw, taylor_order=6):
 
 def phase_dtype(name, prec):
     """Matrix-core input type of a phase under a precision plan."""
-    contract = {"fp64": "fp64", "fp32": "fp32", "bf16": "bf16", "bf16_plain": "bf16"}[prec]
-    prop = "fp64" if prec == "fp64" else "fp32"
+    contract = {"fp64": "fp64", "fp32": "fp32", "bf16": "bf16", "bf16_plain": "bf16",
+                "bf16x3": "bf16"}[prec]
+    prop = {"fp64": "fp64", "bf16x3": "fp32+bf16x3"}.get(prec, "fp32")
     return {"force_bias_gemm": contract, "field_sum_gemm": contract, "exchange": contract,
             "propagate": prop, "overlap_gemm": "fp64"}.get(name)
 
@@ -101,12 +102,23 @@ def _roofline(prof_a, prof_b, steps, cfg, prec):
     tot_s = (prof_a[dom][0] + prof_b[dom][0]) * 1e-3
     achieved = (fl_a * n_a + fl_b * n_b) / tot_s / 1e12
     dtype = phase_dtype(dom, prec)
-    peak = PEAK_TFLOPS[dtype]
+    # split BF16 issues three BF16 products per algorithmic product
+    split = prec in ("bf16", "bf16x3") and dtype in ("bf16", "fp32+bf16x3")
+    if dtype == "fp32+bf16x3":
+        # P halves on the FP32 matrix cores, Taylor terms on the BF16 ones: the
+        # published peaks weighted by the two parts' algorithmic FLOPs
+        K = cfg.taylor_order
+        peak = (2 * 4.0 + K * 8.0) / (2 * 4.0 / PEAK_TFLOPS["fp32"] + K * 8.0 / PEAK_TFLOPS["bf16"])
+        peak_issued = (2 * 4.0 + K * 8.0) / (2 * 4.0 / PEAK_TFLOPS["fp32"]
+                                             + 3 * K * 8.0 / PEAK_TFLOPS["bf16"])
+    else:
+        peak = PEAK_TFLOPS[dtype]
+        peak_issued = peak / 3 if split else peak
     roof = {"bound": "mfma", "kernel": dom, "kernel_dtype": dtype,
             "flops_per_launch": (fl_a * n_a + fl_b * n_b) / max(n_a + n_b, 1),
             "avg_launch_ms": tot_s * 1e3 / max(n_a + n_b, 1),
             "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
-            "traffic": None}
+            "frac_of_issue_peak": achieved / peak_issued, "traffic": None}
     return phases, roof
 
 
@@ -168,6 +180,7 @@ def bench_pair(args):
     gb.profile(False)
     alive = (ga.walkers()["alive"].mean(), gb.walkers()["alive"].mean())
     trace = np.concatenate([x for x in (tr_w, tr_t, tr_p) if len(x)])
+    tuned = [list(lib.autotune(x)) for x in (ga, gb)]  # cached: the shapes the graph used
     phases, roofline = _roofline(prof_a, prof_b, args.profile_steps, cfg, prec)
     roofline["measured_over"] = (f"{args.profile_steps} pair-steps of the same run, direct "
                                  "launches, HIP events around every launch on its stream")
@@ -188,6 +201,7 @@ def bench_pair(args):
                    "parallelism": "single GPU"},
         "roofline": roofline,
         "profiled_ms_per_step": el_prof * 1e3 / args.profile_steps,
+        "tuned_shapes": {"fb_tile/fs_tile/ov_tile/prop_shape": tuned},
         "phases_ms_per_step": {k: round(v["ms_per_step"], 4) for k, v in phases.items()},
         "alive_fraction": [float(alive[0]), float(alive[1])],
         "dE_trace_Eh": [float(x) for x in trace[:, 2]],
@@ -374,7 +388,8 @@ def main():
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--profile-steps", type=int, default=20)
-    ap.add_argument("--precision", default="bf16", choices=["bf16", "fp32", "fp64", "bf16_plain"])
+    ap.add_argument("--precision", default="bf16",
+                    choices=["bf16", "bf16x3", "fp32", "fp64", "bf16_plain"])
     ap.add_argument("--walkers", type=int, default=None, help="override walkers per system")
     ap.add_argument("--pairs", type=int, default=64, help="batch workload: number of pairs")
     ap.add_argument("--lanes", type=int, default=4, help="batch workload: stream lanes")

@@ -50,9 +50,18 @@ typedef enum {
  *   products (one-body halves and Taylor terms) in FP32.
  * AFQMC_BF16_PLAIN: L, L^half, Theta and the field coefficients stored as
  *   single BF16 values, one BF16 product per pair (fastest, least accurate).
+ * AFQMC_BF16X3: as AFQMC_BF16, and the Taylor terms of the propagator also
+ *   in split BF16 (A_w carried as hi + lo planes); the one-body halves P stay
+ *   FP32.  Needs M % 8 == 0 for the split Taylor terms (FP32 otherwise).
  * In every mode the walker determinants, overlaps, determinants,
  * Gram-Schmidt, weights and phases stay FP64. */
-typedef enum { AFQMC_FP64 = 0, AFQMC_FP32 = 1, AFQMC_BF16 = 2, AFQMC_BF16_PLAIN = 3 } afqmc_prec;
+typedef enum {
+    AFQMC_FP64 = 0,
+    AFQMC_FP32 = 1,
+    AFQMC_BF16 = 2,
+    AFQMC_BF16_PLAIN = 3,
+    AFQMC_BF16X3 = 4
+} afqmc_prec;
 
 /* Projection variant.  PHASELESS: the ph-AFQMC step of Sec. II.A with the
  * hybrid weight of Sec. II.D.  FREE: free projection (no force bias, complex
@@ -175,7 +184,8 @@ afqmc_status afqmc_adjoint_backward(afqmc_sys sys, double* dE_dlambda);
 
 /* Launch-shape autotuner.  Times every candidate launch shape of the
  * force-bias, field-sum and overlap GEMMs (64 x 64 or 128 x 128 tiles) and
- * of the fused propagation (waves per workgroup x column blocks per wave) on
+ * of the fused propagation (waves per workgroup x column blocks per wave, B
+ * prefetch or not) on
  * this system's own buffers and keeps the fastest per problem shape in a
  * process-wide table, which every later step of any system of that shape
  * uses.  All candidates sum in the same order, so tuning never changes a
@@ -231,10 +241,12 @@ afqmc_status afqmc_selftest_gemm(afqmc_prec prec, int m, int n, int k, const dou
 
 /* Kernel self-test of the fused propagation: out[w] = P T_K(A_w) P phi[w]
  * (Eq. 3 and Eq. 11, T_K the order-K Taylor polynomial of exp) with the
- * products in precision `prec` (AFQMC_FP64, else FP32), workgroup shape
- * `variant` (0: 8 waves x 2 column blocks, 1: 4 x 4, 2: 4 x 2, 3: 2 x 4,
- * 4: 4 x 1; a shape serves M <= 16 waves blocks; FP64 takes at most 2
- * blocks per wave; E_SHAPE otherwise).  phi, out:
+ * products in precision `prec` (AFQMC_FP64; AFQMC_BF16X3: Taylor terms in
+ * split BF16 and P in FP32; else FP32), workgroup shape `variant` (waves x
+ * column blocks per wave: 0: 8 x 2, 1: 4 x 2, 2: 4 x 1, 3: 2 x 2, with the
+ * next chunk of the matrix operand prefetched; 4..7: the same shapes without
+ * the prefetch, FP32 and split BF16 only; a shape serves M <= 16 waves
+ * blocks; split BF16 needs M % 8 == 0; E_SHAPE otherwise).  phi, out:
  * nw x 2 x N x M (plane 0 real, plane 1 imaginary of orbital columns); P:
  * M x M real symmetric; A: nw x 2 x M x M complex symmetric.  Host float64
  * arrays; synchronises.  For the numerics tests of the propagation kernel. */

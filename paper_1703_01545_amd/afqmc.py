@@ -22,7 +22,7 @@ if not os.path.exists(LIB_PATH):
 _lib = C.CDLL(LIB_PATH)
 
 OK, E_INVALID, E_SHAPE, E_NOMEM, E_DEVICE, E_SINGULAR, E_STATE = 0, -1, -2, -3, -4, -5, -6
-PREC = {"fp64": 0, "fp32": 1, "bf16": 2, "bf16_plain": 3}
+PREC = {"fp64": 0, "fp32": 1, "bf16": 2, "bf16_plain": 3, "bf16x3": 4}
 MODE = {"phaseless": 0, "free": 1}
 
 # Every C-ABI entry point declared in include/afqmc.h.

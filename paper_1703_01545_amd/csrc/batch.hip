@@ -238,16 +238,16 @@ afqmc_status autotune(afqmc_sys s, hipStream_t st) {
     HIPCHK(tune_gemm(2, overlap_gemm(s, s->d_phi.as<double>()), DT_F64, st, &s->tile_ov));
     std::vector<int> cands;
     for (int v = 0; v < kPropVariants; ++v)
-        if (propagate_variant_ok(v, s->M, s->tp)) cands.push_back(v);
+        if (propagate_variant_ok(v, s->M, s->tp, s->ta)) cands.push_back(v);
     if (cands.empty()) return fail(AFQMC_E_SHAPE, "no propagation shape serves this M");
     const void* Pm = s->tp == DT_F64 ? s->d_P.p : s->d_Plp.p;
     // the candidates write the step's scratch output (phinew) only
-    const ShapeKey key{3, s->M, s->N, s->nw, s->par.taylor_order, s->tp, 0, 0};
+    const ShapeKey key{3, s->M, s->N, s->nw, s->par.taylor_order, s->tp, s->ta, 0};
     HIPCHK(pick(key, cands,
                 [&](int v) {
                     return propagate(s->d_phi.as<double>(), s->d_phinew.as<double>(), Pm,
                                      s->d_Af.p, s->d_alive.as<uint8_t>(), s->nw, s->M, s->N,
-                                     s->par.taylor_order, s->tp, v, st);
+                                     s->par.taylor_order, s->tp, s->ta, v, st);
                 },
                 st, &s->prop_var));
     HIPCHK(hipStreamSynchronize(st));

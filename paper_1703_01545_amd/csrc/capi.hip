@@ -174,7 +174,7 @@ afqmc_status one_step(afqmc_sys s, uint64_t seed, uint64_t stream_id, const doub
     }
     {
         PhaseTimer pt(s, PH_UNPACK, st);
-        HIPCHK(unpack_sym(s->d_Apk.p, s->d_Af.p, s->M, 2 * s->nw, s->tp, st));
+        HIPCHK(unpack_sym(s->d_Apk.p, s->d_Af.p, s->M, 2 * s->nw, s->ta, st));
     }
     // Phi' = P T_K(A) P Phi, fused per walker
     {
@@ -182,7 +182,7 @@ afqmc_status one_step(afqmc_sys s, uint64_t seed, uint64_t stream_id, const doub
         PhaseTimer pt(s, PH_PROPAGATE, st);
         HIPCHK(propagate(s->d_phi.as<double>(), s->d_phinew.as<double>(), Pm, s->d_Af.p,
                          s->d_alive.as<uint8_t>(), s->nw, s->M, s->N, s->par.taylor_order, s->tp,
-                         s->prop_var, st));
+                         s->ta, s->prop_var, st));
     }
     if ((r = overlap_theta(s, s->d_phinew.as<double>(), st)) != AFQMC_OK) return r;
     PhaseTimer pt(s, PH_WEIGHTS, st);
@@ -358,7 +358,7 @@ afqmc_status afqmc_init_walkers(afqmc_ham ham, int n_alpha, int n_beta, const do
     if (n_walkers <= 0) return fail(AFQMC_E_INVALID, "n_walkers must be > 0");
     if (!(par->dt > 0.0) || par->taylor_order < 1 || par->ortho_every < 0 || par->measure_every < 0)
         return fail(AFQMC_E_INVALID, "bad params (dt > 0, taylor_order >= 1, periods >= 0)");
-    if (par->contract_prec < AFQMC_FP64 || par->contract_prec > AFQMC_BF16_PLAIN)
+    if (par->contract_prec < AFQMC_FP64 || par->contract_prec > AFQMC_BF16X3)
         return fail(AFQMC_E_INVALID, "bad contract_prec");
     if (par->mode != AFQMC_PHASELESS && par->mode != AFQMC_FREE)
         return fail(AFQMC_E_INVALID, "bad mode");
@@ -375,12 +375,15 @@ afqmc_status afqmc_init_walkers(afqmc_ham ham, int n_alpha, int n_beta, const do
     s->N = n_alpha + n_beta;
     s->nw = n_walkers;
     s->par = *par;
+    s->ta = DT_F64;
     switch (par->contract_prec) {
         case AFQMC_FP64: s->ts = DT_F64; s->tc = DT_F64; s->tp = DT_F64; break;
         case AFQMC_FP32: s->ts = DT_F32; s->tc = DT_F32; s->tp = DT_F32; break;
         case AFQMC_BF16: s->ts = DT_F32; s->tc = DT_SPLIT; s->tp = DT_F32; break;
+        case AFQMC_BF16X3: s->ts = DT_F32; s->tc = DT_SPLIT; s->tp = DT_F32; break;
         default: s->ts = DT_BF16; s->tc = DT_BF16; s->tp = DT_F32; break;
     }
+    s->ta = (par->contract_prec == AFQMC_BF16X3 && M % 8 == 0) ? DT_SPLIT : s->tp;
     auto bail = [&](afqmc_status r) {
         afqmc_free_sys(s);
         return r;
@@ -859,10 +862,11 @@ afqmc_status afqmc_selftest_propagate(afqmc_prec prec, int M, int N, int nw, int
         return fail(AFQMC_E_INVALID, "bad args");
     if (M > 256) return fail(AFQMC_E_SHAPE, "M <= 256");
     const DType t = prec == AFQMC_FP64 ? DT_F64 : DT_F32;
-    if (!propagate_variant_ok(variant, M, t))
-        return fail(AFQMC_E_SHAPE, "workgroup shape does not serve this M / precision");
+    const DType ta = prec == AFQMC_BF16X3 ? DT_SPLIT : t;
+    if (!propagate_variant_ok(variant, M, t, ta))
+        return fail(AFQMC_E_SHAPE, "workgroup shape or precision does not serve this M");
     const size_t nphi = (size_t)nw * 2 * N * M, nA = (size_t)nw * 2 * M * M, nP = (size_t)M * M;
-    DevBuf dphi, dout, dP, dA, dP64, dA64, dlive;
+    DevBuf dphi, dout, dP, dA, dA32, dP64, dA64, dlive;
     HIPCHK(dphi.alloc(nphi * 8));
     HIPCHK(dout.alloc(nphi * 8));
     HIPCHK(dP64.alloc(nP * 8));
@@ -875,9 +879,15 @@ afqmc_status afqmc_selftest_propagate(afqmc_prec prec, int M, int N, int nw, int
     HIPCHK(hipMemcpy(dA64.p, A, nA * 8, hipMemcpyHostToDevice));
     HIPCHK(hipMemset(dlive.p, 1, nw));
     HIPCHK(convert(dP64.as<double>(), dP.p, t, (long)nP, nullptr));
-    HIPCHK(convert(dA64.as<double>(), dA.p, t, (long)nA, nullptr));
+    if (ta == DT_SPLIT) {
+        HIPCHK(dA32.alloc(nA * 4));
+        HIPCHK(convert(dA64.as<double>(), dA32.p, DT_F32, (long)nA, nullptr));
+        HIPCHK(split_planes(dA32.as<float>(), dA.p, (long)nP, 2L * nw, nullptr));
+    } else {
+        HIPCHK(convert(dA64.as<double>(), dA.p, t, (long)nA, nullptr));
+    }
     HIPCHK(propagate(dphi.as<double>(), dout.as<double>(), dP.p, dA.p, dlive.as<uint8_t>(), nw, M,
-                     N, K, t, variant, nullptr));
+                     N, K, t, ta, variant, nullptr));
     HIPCHK(hipDeviceSynchronize());
     HIPCHK(hipMemcpy(out, dout.p, nphi * 8, hipMemcpyDeviceToHost));
     return AFQMC_OK;

@@ -143,6 +143,7 @@ struct afqmc_sys_s {
     afq::DType ts = afq::DT_F64;  // storage type of the contraction operands (L^half, Theta, X, L)
     afq::DType tc = afq::DT_F64;  // compute type of the contractions (DT_SPLIT: split BF16)
     afq::DType tp = afq::DT_F64;  // propagator product type (FP64 or FP32)
+    afq::DType ta = afq::DT_F64;  // Taylor operand A_w: tp, or DT_SPLIT (hi/lo BF16 planes)
     int64_t t = 0;
     double e_shift = 0.0;  // constant energy shift of the weight factor
     bool dead = false;

@@ -60,22 +60,28 @@ struct Gemm {
 hipError_t gemm(const Gemm& g, DType compute, hipStream_t s);
 
 // Packed upper triangle (P = M(M+1)/2 per plane) -> full symmetric M x M,
-// for `planes` consecutive planes (types DT_F64 / DT_F32).
+// for `planes` consecutive planes (types DT_F64 / DT_F32; DT_SPLIT: FP32
+// input, hi/lo BF16 output planes [plane][hi, lo][M][M]).
 hipError_t unpack_sym(const void* pk, void* full, int M, int planes, DType t, hipStream_t s);
+// FP32 planes of n elements -> hi/lo BF16 planes [plane][hi, lo][n].
+hipError_t split_planes(const float* in, void* out, long n, long planes, hipStream_t s);
 
 // Fused propagation of every walker (Eq. 3 and Eq. 11):
 //   Phi_out[w] = P T_K(A_w) P Phi[w],  T_K(A) = sum_{n <= K} A^n / n!
 // phi, phi_out: FP64 walker blocks [w][plane][N][M]; Pm: M x M real
 // symmetric, Af: [w][plane][M][M] complex symmetric, both in type t
-// (DT_F64 or DT_F32, the product precision).  Frozen walkers (live == 0)
+// (DT_F64 or DT_F32, the product precision).  ta: type of Af, equal to t,
+// or DT_SPLIT with t == DT_F32 (Taylor terms in split BF16, Af as hi/lo
+// planes [w][plane][hi, lo][M][M], M % 8 == 0).  Frozen walkers (live == 0)
 // are copied unchanged.  M <= 256.  `variant` selects the workgroup shape
-// (waves per workgroup x column blocks per wave, see kPropShapes); every
-// variant gives bitwise the same result, 0 is the default.
-constexpr int kPropVariants = 5;
-bool propagate_variant_ok(int variant, int M, DType t);
+// (waves per workgroup x column blocks per wave, with or without B prefetch;
+// see kPropShapes); every variant gives bitwise the same result, 0 is the
+// default.
+constexpr int kPropVariants = 8;
+bool propagate_variant_ok(int variant, int M, DType t, DType ta);
 hipError_t propagate(const double* phi, double* phi_out, const void* Pm, const void* Af,
-                     const uint8_t* live, int nw, int M, int N, int K, DType t, int variant,
-                     hipStream_t s);
+                     const uint8_t* live, int nw, int M, int N, int K, DType t, DType ta,
+                     int variant, hipStream_t s);
 
 // Exchange partial sums of the mixed local energy:
 //   out[(w * 2 + spin) * n_gtiles + gt] = sum over gamma in tile gt of

@@ -98,7 +98,7 @@ __device__ __forceinline__ void bload4(__amdgpu_buffer_rsrc_t r, int off, double
 // buffer load of B per chunk, straight into registers (each B column block
 // belongs to one wave, so no staging and no barrier inside the pass).  B
 // loads run one chunk ahead.  Columns >= M of B multiply zero columns of S.
-template <typename T, int MAXB, int NPB>
+template <typename T, int MAXB, int NPB, bool PF>
 __device__ __forceinline__ void pass(__amdgpu_buffer_rsrc_t rb, int M, int Mp, int MB,
                                      const T* S, int SPT, const int* cb,
                                      typename AccT<T>::v (&acc)[MAXB][2]) {
@@ -116,19 +116,24 @@ __device__ __forceinline__ void pass(__amdgpu_buffer_rsrc_t rb, int M, int Mp, i
         acc[s][0] = acc[s][1] = typename AccT<T>::v{0, 0, 0, 0};
     }
     T bc[MAXB][NPB][4], bn[MAXB][NPB][4];
-#pragma unroll
-    for (int s = 0; s < MAXB; ++s)
-        if (cb[s] < MB)
-#pragma unroll
-            for (int p = 0; p < NPB; ++p) bload4(rb, boff[s] + p * plane_b, bc[s][p]);
-    for (int k0 = 0; k0 < Mp; k0 += 16) {
-        const bool more = k0 + 16 < Mp;
-        const int kb = (k0 + 16) * (int)sizeof(T);
+    // Loads are unconditional (straight-line code lets the compiler count
+    // them exactly): blocks >= MB read through an out-of-range offset (zeros)
+    // and the prefetch past the last chunk reads values that are never used.
+    // PF: B runs one chunk ahead; else each chunk loads its own B (fewer
+    // registers, more waves to hide the latency).
+    if constexpr (PF) {
 #pragma unroll
         for (int s = 0; s < MAXB; ++s)
-            if (more && cb[s] < MB)
 #pragma unroll
-                for (int p = 0; p < NPB; ++p) bload4(rb, boff[s] + kb + p * plane_b, bn[s][p]);
+            for (int p = 0; p < NPB; ++p) bload4(rb, boff[s] + p * plane_b, bc[s][p]);
+    }
+    for (int k0 = 0; k0 < Mp; k0 += 16) {
+        const int kb = (k0 + (PF ? 16 : 0)) * (int)sizeof(T);
+#pragma unroll
+        for (int s = 0; s < MAXB; ++s)
+#pragma unroll
+            for (int p = 0; p < NPB; ++p)
+                bload4(rb, boff[s] + kb + p * plane_b, PF ? bn[s][p] : bc[s][p]);
         T sr[4], si[4];
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
@@ -151,12 +156,14 @@ __device__ __forceinline__ void pass(__amdgpu_buffer_rsrc_t rb, int M, int Mp, i
                 }
             }
         }
+        if constexpr (PF) {
 #pragma unroll
-        for (int s = 0; s < MAXB; ++s)
+            for (int s = 0; s < MAXB; ++s)
 #pragma unroll
-            for (int p = 0; p < NPB; ++p)
+                for (int p = 0; p < NPB; ++p)
 #pragma unroll
-                for (int e = 0; e < 4; ++e) bc[s][p][e] = bn[s][p][e];
+                    for (int e = 0; e < 4; ++e) bc[s][p][e] = bn[s][p][e];
+        }
     }
 }
 
@@ -165,7 +172,7 @@ __device__ __forceinline__ void pass(__amdgpu_buffer_rsrc_t rb, int M, int Mp, i
 // walker run back to back on one XCD and A_w streams through its L2; the
 // assignment of column blocks to waves rotates between workgroups so the
 // waves holding an extra block land on different SIMDs.
-template <typename T, int NWAVE, int MAXB>
+template <typename T, int NWAVE, int MAXB, bool PF>
 __global__ __launch_bounds__(64 * NWAVE, 2) void k_propagate(
     const double* __restrict__ phi, double* __restrict__ phi_out, const T* __restrict__ Pm,
     const T* __restrict__ Af, const uint8_t* __restrict__ live, int nw, int M, int N, int K,
@@ -183,7 +190,8 @@ __global__ __launch_bounds__(64 * NWAVE, 2) void k_propagate(
     const long L = (long)(blockIdx.x % 8) * per + blockIdx.x / 8;
     if (L >= nblk) return;
     const int w = (int)(L / nrb), row0 = (int)(L % nrb) * 16;
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // wave-uniform
     const long NM = (long)N * M;
     const double* src = phi + (long)w * 2 * NM;
     double* dst = phi_out + (long)w * 2 * NM;
@@ -225,7 +233,7 @@ __global__ __launch_bounds__(64 * NWAVE, 2) void k_propagate(
         }
     };
     // first one-body half
-    pass<T, MAXB, 1>(rP, M, Mp, MB, S, SPT, cb, acc);
+    pass<T, MAXB, 1, PF>(rP, M, Mp, MB, S, SPT, cb, acc);
     __syncthreads();
 #pragma unroll
     for (int s = 0; s < MAXB; ++s) {
@@ -236,7 +244,7 @@ __global__ __launch_bounds__(64 * NWAVE, 2) void k_propagate(
     __syncthreads();
     // Taylor series of exp(A): term_n = A term_{n-1} / n, z = sum of terms
     for (int n = 1; n <= K; ++n) {
-        pass<T, MAXB, 2>(rA, M, Mp, MB, S, SPT, cb, acc);
+        pass<T, MAXB, 2, PF>(rA, M, Mp, MB, S, SPT, cb, acc);
         __syncthreads();
         const T inv = (T)(1.0 / n);
 #pragma unroll
@@ -255,7 +263,7 @@ __global__ __launch_bounds__(64 * NWAVE, 2) void k_propagate(
         __syncthreads();
     }
     // second one-body half, FP64 result
-    pass<T, MAXB, 1>(rP, M, Mp, MB, S, SPT, cb, acc);
+    pass<T, MAXB, 1, PF>(rP, M, Mp, MB, S, SPT, cb, acc);
 #pragma unroll
     for (int s = 0; s < MAXB; ++s) {
         const int col = cb[s] * 16 + (lane & 15);
@@ -272,7 +280,308 @@ __global__ __launch_bounds__(64 * NWAVE, 2) void k_propagate(
     }
 }
 
-template <typename T, int NWAVE, int MAXB>
+// ---------------------------------------------------------------------------
+// Split-BF16 Taylor terms.  A_w is stored as hi/lo BF16 planes
+// ([w][re, im][hi, lo][M][M]) and the state S as four BF16 planes (re hi,
+// re lo, im hi, im lo); each real product is three BF16 MFMAs 16x16x32
+// (hi hi + hi lo + lo hi) with FP32 accumulation.  The one-body halves P
+// stay FP32 (P is close to the identity, so its rounding is not scaled down).
+
+typedef unsigned int u4v __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ bf8 neg8(bf8 x) {
+    return __builtin_bit_cast(bf8, __builtin_bit_cast(u4v, x) ^ 0x80008000u);
+}
+__device__ __forceinline__ bf8 bload8(__amdgpu_buffer_rsrc_t r, int off) {
+    return __builtin_bit_cast(bf8, __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0));
+}
+
+// acc[s] = S x A_w^T for this wave's column blocks; K in chunks of 32, lane
+// group g supplying k = k0 + 8 g + e (e < 8) for both operands.
+template <int MAXB, bool PF>
+__device__ __forceinline__ void pass_split(__amdgpu_buffer_rsrc_t rb, int M, int Mp, int MB,
+                                           const bf16_t* Sb, int SPB, const int* cb,
+                                           f4 (&acc)[MAXB][2]) {
+    const int lane = threadIdx.x & 63;
+    const int g = lane >> 4, li = lane & 15;
+    const int hl_b = M * M * 2;      // hi -> lo plane, bytes
+    const int pl_b = 2 * hl_b;       // re -> im plane
+    const long spl = 16L * SPB;
+    const bf16_t* s0 = Sb + li * SPB + 8 * g;
+    int boff[MAXB];
+#pragma unroll
+    for (int s = 0; s < MAXB; ++s) {
+        const int m = cb[s] * 16 + li;
+        boff[s] = m < M ? (m * M + 8 * g) * 2 : kOutOfRange;
+        acc[s][0] = acc[s][1] = f4{0, 0, 0, 0};
+    }
+    bf8 bc[MAXB][4], bn[MAXB][4];  // re hi, re lo, im hi, im lo
+    // unconditional loads and the PF choice as in pass()
+    if constexpr (PF) {
+#pragma unroll
+        for (int s = 0; s < MAXB; ++s) {
+            bc[s][0] = bload8(rb, boff[s]);
+            bc[s][1] = bload8(rb, boff[s] + hl_b);
+            bc[s][2] = bload8(rb, boff[s] + pl_b);
+            bc[s][3] = bload8(rb, boff[s] + pl_b + hl_b);
+        }
+    }
+    for (int k0 = 0; k0 < Mp; k0 += 32) {
+        const int kb = (k0 + (PF ? 32 : 0)) * 2;
+#pragma unroll
+        for (int s = 0; s < MAXB; ++s) {
+            bf8* d = PF ? bn[s] : bc[s];
+            d[0] = bload8(rb, boff[s] + kb);
+            d[1] = bload8(rb, boff[s] + kb + hl_b);
+            d[2] = bload8(rb, boff[s] + kb + pl_b);
+            d[3] = bload8(rb, boff[s] + kb + pl_b + hl_b);
+        }
+        const bf8 rh = *reinterpret_cast<const bf8*>(s0 + k0);
+        const bf8 rl = *reinterpret_cast<const bf8*>(s0 + spl + k0);
+        const bf8 ih = *reinterpret_cast<const bf8*>(s0 + 2 * spl + k0);
+        const bf8 il = *reinterpret_cast<const bf8*>(s0 + 3 * spl + k0);
+        const bf8 nh = neg8(ih), nl = neg8(il);
+#pragma unroll
+        for (int s = 0; s < MAXB; ++s) {
+            if (cb[s] >= MB) continue;  // wave-uniform
+            f4 ar = acc[s][0], ai = acc[s][1];
+            // re += Sr Ar - Si Ai
+            ar = mma8(rl, bc[s][0], ar);
+            ar = mma8(rh, bc[s][1], ar);
+            ar = mma8(rh, bc[s][0], ar);
+            ar = mma8(nl, bc[s][2], ar);
+            ar = mma8(nh, bc[s][3], ar);
+            ar = mma8(nh, bc[s][2], ar);
+            // im += Sr Ai + Si Ar
+            ai = mma8(rl, bc[s][2], ai);
+            ai = mma8(rh, bc[s][3], ai);
+            ai = mma8(rh, bc[s][2], ai);
+            ai = mma8(il, bc[s][0], ai);
+            ai = mma8(ih, bc[s][1], ai);
+            ai = mma8(ih, bc[s][0], ai);
+            acc[s][0] = ar;
+            acc[s][1] = ai;
+        }
+        if constexpr (PF) {
+#pragma unroll
+            for (int s = 0; s < MAXB; ++s)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) bc[s][q] = bn[s][q];
+        }
+    }
+}
+
+// As k_propagate (FP32 products) with the Taylor terms in split BF16.  The
+// FP32 state (for the P halves) and the BF16 planes (for the Taylor terms)
+// share the LDS buffer; Mp is M rounded up to 32, and columns >= M of both
+// views are kept zero.
+template <int NWAVE, int MAXB, bool PF>
+__global__ __launch_bounds__(64 * NWAVE, 2) void k_propagate_split(
+    const double* __restrict__ phi, double* __restrict__ phi_out, const float* __restrict__ Pm,
+    const bf16_t* __restrict__ Af, const uint8_t* __restrict__ live, int nw, int M, int N, int K,
+    int nrb) {
+    extern __shared__ __attribute__((aligned(16))) char smem_raw[];
+    float* S = reinterpret_cast<float*>(smem_raw);
+    bf16_t* Sb = reinterpret_cast<bf16_t*>(smem_raw);
+    constexpr int NT = 64 * NWAVE;
+    const int Mp = (M + 31) / 32 * 32;
+    const int MB = (M + 15) / 16;
+    const int SPT = Mp + 4, SPB = Mp + 8;
+    const long splane = 16L * SPT, bplane = 16L * SPB;
+    const long nblk = (long)nw * nrb;
+    const long per = (nblk + 7) / 8;
+    const long L = (long)(blockIdx.x % 8) * per + blockIdx.x / 8;
+    if (L >= nblk) return;
+    const int w = (int)(L / nrb), row0 = (int)(L % nrb) * 16;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // wave-uniform
+    const long NM = (long)N * M;
+    const double* src = phi + (long)w * 2 * NM;
+    double* dst = phi_out + (long)w * 2 * NM;
+    const int nrow = min(16, N - row0);
+    if (nrow <= 0) return;
+    if (!live[w]) {
+        for (int e = tid; e < 2 * nrow * M; e += NT) {
+            const int p = e / (nrow * M), rem = e % (nrow * M);
+            const long o = p * NM + (long)(row0 + rem / M) * M + rem % M;
+            dst[o] = src[o];
+        }
+        return;
+    }
+    for (int e = tid; e < 2 * 16 * Mp; e += NT) {
+        const int p = e / (16 * Mp), rem = e % (16 * Mp);
+        const int r = rem / Mp, m = rem % Mp;
+        double v = 0.0;
+        if (r < nrow && m < M) v = src[p * NM + (long)(row0 + r) * M + m];
+        S[p * splane + r * SPT + m] = (float)v;
+    }
+    const int vw = (wave + (int)(L % NWAVE)) % NWAVE;
+    int cb[MAXB];
+#pragma unroll
+    for (int s = 0; s < MAXB; ++s) cb[s] = vw + s * NWAVE;
+    __syncthreads();
+    f4 acc[MAXB][2], z[MAXB][2];
+    const long Aplane = (long)M * M;
+    const __amdgpu_buffer_rsrc_t rP = make_rsrc(Pm, Aplane);
+    const __amdgpu_buffer_rsrc_t rA = make_rsrc(Af + (long)w * 4 * Aplane, 4 * Aplane);
+    const int li = lane & 15;
+    // zero the BF16 view's columns no block writes (MB * 16 .. Mp)
+    auto zero_b = [&]() {
+        const int pad = Mp - MB * 16;
+        for (int e = tid; e < 4 * 16 * pad; e += NT) {
+            const int q = e / (16 * pad), rem = e % (16 * pad);
+            Sb[q * bplane + (rem / pad) * SPB + MB * 16 + rem % pad] = (bf16_t)0.0f;
+        }
+    };
+    auto zero_f = [&]() {
+        const int pad = Mp - MB * 16;
+        for (int e = tid; e < 2 * 16 * pad; e += NT) {
+            const int q = e / (16 * pad), rem = e % (16 * pad);
+            S[q * splane + (rem / pad) * SPT + MB * 16 + rem % pad] = 0.0f;
+        }
+    };
+    auto put_b = [&](int s, const f4& vr, const f4& vi) {
+        const int col = cb[s] * 16 + li;
+        const bool ok = col < M;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int off = acc_row<float>(lane, r) * SPB + col;
+            const float xr = ok ? vr[r] : 0.0f, xi = ok ? vi[r] : 0.0f;
+            const bf16_t hr = to_bf(xr), hi = to_bf(xi);
+            Sb[off] = hr;
+            Sb[bplane + off] = to_bf(xr - (float)hr);
+            Sb[2 * bplane + off] = hi;
+            Sb[3 * bplane + off] = to_bf(xi - (float)hi);
+        }
+    };
+    auto put_f = [&](int s, const f4& vr, const f4& vi) {
+        const int col = cb[s] * 16 + li;
+        const bool ok = col < M;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int off = acc_row<float>(lane, r) * SPT + col;
+            S[off] = ok ? vr[r] : 0.0f;
+            S[splane + off] = ok ? vi[r] : 0.0f;
+        }
+    };
+    pass<float, MAXB, 1, PF>(rP, M, Mp, MB, S, SPT, cb, acc);
+    __syncthreads();
+    zero_b();
+#pragma unroll
+    for (int s = 0; s < MAXB; ++s) {
+        z[s][0] = acc[s][0];
+        z[s][1] = acc[s][1];
+        if (cb[s] < MB) put_b(s, acc[s][0], acc[s][1]);
+    }
+    __syncthreads();
+    for (int n = 1; n <= K; ++n) {
+        pass_split<MAXB, PF>(rA, M, Mp, MB, Sb, SPB, cb, acc);
+        __syncthreads();
+        const float inv = 1.0f / n;
+        if (n == K) zero_f();
+#pragma unroll
+        for (int s = 0; s < MAXB; ++s) {
+            acc[s][0] *= inv;
+            acc[s][1] *= inv;
+            z[s][0] += acc[s][0];
+            z[s][1] += acc[s][1];
+            if (cb[s] < MB) {
+                if (n == K)
+                    put_f(s, z[s][0], z[s][1]);
+                else
+                    put_b(s, acc[s][0], acc[s][1]);
+            }
+        }
+        __syncthreads();
+    }
+    if (K == 0) {  // no Taylor terms: back to the FP32 view
+        zero_f();
+#pragma unroll
+        for (int s = 0; s < MAXB; ++s)
+            if (cb[s] < MB) put_f(s, z[s][0], z[s][1]);
+        __syncthreads();
+    }
+    pass<float, MAXB, 1, PF>(rP, M, Mp, MB, S, SPT, cb, acc);
+#pragma unroll
+    for (int s = 0; s < MAXB; ++s) {
+        const int col = cb[s] * 16 + li;
+        if (cb[s] >= MB || col >= M) continue;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int row = acc_row<float>(lane, r);
+            if (row < nrow) {
+                const long o = (long)(row0 + row) * M + col;
+                dst[o] = (double)acc[s][0][r];
+                dst[NM + o] = (double)acc[s][1][r];
+            }
+        }
+    }
+}
+
+template <int NWAVE, int MAXB, bool PF>
+hipError_t launch_prop_split(const double* phi, double* phi_out, const void* Pm, const void* Af,
+                             const uint8_t* live, int nw, int M, int N, int K, hipStream_t s) {
+    const int Mp = (M + 31) / 32 * 32;
+    const size_t shm = 4 * 16 * (size_t)(Mp + 8) * sizeof(bf16_t);  // >= the FP32 view
+    const int nrb = (N + 15) / 16;
+    const long nblk = (long)nw * nrb;
+    const long grid = ((nblk + 7) / 8) * 8;
+    hipLaunchKernelGGL((k_propagate_split<NWAVE, MAXB, PF>), dim3(grid), dim3(64 * NWAVE), shm, s,
+                       phi, phi_out, (const float*)Pm, (const bf16_t*)Af, live, nw, M, N, K, nrb);
+    return hipGetLastError();
+}
+
+// x -> (hi, lo) BF16 planes: out[plane][hi, lo][n]
+__global__ void k_split_planes(const float* __restrict__ in, bf16_t* __restrict__ out, long n,
+                               long planes) {
+    const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n * planes) return;
+    const long pl = e / n, i = e % n;
+    const float v = in[e];
+    const bf16_t h = to_bf(v);
+    out[pl * 2 * n + i] = h;
+    out[pl * 2 * n + n + i] = to_bf(v - (float)h);
+}
+
+// Packed upper triangle (FP32) -> full symmetric M x M as hi/lo BF16 planes
+// ([plane][hi, lo][M][M]).
+__global__ __launch_bounds__(256) void k_unpack_split(const float* __restrict__ pk,
+                                                      bf16_t* __restrict__ full, int M) {
+    __shared__ float tile[32][33];
+    const long P = (long)M * (M + 1) / 2;
+    const long plane = blockIdx.y;
+    const int ti = blockIdx.x;
+    const float* src = pk + plane * P;
+    bf16_t* hi = full + plane * 2 * (long)M * M;
+    bf16_t* lo = hi + (long)M * M;
+    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+    const int nt = (M + 31) / 32;
+    auto put = [&](long o, float v) {
+        const bf16_t h = to_bf(v);
+        hi[o] = h;
+        lo[o] = to_bf(v - (float)h);
+    };
+    for (int tj = ti; tj < nt; ++tj) {
+        for (int r = ty; r < 32; r += 8) {
+            const int i = ti * 32 + r, j = tj * 32 + tx;
+            float v = 0.0f;
+            if (i < M && j < M && j >= i) v = src[(long)i * (2 * M - i + 1) / 2 + (j - i)];
+            tile[r][tx] = v;
+        }
+        __syncthreads();
+        for (int r = ty; r < 32; r += 8) {
+            const int i = ti * 32 + r, j = tj * 32 + tx;
+            if (i < M && j < M) put((long)i * M + j, (j >= i) ? tile[r][tx] : tile[tx][r]);
+            if (tj != ti) {
+                const int jm = tj * 32 + r, im = ti * 32 + tx;
+                if (jm < M && im < M) put((long)jm * M + im, tile[tx][r]);
+            }
+        }
+        __syncthreads();
+    }
+}
+
+template <typename T, int NWAVE, int MAXB, bool PF>
 hipError_t launch_prop(const double* phi, double* phi_out, const void* Pm, const void* Af,
                        const uint8_t* live, int nw, int M, int N, int K, hipStream_t s) {
     const int Mp = (M + 15) / 16 * 16;
@@ -280,12 +589,19 @@ hipError_t launch_prop(const double* phi, double* phi_out, const void* Pm, const
     const int nrb = (N + 15) / 16;
     const long nblk = (long)nw * nrb;
     const long grid = ((nblk + 7) / 8) * 8;
-    hipLaunchKernelGGL((k_propagate<T, NWAVE, MAXB>), dim3(grid), dim3(64 * NWAVE), shm, s, phi,
+    hipLaunchKernelGGL((k_propagate<T, NWAVE, MAXB, PF>), dim3(grid), dim3(64 * NWAVE), shm, s, phi,
                        phi_out, (const T*)Pm, (const T*)Af, live, nw, M, N, K, nrb);
     return hipGetLastError();
 }
 
 }  // namespace
+
+hipError_t split_planes(const float* in, void* out, long n, long planes, hipStream_t s) {
+    if (n * planes <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_split_planes, dim3((unsigned)((n * planes + 255) / 256)), dim3(256), 0, s,
+                       in, (bf16_t*)out, n, planes);
+    return hipGetLastError();
+}
 
 hipError_t unpack_sym(const void* pk, void* full, int M, int planes, DType t, hipStream_t s) {
     if (planes <= 0) return hipSuccess;
@@ -296,49 +612,75 @@ hipError_t unpack_sym(const void* pk, void* full, int M, int planes, DType t, hi
     else if (t == DT_F32)
         hipLaunchKernelGGL(k_unpack<float>, grid, dim3(256), 0, s, (const float*)pk, (float*)full,
                            M);
+    else if (t == DT_SPLIT)
+        hipLaunchKernelGGL(k_unpack_split, grid, dim3(256), 0, s, (const float*)pk,
+                           (bf16_t*)full, M);
     else
         return hipErrorInvalidValue;
     return hipGetLastError();
 }
 
-// Workgroup shapes (waves, column blocks per wave): a shape serves M up to
-// 16 * waves * blocks.  Fewer waves per workgroup leave no idle waves at
-// small M; more waves shorten each wave's share at large M.
+// Workgroup shapes (waves, column blocks per wave, B prefetch): a shape
+// serves M up to 16 * waves * blocks.  Fewer waves per workgroup leave no
+// idle waves at small M; more waves shorten each wave's share at large M;
+// without the prefetch a wave holds fewer registers and more waves fit.
 namespace {
 struct PropShape {
     int waves, blocks;
+    bool pf;
 };
-constexpr PropShape kPropShapes[kPropVariants] = {{8, 2}, {4, 4}, {4, 2}, {2, 4}, {4, 1}};
+constexpr PropShape kPropShapes[kPropVariants] = {{8, 2, true},  {4, 2, true},  {4, 1, true},
+                                                  {2, 2, true},  {8, 2, false}, {4, 2, false},
+                                                  {4, 1, false}, {2, 2, false}};
 }  // namespace
 
-bool propagate_variant_ok(int v, int M, DType t) {
+bool propagate_variant_ok(int v, int M, DType t, DType ta) {
     if (v < 0 || v >= kPropVariants || M <= 0) return false;
     if (t != DT_F64 && t != DT_F32) return false;
+    if (ta != t && !(t == DT_F32 && ta == DT_SPLIT && M % 8 == 0)) return false;
     const PropShape p = kPropShapes[v];
-    if (t == DT_F64 && p.blocks > 2) return false;  // register budget of the FP64 state
+    if (t == DT_F64 && !p.pf) return false;  // the FP64 path keeps the prefetching shapes
     return (M + 15) / 16 <= p.waves * p.blocks;
 }
 
 hipError_t propagate(const double* phi, double* phi_out, const void* Pm, const void* Af,
-                     const uint8_t* live, int nw, int M, int N, int K, DType t, int variant,
-                     hipStream_t s) {
+                     const uint8_t* live, int nw, int M, int N, int K, DType t, DType ta,
+                     int variant, hipStream_t s) {
     if (nw <= 0) return hipSuccess;
     if (M > 256 || M <= 0 || N <= 0) return hipErrorInvalidValue;
-    if (!propagate_variant_ok(variant, M, t)) return hipErrorInvalidValue;
-#define AFQ_P(V, T_, W_, B_) \
-    if (variant == V) return launch_prop<T_, W_, B_>(phi, phi_out, Pm, Af, live, nw, M, N, K, s);
+    if (!propagate_variant_ok(variant, M, t, ta)) return hipErrorInvalidValue;
+#define AFQ_P(V, T_, W_, B_, F_)                                                          \
+    if (variant == V)                                                                      \
+        return launch_prop<T_, W_, B_, F_>(phi, phi_out, Pm, Af, live, nw, M, N, K, s);
+#define AFQ_S(V, W_, B_, F_)                                                               \
+    if (variant == V)                                                                      \
+        return launch_prop_split<W_, B_, F_>(phi, phi_out, Pm, Af, live, nw, M, N, K, s);
     if (t == DT_F64) {
-        AFQ_P(0, double, 8, 2)
-        AFQ_P(2, double, 4, 2)
-        AFQ_P(4, double, 4, 1)
+        AFQ_P(0, double, 8, 2, true)
+        AFQ_P(1, double, 4, 2, true)
+        AFQ_P(2, double, 4, 1, true)
+        AFQ_P(3, double, 2, 2, true)
+    } else if (ta == DT_SPLIT) {
+        AFQ_S(0, 8, 2, true)
+        AFQ_S(1, 4, 2, true)
+        AFQ_S(2, 4, 1, true)
+        AFQ_S(3, 2, 2, true)
+        AFQ_S(4, 8, 2, false)
+        AFQ_S(5, 4, 2, false)
+        AFQ_S(6, 4, 1, false)
+        AFQ_S(7, 2, 2, false)
     } else {
-        AFQ_P(0, float, 8, 2)
-        AFQ_P(1, float, 4, 4)
-        AFQ_P(2, float, 4, 2)
-        AFQ_P(3, float, 2, 4)
-        AFQ_P(4, float, 4, 1)
+        AFQ_P(0, float, 8, 2, true)
+        AFQ_P(1, float, 4, 2, true)
+        AFQ_P(2, float, 4, 1, true)
+        AFQ_P(3, float, 2, 2, true)
+        AFQ_P(4, float, 8, 2, false)
+        AFQ_P(5, float, 4, 2, false)
+        AFQ_P(6, float, 4, 1, false)
+        AFQ_P(7, float, 2, 2, false)
     }
 #undef AFQ_P
+#undef AFQ_S
     return hipErrorInvalidValue;
 }
 

@@ -256,11 +256,14 @@ def test_errors(lib):
     assert st == lib.E_INVALID
 
 
-@pytest.mark.parametrize("dims", [(12, 6, 3), (37, 13, 5), (200, 80, 3), (64, 16, 2), (41, 17, 4)])
-@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("dims", [(12, 6, 3), (37, 13, 5), (200, 80, 3), (64, 16, 2), (41, 17, 4),
+                                  (96, 33, 2), (256, 20, 2)])
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3"])
 def test_propagation_kernel(lib, dims, prec):
     """Fused P T_K(A) P kernel vs the same products in numpy (K = 6)."""
     M, N, nw = dims
+    if prec == "bf16x3" and M % 8:
+        pytest.skip("split-BF16 Taylor terms need M % 8 == 0")
     banner(f"propagate kernel {prec} {dims}")
     rng = np.random.default_rng(M + N)
     phi = rng.standard_normal((nw, M, N)) + 1j * rng.standard_normal((nw, M, N))
@@ -277,16 +280,19 @@ def test_propagation_kernel(lib, dims, prec):
             term = A[k] @ term / n
             acc = acc + term
         ref[k] = P @ acc
-    tol = 1e-12 if prec == "fp64" else 2e-5
+    tol = {"fp64": 1e-12, "fp32": 2e-5, "bf16x3": 5e-5}[prec]
     assert rel(got, ref) < tol
 
 
-@pytest.mark.parametrize("dims", [(12, 6, 3), (37, 13, 5), (130, 40, 3), (200, 80, 2), (64, 17, 2)])
-@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("dims", [(12, 6, 3), (37, 13, 5), (130, 40, 3), (200, 80, 2), (64, 17, 2),
+                                  (128, 24, 2)])
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3"])
 def test_propagation_shapes_bitwise(lib, dims, prec):
     """Every workgroup shape the autotuner may pick gives bitwise the result
     of the default shape (same summation order per output element)."""
     M, N, nw = dims
+    if prec == "bf16x3" and M % 8:
+        pytest.skip("split-BF16 Taylor terms need M % 8 == 0")
     banner(f"propagate shapes {prec} {dims}")
     rng = np.random.default_rng(7 * M + N)
     phi = rng.standard_normal((nw, M, N)) + 1j * rng.standard_normal((nw, M, N))
@@ -295,10 +301,11 @@ def test_propagation_shapes_bitwise(lib, dims, prec):
     A = (rng.standard_normal((nw, M, M)) + 1j * rng.standard_normal((nw, M, M))) * (0.4 / np.sqrt(M))
     A = 0.5 * (A + np.swapaxes(A, 1, 2))
     base = lib.selftest_propagate(phi, P, A, 6, prec, variant=0)
-    shapes = {0: (8, 2), 1: (4, 4), 2: (4, 2), 3: (2, 4), 4: (4, 1)}
+    shapes = {0: (8, 2, 1), 1: (4, 2, 1), 2: (4, 1, 1), 3: (2, 2, 1), 4: (8, 2, 0), 5: (4, 2, 0),
+              6: (4, 1, 0), 7: (2, 2, 0)}
     ran = 0
-    for v, (waves, blocks) in shapes.items():
-        ok = (M + 15) // 16 <= waves * blocks and not (prec == "fp64" and blocks > 2)
+    for v, (waves, blocks, pf) in shapes.items():
+        ok = (M + 15) // 16 <= waves * blocks and not (prec == "fp64" and not pf)
         if not ok:
             with pytest.raises(lib.AfqmcError):
                 lib.selftest_propagate(phi, P, A, 6, prec, variant=v)
