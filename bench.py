@@ -47,7 +47,6 @@ def phase_flops(name, M, nc, na, nb, nw, taylor_order=6):
         "field_sum_gemm": 4.0 * nw * nc * P,
         # P T_K(A) P: two real x complex and K complex x complex products
         "propagate": nw * (2 * 4.0 * N * M * M + taylor_order * 8.0 * N * M * M),
-        "overlap_gemm": 4.0 * M * nsq * nw,
         # one launch per spin; the average over the two spin launches
         "exchange": 0.5 * nw * (4.0 * nc * M * nsq + 8.0 * nc * nsq),
     }.get(name)
@@ -59,7 +58,7 @@ def phase_dtype(name, prec):
                 "bf16x3": "bf16"}[prec]
     prop = {"fp64": "fp64", "bf16x3": "fp32+bf16x3"}.get(prec, "fp32")
     return {"force_bias_gemm": contract, "field_sum_gemm": contract, "exchange": contract,
-            "propagate": prop, "overlap_gemm": "fp64"}.get(name)
+            "propagate": prop}.get(name)
 
 
 def cpu_baseline(cfg, n_walkers, n_steps):
@@ -156,6 +155,13 @@ def bench_pair(args):
         return lib.pair_batch_step([(a, b)], [args.seed], n, lanes=1)[0]
 
     H, ga, gb = make(prec)
+    if args.copy_probe_mib:
+        n = args.copy_probe_mib * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     torch.cuda.synchronize()
     tr_w = run(ga, gb, args.warmup)
     print(f"[bench] warmup done ({args.warmup} steps)", file=sys.stderr, flush=True)
@@ -201,7 +207,7 @@ def bench_pair(args):
                    "parallelism": "single GPU"},
         "roofline": roofline,
         "profiled_ms_per_step": el_prof * 1e3 / args.profile_steps,
-        "tuned_shapes": {"fb_tile/fs_tile/ov_tile/prop_shape": tuned},
+        "tuned_shapes": {"fb_tile/fs_tile/prop_shape": tuned},
         "phases_ms_per_step": {k: round(v["ms_per_step"], 4) for k, v in phases.items()},
         "alive_fraction": [float(alive[0]), float(alive[1])],
         "dE_trace_Eh": [float(x) for x in trace[:, 2]],
@@ -284,7 +290,7 @@ def bench_batch(args):
     for a, b in pairs:
         for s in (a, b):
             ch = lib.autotune(s)  # cached: returns the shapes the graph uses
-            key = f"prop{ch[3]}/fb{ch[0]}/fs{ch[1]}/ov{ch[2]}"
+            key = f"prop{ch[2]}/fb{ch[0]}/fs{ch[1]}"
             choices[key] = choices.get(key, 0) + 1
     ws = 2 * walkers * args.steps / el
     fl = 0.0
@@ -397,6 +403,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-walkers", type=int, default=4)
     ap.add_argument("--cpu-steps", type=int, default=100)
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="copy a buffer of this size once (device to device) before the timed "
+                         "steps: the reference kernel for scaling HBM traffic counters")
     ap.add_argument("--no-fp64-check", action="store_true",
                     help="skip the FP64 rerun that measures the energy-difference error")
     args = ap.parse_args()

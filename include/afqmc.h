@@ -183,15 +183,15 @@ afqmc_status afqmc_adjoint_forward(afqmc_sys sys, const double* V, uint64_t seed
 afqmc_status afqmc_adjoint_backward(afqmc_sys sys, double* dE_dlambda);
 
 /* Launch-shape autotuner.  Times every candidate launch shape of the
- * force-bias, field-sum and overlap GEMMs (64 x 64 or 128 x 128 tiles) and
- * of the fused propagation (waves per workgroup x column blocks per wave, B
- * prefetch or not) on
- * this system's own buffers and keeps the fastest per problem shape in a
- * process-wide table, which every later step of any system of that shape
- * uses.  All candidates sum in the same order, so tuning never changes a
- * result bit.  The walker state is left unchanged.  choice (optional, host,
- * 4 ints): the chosen force-bias tile, field-sum tile, overlap tile
- * (1: 64 x 64, 2: 128 x 128) and propagation shape index.  Synchronises. */
+ * force-bias and field-sum GEMMs (64 x 64 or 128 x 128 tiles) and of the
+ * fused propagation (waves per workgroup x column blocks per wave, B
+ * prefetch or not) on this system's own buffers and keeps the fastest per
+ * problem shape in a process-wide table, so tuning another system of the
+ * same shape costs nothing.  All candidates sum in the same order, so tuning
+ * never changes a result bit.  The walker state is left unchanged.  choice
+ * (optional, host, 3 ints): the chosen force-bias tile and field-sum tile
+ * (1: 64 x 64, 2: 128 x 128) and the propagation shape index.
+ * Synchronises. */
 afqmc_status afqmc_autotune(afqmc_sys sys, int* choice);
 
 /* Read back walker state: phi (n_walkers x 2 x N x M: plane 0 = real,
@@ -223,9 +223,9 @@ const char* afqmc_last_error(void);
  * afqmc_profile_enable(sys, 1) clears the counters and starts recording a
  * start/stop event pair around every kernel launch of every later step
  * (phases: 0 force-bias GEMM, 1 fields, 2 field-sum GEMM, 3 unpacking of
- * the symmetric A, 4 fused propagation P T_K(A) P, 5 overlap GEMM,
- * 6 determinants and Theta, 7 weights, 8 Gram-Schmidt, 9 exchange (one
- * launch per spin), 10 local/mixed energy); 0 stops.  afqmc_profile_read
+ * the symmetric A, 4 fused propagation P T_K(A) P, 5 overlaps, determinants
+ * and Theta, 6 weights, 7 Gram-Schmidt, 8 exchange (one launch per spin),
+ * 9 local/mixed energy); 0 stops.  afqmc_profile_read
  * synchronises and returns the summed milliseconds and the launch count of
  * one phase.  afqmc_phase_name returns a phase's name, NULL past the last. */
 afqmc_status afqmc_profile_enable(afqmc_sys sys, int enable);

@@ -285,9 +285,9 @@ def pair_batch_step(pairs, seeds, n_steps: int, lanes: int = 0, graph: bool = Tr
 
 
 def autotune(system: System):
-    """Autotune the system's launch shapes; returns (fb tile, field-sum tile,
-    overlap tile, propagation shape)."""
-    ch = (C.c_int * 4)()
+    """Autotune the system's launch shapes; returns (force-bias tile,
+    field-sum tile, propagation shape)."""
+    ch = (C.c_int * 3)()
     _check(_lib.afqmc_autotune(system._s, ch))
     return tuple(ch)
 

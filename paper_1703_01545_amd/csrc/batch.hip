@@ -235,7 +235,6 @@ long gcd_l(long x, long y) { return y ? gcd_l(y, x % y) : x; }
 afqmc_status autotune(afqmc_sys s, hipStream_t st) {
     HIPCHK(tune_gemm(0, force_bias_gemm(s), s->tc, st, &s->tile_fb));
     HIPCHK(tune_gemm(1, field_sum_gemm(s), s->tc, st, &s->tile_fs));
-    HIPCHK(tune_gemm(2, overlap_gemm(s, s->d_phi.as<double>()), DT_F64, st, &s->tile_ov));
     std::vector<int> cands;
     for (int v = 0; v < kPropVariants; ++v)
         if (propagate_variant_ok(v, s->M, s->tp, s->ta)) cands.push_back(v);
@@ -276,8 +275,7 @@ afqmc_status afqmc_autotune(afqmc_sys s, int* choice) {
     if (choice) {
         choice[0] = s->tile_fb;
         choice[1] = s->tile_fs;
-        choice[2] = s->tile_ov;
-        choice[3] = s->prop_var;
+        choice[2] = s->prop_var;
     }
     return AFQMC_OK;
 }

@@ -54,8 +54,8 @@ void expm_host(const std::vector<double>& X, int n, std::vector<double>& out) {
 
 
 const char* const kPhaseNames[PH_COUNT] = {
-    "force_bias_gemm", "fields",       "field_sum_gemm", "unpack_a", "propagate", "overlap_gemm",
-    "det_theta",       "weights",      "mgs",            "exchange", "energy"};
+    "force_bias_gemm", "fields", "field_sum_gemm", "unpack_a", "propagate",
+    "det_theta",       "weights", "mgs",            "exchange", "energy"};
 
 
 Gemm force_bias_gemm(afqmc_sys s) {
@@ -86,35 +86,10 @@ afqmc_status force_bias(afqmc_sys s, hipStream_t st) {
     return AFQMC_OK;
 }
 
-Gemm overlap_gemm(afqmc_sys s, const double* phi) {
-    // O[(w,p,i), j] = sum_m Phi[(w,p,i), m] trial[j, m]
-    Gemm g{};
-    g.A = phi;
-    g.ta = DT_F64;
-    g.ra = rows_strided(s->M);
-    g.B = s->d_trialT.p;
-    g.tb = DT_F64;
-    g.rb = rows_strided(s->M);
-    g.C = s->d_ov.p;
-    g.tc = DT_F64;
-    g.rc = rows_strided(s->N);
-    g.alpha = 1.0;
-    g.m = 2 * s->N * s->nw;
-    g.n = s->N;
-    g.k = s->M;
-    g.batch = 1;
-    g.tile = s->tile_ov;
-    return g;
-}
-
 afqmc_status overlap_theta(afqmc_sys s, double* phi, hipStream_t st) {
-    const Gemm g = overlap_gemm(s, phi);
-    {
-        PhaseTimer pt(s, PH_OVERLAP, st);
-        HIPCHK(gemm(g, DT_F64, st));
-    }
+    // overlap, ln det and Theta in one launch per (walker, spin)
     PhaseTimer pt(s, PH_DET_THETA, st);
-    HIPCHK(lu_theta(s->d_ov.as<double>(), phi, s->d_theta.as<double>(),
+    HIPCHK(lu_theta(phi, s->d_trialT.as<double>(), s->d_theta.as<double>(),
                     s->ts == DT_F64 ? nullptr : s->d_theta_lp.p, s->ts, s->d_lnd.as<double>(),
                     s->d_alive.as<uint8_t>(), s->nw, s->M, s->N, s->na, s->nb, st));
     return AFQMC_OK;
@@ -415,7 +390,6 @@ afqmc_status afqmc_init_walkers(afqmc_ham ham, int n_alpha, int n_beta, const do
         {&s->d_simp, (size_t)nw * 4 * 8},
         {&s->d_Apk, (size_t)nw * 2 * P * dt_size(s->tp)},
         {&s->d_Af, (size_t)nw * 2 * M * M * dt_size(s->tp)},
-        {&s->d_ov, (size_t)nw * 2 * N * N * 8},
         {&s->d_lnd, (size_t)nw * 4 * 8},
         {&s->d_exch, (size_t)nw * 2 * s->n_gt * 2 * 8},
         {&s->d_el, (size_t)nw * 2 * 8},
@@ -616,7 +590,7 @@ void afqmc_free_sys(afqmc_sys s) {
     for (DevBuf* b : {&s->d_trialT, &s->d_P, &s->d_Plp, &s->d_a, &s->d_lhx, &s->d_lhx_lp,
                       &s->d_phi, &s->d_phinew, &s->d_theta, &s->d_theta_lp, &s->d_w, &s->d_lnov,
                       &s->d_alive, &s->d_F, &s->d_X, &s->d_simp, &s->d_Apk, &s->d_Af,
-                      &s->d_ov, &s->d_lnd, &s->d_exch, &s->d_el, &s->d_sums})
+                      &s->d_lnd, &s->d_exch, &s->d_el, &s->d_sums})
         b->release();
     drop_batch_plans(s->id);
     free_adjoint(s);

@@ -60,7 +60,6 @@ enum Phase {
     PH_FIELD_SUM,
     PH_UNPACK,
     PH_PROPAGATE,
-    PH_OVERLAP,
     PH_DET_THETA,
     PH_WEIGHTS,
     PH_MGS,
@@ -155,11 +154,11 @@ struct afqmc_sys_s {
     // walker state
     afq::host::DevBuf d_phi, d_phinew, d_theta, d_theta_lp, d_w, d_lnov, d_alive;
     // step scratch
-    afq::host::DevBuf d_F, d_X, d_simp, d_Apk, d_Af, d_ov, d_lnd, d_exch, d_el, d_sums;
+    afq::host::DevBuf d_F, d_X, d_simp, d_Apk, d_Af, d_lnd, d_exch, d_el, d_sums;
     int n_gt_a = 0, n_gt_b = 0, n_gt = 0;
     // launch shapes (autotuned; 0 = size heuristic): GEMM tiles of the force
-    // bias, field sum and overlap, and the propagation workgroup shape
-    int tile_fb = 0, tile_fs = 0, tile_ov = 0, prop_var = 0;
+    // bias and the field sum, and the propagation workgroup shape
+    int tile_fb = 0, tile_fs = 0, prop_var = 0;
     // graph capture: the Philox step word is read from *t_dev (plus the
     // step's offset t - t_base) instead of being baked into the launch
     const int64_t* t_dev = nullptr;
@@ -212,7 +211,6 @@ struct PhaseTimer {
 // tuned shapes).
 Gemm force_bias_gemm(afqmc_sys s);
 Gemm field_sum_gemm(afqmc_sys s);
-Gemm overlap_gemm(afqmc_sys s, const double* phi);
 
 // Device phases of one step of one system on stream st (Sec. II.A, II.D).
 afqmc_status force_bias(afqmc_sys s, hipStream_t st);
@@ -222,8 +220,7 @@ afqmc_status one_step(afqmc_sys s, uint64_t seed, uint64_t stream_id, const doub
 afqmc_status ortho(afqmc_sys s, hipStream_t st);
 afqmc_status measure(afqmc_sys s, hipStream_t st);
 
-// Autotuner: fills the system's launch shapes (tile_fb, tile_fs, tile_ov,
-// prop_var) from the process-wide table, timing the candidates of shapes not
+// Autotuner: fills the system's launch shapes (tile_fb, tile_fs, prop_var) from the process-wide table, timing the candidates of shapes not
 // seen before.  Synchronises st.
 afqmc_status autotune(afqmc_sys s, hipStream_t st);
 // Drops every cached batch graph that references system `id`.

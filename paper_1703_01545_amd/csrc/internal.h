@@ -116,13 +116,14 @@ hipError_t fields(const FieldArgs& f, hipStream_t s);
 hipError_t philox_normals(uint64_t seed, uint64_t stream, int64_t t, int nw, int n_chol,
                           double* out, hipStream_t s);
 
-// Overlap matrices ov[w][plane][N][N] (row = walker orbital i, col = trial
-// orbital j) -> per spin block: ln det (lnd[w][spin] complex) and
+// Per walker and spin block: the overlap O = Phi_T^T Phi (trialT: [N][M],
+// rows = trial orbitals), ln det O (lnd[w][spin] complex) and
 // Theta = Phi O^{-1} written to theta (FP64, [w][2][N][M]); optional low
-// precision copy theta_lp (type tlp) for the contractions.
-hipError_t lu_theta(const double* ov, const double* phi, double* theta, void* theta_lp, DType tlp,
-                    double* lnd, const uint8_t* live, int nw, int M, int N, int na, int nb,
-                    hipStream_t s);
+// precision copy theta_lp (type tlp) for the contractions.  Spin blocks of
+// at most 64 orbitals.
+hipError_t lu_theta(const double* phi, const double* trialT, double* theta, void* theta_lp,
+                    DType tlp, double* lnd, const uint8_t* live, int nw, int M, int N, int na,
+                    int nb, hipStream_t s);
 
 // Weight update: lnR = sum_s lnd - lnov + s; lnI = lnR + imp;
 // phaseless: w *= exp(Re lnI + shift) max(0, cos Im lnR), frozen when not

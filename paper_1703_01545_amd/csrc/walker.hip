@@ -139,12 +139,30 @@ __global__ void k_philox_normals(uint64_t seed, uint64_t stream, int64_t t, int 
     }
 }
 
-// Per (walker, spin) block: Gauss-Jordan with partial pivoting on [O | I],
-// O[j][i] = sum_m PhiT[m][j] Phi[m][i] (j: trial orbital, i: walker
-// orbital).  ln det O = sum_k ln(pivot_k) + i pi (row swaps mod 2).  The
-// right block ends as O^{-1}; Theta = Phi O^{-1}.
-__global__ __launch_bounds__(256) void k_lu_theta(const double* __restrict__ ov,
-                                                  const double* __restrict__ phi,
+// Per (walker, spin block), one workgroup, three phases:
+// (1) the transposed overlap B = O^T, B[i][j] = sum_m Phi[i][m] Phi_T[j][m]
+//     (i the walker orbital, j the trial orbital), on the FP64 matrix cores
+//     straight into LDS (each lane reads 4 consecutive basis elements per
+//     16-wide chunk: k = k0 + 4 g + s at sub-step s);
+// (2) in-place Gauss-Jordan inversion of B with partial pivoting (rows are
+//     swapped as the elimination goes; rho records which row of B sits at
+//     each position, so B^{-1}[r][rho(i)] = R[r][i] for the result R), and
+//     ln det B = sum_k ln pivot_k + i pi (number of swaps mod 2);
+// (3) Theta^T = B^{-1} Phi^T, i.e. Theta rows c = sum_i R[c][i] Phi rows
+//     rho(i), on the FP64 matrix cores: per 16-wide block of the basis index
+//     a wave first loads the gathered Phi operand for every k, then runs the
+//     orbital blocks against it.
+typedef double d4v __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ d4v mma64(double a, double b, d4v c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+// EPT: matrix elements per thread in the elimination (n * n <= 256 EPT);
+// KS: k steps of 4 in phase (3) (n <= 4 KS).
+template <int EPT, int KS>
+__global__ __launch_bounds__(256) void k_lu_theta(const double* __restrict__ phi,
+                                                  const double* __restrict__ trialT,
                                                   double* __restrict__ theta, void* theta_lp,
                                                   DType tlp, double* __restrict__ lnd,
                                                   const uint8_t* __restrict__ live, int M, int N,
@@ -152,39 +170,75 @@ __global__ __launch_bounds__(256) void k_lu_theta(const double* __restrict__ ov,
     extern __shared__ double sh[];
     const int w = blockIdx.x, spin = blockIdx.y;
     const int off = spin ? na : 0, n = spin ? nb : na;
-    const int tid = threadIdx.x;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int li = lane & 15, g = lane >> 4;
     double* out_lnd = lnd + ((long)w * 2 + spin) * 2;
     if (n == 0) {
         if (tid == 0) out_lnd[0] = out_lnd[1] = 0.0;
         return;
     }
     if (!live[w]) return;
-    const int ld = 2 * n + 1;
-    double* Ar = sh;
-    double* Ai = sh + n * ld;
-    __shared__ int s_piv;
-    const long NM = (long)N * M, NN = (long)N * N;
-    const double* ovr = ov + (long)w * 2 * NN;
-    const double* ovi = ovr + NN;
-    for (int idx = tid; idx < n * n; idx += 256) {
-        const int i = idx / n, j = idx % n;  // ov row = walker orbital i, col = trial j
-        Ar[j * ld + i] = ovr[(long)(off + i) * N + off + j];
-        Ai[j * ld + i] = ovi[(long)(off + i) * N + off + j];
+    const int LP = n + 1;  // odd row pitch
+    double* ar = sh;
+    double* ai = sh + n * LP;
+    __shared__ int rho[64];
+    __shared__ double piv_r[64], piv_i[64];
+    __shared__ int s_piv, s_swaps;
+    const long NM = (long)N * M;
+    const double* phr = phi + (long)w * 2 * NM;
+    const double* phi_i = phr + NM;
+    // (1) overlap
+    const int nbk = (n + 15) / 16;
+    for (int t = wave; t < nbk * nbk; t += 4) {
+        const int ib = t / nbk, jb = t % nbk;
+        const int i = ib * 16 + li, j = jb * 16 + li;
+        const double* pr_row = phr + (long)(off + (i < n ? i : 0)) * M;
+        const double* pi_row = phi_i + (long)(off + (i < n ? i : 0)) * M;
+        const double* t_row = trialT + (long)(off + (j < n ? j : 0)) * M;
+        d4v accr = {0, 0, 0, 0}, acci = {0, 0, 0, 0};
+        for (int k0 = 0; k0 < M; k0 += 16) {
+            double xr[4], xi[4], tv[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int m = k0 + 4 * g + q;
+                const bool okm = m < M;
+                xr[q] = (okm && i < n) ? pr_row[m] : 0.0;
+                xi[q] = (okm && i < n) ? pi_row[m] : 0.0;
+                tv[q] = (okm && j < n) ? t_row[m] : 0.0;
+            }
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                accr = mma64(xr[q], tv[q], accr);
+                acci = mma64(xi[q], tv[q], acci);
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int row = ib * 16 + g + 4 * r, col = jb * 16 + li;
+            if (row < n && col < n) {
+                ar[row * LP + col] = accr[r];
+                ai[row * LP + col] = acci[r];
+            }
+        }
     }
-    for (int idx = tid; idx < n * n; idx += 256) {
-        const int r = idx / n, c = idx % n;
-        Ar[r * ld + n + c] = (r == c) ? 1.0 : 0.0;
-        Ai[r * ld + n + c] = 0.0;
+    if (tid < 64) rho[tid] = tid;
+    if (tid == 0) s_swaps = 0;
+    // element (r, c) of this thread's slots in the elimination
+    int er[EPT], ec[EPT];
+#pragma unroll
+    for (int q = 0; q < EPT; ++q) {
+        const int e = tid + 256 * q;
+        er[q] = e < n * n ? e / n : -1;
+        ec[q] = e < n * n ? e % n : 0;
     }
     __syncthreads();
-    __shared__ double piv_r[64], piv_i[64];
-    int swaps = 0;
-    const int tx = tid & 63, ty = tid >> 6;  // 64 columns x 4 row groups
+    // (2) Gauss-Jordan
     for (int k = 0; k < n; ++k) {
-        if (tid < 64) {
-            const int r = k + tid;
+        if (wave == 0) {
+            const int r = k + lane;
             double v = -1.0;
-            if (r < n) v = fabs(Ar[r * ld + k]) + fabs(Ai[r * ld + k]);
+            if (r < n) v = fabs(ar[r * LP + k]) + fabs(ai[r * LP + k]);
             int best = r;
             // argmax, ties to the smaller row index
 #pragma unroll
@@ -196,108 +250,121 @@ __global__ __launch_bounds__(256) void k_lu_theta(const double* __restrict__ ov,
                     best = b2;
                 }
             }
-            if (tid == 0) s_piv = best;
+            if (lane == 0) s_piv = best;
         }
         __syncthreads();
         const int p = s_piv;
-        if (p != k) {
-            for (int c = tid; c < 2 * n; c += 256) {
-                double t0 = Ar[k * ld + c], t1 = Ai[k * ld + c];
-                Ar[k * ld + c] = Ar[p * ld + c];
-                Ai[k * ld + c] = Ai[p * ld + c];
-                Ar[p * ld + c] = t0;
-                Ai[p * ld + c] = t1;
+        const double pr = ar[p * LP + k], pi = ai[p * LP + k];
+        const double den = pr * pr + pi * pi;
+        const double qr = pr / den, qi = -pi / den;  // 1 / pivot
+        double nr[EPT], ni[EPT];
+#pragma unroll
+        for (int q = 0; q < EPT; ++q) {
+            const int r = er[q], c = ec[q];
+            if (r < 0) continue;
+            // pivot row element (column k replaced by 1), scaled by 1 / pivot
+            const double br = c == k ? 1.0 : ar[p * LP + c];
+            const double bi = c == k ? 0.0 : ai[p * LP + c];
+            const double sr = br * qr - bi * qi, si = br * qi + bi * qr;
+            if (r == k) {
+                nr[q] = sr;
+                ni[q] = si;
+            } else {
+                const int pr_ = r == p ? k : r;  // row r of the swapped matrix
+                const double fr = ar[pr_ * LP + k], fi = ai[pr_ * LP + k];
+                const double xr = c == k ? 0.0 : ar[pr_ * LP + c];
+                const double xi = c == k ? 0.0 : ai[pr_ * LP + c];
+                nr[q] = xr - (fr * sr - fi * si);
+                ni[q] = xi - (fr * si + fi * sr);
             }
-            ++swaps;
         }
         __syncthreads();
-        const double pr = Ar[k * ld + k], pi = Ai[k * ld + k];
+#pragma unroll
+        for (int q = 0; q < EPT; ++q) {
+            if (er[q] < 0) continue;
+            ar[er[q] * LP + ec[q]] = nr[q];
+            ai[er[q] * LP + ec[q]] = ni[q];
+        }
         if (tid == 0) {
             piv_r[k] = pr;
             piv_i[k] = pi;
-        }
-        // 1 / pivot
-        const double den = pr * pr + pi * pi;
-        const double qr = pr / den, qi = -pi / den;
-        __syncthreads();
-        for (int c = k + 1 + tid; c < 2 * n; c += 256) {
-            const double xr = Ar[k * ld + c], xi = Ai[k * ld + c];
-            Ar[k * ld + c] = xr * qr - xi * qi;
-            Ai[k * ld + c] = xr * qi + xi * qr;
-        }
-        __syncthreads();
-        for (int r = ty; r < n; r += 4) {
-            if (r == k) continue;
-            const double fr = Ar[r * ld + k], fi = Ai[r * ld + k];
-            for (int c = k + 1 + tx; c < 2 * n; c += 64) {
-                const double br = Ar[k * ld + c], bi = Ai[k * ld + c];
-                Ar[r * ld + c] -= fr * br - fi * bi;
-                Ai[r * ld + c] -= fr * bi + fi * br;
+            if (p != k) {
+                const int t = rho[k];
+                rho[k] = rho[p];
+                rho[p] = t;
+                ++s_swaps;
             }
         }
         __syncthreads();
     }
     // ln det = sum_k ln(pivot_k) + i pi (swaps mod 2), summed in index order
-    if (tid < 64) {
+    if (wave == 0) {
         double lr = 0.0, la = 0.0;
         bool sing = false;
-        if (tid < n) {
-            const double pr = piv_r[tid], pi = piv_i[tid];
-            sing = (pr == 0.0 && pi == 0.0);
-            lr = log(hypot(pr, pi));
-            la = atan2(pi, pr);
+        if (lane < n) {
+            const double a = piv_r[lane], b = piv_i[lane];
+            sing = (a == 0.0 && b == 0.0);
+            lr = log(hypot(a, b));
+            la = atan2(b, a);
         }
         lr = wave_sum(lr);
         la = wave_sum(la);
         const bool any_sing = __any(sing);
-        if (tid == 0) {
+        if (lane == 0) {
             if (any_sing) {
                 out_lnd[0] = -INFINITY;
                 out_lnd[1] = 0.0;
             } else {
                 out_lnd[0] = lr;
-                out_lnd[1] = la + ((swaps & 1) ? M_PI : 0.0);
+                out_lnd[1] = la + ((s_swaps & 1) ? M_PI : 0.0);
             }
         }
     }
-    // Theta[m][c] = sum_l Phi[m][l] Inv[l][c]; Inv[l][c] = A[l][n + c].
-    // One basis row m per thread (coalesced Phi loads), CC output columns in
-    // registers, the Inv row broadcast from LDS.
-    const double* pr_ = phi + (long)w * 2 * NM;
-    const double* pi_ = pr_ + NM;
+    // (3) Theta rows c = sum_i R[c][i] Phi rows rho(i)
     double* tr_ = theta + (long)w * 2 * NM;
     double* ti_ = tr_ + NM;
-    constexpr int CC = 20;
-    for (int c0 = 0; c0 < n; c0 += CC) {
-        for (int m = tid; m < M; m += 256) {
-            double accr[CC], acci[CC];
+    const int nmb = (M + 15) / 16;
+    const int nks = (n + 3) / 4;
+    for (int mb = wave; mb < nmb; mb += 4) {
+        const int m = mb * 16 + li;
+        double br[KS], bi[KS];
 #pragma unroll
-            for (int q = 0; q < CC; ++q) accr[q] = acci[q] = 0.0;
-#pragma unroll 4
-            for (int l = 0; l < n; ++l) {
-                const double xr = pr_[(long)(off + l) * M + m];
-                const double xi = pi_[(long)(off + l) * M + m];
-                const double* vr_ = Ar + l * ld + n + c0;
-                const double* vi_ = Ai + l * ld + n + c0;
-#pragma unroll
-                for (int q = 0; q < CC; ++q) {
-                    if (c0 + q < n) {
-                        const double vr = vr_[q], vi = vi_[q];
-                        accr[q] += xr * vr - xi * vi;
-                        acci[q] += xr * vi + xi * vr;
-                    }
-                }
+        for (int s = 0; s < KS; ++s) {
+            const int k = 4 * s + g;
+            br[s] = bi[s] = 0.0;
+            if (s < nks && k < n && m < M) {
+                const long o = (long)(off + rho[k]) * M + m;
+                br[s] = phr[o];
+                bi[s] = phi_i[o];
             }
+        }
+        for (int cb = 0; cb < nbk; ++cb) {
+            const int c = cb * 16 + li;
+            d4v accr = {0, 0, 0, 0}, acci = {0, 0, 0, 0};
 #pragma unroll
-            for (int q = 0; q < CC; ++q) {
-                if (c0 + q < n) {
-                    const long o = (long)(off + c0 + q) * M + m;
-                    tr_[o] = accr[q];
-                    ti_[o] = acci[q];
+            for (int s = 0; s < KS; ++s) {
+                if (s >= nks) continue;
+                const int k = 4 * s + g;
+                const bool ok = k < n && c < n;
+                const double a_r = ok ? ar[c * LP + k] : 0.0;
+                const double a_i = ok ? ai[c * LP + k] : 0.0;
+                accr = mma64(a_r, br[s], accr);
+                accr = mma64(-a_i, bi[s], accr);
+                acci = mma64(a_r, bi[s], acci);
+                acci = mma64(a_i, br[s], acci);
+            }
+            if (m < M) {
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int row = cb * 16 + g + 4 * r;
+                    if (row >= n) continue;
+                    const long o = (long)(off + row) * M + m;
+                    tr_[o] = accr[r];
+                    ti_[o] = acci[r];
                     if (theta_lp) {
                         const long base = (long)w * 2 * NM;
-                        put_dt(theta_lp, tlp, base + o, accr[q]);
-                        put_dt(theta_lp, tlp, base + NM + o, acci[q]);
+                        put_dt(theta_lp, tlp, base + o, accr[r]);
+                        put_dt(theta_lp, tlp, base + NM + o, acci[r]);
                     }
                 }
             }
@@ -588,21 +655,32 @@ hipError_t philox_normals(uint64_t seed, uint64_t stream, int64_t t, int nw, int
     return hipGetLastError();
 }
 
-hipError_t lu_theta(const double* ov, const double* phi, double* theta, void* theta_lp, DType tlp,
-                    double* lnd, const uint8_t* live, int nw, int M, int N, int na, int nb,
-                    hipStream_t s) {
+hipError_t lu_theta(const double* phi, const double* trialT, double* theta, void* theta_lp,
+                    DType tlp, double* lnd, const uint8_t* live, int nw, int M, int N, int na,
+                    int nb, hipStream_t s) {
     if (nw <= 0) return hipSuccess;
     const int nmax = na > nb ? na : nb;
-    const size_t shm = (size_t)2 * nmax * (2 * nmax + 1) * sizeof(double);
+    if (nmax > 64) return hipErrorInvalidValue;
+    const size_t shm = (size_t)2 * nmax * (nmax + 1) * sizeof(double);
     static size_t allowed = 65536;  // raised once per new size, outside graph capture
     if (shm > allowed) {
-        hipError_t e = hipFuncSetAttribute((const void*)k_lu_theta,
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
-        if (e != hipSuccess) return e;
+        for (const void* f : {(const void*)k_lu_theta<4, 8>, (const void*)k_lu_theta<9, 12>,
+                              (const void*)k_lu_theta<16, 16>}) {
+            hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                               (int)shm);
+            if (e != hipSuccess) return e;
+        }
         allowed = shm;
     }
-    hipLaunchKernelGGL(k_lu_theta, dim3(nw, 2), dim3(256), shm, s, ov, phi, theta, theta_lp, tlp,
-                       lnd, live, M, N, na, nb);
+    if (nmax <= 32)
+        hipLaunchKernelGGL((k_lu_theta<4, 8>), dim3(nw, 2), dim3(256), shm, s, phi, trialT, theta,
+                           theta_lp, tlp, lnd, live, M, N, na, nb);
+    else if (nmax <= 48)
+        hipLaunchKernelGGL((k_lu_theta<9, 12>), dim3(nw, 2), dim3(256), shm, s, phi, trialT, theta,
+                           theta_lp, tlp, lnd, live, M, N, na, nb);
+    else
+        hipLaunchKernelGGL((k_lu_theta<16, 16>), dim3(nw, 2), dim3(256), shm, s, phi, trialT,
+                           theta, theta_lp, tlp, lnd, live, M, N, na, nb);
     return hipGetLastError();
 }
 
