@@ -14,7 +14,8 @@ from typing import Optional
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libafqmc.so")
+# AFQMC_LIB may name another build of the same sources (e.g. for A/B timing)
+LIB_PATH = os.environ.get("AFQMC_LIB") or os.path.join(_HERE, "libafqmc.so")
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"libafqmc.so not built at {LIB_PATH}; run python -m paper_1703_01545_amd.build")

@@ -437,17 +437,16 @@ __global__ void k_mask(double* __restrict__ v, const uint8_t* __restrict__ mode,
     if (i < per * nw && mode[i / per] != ACTIVE) v[i] = 0.0;
 }
 
-// acc[slot] += sum over ACTIVE walkers of sum_k a[w][k] b[w][k] (one block,
-// fixed order: deterministic).
-__global__ __launch_bounds__(256) void k_dot(const double* __restrict__ a,
-                                             const double* __restrict__ b,
-                                             const uint8_t* __restrict__ mode, long per, int nw,
-                                             double* acc, int slot) {
+// part[w] = sum_k a[w][k] b[w][k] for ACTIVE walkers, else 0 (one block per
+// walker, fixed-order reduction).
+__global__ __launch_bounds__(256) void k_dot_part(const double* __restrict__ a,
+                                                  const double* __restrict__ b,
+                                                  const uint8_t* __restrict__ mode, long per,
+                                                  double* __restrict__ part) {
     __shared__ double red[4];
-    const int tid = threadIdx.x;
+    const int w = blockIdx.x, tid = threadIdx.x;
     double s = 0.0;
-    for (int w = 0; w < nw; ++w) {
-        if (mode[w] != ACTIVE) continue;
+    if (mode[w] == ACTIVE) {
         const double* x = a + (long)w * per;
         const double* y = b + (long)w * per;
         for (long k = tid; k < per; k += 256) s += x[k] * y[k];
@@ -455,7 +454,26 @@ __global__ __launch_bounds__(256) void k_dot(const double* __restrict__ a,
     s = wsum(s);
     if ((tid & 63) == 0) red[tid >> 6] = s;
     __syncthreads();
+    if (tid == 0) part[w] = (red[0] + red[1]) + (red[2] + red[3]);
+}
+
+// acc[slot] += sum_w part[w]  (one block, fixed order)
+__global__ __launch_bounds__(256) void k_dot_sum(const double* __restrict__ part, int nw,
+                                                 double* acc, int slot) {
+    __shared__ double red[4];
+    const int tid = threadIdx.x;
+    double s = 0.0;
+    for (int w = tid; w < nw; w += 256) s += part[w];
+    s = wsum(s);
+    if ((tid & 63) == 0) red[tid >> 6] = s;
+    __syncthreads();
     if (tid == 0) acc[slot] += (red[0] + red[1]) + (red[2] + red[3]);
+}
+
+void dot_acc(const double* a, const double* b, const uint8_t* mode, long per, int nw,
+             double* part, double* acc, int slot, hipStream_t st) {
+    hipLaunchKernelGGL(k_dot_part, dim3(nw), dim3(256), 0, st, a, b, mode, per, part);
+    hipLaunchKernelGGL(k_dot_sum, dim3(1), dim3(256), 0, st, part, nw, acc, slot);
 }
 
 // Energy adjoint set-up at the end of the window (one block): W = sum w,
@@ -556,7 +574,7 @@ struct AdjState {
     std::vector<int64_t> t_t;
     // scratch
     DevBuf xc, simp_s, apk, A, x, tA, tB, y, tT, tbT, ybar, Abar, Abpk, G, Fbar, thbar, phibar,
-        phibar2, wbar, wbar2, mode, lnrb, lnib, th_s, y_s, z, acc, ebuf, scale, Tb, U, vd, cp;
+        phibar2, wbar, wbar2, mode, lnrb, lnib, th_s, y_s, z, acc, ebuf, scale, Tb, U, vd, cp, part;
 };
 
 namespace {
@@ -714,7 +732,7 @@ afqmc_status adj_setup(afqmc_sys s, AdjState* a, hipStream_t st) {
         {&a->wbar2, (size_t)nw * 8}, {&a->mode, (size_t)nw}, {&a->lnrb, (size_t)nw * 16},
         {&a->lnib, (size_t)nw * 8}, {&a->th_s, rowb}, {&a->y_s, rowb}, {&a->z, rowb},
         {&a->acc, 64 * 8}, {&a->ebuf, 16}, {&a->scale, (size_t)nw * 8}, {&a->U, rowb},
-        {&a->vd, (size_t)nw * 2 * 8}, {&a->cp, rowb},
+        {&a->vd, (size_t)nw * 2 * 8}, {&a->cp, rowb}, {&a->part, (size_t)nw * 8},
     };
     for (auto& b : bufs) HIPCHK(b.b->alloc(b.n));
     const int nmax = std::max(s->na, s->nb);
@@ -895,8 +913,8 @@ afqmc_status reverse_step(afqmc_sys s, AdjState* a, int j, const double* phi_nex
     }
     // dE/dlambda += <phi_bar', dP y>
     HIPCHK(rgemm(a->dP.as<double>(), y, a->z.as<double>(), rows, M, pr, st));
-    hipLaunchKernelGGL(k_dot, dim3(1), dim3(256), 0, st, pb, a->z.as<double>(), mode, 2 * NM, nw,
-                       a->acc.as<double>(), 0);
+    dot_acc(pb, a->z.as<double>(), mode, 2 * NM, nw, a->part.as<double>(), a->acc.as<double>(),
+            0, st);
     // y_bar = P phi_bar'; Taylor terms backwards
     double* yb = a->ybar.as<double>();
     HIPCHK(rgemm(s->d_P.as<double>(), pb, yb, rows, M, pr, st));
@@ -973,8 +991,8 @@ afqmc_status reverse_step(afqmc_sys s, AdjState* a, int j, const double* phi_nex
     double* pn = a->phibar2.as<double>();
     HIPCHK(rgemm(s->d_P.as<double>(), ub, pn, rows, M, pr, st));
     HIPCHK(rgemm(a->dP.as<double>(), phi_in, a->z.as<double>(), rows, M, pr, st));
-    hipLaunchKernelGGL(k_dot, dim3(1), dim3(256), 0, st, ub, a->z.as<double>(), mode, 2 * NM, nw,
-                       a->acc.as<double>(), 0);
+    dot_acc(ub, a->z.as<double>(), mode, 2 * NM, nw, a->part.as<double>(), a->acc.as<double>(),
+            0, st);
     r = det_adj(s, a, phi_in, a->thbar.as<double>(), a->lnrb.as<double>(), -1.0, mode, pn, st);
     if (r != AFQMC_OK) return r;
     hipLaunchKernelGGL(k_mask, dim3(nblk(nel, 256)), dim3(256), 0, st, pn, mode, 2 * NM, nw);

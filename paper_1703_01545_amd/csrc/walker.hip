@@ -184,7 +184,7 @@ __global__ __launch_bounds__(256) void k_lu_theta(const double* __restrict__ phi
     double* ai = sh + n * LP;
     __shared__ int rho[64];
     __shared__ double piv_r[64], piv_i[64];
-    __shared__ int s_piv, s_swaps;
+    __shared__ int s_swaps;
     const long NM = (long)N * M;
     const double* phr = phi + (long)w * 2 * NM;
     const double* phi_i = phr + NM;
@@ -233,9 +233,11 @@ __global__ __launch_bounds__(256) void k_lu_theta(const double* __restrict__ phi
         ec[q] = e < n * n ? e % n : 0;
     }
     __syncthreads();
-    // (2) Gauss-Jordan
+    // (2) Gauss-Jordan.  Every wave finds the pivot row itself (no broadcast
+    // and no extra barrier); two barriers per column.
     for (int k = 0; k < n; ++k) {
-        if (wave == 0) {
+        int p;
+        {
             const int r = k + lane;
             double v = -1.0;
             if (r < n) v = fabs(ar[r * LP + k]) + fabs(ai[r * LP + k]);
@@ -250,10 +252,8 @@ __global__ __launch_bounds__(256) void k_lu_theta(const double* __restrict__ phi
                     best = b2;
                 }
             }
-            if (lane == 0) s_piv = best;
+            p = __builtin_amdgcn_readfirstlane(best);
         }
-        __syncthreads();
-        const int p = s_piv;
         const double pr = ar[p * LP + k], pi = ai[p * LP + k];
         const double den = pr * pr + pi * pi;
         const double qr = pr / den, qi = -pi / den;  // 1 / pivot
