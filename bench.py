@@ -394,7 +394,7 @@ def main():
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--profile-steps", type=int, default=20)
-    ap.add_argument("--precision", default="bf16",
+    ap.add_argument("--precision", default="bf16x3",
                     choices=["bf16", "bf16x3", "fp32", "fp64", "bf16_plain"])
     ap.add_argument("--walkers", type=int, default=None, help="override walkers per system")
     ap.add_argument("--pairs", type=int, default=64, help="batch workload: number of pairs")

@@ -74,10 +74,10 @@ hipError_t split_planes(const float* in, void* out, long n, long planes, hipStre
 // or DT_SPLIT with t == DT_F32 (Taylor terms in split BF16, Af as hi/lo
 // planes [w][plane][hi, lo][M][M], M % 8 == 0).  Frozen walkers (live == 0)
 // are copied unchanged.  M <= 256.  `variant` selects the workgroup shape
-// (waves per workgroup x column blocks per wave, with or without B prefetch;
-// see kPropShapes); every variant gives bitwise the same result, 0 is the
-// default.
-constexpr int kPropVariants = 8;
+// (waves per workgroup x column blocks per wave, with or without B prefetch,
+// one or two row blocks per workgroup; see kPropShapes); every variant gives
+// bitwise the same result, 0 is the default.
+constexpr int kPropVariants = 10;
 bool propagate_variant_ok(int variant, int M, DType t, DType ta);
 hipError_t propagate(const double* phi, double* phi_out, const void* Pm, const void* Af,
                      const uint8_t* live, int nw, int M, int N, int K, DType t, DType ta,

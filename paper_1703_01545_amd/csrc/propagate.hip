@@ -10,6 +10,11 @@
 // products run on the matrix cores (FP32 or FP64 MFMA 16x16x4).
 #include "mfma.h"
 
+// No contraction of a multiply and an add into one fused operation anywhere
+// in this file: the Taylor-term scaling and the running sum must round the
+// same way in every workgroup shape.
+#pragma clang fp contract(off)
+
 namespace afq {
 namespace {
 
@@ -86,6 +91,32 @@ __device__ __forceinline__ void bload4(__amdgpu_buffer_rsrc_t r, int off, double
     v[1] = x[1];
     v[2] = y[0];
     v[3] = y[1];
+}
+
+// 1 / n as a compile-time table (correctly rounded by the compiler), so
+// every kernel shape scales the Taylor terms by the same value.
+__device__ __forceinline__ double inv_n_d(int n) {
+    constexpr double t[17] = {0.0,        1.0,        1.0 / 2,  1.0 / 3,  1.0 / 4,  1.0 / 5,
+                              1.0 / 6,    1.0 / 7,    1.0 / 8,  1.0 / 9,  1.0 / 10, 1.0 / 11,
+                              1.0 / 12,   1.0 / 13,   1.0 / 14, 1.0 / 15, 1.0 / 16};
+    return n <= 16 ? t[n] : 1.0 / n;
+}
+__device__ __forceinline__ float inv_n_f(int n) {
+    constexpr float t[17] = {0.0f,        1.0f,        1.0f / 2,  1.0f / 3,  1.0f / 4,  1.0f / 5,
+                             1.0f / 6,    1.0f / 7,    1.0f / 8,  1.0f / 9,  1.0f / 10, 1.0f / 11,
+                             1.0f / 12,   1.0f / 13,   1.0f / 14, 1.0f / 15, 1.0f / 16};
+    return n <= 16 ? t[n] : 1.0f / n;
+}
+
+// acc <- acc / n and z <- z + acc with separate roundings (no contraction
+// into a fused multiply-add, so every workgroup shape rounds alike).
+template <typename V, typename S_>
+__device__ __forceinline__ void term_update(V& acc, V& z, S_ inv) {
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        acc[e] = acc[e] * inv;  // contraction is off in this file
+        z[e] = z[e] + acc[e];
+    }
 }
 
 // One pass: acc[s] = S (16 x Mp, 2 planes in LDS) x B^T for this wave's
@@ -246,13 +277,11 @@ __global__ __launch_bounds__(64 * NWAVE, 2) void k_propagate(
     for (int n = 1; n <= K; ++n) {
         pass<T, MAXB, 2, PF>(rA, M, Mp, MB, S, SPT, cb, acc);
         __syncthreads();
-        const T inv = (T)(1.0 / n);
+        const T inv = sizeof(T) == 8 ? (T)inv_n_d(n) : (T)inv_n_f(n);
 #pragma unroll
         for (int s = 0; s < MAXB; ++s) {
-            acc[s][0] *= inv;
-            acc[s][1] *= inv;
-            z[s][0] += acc[s][0];
-            z[s][1] += acc[s][1];
+            term_update(acc[s][0], z[s][0], inv);
+            term_update(acc[s][1], z[s][1], inv);
             if (cb[s] < MB) {
                 if (n == K)
                     put(s, z[s][0], z[s][1]);
@@ -477,14 +506,12 @@ __global__ __launch_bounds__(64 * NWAVE, 2) void k_propagate_split(
     for (int n = 1; n <= K; ++n) {
         pass_split<MAXB, PF>(rA, M, Mp, MB, Sb, SPB, cb, acc);
         __syncthreads();
-        const float inv = 1.0f / n;
+        const float inv = inv_n_f(n);
         if (n == K) zero_f();
 #pragma unroll
         for (int s = 0; s < MAXB; ++s) {
-            acc[s][0] *= inv;
-            acc[s][1] *= inv;
-            z[s][0] += acc[s][0];
-            z[s][1] += acc[s][1];
+            term_update(acc[s][0], z[s][0], inv);
+            term_update(acc[s][1], z[s][1], inv);
             if (cb[s] < MB) {
                 if (n == K)
                     put_f(s, z[s][0], z[s][1]);
@@ -516,6 +543,312 @@ __global__ __launch_bounds__(64 * NWAVE, 2) void k_propagate_split(
             }
         }
     }
+}
+
+// ---------------------------------------------------------------------------
+// RB row blocks per workgroup (16 RB orbitals of one walker): every operand
+// fragment of A_w or P a wave loads serves RB row blocks, so the loads per
+// matrix-core product drop by RB.  Operands are loaded chunk by chunk (no
+// prefetch); row blocks past the walker's last orbital are skipped.
+
+template <int MAXB, int RB>
+__device__ __forceinline__ void pass_rb(__amdgpu_buffer_rsrc_t rb, int M, int Mp, int MB, int nrbv,
+                                        const float* S, int SPT, const int* cb,
+                                        f4 (&acc)[RB][MAXB][2]) {
+    const int lane = threadIdx.x & 63;
+    const int g = lane >> 4, li = lane & 15;
+    const long splane = 16L * RB * SPT;
+    int boff[MAXB];
+#pragma unroll
+    for (int s = 0; s < MAXB; ++s) {
+        const int m = cb[s] * 16 + li;
+        boff[s] = m < M ? (m * M + 4 * g) * 4 : kOutOfRange;
+#pragma unroll
+        for (int r = 0; r < RB; ++r) acc[r][s][0] = acc[r][s][1] = f4{0, 0, 0, 0};
+    }
+    for (int k0 = 0; k0 < Mp; k0 += 16) {
+        float bc[MAXB][4];
+#pragma unroll
+        for (int s = 0; s < MAXB; ++s) bload4(rb, boff[s] + k0 * 4, bc[s]);
+#pragma unroll
+        for (int r = 0; r < RB; ++r) {
+            if (r >= nrbv) continue;  // wave-uniform
+            const float* sr_ = S + (r * 16 + li) * SPT + 4 * g + k0;
+            const f4 xr = *reinterpret_cast<const f4*>(sr_);
+            const f4 xi = *reinterpret_cast<const f4*>(sr_ + splane);
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+#pragma unroll
+                for (int s = 0; s < MAXB; ++s) {
+                    if (cb[s] >= MB) continue;  // wave-uniform
+                    acc[r][s][0] = mma1(xr[j], bc[s][j], acc[r][s][0]);
+                    acc[r][s][1] = mma1(xi[j], bc[s][j], acc[r][s][1]);
+                }
+        }
+    }
+}
+
+template <int MAXB, int RB>
+__device__ __forceinline__ void pass_split_rb(__amdgpu_buffer_rsrc_t rb, int M, int Mp, int MB,
+                                              int nrbv, const bf16_t* Sb, int SPB, const int* cb,
+                                              f4 (&acc)[RB][MAXB][2]) {
+    const int lane = threadIdx.x & 63;
+    const int g = lane >> 4, li = lane & 15;
+    const int hl_b = M * M * 2;
+    const int pl_b = 2 * hl_b;
+    const long spl = 16L * RB * SPB;
+    int boff[MAXB];
+#pragma unroll
+    for (int s = 0; s < MAXB; ++s) {
+        const int m = cb[s] * 16 + li;
+        boff[s] = m < M ? (m * M + 8 * g) * 2 : kOutOfRange;
+#pragma unroll
+        for (int r = 0; r < RB; ++r) acc[r][s][0] = acc[r][s][1] = f4{0, 0, 0, 0};
+    }
+    for (int k0 = 0; k0 < Mp; k0 += 32) {
+        bf8 bc[MAXB][4];  // re hi, re lo, im hi, im lo
+#pragma unroll
+        for (int s = 0; s < MAXB; ++s) {
+            const int o = boff[s] + k0 * 2;
+            bc[s][0] = bload8(rb, o);
+            bc[s][1] = bload8(rb, o + hl_b);
+            bc[s][2] = bload8(rb, o + pl_b);
+            bc[s][3] = bload8(rb, o + pl_b + hl_b);
+        }
+#pragma unroll
+        for (int r = 0; r < RB; ++r) {
+            if (r >= nrbv) continue;  // wave-uniform
+            const bf16_t* s0 = Sb + (r * 16 + li) * SPB + 8 * g + k0;
+            const bf8 rh = *reinterpret_cast<const bf8*>(s0);
+            const bf8 rl = *reinterpret_cast<const bf8*>(s0 + spl);
+            const bf8 ih = *reinterpret_cast<const bf8*>(s0 + 2 * spl);
+            const bf8 il = *reinterpret_cast<const bf8*>(s0 + 3 * spl);
+            const bf8 nh = neg8(ih), nl = neg8(il);
+#pragma unroll
+            for (int s = 0; s < MAXB; ++s) {
+                if (cb[s] >= MB) continue;  // wave-uniform
+                f4 ar = acc[r][s][0], ai = acc[r][s][1];
+                ar = mma8(rl, bc[s][0], ar);
+                ar = mma8(rh, bc[s][1], ar);
+                ar = mma8(rh, bc[s][0], ar);
+                ar = mma8(nl, bc[s][2], ar);
+                ar = mma8(nh, bc[s][3], ar);
+                ar = mma8(nh, bc[s][2], ar);
+                ai = mma8(rl, bc[s][2], ai);
+                ai = mma8(rh, bc[s][3], ai);
+                ai = mma8(rh, bc[s][2], ai);
+                ai = mma8(il, bc[s][0], ai);
+                ai = mma8(ih, bc[s][1], ai);
+                ai = mma8(ih, bc[s][0], ai);
+                acc[r][s][0] = ar;
+                acc[r][s][1] = ai;
+            }
+            // keep each row block's operand fragments from being hoisted
+            // together (register budget of the 16-wave shape)
+            __builtin_amdgcn_sched_barrier(0);
+        }
+    }
+}
+
+template <int NWAVE, int MAXB, int RB>
+__global__ __launch_bounds__(64 * NWAVE, 1) void k_propagate_split_rb(
+    const double* __restrict__ phi, double* __restrict__ phi_out, const float* __restrict__ Pm,
+    const bf16_t* __restrict__ Af, const uint8_t* __restrict__ live, int nw, int M, int N, int K,
+    int nrb) {
+    extern __shared__ __attribute__((aligned(16))) char smem_raw[];
+    constexpr int NT = 64 * NWAVE;
+    constexpr int ROWS = 16 * RB;
+    const int Mp = (M + 31) / 32 * 32;
+    const int MB = (M + 15) / 16;
+    const int SPT = Mp + 4, SPB = Mp + 8;
+    const long splane = (long)ROWS * SPT, bplane = (long)ROWS * SPB;
+    float* S = reinterpret_cast<float*>(smem_raw);
+    bf16_t* Sb = reinterpret_cast<bf16_t*>(smem_raw);
+    // running Taylor sum, FP32, same layout as the FP32 view (own elements
+    // only: no barrier needed for its updates)
+    float* Zs = reinterpret_cast<float*>(smem_raw + 4 * bplane * sizeof(bf16_t));
+    const long nblk = (long)nw * nrb;
+    const long per = (nblk + 7) / 8;
+    const long L = (long)(blockIdx.x % 8) * per + blockIdx.x / 8;
+    if (L >= nblk) return;
+    const int w = (int)(L / nrb), row0 = (int)(L % nrb) * ROWS;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const long NM = (long)N * M;
+    const double* src = phi + (long)w * 2 * NM;
+    double* dst = phi_out + (long)w * 2 * NM;
+    const int nrow = min(ROWS, N - row0);
+    if (nrow <= 0) return;
+    const int nrbv = (nrow + 15) / 16;  // row blocks holding orbitals
+    if (!live[w]) {
+        for (int e = tid; e < 2 * nrow * M; e += NT) {
+            const int p = e / (nrow * M), rem = e % (nrow * M);
+            const long o = p * NM + (long)(row0 + rem / M) * M + rem % M;
+            dst[o] = src[o];
+        }
+        return;
+    }
+    for (int e = tid; e < 2 * ROWS * Mp; e += NT) {
+        const int p = e / (ROWS * Mp), rem = e % (ROWS * Mp);
+        const int r = rem / Mp, m = rem % Mp;
+        double v = 0.0;
+        if (r < nrow && m < M) v = src[p * NM + (long)(row0 + r) * M + m];
+        S[p * splane + r * SPT + m] = (float)v;
+    }
+    const int vw = (wave + (int)(L % NWAVE)) % NWAVE;
+    int cb[MAXB];
+#pragma unroll
+    for (int s = 0; s < MAXB; ++s) cb[s] = vw + s * NWAVE;
+    __syncthreads();
+    f4 acc[RB][MAXB][2];
+    const long Aplane = (long)M * M;
+    const __amdgpu_buffer_rsrc_t rP = make_rsrc(Pm, Aplane);
+    const __amdgpu_buffer_rsrc_t rA = make_rsrc(Af + (long)w * 4 * Aplane, 4 * Aplane);
+    const int li = lane & 15;
+    const int pad = Mp - MB * 16;
+    auto zero_b = [&]() {
+        for (int e = tid; e < 4 * ROWS * pad; e += NT) {
+            const int q = e / (ROWS * pad), rem = e % (ROWS * pad);
+            Sb[q * bplane + (rem / pad) * SPB + MB * 16 + rem % pad] = (bf16_t)0.0f;
+        }
+    };
+    auto zero_f = [&]() {
+        for (int e = tid; e < 2 * ROWS * pad; e += NT) {
+            const int q = e / (ROWS * pad), rem = e % (ROWS * pad);
+            S[q * splane + (rem / pad) * SPT + MB * 16 + rem % pad] = 0.0f;
+        }
+    };
+    auto put_b = [&](int r, int s, const f4& vr, const f4& vi) {
+        const int col = cb[s] * 16 + li;
+        const bool ok = col < M;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int off = (r * 16 + acc_row<float>(lane, q)) * SPB + col;
+            const float xr = ok ? vr[q] : 0.0f, xi = ok ? vi[q] : 0.0f;
+            const bf16_t hr = to_bf(xr), hi = to_bf(xi);
+            Sb[off] = hr;
+            Sb[bplane + off] = to_bf(xr - (float)hr);
+            Sb[2 * bplane + off] = hi;
+            Sb[3 * bplane + off] = to_bf(xi - (float)hi);
+        }
+    };
+    auto put_f = [&](int r, int s, const f4& vr, const f4& vi) {
+        const int col = cb[s] * 16 + li;
+        const bool ok = col < M;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int off = (r * 16 + acc_row<float>(lane, q)) * SPT + col;
+            S[off] = ok ? vr[q] : 0.0f;
+            S[splane + off] = ok ? vi[q] : 0.0f;
+        }
+    };
+    // z (this thread's elements) <- v, or += v
+    auto zacc = [&](int r, int s, f4& vr, f4& vi, bool first) {
+        const int col = cb[s] * 16 + li;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int off = (r * 16 + acc_row<float>(lane, q)) * SPT + col;
+            if (first) {
+                Zs[off] = vr[q];
+                Zs[splane + off] = vi[q];
+            } else {
+                vr[q] = Zs[off] = Zs[off] + vr[q];
+                vi[q] = Zs[splane + off] = Zs[splane + off] + vi[q];
+            }
+        }
+    };
+    // rows past the walker's orbitals (r >= nrbv) are never read: their S
+    // rows stay as loaded (zeros) and their accumulators are not stored
+    pass_rb<MAXB, RB>(rP, M, Mp, MB, nrbv, S, SPT, cb, acc);
+    __syncthreads();
+    zero_b();
+#pragma unroll
+    for (int r = 0; r < RB; ++r)
+#pragma unroll
+        for (int s = 0; s < MAXB; ++s)
+            if (r < nrbv && cb[s] < MB) {
+                put_b(r, s, acc[r][s][0], acc[r][s][1]);
+                zacc(r, s, acc[r][s][0], acc[r][s][1], true);
+            }
+    __syncthreads();
+    for (int n = 1; n <= K; ++n) {
+        pass_split_rb<MAXB, RB>(rA, M, Mp, MB, nrbv, Sb, SPB, cb, acc);
+        __syncthreads();
+        const float inv = inv_n_f(n);
+        if (n == K) zero_f();
+#pragma unroll
+        for (int r = 0; r < RB; ++r)
+#pragma unroll
+            for (int s = 0; s < MAXB; ++s) {
+                if (r >= nrbv || cb[s] >= MB) continue;
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    acc[r][s][0][q] = acc[r][s][0][q] * inv;
+                    acc[r][s][1][q] = acc[r][s][1][q] * inv;
+                }
+                if (n == K) {
+                    zacc(r, s, acc[r][s][0], acc[r][s][1], false);  // acc <- z
+                    put_f(r, s, acc[r][s][0], acc[r][s][1]);
+                } else {
+                    put_b(r, s, acc[r][s][0], acc[r][s][1]);
+                    f4 tr = acc[r][s][0], ti = acc[r][s][1];
+                    zacc(r, s, tr, ti, false);
+                }
+            }
+        __syncthreads();
+    }
+    if (K == 0) {
+        zero_f();
+#pragma unroll
+        for (int r = 0; r < RB; ++r)
+#pragma unroll
+            for (int s = 0; s < MAXB; ++s)
+                if (r < nrbv && cb[s] < MB) {
+                    f4 tr = f4{0, 0, 0, 0}, ti = f4{0, 0, 0, 0};
+                    zacc(r, s, tr, ti, false);
+                    put_f(r, s, tr, ti);
+                }
+        __syncthreads();
+    }
+    pass_rb<MAXB, RB>(rP, M, Mp, MB, nrbv, S, SPT, cb, acc);
+#pragma unroll
+    for (int r = 0; r < RB; ++r)
+#pragma unroll
+        for (int s = 0; s < MAXB; ++s) {
+            const int col = cb[s] * 16 + li;
+            if (r >= nrbv || cb[s] >= MB || col >= M) continue;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int row = r * 16 + acc_row<float>(lane, q);
+                if (row < nrow) {
+                    const long o = (long)(row0 + row) * M + col;
+                    dst[o] = (double)acc[r][s][0][q];
+                    dst[NM + o] = (double)acc[r][s][1][q];
+                }
+            }
+        }
+}
+
+template <int NWAVE, int MAXB, int RB>
+hipError_t launch_prop_split_rb(const double* phi, double* phi_out, const void* Pm, const void* Af,
+                                const uint8_t* live, int nw, int M, int N, int K, hipStream_t s) {
+    const int Mp = (M + 31) / 32 * 32;
+    // BF16 view (>= the FP32 view) + the FP32 running sum
+    const size_t shm = 4 * 16 * RB * (size_t)(Mp + 8) * sizeof(bf16_t) +
+                       2 * 16 * RB * (size_t)(Mp + 4) * sizeof(float);
+    const int nrb = (N + 16 * RB - 1) / (16 * RB);
+    const long nblk = (long)nw * nrb;
+    const long grid = ((nblk + 7) / 8) * 8;
+    static bool attr = false;
+    if (!attr && shm > 65536) {
+        hipError_t e = hipFuncSetAttribute((const void*)k_propagate_split_rb<NWAVE, MAXB, RB>,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+        if (e != hipSuccess) return e;
+        attr = true;
+    }
+    hipLaunchKernelGGL((k_propagate_split_rb<NWAVE, MAXB, RB>), dim3(grid), dim3(64 * NWAVE), shm,
+                       s, phi, phi_out, (const float*)Pm, (const bf16_t*)Af, live, nw, M, N, K, nrb);
+    return hipGetLastError();
 }
 
 template <int NWAVE, int MAXB, bool PF>
@@ -628,10 +961,11 @@ namespace {
 struct PropShape {
     int waves, blocks;
     bool pf;
+    int rows;  // row blocks per workgroup (split BF16 only when > 1)
 };
-constexpr PropShape kPropShapes[kPropVariants] = {{8, 2, true},  {4, 2, true},  {4, 1, true},
-                                                  {2, 2, true},  {8, 2, false}, {4, 2, false},
-                                                  {4, 1, false}, {2, 2, false}};
+constexpr PropShape kPropShapes[kPropVariants] = {
+    {8, 2, true, 1},  {4, 2, true, 1},  {4, 1, true, 1},  {2, 2, true, 1},  {8, 2, false, 1},
+    {4, 2, false, 1}, {4, 1, false, 1}, {2, 2, false, 1}, {16, 1, false, 2}, {8, 1, false, 2}};
 }  // namespace
 
 bool propagate_variant_ok(int v, int M, DType t, DType ta) {
@@ -640,6 +974,7 @@ bool propagate_variant_ok(int v, int M, DType t, DType ta) {
     if (ta != t && !(t == DT_F32 && ta == DT_SPLIT && M % 8 == 0)) return false;
     const PropShape p = kPropShapes[v];
     if (t == DT_F64 && !p.pf) return false;  // the FP64 path keeps the prefetching shapes
+    if (p.rows > 1 && ta != DT_SPLIT) return false;
     return (M + 15) / 16 <= p.waves * p.blocks;
 }
 
@@ -669,6 +1004,10 @@ hipError_t propagate(const double* phi, double* phi_out, const void* Pm, const v
         AFQ_S(5, 4, 2, false)
         AFQ_S(6, 4, 1, false)
         AFQ_S(7, 2, 2, false)
+        if (variant == 8)
+            return launch_prop_split_rb<16, 1, 2>(phi, phi_out, Pm, Af, live, nw, M, N, K, s);
+        if (variant == 9)
+            return launch_prop_split_rb<8, 1, 2>(phi, phi_out, Pm, Af, live, nw, M, N, K, s);
     } else {
         AFQ_P(0, float, 8, 2, true)
         AFQ_P(1, float, 4, 2, true)

@@ -301,11 +301,13 @@ def test_propagation_shapes_bitwise(lib, dims, prec):
     A = (rng.standard_normal((nw, M, M)) + 1j * rng.standard_normal((nw, M, M))) * (0.4 / np.sqrt(M))
     A = 0.5 * (A + np.swapaxes(A, 1, 2))
     base = lib.selftest_propagate(phi, P, A, 6, prec, variant=0)
-    shapes = {0: (8, 2, 1), 1: (4, 2, 1), 2: (4, 1, 1), 3: (2, 2, 1), 4: (8, 2, 0), 5: (4, 2, 0),
-              6: (4, 1, 0), 7: (2, 2, 0)}
+    # variant: (waves, column blocks per wave, prefetch, row blocks per workgroup)
+    shapes = {0: (8, 2, 1, 1), 1: (4, 2, 1, 1), 2: (4, 1, 1, 1), 3: (2, 2, 1, 1), 4: (8, 2, 0, 1),
+              5: (4, 2, 0, 1), 6: (4, 1, 0, 1), 7: (2, 2, 0, 1), 8: (16, 1, 0, 2), 9: (8, 1, 0, 2)}
     ran = 0
-    for v, (waves, blocks, pf) in shapes.items():
-        ok = (M + 15) // 16 <= waves * blocks and not (prec == "fp64" and not pf)
+    for v, (waves, blocks, pf, rows) in shapes.items():
+        ok = ((M + 15) // 16 <= waves * blocks and not (prec == "fp64" and not pf)
+              and not (rows > 1 and prec != "bf16x3"))
         if not ok:
             with pytest.raises(lib.AfqmcError):
                 lib.selftest_propagate(phi, P, A, 6, prec, variant=v)
