@@ -245,8 +245,9 @@ afqmc_status afqmc_selftest_gemm(afqmc_prec prec, int m, int n, int k, const dou
  * split BF16 and P in FP32; else FP32), workgroup shape `variant` (waves x
  * column blocks per wave: 0: 8 x 2, 1: 4 x 2, 2: 4 x 1, 3: 2 x 2, with the
  * next chunk of the matrix operand prefetched; 4..7: the same shapes without
- * the prefetch, FP32 and split BF16 only; 8: 16 x 1 and 9: 8 x 1 with two
- * row blocks (32 orbitals) per workgroup, split BF16 only; a shape serves
+ * the prefetch, FP32 and split BF16 only; 8: 16 x 1, 9: 8 x 1, 10: 8 x 2 and
+ * 11: 4 x 2 with two row blocks (32 orbitals) per workgroup, split BF16
+ * only (8, 9 keep the running Taylor sum in LDS); a shape serves
  * M <= 16 waves blocks; split BF16 needs M % 8 == 0; E_SHAPE otherwise).
  * phi, out:
  * nw x 2 x N x M (plane 0 real, plane 1 imaginary of orbital columns); P:

@@ -114,7 +114,7 @@ __global__ __launch_bounds__(64 * WGM * WGN) void k_exchange(
     typedef Core<TS, TS, TC, BM, BN, BK, WGM, WGN, V, V, AL> C;
     constexpr int NT = C::NT;
     typedef typename std::conditional<std::is_same<TC, double>::value, double, float>::type accs;
-    constexpr int SP = BN + 1;
+    constexpr int SP = BN + 4;  // 4 SP = 16 (mod 64 banks): conflict-free tile stores
     constexpr int OPB = (C::LDS_A + C::LDS_B) * sizeof(typename C::LT);
     constexpr int SB = BM * SP * sizeof(accs);
     constexpr int SMEM = OPB > SB ? OPB : SB;

@@ -62,6 +62,10 @@ __global__ __launch_bounds__(256) void k_unpack(const T* __restrict__ pk, T* __r
 
 // Raw buffer loads: 32-bit byte offsets against a descriptor of the operand
 // (no 64-bit address registers; offsets past the end read as zero).
+// LDS row pitches of the propagation state for M <= 256 (elements): 16-byte
+// aligned rows whose starts step across the banks.
+constexpr int kPitchF = 260, kPitchB = 264;
+
 constexpr int kBufFlags = 0x00020000;  // gfx9-family raw buffer descriptor word 3
 constexpr int kOutOfRange = 0x40000000;
 
@@ -129,9 +133,9 @@ __device__ __forceinline__ void term_update(V& acc, V& z, S_ inv) {
 // buffer load of B per chunk, straight into registers (each B column block
 // belongs to one wave, so no staging and no barrier inside the pass).  B
 // loads run one chunk ahead.  Columns >= M of B multiply zero columns of S.
-template <typename T, int MAXB, int NPB, bool PF>
+template <typename T, int MAXB, int NPB, bool PF, int SPT>
 __device__ __forceinline__ void pass(__amdgpu_buffer_rsrc_t rb, int M, int Mp, int MB,
-                                     const T* S, int SPT, const int* cb,
+                                     const T* S, const int* cb,
                                      typename AccT<T>::v (&acc)[MAXB][2]) {
     const int lane = threadIdx.x & 63;
     const int g = lane >> 4, li = lane & 15;
@@ -214,8 +218,10 @@ __global__ __launch_bounds__(64 * NWAVE, 2) void k_propagate(
     constexpr int NT = 64 * NWAVE;
     const int Mp = (M + 15) / 16 * 16;
     const int MB = Mp / 16;
-    const int SPT = Mp + 4;  // 16-byte aligned rows, staggered banks
-    const long splane = 16L * SPT;
+    // fixed row pitch for M <= 256 (16-byte aligned rows, staggered banks):
+    // LDS offsets become instruction immediates
+    constexpr int SPT = kPitchF;
+    constexpr long splane = 16L * SPT;
     const long nblk = (long)nw * nrb;
     const long per = (nblk + 7) / 8;
     const long L = (long)(blockIdx.x % 8) * per + blockIdx.x / 8;
@@ -264,7 +270,7 @@ __global__ __launch_bounds__(64 * NWAVE, 2) void k_propagate(
         }
     };
     // first one-body half
-    pass<T, MAXB, 1, PF>(rP, M, Mp, MB, S, SPT, cb, acc);
+    pass<T, MAXB, 1, PF, SPT>(rP, M, Mp, MB, S, cb, acc);
     __syncthreads();
 #pragma unroll
     for (int s = 0; s < MAXB; ++s) {
@@ -275,7 +281,7 @@ __global__ __launch_bounds__(64 * NWAVE, 2) void k_propagate(
     __syncthreads();
     // Taylor series of exp(A): term_n = A term_{n-1} / n, z = sum of terms
     for (int n = 1; n <= K; ++n) {
-        pass<T, MAXB, 2, PF>(rA, M, Mp, MB, S, SPT, cb, acc);
+        pass<T, MAXB, 2, PF, SPT>(rA, M, Mp, MB, S, cb, acc);
         __syncthreads();
         const T inv = sizeof(T) == 8 ? (T)inv_n_d(n) : (T)inv_n_f(n);
 #pragma unroll
@@ -292,7 +298,7 @@ __global__ __launch_bounds__(64 * NWAVE, 2) void k_propagate(
         __syncthreads();
     }
     // second one-body half, FP64 result
-    pass<T, MAXB, 1, PF>(rP, M, Mp, MB, S, SPT, cb, acc);
+    pass<T, MAXB, 1, PF, SPT>(rP, M, Mp, MB, S, cb, acc);
 #pragma unroll
     for (int s = 0; s < MAXB; ++s) {
         const int col = cb[s] * 16 + (lane & 15);
@@ -327,9 +333,9 @@ __device__ __forceinline__ bf8 bload8(__amdgpu_buffer_rsrc_t r, int off) {
 
 // acc[s] = S x A_w^T for this wave's column blocks; K in chunks of 32, lane
 // group g supplying k = k0 + 8 g + e (e < 8) for both operands.
-template <int MAXB, bool PF>
+template <int MAXB, bool PF, int SPB>
 __device__ __forceinline__ void pass_split(__amdgpu_buffer_rsrc_t rb, int M, int Mp, int MB,
-                                           const bf16_t* Sb, int SPB, const int* cb,
+                                           const bf16_t* Sb, const int* cb,
                                            f4 (&acc)[MAXB][2]) {
     const int lane = threadIdx.x & 63;
     const int g = lane >> 4, li = lane & 15;
@@ -415,8 +421,8 @@ __global__ __launch_bounds__(64 * NWAVE, 2) void k_propagate_split(
     constexpr int NT = 64 * NWAVE;
     const int Mp = (M + 31) / 32 * 32;
     const int MB = (M + 15) / 16;
-    const int SPT = Mp + 4, SPB = Mp + 8;
-    const long splane = 16L * SPT, bplane = 16L * SPB;
+    constexpr int SPT = kPitchF, SPB = kPitchB;  // fixed pitches (M <= 256)
+    constexpr long splane = 16L * SPT, bplane = 16L * SPB;
     const long nblk = (long)nw * nrb;
     const long per = (nblk + 7) / 8;
     const long L = (long)(blockIdx.x % 8) * per + blockIdx.x / 8;
@@ -493,7 +499,7 @@ __global__ __launch_bounds__(64 * NWAVE, 2) void k_propagate_split(
             S[splane + off] = ok ? vi[r] : 0.0f;
         }
     };
-    pass<float, MAXB, 1, PF>(rP, M, Mp, MB, S, SPT, cb, acc);
+    pass<float, MAXB, 1, PF, SPT>(rP, M, Mp, MB, S, cb, acc);
     __syncthreads();
     zero_b();
 #pragma unroll
@@ -504,7 +510,7 @@ __global__ __launch_bounds__(64 * NWAVE, 2) void k_propagate_split(
     }
     __syncthreads();
     for (int n = 1; n <= K; ++n) {
-        pass_split<MAXB, PF>(rA, M, Mp, MB, Sb, SPB, cb, acc);
+        pass_split<MAXB, PF, SPB>(rA, M, Mp, MB, Sb, cb, acc);
         __syncthreads();
         const float inv = inv_n_f(n);
         if (n == K) zero_f();
@@ -528,7 +534,7 @@ __global__ __launch_bounds__(64 * NWAVE, 2) void k_propagate_split(
             if (cb[s] < MB) put_f(s, z[s][0], z[s][1]);
         __syncthreads();
     }
-    pass<float, MAXB, 1, PF>(rP, M, Mp, MB, S, SPT, cb, acc);
+    pass<float, MAXB, 1, PF, SPT>(rP, M, Mp, MB, S, cb, acc);
 #pragma unroll
     for (int s = 0; s < MAXB; ++s) {
         const int col = cb[s] * 16 + li;
@@ -619,11 +625,10 @@ __device__ __forceinline__ void pass_split_rb(__amdgpu_buffer_rsrc_t rb, int M, 
         for (int r = 0; r < RB; ++r) {
             if (r >= nrbv) continue;  // wave-uniform
             const bf16_t* s0 = Sb + (r * 16 + li) * SPB + 8 * g + k0;
+            // real-part fragments first, then the imaginary ones (fewer live
+            // registers; each accumulator sees the same product order)
             const bf8 rh = *reinterpret_cast<const bf8*>(s0);
             const bf8 rl = *reinterpret_cast<const bf8*>(s0 + spl);
-            const bf8 ih = *reinterpret_cast<const bf8*>(s0 + 2 * spl);
-            const bf8 il = *reinterpret_cast<const bf8*>(s0 + 3 * spl);
-            const bf8 nh = neg8(ih), nl = neg8(il);
 #pragma unroll
             for (int s = 0; s < MAXB; ++s) {
                 if (cb[s] >= MB) continue;  // wave-uniform
@@ -631,12 +636,22 @@ __device__ __forceinline__ void pass_split_rb(__amdgpu_buffer_rsrc_t rb, int M, 
                 ar = mma8(rl, bc[s][0], ar);
                 ar = mma8(rh, bc[s][1], ar);
                 ar = mma8(rh, bc[s][0], ar);
-                ar = mma8(nl, bc[s][2], ar);
-                ar = mma8(nh, bc[s][3], ar);
-                ar = mma8(nh, bc[s][2], ar);
                 ai = mma8(rl, bc[s][2], ai);
                 ai = mma8(rh, bc[s][3], ai);
                 ai = mma8(rh, bc[s][2], ai);
+                acc[r][s][0] = ar;
+                acc[r][s][1] = ai;
+            }
+            const bf8 ih = *reinterpret_cast<const bf8*>(s0 + 2 * spl);
+            const bf8 il = *reinterpret_cast<const bf8*>(s0 + 3 * spl);
+            const bf8 nh = neg8(ih), nl = neg8(il);
+#pragma unroll
+            for (int s = 0; s < MAXB; ++s) {
+                if (cb[s] >= MB) continue;  // wave-uniform
+                f4 ar = acc[r][s][0], ai = acc[r][s][1];
+                ar = mma8(nl, bc[s][2], ar);
+                ar = mma8(nh, bc[s][3], ar);
+                ar = mma8(nh, bc[s][2], ar);
                 ai = mma8(il, bc[s][0], ai);
                 ai = mma8(ih, bc[s][1], ai);
                 ai = mma8(ih, bc[s][0], ai);
@@ -650,7 +665,8 @@ __device__ __forceinline__ void pass_split_rb(__amdgpu_buffer_rsrc_t rb, int M, 
     }
 }
 
-template <int NWAVE, int MAXB, int RB>
+// ZREG: the running Taylor sum in registers (else in LDS beside the state).
+template <int NWAVE, int MAXB, int RB, bool ZREG>
 __global__ __launch_bounds__(64 * NWAVE, 1) void k_propagate_split_rb(
     const double* __restrict__ phi, double* __restrict__ phi_out, const float* __restrict__ Pm,
     const bf16_t* __restrict__ Af, const uint8_t* __restrict__ live, int nw, int M, int N, int K,
@@ -660,8 +676,9 @@ __global__ __launch_bounds__(64 * NWAVE, 1) void k_propagate_split_rb(
     constexpr int ROWS = 16 * RB;
     const int Mp = (M + 31) / 32 * 32;
     const int MB = (M + 15) / 16;
-    const int SPT = Mp + 4, SPB = Mp + 8;
-    const long splane = (long)ROWS * SPT, bplane = (long)ROWS * SPB;
+    // fixed row pitches (M <= 256): LDS offsets become instruction immediates
+    constexpr int SPT = kPitchF, SPB = kPitchB;
+    constexpr long splane = (long)ROWS * SPT, bplane = (long)ROWS * SPB;
     float* S = reinterpret_cast<float*>(smem_raw);
     bf16_t* Sb = reinterpret_cast<bf16_t*>(smem_raw);
     // running Taylor sum, FP32, same layout as the FP32 view (own elements
@@ -701,6 +718,7 @@ __global__ __launch_bounds__(64 * NWAVE, 1) void k_propagate_split_rb(
     for (int s = 0; s < MAXB; ++s) cb[s] = vw + s * NWAVE;
     __syncthreads();
     f4 acc[RB][MAXB][2];
+    f4 zr[ZREG ? RB : 1][MAXB][2];
     const long Aplane = (long)M * M;
     const __amdgpu_buffer_rsrc_t rP = make_rsrc(Pm, Aplane);
     const __amdgpu_buffer_rsrc_t rA = make_rsrc(Af + (long)w * 4 * Aplane, 4 * Aplane);
@@ -744,6 +762,16 @@ __global__ __launch_bounds__(64 * NWAVE, 1) void k_propagate_split_rb(
     };
     // z (this thread's elements) <- v, or += v
     auto zacc = [&](int r, int s, f4& vr, f4& vi, bool first) {
+        if constexpr (ZREG) {
+            if (first) {
+                zr[r][s][0] = vr;
+                zr[r][s][1] = vi;
+            } else {
+                vr = zr[r][s][0] = zr[r][s][0] + vr;
+                vi = zr[r][s][1] = zr[r][s][1] + vi;
+            }
+            return;
+        }
         const int col = cb[s] * 16 + li;
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
@@ -829,24 +857,25 @@ __global__ __launch_bounds__(64 * NWAVE, 1) void k_propagate_split_rb(
         }
 }
 
-template <int NWAVE, int MAXB, int RB>
+template <int NWAVE, int MAXB, int RB, bool ZREG>
 hipError_t launch_prop_split_rb(const double* phi, double* phi_out, const void* Pm, const void* Af,
                                 const uint8_t* live, int nw, int M, int N, int K, hipStream_t s) {
     const int Mp = (M + 31) / 32 * 32;
     // BF16 view (>= the FP32 view) + the FP32 running sum
-    const size_t shm = 4 * 16 * RB * (size_t)(Mp + 8) * sizeof(bf16_t) +
-                       2 * 16 * RB * (size_t)(Mp + 4) * sizeof(float);
+    (void)Mp;
+    const size_t shm = 4 * 16 * RB * (size_t)kPitchB * sizeof(bf16_t) +
+                       (ZREG ? 0 : 2 * 16 * RB * (size_t)kPitchF * sizeof(float));
     const int nrb = (N + 16 * RB - 1) / (16 * RB);
     const long nblk = (long)nw * nrb;
     const long grid = ((nblk + 7) / 8) * 8;
     static bool attr = false;
     if (!attr && shm > 65536) {
-        hipError_t e = hipFuncSetAttribute((const void*)k_propagate_split_rb<NWAVE, MAXB, RB>,
+        hipError_t e = hipFuncSetAttribute((const void*)k_propagate_split_rb<NWAVE, MAXB, RB, ZREG>,
                                            hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
         if (e != hipSuccess) return e;
         attr = true;
     }
-    hipLaunchKernelGGL((k_propagate_split_rb<NWAVE, MAXB, RB>), dim3(grid), dim3(64 * NWAVE), shm,
+    hipLaunchKernelGGL((k_propagate_split_rb<NWAVE, MAXB, RB, ZREG>), dim3(grid), dim3(64 * NWAVE), shm,
                        s, phi, phi_out, (const float*)Pm, (const bf16_t*)Af, live, nw, M, N, K, nrb);
     return hipGetLastError();
 }
@@ -854,8 +883,7 @@ hipError_t launch_prop_split_rb(const double* phi, double* phi_out, const void* 
 template <int NWAVE, int MAXB, bool PF>
 hipError_t launch_prop_split(const double* phi, double* phi_out, const void* Pm, const void* Af,
                              const uint8_t* live, int nw, int M, int N, int K, hipStream_t s) {
-    const int Mp = (M + 31) / 32 * 32;
-    const size_t shm = 4 * 16 * (size_t)(Mp + 8) * sizeof(bf16_t);  // >= the FP32 view
+    const size_t shm = 4 * 16 * (size_t)kPitchB * sizeof(bf16_t);  // >= the FP32 view
     const int nrb = (N + 15) / 16;
     const long nblk = (long)nw * nrb;
     const long grid = ((nblk + 7) / 8) * 8;
@@ -917,8 +945,7 @@ __global__ __launch_bounds__(256) void k_unpack_split(const float* __restrict__ 
 template <typename T, int NWAVE, int MAXB, bool PF>
 hipError_t launch_prop(const double* phi, double* phi_out, const void* Pm, const void* Af,
                        const uint8_t* live, int nw, int M, int N, int K, hipStream_t s) {
-    const int Mp = (M + 15) / 16 * 16;
-    const size_t shm = 2 * 16 * (size_t)(Mp + 4) * sizeof(T);
+    const size_t shm = 2 * 16 * (size_t)kPitchF * sizeof(T);
     const int nrb = (N + 15) / 16;
     const long nblk = (long)nw * nrb;
     const long grid = ((nblk + 7) / 8) * 8;
@@ -964,8 +991,9 @@ struct PropShape {
     int rows;  // row blocks per workgroup (split BF16 only when > 1)
 };
 constexpr PropShape kPropShapes[kPropVariants] = {
-    {8, 2, true, 1},  {4, 2, true, 1},  {4, 1, true, 1},  {2, 2, true, 1},  {8, 2, false, 1},
-    {4, 2, false, 1}, {4, 1, false, 1}, {2, 2, false, 1}, {16, 1, false, 2}, {8, 1, false, 2}};
+    {8, 2, true, 1},   {4, 2, true, 1},   {4, 1, true, 1}, {2, 2, true, 1},
+    {8, 2, false, 1},  {4, 2, false, 1},  {4, 1, false, 1}, {2, 2, false, 1},
+    {16, 1, false, 2}, {8, 1, false, 2},  {8, 2, false, 2}, {4, 2, false, 2}};
 }  // namespace
 
 bool propagate_variant_ok(int v, int M, DType t, DType ta) {
@@ -1005,9 +1033,14 @@ hipError_t propagate(const double* phi, double* phi_out, const void* Pm, const v
         AFQ_S(6, 4, 1, false)
         AFQ_S(7, 2, 2, false)
         if (variant == 8)
-            return launch_prop_split_rb<16, 1, 2>(phi, phi_out, Pm, Af, live, nw, M, N, K, s);
+            return launch_prop_split_rb<16, 1, 2, false>(phi, phi_out, Pm, Af, live, nw, M, N, K,
+                                                         s);
         if (variant == 9)
-            return launch_prop_split_rb<8, 1, 2>(phi, phi_out, Pm, Af, live, nw, M, N, K, s);
+            return launch_prop_split_rb<8, 1, 2, false>(phi, phi_out, Pm, Af, live, nw, M, N, K, s);
+        if (variant == 10)
+            return launch_prop_split_rb<8, 2, 2, true>(phi, phi_out, Pm, Af, live, nw, M, N, K, s);
+        if (variant == 11)
+            return launch_prop_split_rb<4, 2, 2, true>(phi, phi_out, Pm, Af, live, nw, M, N, K, s);
     } else {
         AFQ_P(0, float, 8, 2, true)
         AFQ_P(1, float, 4, 2, true)

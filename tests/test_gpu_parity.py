@@ -303,7 +303,8 @@ def test_propagation_shapes_bitwise(lib, dims, prec):
     base = lib.selftest_propagate(phi, P, A, 6, prec, variant=0)
     # variant: (waves, column blocks per wave, prefetch, row blocks per workgroup)
     shapes = {0: (8, 2, 1, 1), 1: (4, 2, 1, 1), 2: (4, 1, 1, 1), 3: (2, 2, 1, 1), 4: (8, 2, 0, 1),
-              5: (4, 2, 0, 1), 6: (4, 1, 0, 1), 7: (2, 2, 0, 1), 8: (16, 1, 0, 2), 9: (8, 1, 0, 2)}
+              5: (4, 2, 0, 1), 6: (4, 1, 0, 1), 7: (2, 2, 0, 1), 8: (16, 1, 0, 2), 9: (8, 1, 0, 2),
+              10: (8, 2, 0, 2), 11: (4, 2, 0, 2)}
     ran = 0
     for v, (waves, blocks, pf, rows) in shapes.items():
         ok = ((M + 15) // 16 <= waves * blocks and not (prec == "fp64" and not pf)
