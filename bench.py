@@ -86,6 +86,29 @@ def cpu_baseline(cfg, n_walkers, n_steps):
                       f"{cfg.measure_every}), FP64 numpy, {el:.1f} s"}
 
 
+def _traffic(roof, cfg, prec, shapes):
+    """HBM bytes per launch of the dominant kernel from the committed counter
+    summary (FETCH_SIZE / WRITE_SIZE scaled by a copy kernel of known size),
+    only while the kernel source, shape and workload are the ones profiled."""
+    import glob
+    import hashlib
+    for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "traffic_*.json"))):
+        with open(path) as f:
+            t = json.load(f)
+        src = os.path.join(ROOT, t["source"])
+        with open(src, "rb") as f:
+            sha = hashlib.sha256(f.read()).hexdigest()
+        if (roof["kernel"] == "propagate" and sha == t["source_sha256"] and prec == t["precision"]
+                and cfg.M == t["M"] and cfg.n_walkers == t["n_walkers"]
+                and all(s[2] == t["prop_shape"] for s in shapes)):
+            rd, wr = t["read_bytes_per_launch"], t["write_bytes_per_launch"]
+            roof["traffic"] = rd + wr
+            roof["traffic_detail"] = {"read_bytes": rd, "write_bytes": wr,
+                                      "kernel": t["kernel"],
+                                      "source": "profiles/" + os.path.basename(path)}
+            return
+
+
 def _roofline(prof_a, prof_b, steps, cfg, prec):
     phases = {}
     for name in prof_a:
@@ -188,6 +211,7 @@ def bench_pair(args):
     trace = np.concatenate([x for x in (tr_w, tr_t, tr_p) if len(x)])
     tuned = [list(lib.autotune(x)) for x in (ga, gb)]  # cached: the shapes the graph used
     phases, roofline = _roofline(prof_a, prof_b, args.profile_steps, cfg, prec)
+    _traffic(roofline, cfg, prec, tuned)
     roofline["measured_over"] = (f"{args.profile_steps} pair-steps of the same run, direct "
                                  "launches, HIP events around every launch on its stream")
 

@@ -159,7 +159,8 @@ __device__ __forceinline__ d4v mma64(double a, double b, d4v c) {
 }
 
 // EPT: matrix elements per thread in the elimination (n * n <= 256 EPT);
-// KS: k steps of 4 in phase (3) (n <= 4 KS).
+// KS: k steps of 4 in phase (3) (n <= 4 KS); the LDS row pitch 4 KS + 1 is
+// a compile-time constant (odd, so column walks cross the banks).
 template <int EPT, int KS>
 __global__ __launch_bounds__(256) void k_lu_theta(const double* __restrict__ phi,
                                                   const double* __restrict__ trialT,
@@ -179,9 +180,9 @@ __global__ __launch_bounds__(256) void k_lu_theta(const double* __restrict__ phi
         return;
     }
     if (!live[w]) return;
-    const int LP = n + 1;  // odd row pitch
+    constexpr int LP = 4 * KS + 1;
     double* ar = sh;
-    double* ai = sh + n * LP;
+    double* ai = sh + 4 * KS * LP;
     __shared__ int rho[64];
     __shared__ double piv_r[64], piv_i[64];
     __shared__ int s_swaps;
@@ -661,7 +662,8 @@ hipError_t lu_theta(const double* phi, const double* trialT, double* theta, void
     if (nw <= 0) return hipSuccess;
     const int nmax = na > nb ? na : nb;
     if (nmax > 64) return hipErrorInvalidValue;
-    const size_t shm = (size_t)2 * nmax * (nmax + 1) * sizeof(double);
+    const int cap = nmax <= 32 ? 32 : (nmax <= 48 ? 48 : 64);  // 4 KS of the variant
+    const size_t shm = (size_t)2 * cap * (cap + 1) * sizeof(double);
     static size_t allowed = 65536;  // raised once per new size, outside graph capture
     if (shm > allowed) {
         for (const void* f : {(const void*)k_lu_theta<4, 8>, (const void*)k_lu_theta<9, 12>,
