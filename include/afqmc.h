@@ -206,7 +206,8 @@ afqmc_status afqmc_get_walkers(afqmc_sys sys, double* phi, double* w, double* lo
 afqmc_status afqmc_sys_info(afqmc_sys sys, int* M, int* n_chol, int* n_alpha, int* n_beta,
                             int* n_walkers, int64_t* step);
 
-/* Snapshot of the walker state (phi, weights, overlaps, Theta, alive, step
+/* Snapshot of the walker state (phi, weights, overlaps, Theta as the step
+ * stores it (FP64 for AFQMC_FP64, else the FP32/BF16 copy), alive, step
  * counter).  dst NULL: *bytes receives the size needed.  Restoring a snapshot
  * and stepping again with the same seed reproduces the original run bit for
  * bit (the fields are a pure function of the step counter). */

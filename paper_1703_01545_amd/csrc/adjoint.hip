@@ -1014,7 +1014,12 @@ afqmc_status energy_adjoint(afqmc_sys s, AdjState* a, hipStream_t st) {
                        a->mode.as<uint8_t>(), a->ebuf.as<double>());
     HIPCHK(hipGetLastError());
     HIPCHK(fbar_to_thbar(s, a, st));
-    // exchange: U = sum_g L^half_g^T T_g^T per spin, T_g = L^half_g Theta
+    // exchange: U = sum_g L^half_g^T T_g^T per spin, T_g = L^half_g Theta, with
+    // the FP64 Theta (the lower-precision plans keep only their copy in the step)
+    if (s->ts != DT_F64)
+        HIPCHK(lu_theta(s->d_phi.as<double>(), s->d_trialT.as<double>(), s->d_theta.as<double>(),
+                        nullptr, DT_F64, s->d_lnd.as<double>(), s->d_alive.as<uint8_t>(), nw, M,
+                        s->N, s->na, s->nb, s->d_ovl.p, st));
     const double* th = s->d_theta.as<double>();
     for (int sp = 0; sp < 2 && nc > 0; ++sp) {
         const int off = sp ? s->na : 0, n = sp ? s->nb : s->na;

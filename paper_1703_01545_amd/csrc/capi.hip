@@ -91,7 +91,7 @@ afqmc_status overlap_theta(afqmc_sys s, double* phi, hipStream_t st) {
     PhaseTimer pt(s, PH_DET_THETA, st);
     HIPCHK(lu_theta(phi, s->d_trialT.as<double>(), s->d_theta.as<double>(),
                     s->ts == DT_F64 ? nullptr : s->d_theta_lp.p, s->ts, s->d_lnd.as<double>(),
-                    s->d_alive.as<uint8_t>(), s->nw, s->M, s->N, s->na, s->nb, st));
+                    s->d_alive.as<uint8_t>(), s->nw, s->M, s->N, s->na, s->nb, s->d_ovl.p, st));
     return AFQMC_OK;
 }
 
@@ -391,6 +391,7 @@ afqmc_status afqmc_init_walkers(afqmc_ham ham, int n_alpha, int n_beta, const do
         {&s->d_Apk, (size_t)nw * 2 * P * dt_size(s->tp)},
         {&s->d_Af, (size_t)nw * 2 * M * M * dt_size(s->tp)},
         {&s->d_lnd, (size_t)nw * 4 * 8},
+        {&s->d_ovl, lu_theta_ws_bytes(nw, n_alpha, n_beta)},
         {&s->d_exch, (size_t)nw * 2 * s->n_gt * 2 * 8},
         {&s->d_el, (size_t)nw * 2 * 8},
         {&s->d_sums, 8 * 8},
@@ -590,7 +591,7 @@ void afqmc_free_sys(afqmc_sys s) {
     for (DevBuf* b : {&s->d_trialT, &s->d_P, &s->d_Plp, &s->d_a, &s->d_lhx, &s->d_lhx_lp,
                       &s->d_phi, &s->d_phinew, &s->d_theta, &s->d_theta_lp, &s->d_w, &s->d_lnov,
                       &s->d_alive, &s->d_F, &s->d_X, &s->d_simp, &s->d_Apk, &s->d_Af,
-                      &s->d_lnd, &s->d_exch, &s->d_el, &s->d_sums})
+                      &s->d_lnd, &s->d_ovl, &s->d_exch, &s->d_el, &s->d_sums})
         b->release();
     drop_batch_plans(s->id);
     free_adjoint(s);
@@ -716,7 +717,10 @@ afqmc_status afqmc_checkpoint(afqmc_sys s, void* dst, size_t* bytes) {
     if (r != AFQMC_OK) return r;
     if (!bytes) return fail(AFQMC_E_INVALID, "bytes is null");
     const size_t nphi = (size_t)s->nw * 2 * s->NM() * 8;
-    const size_t need = 64 + 2 * nphi + s->d_w.n + s->d_lnov.n + s->nw;
+    // Theta as the step stores it: FP64, or the copy in the storage type
+    const DevBuf& th = s->ts == DT_F64 ? s->d_theta : s->d_theta_lp;
+    const size_t nth = (size_t)s->nw * 2 * s->NM() * dt_size(s->ts);
+    const size_t need = 64 + nphi + nth + s->d_w.n + s->d_lnov.n + s->nw;
     if (!dst) {
         *bytes = need;
         return AFQMC_OK;
@@ -729,8 +733,8 @@ afqmc_status afqmc_checkpoint(afqmc_sys s, void* dst, size_t* bytes) {
     p += 64;
     HIPCHK(hipMemcpy(p, s->d_phi.p, nphi, hipMemcpyDeviceToHost));
     p += nphi;
-    HIPCHK(hipMemcpy(p, s->d_theta.p, nphi, hipMemcpyDeviceToHost));
-    p += nphi;
+    HIPCHK(hipMemcpy(p, th.p, nth, hipMemcpyDeviceToHost));
+    p += nth;
     HIPCHK(hipMemcpy(p, s->d_w.p, s->d_w.n, hipMemcpyDeviceToHost));
     p += s->d_w.n;
     HIPCHK(hipMemcpy(p, s->d_lnov.p, s->d_lnov.n, hipMemcpyDeviceToHost));
@@ -745,7 +749,9 @@ afqmc_status afqmc_restore(afqmc_sys s, const void* src, size_t bytes) {
     if (r != AFQMC_OK) return r;
     if (!src) return fail(AFQMC_E_INVALID, "src is null");
     const size_t nphi = (size_t)s->nw * 2 * s->NM() * 8;
-    const size_t need = 64 + 2 * nphi + s->d_w.n + s->d_lnov.n + s->nw;
+    const DevBuf& th = s->ts == DT_F64 ? s->d_theta : s->d_theta_lp;
+    const size_t nth = (size_t)s->nw * 2 * s->NM() * dt_size(s->ts);
+    const size_t need = 64 + nphi + nth + s->d_w.n + s->d_lnov.n + s->nw;
     int64_t hdr[8];
     if (bytes < need) return fail(AFQMC_E_SHAPE, "checkpoint too small for this system");
     memcpy(hdr, src, 64);
@@ -757,17 +763,14 @@ afqmc_status afqmc_restore(afqmc_sys s, const void* src, size_t bytes) {
     HIPCHK(hipStreamSynchronize(st));
     HIPCHK(hipMemcpy(s->d_phi.p, p, nphi, hipMemcpyHostToDevice));
     p += nphi;
-    HIPCHK(hipMemcpy(s->d_theta.p, p, nphi, hipMemcpyHostToDevice));
-    p += nphi;
+    HIPCHK(hipMemcpy(th.p, p, nth, hipMemcpyHostToDevice));
+    p += nth;
     HIPCHK(hipMemcpy(s->d_w.p, p, s->d_w.n, hipMemcpyHostToDevice));
     p += s->d_w.n;
     HIPCHK(hipMemcpy(s->d_lnov.p, p, s->d_lnov.n, hipMemcpyHostToDevice));
     p += s->d_lnov.n;
     HIPCHK(hipMemcpy(s->d_alive.p, p, s->nw, hipMemcpyHostToDevice));
-    if (s->ts != DT_F64) {
-        HIPCHK(convert(s->d_theta.as<double>(), s->d_theta_lp.p, s->ts, (long)s->nw * 2 * s->NM(), st));
-        HIPCHK(hipStreamSynchronize(st));
-    }
+
     s->t = hdr[1];
     return AFQMC_OK;
 }

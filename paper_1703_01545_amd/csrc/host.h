@@ -155,6 +155,7 @@ struct afqmc_sys_s {
     afq::host::DevBuf d_phi, d_phinew, d_theta, d_theta_lp, d_w, d_lnov, d_alive;
     // step scratch
     afq::host::DevBuf d_F, d_X, d_simp, d_Apk, d_Af, d_lnd, d_exch, d_el, d_sums;
+    afq::host::DevBuf d_ovl;  // overlap matrices of the determinant kernels
     int n_gt_a = 0, n_gt_b = 0, n_gt = 0;
     // launch shapes (autotuned; 0 = size heuristic): GEMM tiles of the force
     // bias and the field sum, and the propagation workgroup shape

@@ -118,12 +118,16 @@ hipError_t philox_normals(uint64_t seed, uint64_t stream, int64_t t, int nw, int
 
 // Per walker and spin block: the overlap O = Phi_T^T Phi (trialT: [N][M],
 // rows = trial orbitals), ln det O (lnd[w][spin] complex) and
-// Theta = Phi O^{-1} written to theta (FP64, [w][2][N][M]); optional low
-// precision copy theta_lp (type tlp) for the contractions.  Spin blocks of
-// at most 64 orbitals.
+// Theta = Phi O^{-1}, [w][2][N][M]: with theta_lp NULL the FP64 Theta into
+// theta (FP64 matrix-core products); otherwise Theta in type tlp (DT_F32 or
+// DT_BF16) into theta_lp from FP32 matrix-core products of the rounded FP64
+// operands, theta untouched for spin blocks of at most 48 orbitals (49..64:
+// both written).  Spin blocks of at most 64 orbitals.
+// ws: workspace of lu_theta_ws_bytes(nw, na, nb) bytes (the overlap matrices).
 hipError_t lu_theta(const double* phi, const double* trialT, double* theta, void* theta_lp,
                     DType tlp, double* lnd, const uint8_t* live, int nw, int M, int N, int na,
-                    int nb, hipStream_t s);
+                    int nb, void* ws, hipStream_t s);
+size_t lu_theta_ws_bytes(int nw, int na, int nb);
 
 // Weight update: lnR = sum_s lnd - lnov + s; lnI = lnR + imp;
 // phaseless: w *= exp(Re lnI + shift) max(0, cos Im lnR), frozen when not

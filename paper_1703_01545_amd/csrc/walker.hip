@@ -6,6 +6,7 @@
 #include <math.h>
 
 #include "internal.h"
+#include "mfma.h"
 
 namespace afq {
 namespace {
@@ -373,6 +374,374 @@ __global__ __launch_bounds__(256) void k_lu_theta(const double* __restrict__ phi
     }
 }
 
+// Overlap, determinant and Theta for spin blocks of up to 48 orbitals, in two
+// kernels per (walker, spin block):
+// k_overlap: the transposed overlap B = O^T, B[j][i] = sum_m Phi[j][m]
+//   Phi_T[i][m] (j the walker orbital, i the trial orbital), on the FP64
+//   matrix cores, into a complex workspace [w][spin][j][i] (row pitch nmax);
+// k_det_theta, one wavefront each:
+//   (1) lane j loads row j of B into registers (NC complex entries);
+//   (2) Gauss-Jordan inversion in registers with partial pivoting and no row
+//       exchange.  At step k the column being eliminated is register column
+//       0.  The pivot lane p_k (largest |Re| + |Im| among rows not yet used)
+//       publishes its row through LDS; every lane forms row - mu prow with
+//       mu = row[0] / pivot, shifted one column to the left, and appends -mu
+//       as the new last column (the pivot lane itself: prow / pivot and
+//       1 / pivot, i.e. mu = -1 / pivot and its row zeroed).  After n steps
+//       lane p_c holds (O^{-1})[p_k][c] in register column NC - n + k, and
+//       ln det O = sum_k ln pivot_k + i pi (parity of k -> p_k);
+//   (3) Theta[m][c] = sum_k Phi[m][p_k] (O^{-1})[p_k][c] on the matrix cores:
+//       FP64 into the FP64 Theta (TO = double), or FP32 products of the FP64
+//       operands rounded to FP32 into the lower-precision copy (TO = float or
+//       bf16_t) that the force-bias and exchange contractions read.
+using dev::acc_row;
+using dev::d2;
+using dev::d4;
+using dev::f4;
+using dev::mma1;
+
+template <typename TO>
+struct ThetaMode {
+    typedef float T;  // MFMA operand / accumulator element
+    typedef f4 V;
+};
+template <>
+struct ThetaMode<double> {
+    typedef double T;
+    typedef d4 V;
+};
+
+__device__ __forceinline__ double rdlane(double v, int l) {
+    const unsigned long long x = __builtin_bit_cast(unsigned long long, v);
+    const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)x, l);
+    const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(x >> 32), l);
+    return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
+}
+
+// Maximum of a 64-bit key over the wavefront: DPP prefix maxima within rows
+// of 16 lanes (row_shr 1, 2, 4, 8), then across rows (row_bcast 15 into rows
+// 1 and 3, row_bcast 31 into rows 2 and 3); lane 63 ends with the maximum.
+template <int CTRL, int ROWS>
+__device__ __forceinline__ unsigned long long dpp_max_step(unsigned long long x) {
+    const int lo = (int)(unsigned)x, hi = (int)(unsigned)(x >> 32);
+    const unsigned l2 = (unsigned)__builtin_amdgcn_update_dpp(lo, lo, CTRL, ROWS, 0xF, false);
+    const unsigned h2 = (unsigned)__builtin_amdgcn_update_dpp(hi, hi, CTRL, ROWS, 0xF, false);
+    const unsigned long long y = ((unsigned long long)h2 << 32) | l2;
+    return y > x ? y : x;
+}
+
+__device__ __forceinline__ unsigned long long wave_max_u64(unsigned long long x) {
+    x = dpp_max_step<0x111, 0xF>(x);
+    x = dpp_max_step<0x112, 0xF>(x);
+    x = dpp_max_step<0x114, 0xF>(x);
+    x = dpp_max_step<0x118, 0xF>(x);
+    x = dpp_max_step<0x142, 0xA>(x);
+    x = dpp_max_step<0x143, 0xC>(x);
+    const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)x, 63);
+    const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(x >> 32), 63);
+    return ((unsigned long long)hi << 32) | lo;
+}
+
+// Four consecutive elements m .. m+3 of a row (zeros past M or for an
+// absent row): loads from clamped, valid addresses, masked afterwards.
+__device__ __forceinline__ void row4(const double* __restrict__ row, int m, int M, bool ok,
+                                     double* v) {
+    if ((M & 3) == 0) {
+        const int mc = m < M ? m : M - 4;
+        const d2 a = *(const d2*)(row + mc), b = *(const d2*)(row + mc + 2);
+        const bool t = ok && m < M;
+        v[0] = t ? a[0] : 0.0;
+        v[1] = t ? a[1] : 0.0;
+        v[2] = t ? b[0] : 0.0;
+        v[3] = t ? b[1] : 0.0;
+    } else {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const double x = row[m + q < M ? m + q : M - 1];
+            v[q] = (ok && m + q < M) ? x : 0.0;
+        }
+    }
+}
+
+template <typename TO>
+__device__ __forceinline__ void store_theta(TO* p, double v);
+template <>
+__device__ __forceinline__ void store_theta<double>(double* p, double v) {
+    *p = v;
+}
+template <>
+__device__ __forceinline__ void store_theta<float>(float* p, double v) {
+    *p = (float)v;
+}
+template <>
+__device__ __forceinline__ void store_theta<bf16_t>(bf16_t* p, double v) {
+    *p = (bf16_t)(float)v;
+}
+
+// One wavefront per (walker, spin block); NB 16-wide blocks of orbitals.
+// Each lane reads 4 consecutive basis elements per 16-wide chunk of a row
+// (k = k0 + 4 g + q at sub-step q), so the 16 x 16 tiles take whole row runs.
+template <int NB>
+__global__ __launch_bounds__(64) void k_overlap(const double* __restrict__ phi,
+                                                const double* __restrict__ trialT,
+                                                d2* __restrict__ ovl,
+                                                const uint8_t* __restrict__ live, int M, int N,
+                                                int na, int nb, int nmax) {
+    const int w = blockIdx.x, spin = blockIdx.y;
+    const int off = spin ? na : 0, n = spin ? nb : na;
+    if (n == 0 || !live[w]) return;
+    const int lane = threadIdx.x, li = lane & 15, g = lane >> 4;
+    const long NM = (long)N * M;
+    const double* phr = phi + (long)w * 2 * NM;
+    const int nbn = (n + 15) >> 4;
+    d2* out = ovl + ((long)w * 2 + spin) * nmax * nmax;
+    for (int ib = 0; ib < nbn; ++ib) {
+        const int j = ib * 16 + li;
+        const bool okj = j < n;
+        const double* xr_row = phr + (long)(off + (okj ? j : 0)) * M;
+        const double* xi_row = xr_row + NM;
+        d4 accr[NB], acci[NB];
+#pragma unroll
+        for (int b = 0; b < NB; ++b) accr[b] = acci[b] = (d4){0, 0, 0, 0};
+        for (int k0 = 0; k0 < M; k0 += 16) {
+            const int m = k0 + 4 * g;
+            double xr[4], xi[4];
+            row4(xr_row, m, M, okj, xr);
+            row4(xi_row, m, M, okj, xi);
+#pragma unroll
+            for (int b = 0; b < NB; ++b) {
+                if (b >= nbn) break;
+                const int i = b * 16 + li;
+                double tv[4];
+                row4(trialT + (long)(off + (i < n ? i : 0)) * M, m, M, i < n, tv);
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    accr[b] = __builtin_amdgcn_mfma_f64_16x16x4f64(xr[q], tv[q], accr[b], 0, 0, 0);
+                    acci[b] = __builtin_amdgcn_mfma_f64_16x16x4f64(xi[q], tv[q], acci[b], 0, 0, 0);
+                }
+            }
+        }
+        // element (row j = ib 16 + g + 4 r, column i = b 16 + li)
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+            const int i = b * 16 + li;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int jr = ib * 16 + g + 4 * r;
+                if (b < nbn && jr < n && i < n) out[(long)jr * nmax + i] = (d2){accr[b][r], acci[b][r]};
+            }
+        }
+    }
+}
+
+template <int NC, typename TO>
+__global__ __launch_bounds__(64, NC <= 40 ? 2 : 1) void k_det_theta(
+    const double* __restrict__ phi, const d2* __restrict__ ovl, TO* __restrict__ theta,
+    double* __restrict__ lnd, const uint8_t* __restrict__ live, int M, int N, int na, int nb,
+    int nmax) {
+    typedef typename ThetaMode<TO>::T ET;
+    typedef typename ThetaMode<TO>::V EV;
+    constexpr int NB = (NC + 15) / 16;  // 16-wide blocks
+    constexpr int KS = NC / 4;          // k steps of 4 in (3)
+    constexpr int SP = NC + 1;          // pitch (complex) of the inverse
+    __shared__ __align__(16) unsigned char buf[NC * SP * 2 * sizeof(ET)];
+    __shared__ double pv[2 * NC];
+    __shared__ int ptab[NC];
+
+    const int w = blockIdx.x, spin = blockIdx.y;
+    const int off = spin ? na : 0, n = spin ? nb : na;
+    const int lane = threadIdx.x;
+    double* out_lnd = lnd + ((long)w * 2 + spin) * 2;
+    if (n == 0) {
+        if (lane == 0) out_lnd[0] = out_lnd[1] = 0.0;
+        return;
+    }
+    if (!live[w]) return;
+    const long NM = (long)N * M;
+    const double* phr = phi + (long)w * 2 * NM;
+    const double* phm = phr + NM;
+    const int nbn = (n + 15) >> 4;
+    const int li = lane & 15, g = lane >> 4;
+
+    // (1) row j of B into lane j (unconditional loads from valid addresses,
+    // masked afterwards)
+    double ar[NC], ai[NC];
+    {
+        const d2* row = ovl + ((long)w * 2 + spin) * nmax * nmax + (long)(lane < n ? lane : 0) * nmax;
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            const d2 v = row[c < n ? c : 0];
+            const bool ok = lane < n && c < n;
+            ar[c] = ok ? v[0] : 0.0;
+            ai[c] = ok ? v[1] : 0.0;
+        }
+    }
+
+    // (2) Gauss-Jordan; the pivot row goes from the pivot lane to the others
+    // by lane reads into scalar registers (no LDS traffic in the loop)
+    bool used = lane >= n;
+    int mystep = 0;
+    for (int k = 0; k < n; ++k) {
+        // pivot: the largest |Re| + |Im| among unused rows; key = its bit
+        // pattern (non-negative doubles order as integers) with the low six
+        // bits replaced by 63 - lane, so ties and near-ties (2^-46 relative)
+        // go to the smaller lane; NaN rows are never chosen
+        const double v = fabs(ar[0]) + fabs(ai[0]);
+        const bool sel = !used && v >= 0.0;
+        const unsigned long long key =
+            sel ? ((__builtin_bit_cast(unsigned long long, v) & ~63ull) | (unsigned)(63 - lane))
+                : 0ull;
+        const unsigned long long kmax = wave_max_u64(key);
+        const int p = kmax ? 63 - (int)(kmax & 63) : __ffsll((long long)__ballot(!used)) - 1;
+        const double pr = rdlane(ar[0], p), pi = rdlane(ai[0], p);
+        const double rden = 1.0 / (pr * pr + pi * pi);
+        const double qr = pr * rden, qi = -pi * rden;  // 1 / pivot
+        const bool me = lane == p;
+        if (me) {
+            used = true;
+            mystep = k;
+            pv[2 * k] = pr;
+            pv[2 * k + 1] = pi;
+            ptab[k] = p;
+        }
+        const double mr = me ? -qr : ar[0] * qr - ai[0] * qi;
+        const double mi = me ? -qi : ar[0] * qi + ai[0] * qr;
+        const double al = me ? 0.0 : 1.0;
+#pragma unroll
+        for (int c = 1; c < NC; ++c) {
+            const double sr = rdlane(ar[c], p), si = rdlane(ai[c], p);
+            ar[c - 1] = al * ar[c] - (mr * sr - mi * si);
+            ai[c - 1] = al * ai[c] - (mr * si + mi * sr);
+            // bounded look-ahead of the lane reads (scalar register pressure)
+            if ((c & 7) == 0) __builtin_amdgcn_sched_barrier(0);
+        }
+        ar[NC - 1] = -mr;
+        ai[NC - 1] = -mi;
+    }
+    __syncthreads();
+    // ln det = sum_k ln pivot_k + i pi (inversions of k -> p_k mod 2)
+    {
+        double lr = 0.0, la = 0.0;
+        int inv = 0;
+        bool sing = false;
+        if (lane < n) {
+            const double a = pv[2 * lane], b = pv[2 * lane + 1];
+            sing = (a == 0.0 && b == 0.0);
+            lr = log(hypot(a, b));
+            la = atan2(b, a);
+            const int pk = ptab[lane];
+            for (int k2 = lane + 1; k2 < n; ++k2) inv += ptab[k2] < pk;
+        }
+        lr = wave_sum(lr);
+        la = wave_sum(la);
+#pragma unroll
+        for (int o = 32; o >= 1; o >>= 1) inv += __shfl_xor(inv, o, 64);
+        const bool any_sing = __any(sing);
+        if (lane == 0) {
+            if (any_sing) {
+                out_lnd[0] = -INFINITY;
+                out_lnd[1] = 0.0;
+            } else {
+                out_lnd[0] = lr;
+                out_lnd[1] = la + ((inv & 1) ? M_PI : 0.0);
+            }
+        }
+    }
+    // the inverse into LDS: row c = the step of this lane, column k
+    typedef ET __attribute__((ext_vector_type(2))) E2;
+    E2* S = (E2*)buf;
+    if (lane < n) {
+#pragma unroll
+        for (int c = 0; c < NC; ++c)
+            if (c >= NC - n) S[mystep * SP + c - (NC - n)] = (E2){(ET)ar[c], (ET)ai[c]};
+    }
+    __syncthreads();
+
+    // (3) Theta rows c = sum_k S[c][k] Phi rows p_k.  Every load is issued
+    // unconditionally from a valid address and masked afterwards, so the
+    // loops unroll and the loads of one column block go out together.
+    long roff[KS];
+    bool kok[KS];
+#pragma unroll
+    for (int s = 0; s < KS; ++s) {
+        const int k = 4 * s + g;
+        kok[s] = k < n;
+        roff[s] = (long)(off + ptab[kok[s] ? k : 0]) * M;
+    }
+    // the inverse operand: element (c, k) of S, zero outside n x n (held in
+    // registers for FP32; re-read from LDS for FP64, which has no room)
+    auto a_op = [&](int cb, int s) -> E2 {
+        const int c = cb * 16 + li, k = 4 * s + g;
+        const E2 v = S[(c < n ? c : 0) * SP + (kok[s] ? k : 0)];
+        const bool ok = c < n && kok[s];
+        return (E2){ok ? v[0] : (ET)0, ok ? v[1] : (ET)0};
+    };
+    constexpr bool HOLD = sizeof(ET) == 4;
+    E2 a_h[HOLD ? NB : 1][HOLD ? KS : 1];
+    if constexpr (HOLD) {
+#pragma unroll
+        for (int cb = 0; cb < NB; ++cb)
+#pragma unroll
+            for (int s = 0; s < KS; ++s) a_h[cb][s] = a_op(cb, s);
+    }
+    TO* tr_ = theta + (long)w * 2 * NM;
+    TO* ti_ = tr_ + NM;
+    const int nmb = (M + 15) >> 4;
+    // the Phi operand of the next column block is loaded while the current
+    // one is on the matrix cores
+    double xr[KS], xi[KS];
+    auto load_b = [&](int mb_) {
+        const int mm = mb_ * 16 + li;
+        const int mc = mm < M ? mm : M - 1;
+#pragma unroll
+        for (int s = 0; s < KS; ++s) {
+            xr[s] = phr[roff[s] + mc];
+            xi[s] = phm[roff[s] + mc];
+        }
+    };
+    load_b(0);
+    for (int mb = 0; mb < nmb; ++mb) {
+        const int m = mb * 16 + li;
+        const bool mok = m < M;
+        ET br[KS], bi[KS];
+#pragma unroll
+        for (int s = 0; s < KS; ++s) {
+            br[s] = (kok[s] && mok) ? (ET)xr[s] : (ET)0;
+            bi[s] = (kok[s] && mok) ? (ET)xi[s] : (ET)0;
+        }
+        load_b(mb + 1 < nmb ? mb + 1 : mb);
+#pragma unroll
+        for (int cb = 0; cb < NB; ++cb) {
+            if (cb < nbn) {
+                EV cr = {0, 0, 0, 0}, ci = {0, 0, 0, 0};
+#pragma unroll
+                for (int s = 0; s < KS; ++s) {
+                    E2 a;
+                    if constexpr (HOLD)
+                        a = a_h[cb][s];
+                    else
+                        a = a_op(cb, s);
+                    cr = mma1(a[0], br[s], cr);
+                    cr = mma1(-a[1], bi[s], cr);
+                    ci = mma1(a[0], bi[s], ci);
+                    ci = mma1(a[1], br[s], ci);
+                }
+                if (mok) {
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const int row = cb * 16 + acc_row<ET>(lane, r);
+                        if (row < n) {
+                            const long o = (long)(off + row) * M + m;
+                            store_theta<TO>(tr_ + o, cr[r]);
+                            store_theta<TO>(ti_ + o, ci[r]);
+                        }
+                    }
+                }
+            }
+        }
+    }
+}
+
 __global__ void k_weights(const double* __restrict__ lnd, const double* __restrict__ s_imp,
                           double* __restrict__ lnov, double* __restrict__ w,
                           uint8_t* __restrict__ alive, int nw, int mode, int commit,
@@ -656,33 +1025,62 @@ hipError_t philox_normals(uint64_t seed, uint64_t stream, int64_t t, int nw, int
     return hipGetLastError();
 }
 
+template <int NC>
+hipError_t det_theta_nc(const double* phi, const double* trialT, double* theta, void* theta_lp,
+                        DType tlp, double* lnd, const uint8_t* live, int nw, int M, int N, int na,
+                        int nb, void* ws, hipStream_t s) {
+    const dim3 grid(nw, 2), blk(64);
+    const int nmax = na > nb ? na : nb;
+    d2* ovl = (d2*)ws;
+    hipLaunchKernelGGL((k_overlap<(NC + 15) / 16>), grid, blk, 0, s, phi, trialT, ovl, live, M, N,
+                       na, nb, nmax);
+    if (!theta_lp)
+        hipLaunchKernelGGL((k_det_theta<NC, double>), grid, blk, 0, s, phi, ovl, theta, lnd, live,
+                           M, N, na, nb, nmax);
+    else if (tlp == DT_F32)
+        hipLaunchKernelGGL((k_det_theta<NC, float>), grid, blk, 0, s, phi, ovl, (float*)theta_lp,
+                           lnd, live, M, N, na, nb, nmax);
+    else
+        hipLaunchKernelGGL((k_det_theta<NC, bf16_t>), grid, blk, 0, s, phi, ovl,
+                           (bf16_t*)theta_lp, lnd, live, M, N, na, nb, nmax);
+    return hipGetLastError();
+}
+
+size_t lu_theta_ws_bytes(int nw, int na, int nb) {
+    const int nmax = na > nb ? na : nb;
+    return nmax <= 48 ? (size_t)nw * 2 * nmax * nmax * 16 : 0;
+}
+
 hipError_t lu_theta(const double* phi, const double* trialT, double* theta, void* theta_lp,
                     DType tlp, double* lnd, const uint8_t* live, int nw, int M, int N, int na,
-                    int nb, hipStream_t s) {
+                    int nb, void* ws, hipStream_t s) {
     if (nw <= 0) return hipSuccess;
     const int nmax = na > nb ? na : nb;
-    if (nmax > 64) return hipErrorInvalidValue;
-    const int cap = nmax <= 32 ? 32 : (nmax <= 48 ? 48 : 64);  // 4 KS of the variant
-    const size_t shm = (size_t)2 * cap * (cap + 1) * sizeof(double);
-    static size_t allowed = 65536;  // raised once per new size, outside graph capture
-    if (shm > allowed) {
-        for (const void* f : {(const void*)k_lu_theta<4, 8>, (const void*)k_lu_theta<9, 12>,
-                              (const void*)k_lu_theta<16, 16>}) {
-            hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                               (int)shm);
-            if (e != hipSuccess) return e;
-        }
-        allowed = shm;
+    if (nmax > 64 || (theta_lp && tlp == DT_F64)) return hipErrorInvalidValue;
+    // one wavefront per block, the rows in registers, up to 48 orbitals
+#define AFQ_DET(NC) \
+    if (nmax <= NC) \
+        return det_theta_nc<NC>(phi, trialT, theta, theta_lp, tlp, lnd, live, nw, M, N, na, nb, \
+                                ws, s);
+    AFQ_DET(8)
+    AFQ_DET(16)
+    AFQ_DET(24)
+    AFQ_DET(32)
+    AFQ_DET(40)
+    AFQ_DET(48)
+#undef AFQ_DET
+    // larger blocks: one workgroup of four wavefronts per block, the matrix in
+    // LDS (writes the FP64 Theta and, if requested, the copy)
+    const size_t shm = (size_t)2 * 64 * 65 * sizeof(double);
+    static bool attr = false;  // set once, outside graph capture
+    if (!attr) {
+        hipError_t e = hipFuncSetAttribute((const void*)k_lu_theta<16, 16>,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+        if (e != hipSuccess) return e;
+        attr = true;
     }
-    if (nmax <= 32)
-        hipLaunchKernelGGL((k_lu_theta<4, 8>), dim3(nw, 2), dim3(256), shm, s, phi, trialT, theta,
-                           theta_lp, tlp, lnd, live, M, N, na, nb);
-    else if (nmax <= 48)
-        hipLaunchKernelGGL((k_lu_theta<9, 12>), dim3(nw, 2), dim3(256), shm, s, phi, trialT, theta,
-                           theta_lp, tlp, lnd, live, M, N, na, nb);
-    else
-        hipLaunchKernelGGL((k_lu_theta<16, 16>), dim3(nw, 2), dim3(256), shm, s, phi, trialT,
-                           theta, theta_lp, tlp, lnd, live, M, N, na, nb);
+    hipLaunchKernelGGL((k_lu_theta<16, 16>), dim3(nw, 2), dim3(256), shm, s, phi, trialT, theta,
+                       theta_lp, tlp, lnd, live, M, N, na, nb);
     return hipGetLastError();
 }
 

@@ -68,7 +68,7 @@ def test_device_fields_match_oracle_generator(lib):
 
 
 def _run_pair_both(lib, torch, wl: Workload, n_steps, ortho, meas, fields=None, philox_seed=None,
-                   K=6, walkers_sub=None):
+                   K=6, walkers_sub=None, precision="fp64"):
     sa, sb = wl.oracle_systems(K)
     wa, wb = O.init_walkers(sa, wl.nw if walkers_sub is None else len(walkers_sub)), None
     wb = O.init_walkers(sb, wl.nw if walkers_sub is None else len(walkers_sub))
@@ -79,7 +79,8 @@ def _run_pair_both(lib, torch, wl: Workload, n_steps, ortho, meas, fields=None, 
         ff = O.PhiloxFields(philox_seed, 0, wl.n_chol, walkers=walkers_sub)
         dev = None
     ref = O.run_pair(sa, sb, wa, wb, ff, n_steps, ortho, meas)
-    H, (ga, gb) = wl.gpu_systems(lib, K=K, ortho_every=ortho, measure_every=meas)
+    H, (ga, gb) = wl.gpu_systems(lib, precision=precision, K=K, ortho_every=ortho,
+                                 measure_every=meas)
     tr = lib.pair_step(ga, gb, n_steps, seed=philox_seed or 0, fields=dev)
     torch.cuda.synchronize()
     return ref, tr, (wa, wb), (ga, gb), (sa, sb)
@@ -129,7 +130,8 @@ def test_parity_pair_m12_device_philox(lib, torch_mod):
 
 
 @pytest.mark.parametrize("dims", [(37, 75, 7, 6, 7, 5, 37), (19, 9, 4, 0, 3, 0, 70),
-                                  (64, 130, 16, 16, 16, 15, 5)])
+                                  (64, 130, 16, 16, 16, 15, 5), (60, 90, 44, 41, 44, 40, 6),
+                                  (70, 100, 56, 50, 56, 49, 4)])
 def test_parity_ragged(lib, torch_mod, dims):
     """Sizes that leave ragged tails in every tile dimension."""
     M, nc, a1, b1, a2, b2, nw = dims
@@ -142,6 +144,26 @@ def test_parity_ragged(lib, torch_mod, dims):
         assert np.max(np.abs(tr[:, col] - r) / np.maximum(np.abs(r), 1e-3)) < TOL, key
     _compare_walkers(ga, wa)
     _compare_walkers(gb, wb)
+
+
+# Reduced-precision plans against the FP64 oracle on the same fields.  FP32
+# storage (unit roundoff 6e-8) and split-BF16 products (about 2^-17 relative
+# per product, averaged over the contractions) leave about 1e-6 relative in
+# the energies over 40 steps; the bound 1e-5 keeps a 10x margin and still
+# fails on a dropped split term (plain BF16 products: about 4e-4).
+@pytest.mark.parametrize("dims", [(37, 75, 7, 6, 7, 5, 37), (64, 130, 16, 16, 16, 15, 16)])
+@pytest.mark.parametrize("prec,tol", [("fp32", 1e-5), ("bf16", 1e-5), ("bf16x3", 1e-5),
+                                      ("bf16_plain", 5e-3)])
+def test_reduced_precision_close_to_oracle(lib, torch_mod, dims, prec, tol):
+    M, nc, a1, b1, a2, b2, nw = dims
+    banner(f"{prec} vs oracle {dims}")
+    wl = Workload(M, nc, a1, b1, a2, b2, nw, 0.01, ham_seed=3, e_core=1.25)
+    x = wl.fields(40, seed=5)
+    ref, tr, _, _, _ = _run_pair_both(lib, torch_mod, wl, 40, 5, 4, fields=x, precision=prec)
+    scale = max(np.max(np.abs(ref["EA"])), np.max(np.abs(ref["EB"])))
+    for col, key in enumerate(("EA", "EB", "dE")):
+        err = np.max(np.abs(tr[:, col] - np.asarray(ref[key])))
+        assert err <= tol * scale, (key, err, scale)
 
 
 def test_parity_m100_sampled_walkers(lib, torch_mod):
