@@ -173,7 +173,7 @@ afqmc_status ortho(afqmc_sys s, hipStream_t st) {
     {
         PhaseTimer pt(s, PH_MGS, st);
         HIPCHK(mgs(s->d_phi.as<double>(), s->d_alive.as<uint8_t>(), s->nw, s->M, s->N, s->na, s->nb,
-               st));
+                   s->d_ovl.p, st));
     }
     afqmc_status r = overlap_theta(s, s->d_phi.as<double>(), st);
     if (r != AFQMC_OK) return r;
@@ -365,8 +365,8 @@ afqmc_status afqmc_init_walkers(afqmc_ham ham, int n_alpha, int n_beta, const do
     };
     const int N = s->N, nc = s->n_chol, nw = n_walkers;
     const long NM = s->NM(), P = s->P();
-    s->n_gt_a = exchange_gtiles(nc, s->na, s->tc);
-    s->n_gt_b = exchange_gtiles(nc, s->nb, s->tc);  // tiles depend on the compute type
+    s->n_gt_a = exchange_gtiles(nc, s->na, M, s->tc);
+    s->n_gt_b = exchange_gtiles(nc, s->nb, M, s->tc);  // tiles depend on the compute type
     s->n_gt = std::max(1, std::max(s->n_gt_a, s->n_gt_b));
     struct A_ {
         DevBuf* b;

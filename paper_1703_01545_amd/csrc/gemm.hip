@@ -175,6 +175,7 @@ __global__ __launch_bounds__(64 * WGM * WGN) void k_exchange(
             const int g = idx / nsig, i = idx % nsig;
             if (g0 + g >= n_chol) break;
             const int rb = g * nsig;
+#pragma unroll 4
             for (int j = 0; j < nsig; ++j) {
                 const double tr_ij = S[(rb + i) * SP + cb + j];
                 const double ti_ij = S[(rb + i) * SP + cb + nsig + j];
@@ -188,18 +189,135 @@ __global__ __launch_bounds__(64 * WGM * WGN) void k_exchange(
     red[2 * tid] = sr;
     red[2 * tid + 1] = si;
     __syncthreads();
-    if (tid < W) {
-        const int w = w0 + tid;
-        if (w < nw) {
-            double a = 0.0, b = 0.0;
-            for (int t = tid * tpu; t < tid * tpu + tpu; ++t) {
-                a += red[2 * t];
-                b += red[2 * t + 1];
-            }
+    // walker u: the partial sums of its tpu threads, strided over one
+    // wavefront's lanes and folded by a butterfly (fixed order)
+    for (int uu = wave; uu < W; uu += NT / 64) {
+        double a = 0.0, b = 0.0;
+        for (int t = uu * tpu + lane; t < uu * tpu + tpu; t += 64) {
+            a += red[2 * t];
+            b += red[2 * t + 1];
+        }
+#pragma unroll
+        for (int o = 32; o >= 1; o >>= 1) {
+            a += __shfl_xor(a, o, 64);
+            b += __shfl_xor(b, o, 64);
+        }
+        const int w = w0 + uu;
+        if (lane == 0 && w < nw) {
             double* o = out + ((long)(w * 2 + spin) * n_gt + gt) * 2;
             o[0] = a;
             o[1] = b;
         }
+    }
+}
+
+// Exchange with whole gamma blocks per wavefront, for spin blocks of 17..48
+// orbitals padded to NB (a multiple of 8).  Wavefront (wm, wn) of the 2 x 2
+// workgroup owns G gamma blocks (rows gamma, i: R = G NB, a multiple of 16)
+// of one walker (columns plane, j: C = 2 NB), so its R x C tile holds whole
+// N_s x N_s blocks and the pairing T_ij T_ji stays inside the wavefront: the
+// tile goes to a private LDS region (odd pitch; two rounds of two
+// wavefronts reuse the operand buffers) and each block's sum is folded by a
+// butterfly.  Output slot: walker, spin, gamma group gg (G blocks each).
+template <int NB, int G>
+struct ExchBlk {
+    static constexpr int R = G * NB, C = 2 * NB, BM = 2 * R, BN = 2 * C, P = R + 4;
+    typedef Core<float, float, Split, BM, BN, 32, 2, 2, 4, 4, true> Cr;
+    static constexpr int OPB = (Cr::LDS_A + Cr::LDS_B) * (int)sizeof(bf16_t);
+    static constexpr int EPB = 2 * C * P * (int)sizeof(float);
+    static constexpr int SMEM = OPB > EPB ? OPB : EPB;
+};
+
+template <int NB, int G>
+__global__ __launch_bounds__(256, 2) void k_exchange_blk(const float* __restrict__ lhalf,
+                                                      const float* __restrict__ theta,
+                                                      double* __restrict__ out, int nw, int M,
+                                                      int N, int n_chol, int off, int nsig,
+                                                      int spin, int n_gt, int n_gtw, int n_wt) {
+    typedef ExchBlk<NB, G> E;
+    typedef typename E::Cr Cr;
+    constexpr int R = E::R, C = E::C, P = E::P;
+    __shared__ __attribute__((aligned(16))) char smem[E::SMEM];
+    bf16_t* As = reinterpret_cast<bf16_t*>(smem);
+    bf16_t* Bs = As + Cr::LDS_A;
+    float* S = reinterpret_cast<float*>(smem);
+
+    // XCD-aware tile order: each XCD takes a contiguous range of logical
+    // tiles, walked in super-tiles of 8 gamma groups x 8 walker pairs, so the
+    // workgroups one XCD runs together share 8 L^half and 8 Theta tiles in
+    // its L2 instead of streaming one operand from memory
+    const int n_sg = (n_gtw + 7) / 8, n_sw = (n_wt + 7) / 8;
+    const long nblk = (long)n_sg * n_sw * 64;
+    const long per = (nblk + 7) / 8;
+    const long L = (long)(blockIdx.x % 8) * per + blockIdx.x / 8;
+    if (L >= nblk) return;
+    const long st = L / 64;
+    const int loc = (int)(L % 64);
+    const int gt = (int)(st % n_sg) * 8 + (loc & 7), wt = (int)(st / n_sg) * 8 + (loc >> 3);
+    if (gt >= n_gtw || wt >= n_wt) return;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wm = wave >> 1, wn = wave & 1;
+    const long NM = (long)N * M;
+    const int g0 = gt * 2 * G, w0 = wt * 2;
+    long aoff[Cr::LA], boff[Cr::LB];
+#pragma unroll
+    for (int j = 0; j < Cr::LA; ++j) {
+        const int r = Cr::arow(j);
+        const int g = g0 + r / NB, i = r % NB;
+        aoff[j] = (i < nsig && g < n_chol) ? (long)g * NM + (long)(off + i) * M : -1;
+    }
+#pragma unroll
+    for (int j = 0; j < Cr::LB; ++j) {
+        const int c = Cr::brow(j);
+        const int u = c / (2 * NB), p = (c / NB) & 1, jj = c % NB;
+        const int w = w0 + u;
+        boff[j] = (jj < nsig && w < nw) ? (long)(2 * w + p) * NM + (long)(off + jj) * M : -1;
+    }
+    typename Cr::accv acc[Cr::TM][Cr::TN];
+    Cr::run(lhalf, aoff, theta, boff, M, As, Bs, acc);
+    // the tile column-major (column = plane, j; row = gamma, i), four rows per
+    // 16-byte store; pairs (i, j = i + d mod NB), d = 0 .. NB / 2, cover each
+    // unordered pair once (weight 2; the diagonal and d = NB / 2 weight 1),
+    // and both reads of a pair walk the lanes with the odd stride P + 1
+    constexpr int D = NB / 2 + 1;
+    float fr = 0.0f, fi = 0.0f;
+    for (int round = 0; round < 2; ++round) {
+        float* Sx = S + (wave & 1) * C * P;
+        if ((wave >> 1) == round) {
+#pragma unroll
+            for (int a = 0; a < Cr::TM; ++a)
+#pragma unroll
+                for (int b = 0; b < Cr::TN; ++b)
+                    *reinterpret_cast<f4*>(&Sx[(b * 16 + (lane & 15)) * P + a * 16 +
+                                               4 * (lane >> 4)]) = acc[a][b];
+        }
+        __syncthreads();
+        if ((wave >> 1) == round) {
+            for (int e = lane; e < G * D * NB; e += 64) {
+                const int gl = e / (D * NB), q = e % (D * NB);
+                const int d = q / NB, i = q % NB;
+                const int j = i + d < NB ? i + d : i + d - NB;
+                const float wgt = (d == 0 || 2 * d == NB) ? 1.0f : 2.0f;
+                const int r0 = gl * NB;
+                const float a_ij = Sx[j * P + r0 + i], b_ij = Sx[(NB + j) * P + r0 + i];
+                const float a_ji = Sx[i * P + r0 + j], b_ji = Sx[(NB + i) * P + r0 + j];
+                fr += wgt * (a_ij * a_ji - b_ij * b_ji);
+                fi += wgt * (a_ij * b_ji + b_ij * a_ji);
+            }
+        }
+        __syncthreads();
+    }
+    double sr = fr, si = fi;
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) {
+        sr += __shfl_xor(sr, o, 64);
+        si += __shfl_xor(si, o, 64);
+    }
+    const int w = w0 + wn, gg = gt * 2 + wm;
+    if (lane == 0 && w < nw && gg < n_gt) {
+        double* o = out + ((long)(w * 2 + spin) * n_gt + gg) * 2;
+        o[0] = sr;
+        o[1] = si;
     }
 }
 
@@ -241,6 +359,27 @@ constexpr DType dt_of() {
                       : (std::is_same<T, bf16_t>::value ? DT_BF16 : DT_SPLIT));
 }
 
+// Gamma blocks per wavefront of the block kernel (0: not used for this
+// spin block): split-BF16 contractions, 17..48 orbitals, M a multiple of 4.
+int exch_blk_g(int nsig, int M, DType t) {
+    if (t != DT_SPLIT || M % 4 || nsig <= 16 || nsig > 48) return 0;
+    const int nb = (nsig + 7) / 8 * 8;
+    return nb == 48 ? 1 : 2;
+}
+
+template <int NB, int G>
+hipError_t launch_exchange_blk(const void* lhalf, const void* theta, double* out, int nw, int M,
+                               int N, int n_chol, int off, int nsig, int spin, int n_gt,
+                               hipStream_t s) {
+    const int n_gtw = (n_chol + 2 * G - 1) / (2 * G), n_wt = (nw + 1) / 2;
+    const long nblk = (long)((n_gtw + 7) / 8) * ((n_wt + 7) / 8) * 64;
+    const long grid = ((nblk + 7) / 8) * 8;
+    hipLaunchKernelGGL((k_exchange_blk<NB, G>), dim3(grid), dim3(256), 0, s, (const float*)lhalf,
+                       (const float*)theta, out, nw, M, N, n_chol, off, nsig, spin, n_gt, n_gtw,
+                       n_wt);
+    return hipGetLastError();
+}
+
 }  // namespace
 
 hipError_t gemm(const Gemm& g, DType compute, hipStream_t s) {
@@ -265,9 +404,10 @@ hipError_t gemm(const Gemm& g, DType compute, hipStream_t s) {
     return hipErrorInvalidValue;
 }
 
-int exchange_gtiles(int n_chol, int nsig, DType t) {
+int exchange_gtiles(int n_chol, int nsig, int M, DType t) {
     if (nsig <= 0) return 0;
-    const int G = exch_cfg(t).BM / nsig;
+    const int gb = exch_blk_g(nsig, M, t);
+    const int G = gb ? gb : exch_cfg(t).BM / nsig;
     return (n_chol + G - 1) / G;
 }
 
@@ -289,6 +429,23 @@ hipError_t exchange(const void* lhalf, const void* theta, double* out, int nw, i
                                                                       n_chol, off, nsig, spin,
                                                                       n_gt, s);
         case DT_SPLIT:
+            if (exch_blk_g(nsig, M, t) && (uintptr_t)lhalf % 16 == 0 &&
+                (uintptr_t)theta % 16 == 0) {
+                switch ((nsig + 7) / 8 * 8) {
+                    case 24:
+                        return launch_exchange_blk<24, 2>(lhalf, theta, out, nw, M, N, n_chol, off,
+                                                          nsig, spin, n_gt, s);
+                    case 32:
+                        return launch_exchange_blk<32, 2>(lhalf, theta, out, nw, M, N, n_chol, off,
+                                                          nsig, spin, n_gt, s);
+                    case 40:
+                        return launch_exchange_blk<40, 2>(lhalf, theta, out, nw, M, N, n_chol, off,
+                                                          nsig, spin, n_gt, s);
+                    default:
+                        return launch_exchange_blk<48, 1>(lhalf, theta, out, nw, M, N, n_chol, off,
+                                                          nsig, spin, n_gt, s);
+                }
+            }
             return launch_exchange<float, Split, 128, 256, 32, 2, 4>(lhalf, theta, out, nw, M, N,
                                                                     n_chol, off, nsig, spin, n_gt,
                                                                     s);

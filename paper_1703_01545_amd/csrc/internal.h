@@ -87,11 +87,12 @@ hipError_t propagate(const double* phi, double* phi_out, const void* Pm, const v
 //   out[(w * 2 + spin) * n_gtiles + gt] = sum over gamma in tile gt of
 //   sum_ij T_ij T_ji,  T = L^half_{gamma, spin} Theta^spin_w   (complex, 2 doubles)
 // lhalf: [(n_chol + 1)][N][M] in type t (last row unused here);
-// theta: [w][plane][N][M] in type t.  Returns n_gtiles through *ntiles.
+// theta: [w][plane][N][M] in type t.  exchange_gtiles: the slot count of a
+// spin block for the kernel exchange() launches (depends on nsig, M and t).
 hipError_t exchange(const void* lhalf, const void* theta, double* out, int nw, int M, int N,
                     int n_chol, int off, int nsig, int spin, int n_gtiles_alloc, DType t,
                     hipStream_t s);
-int exchange_gtiles(int n_chol, int nsig, DType t);
+int exchange_gtiles(int n_chol, int nsig, int M, DType t);
 
 // ---------------------------------------------------------------- walker-wise
 struct FieldArgs {
@@ -137,7 +138,11 @@ size_t lu_theta_ws_bytes(int nw, int na, int nb);
 hipError_t weights(const double* lnd, const double* s_imp, double* lnov, double* w, uint8_t* alive,
                    int nw, int mode, int commit, double shift, hipStream_t s);
 
-hipError_t mgs(double* phi, const uint8_t* live, int nw, int M, int N, int na, int nb,
+// Orthonormalize every spin block of every live walker in place (the QR
+// factor Q with positive diagonal R, as modified Gram-Schmidt gives it):
+// blocks of at most 48 orbitals through the Gram matrix and its Cholesky
+// factor (ws: lu_theta_ws_bytes bytes), larger ones column by column.
+hipError_t mgs(double* phi, const uint8_t* live, int nw, int M, int N, int na, int nb, void* ws,
                hipStream_t s);
 
 // E_L[w] (complex) from F (f_g and the one-body trace at column n_chol) and

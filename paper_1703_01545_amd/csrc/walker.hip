@@ -534,16 +534,113 @@ __global__ __launch_bounds__(64) void k_overlap(const double* __restrict__ phi,
     }
 }
 
+// Output rows c = sum_k S[c][k] Phi rows rowk[k] (c, k < n; S complex in LDS
+// with pitch NC + 1) on the matrix cores: FP64 for TO = double, FP32 products
+// of the rounded operands otherwise.  Every load is issued unconditionally
+// from a valid address and masked afterwards, so the loops unroll and the
+// loads of one column block go out together; the Phi operand of the next
+// column block is loaded while the current one is on the matrix cores, and
+// a column block is read in full before its output is stored (the output may
+// be Phi itself).  One wavefront.
+template <int NC, typename TO>
+__device__ __forceinline__ void rows_times_phi(
+    const typename ThetaMode<TO>::T __attribute__((ext_vector_type(2)))* S, const int* rowk,
+    int n, const double* phr, const double* phm, int M, int off, TO* tr_, TO* ti_) {
+    typedef typename ThetaMode<TO>::T ET;
+    typedef typename ThetaMode<TO>::V EV;
+    typedef ET __attribute__((ext_vector_type(2))) E2;
+    constexpr int NB = (NC + 15) / 16;
+    constexpr int KS = NC / 4;
+    constexpr int SP = NC + 1;
+    const int lane = threadIdx.x & 63, li = lane & 15, g = lane >> 4;
+    const int nbn = (n + 15) >> 4;
+    long roff[KS];
+    bool kok[KS];
+#pragma unroll
+    for (int s = 0; s < KS; ++s) {
+        const int k = 4 * s + g;
+        kok[s] = k < n;
+        roff[s] = (long)(off + rowk[kok[s] ? k : 0]) * M;
+    }
+    // the inverse operand: element (c, k) of S, zero outside n x n (held in
+    // registers for FP32; re-read from LDS for FP64, which has no room)
+    auto a_op = [&](int cb, int s) -> E2 {
+        const int c = cb * 16 + li, k = 4 * s + g;
+        const E2 v = S[(c < n ? c : 0) * SP + (kok[s] ? k : 0)];
+        const bool ok = c < n && kok[s];
+        return (E2){ok ? v[0] : (ET)0, ok ? v[1] : (ET)0};
+    };
+    constexpr bool HOLD = sizeof(ET) == 4;
+    E2 a_h[HOLD ? NB : 1][HOLD ? KS : 1];
+    if constexpr (HOLD) {
+#pragma unroll
+        for (int cb = 0; cb < NB; ++cb)
+#pragma unroll
+            for (int s = 0; s < KS; ++s) a_h[cb][s] = a_op(cb, s);
+    }
+    const int nmb = (M + 15) >> 4;
+    // the Phi operand of the next column block is loaded while the current
+    // one is on the matrix cores
+    double xr[KS], xi[KS];
+    auto load_b = [&](int mb_) {
+        const int mm = mb_ * 16 + li;
+        const int mc = mm < M ? mm : M - 1;
+#pragma unroll
+        for (int s = 0; s < KS; ++s) {
+            xr[s] = phr[roff[s] + mc];
+            xi[s] = phm[roff[s] + mc];
+        }
+    };
+    load_b(0);
+    for (int mb = 0; mb < nmb; ++mb) {
+        const int m = mb * 16 + li;
+        const bool mok = m < M;
+        ET br[KS], bi[KS];
+#pragma unroll
+        for (int s = 0; s < KS; ++s) {
+            br[s] = (kok[s] && mok) ? (ET)xr[s] : (ET)0;
+            bi[s] = (kok[s] && mok) ? (ET)xi[s] : (ET)0;
+        }
+        load_b(mb + 1 < nmb ? mb + 1 : mb);
+#pragma unroll
+        for (int cb = 0; cb < NB; ++cb) {
+            if (cb < nbn) {
+                EV cr = {0, 0, 0, 0}, ci = {0, 0, 0, 0};
+#pragma unroll
+                for (int s = 0; s < KS; ++s) {
+                    E2 a;
+                    if constexpr (HOLD)
+                        a = a_h[cb][s];
+                    else
+                        a = a_op(cb, s);
+                    cr = mma1(a[0], br[s], cr);
+                    cr = mma1(-a[1], bi[s], cr);
+                    ci = mma1(a[0], bi[s], ci);
+                    ci = mma1(a[1], br[s], ci);
+                }
+                if (mok) {
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const int row = cb * 16 + acc_row<ET>(lane, r);
+                        if (row < n) {
+                            const long o = (long)(off + row) * M + m;
+                            store_theta<TO>(tr_ + o, cr[r]);
+                            store_theta<TO>(ti_ + o, ci[r]);
+                        }
+                    }
+                }
+            }
+        }
+    }
+}
+
 template <int NC, typename TO>
 __global__ __launch_bounds__(64, NC <= 40 ? 2 : 1) void k_det_theta(
     const double* __restrict__ phi, const d2* __restrict__ ovl, TO* __restrict__ theta,
     double* __restrict__ lnd, const uint8_t* __restrict__ live, int M, int N, int na, int nb,
     int nmax) {
     typedef typename ThetaMode<TO>::T ET;
-    typedef typename ThetaMode<TO>::V EV;
-    constexpr int NB = (NC + 15) / 16;  // 16-wide blocks
-    constexpr int KS = NC / 4;          // k steps of 4 in (3)
-    constexpr int SP = NC + 1;          // pitch (complex) of the inverse
+    constexpr int SP = NC + 1;  // pitch (complex) of the inverse
     __shared__ __align__(16) unsigned char buf[NC * SP * 2 * sizeof(ET)];
     __shared__ double pv[2 * NC];
     __shared__ int ptab[NC];
@@ -560,8 +657,6 @@ __global__ __launch_bounds__(64, NC <= 40 ? 2 : 1) void k_det_theta(
     const long NM = (long)N * M;
     const double* phr = phi + (long)w * 2 * NM;
     const double* phm = phr + NM;
-    const int nbn = (n + 15) >> 4;
-    const int li = lane & 15, g = lane >> 4;
 
     // (1) row j of B into lane j (unconditional loads from valid addresses,
     // masked afterwards)
@@ -657,89 +752,135 @@ __global__ __launch_bounds__(64, NC <= 40 ? 2 : 1) void k_det_theta(
     }
     __syncthreads();
 
-    // (3) Theta rows c = sum_k S[c][k] Phi rows p_k.  Every load is issued
-    // unconditionally from a valid address and masked afterwards, so the
-    // loops unroll and the loads of one column block go out together.
-    long roff[KS];
-    bool kok[KS];
+    // (3) Theta rows c = sum_k S[c][k] Phi rows p_k
+    rows_times_phi<NC, TO>(S, ptab, n, phr, phm, M, off, theta + (long)w * 2 * NM,
+                           theta + (long)w * 2 * NM + NM);
+}
+
+// Orthonormalization of a spin block (Sec. II.D): the modified Gram-Schmidt
+// result Phi = Q R (R upper triangular with positive diagonal, Q^H Q = 1)
+// is the unique QR factorization, obtained here from the Gram matrix
+// S = Phi^H Phi = R^H R, in two kernels per (walker, spin block):
+// k_gram: S on the FP64 matrix cores into the complex workspace [w][spin][i][j]
+//   (row pitch nmax; real part sum (Re_i Re_j + Im_i Im_j), imaginary part
+//   sum (Re_i Im_j - Im_i Re_j));
+// k_cholqr, one wavefront: lane i loads row i of S; forward elimination in
+//   order (pivot k at step k, no exchange) with the register rotation of
+//   k_det_theta turns the identity into L^{-1} of S = L D L^H, so
+//   R^{-1} = L^{-H} D^{-1/2}; Q row i = D_i^{-1/2} sum_{k <= i}
+//   conj(L^{-1}[i][k]) Phi row k, on the FP64 matrix cores, in place.
+template <int NB>
+__global__ __launch_bounds__(64) void k_gram(const double* __restrict__ phi, d2* __restrict__ ovl,
+                                             const uint8_t* __restrict__ live, int M, int N,
+                                             int na, int nb, int nmax) {
+    const int w = blockIdx.x, spin = blockIdx.y;
+    const int off = spin ? na : 0, n = spin ? nb : na;
+    if (n == 0 || !live[w]) return;
+    const int lane = threadIdx.x, li = lane & 15, g = lane >> 4;
+    const long NM = (long)N * M;
+    const double* phr = phi + (long)w * 2 * NM;
+    const int nbn = (n + 15) >> 4;
+    d2* out = ovl + ((long)w * 2 + spin) * nmax * nmax;
+    for (int ib = 0; ib < nbn; ++ib) {
+        const int i = ib * 16 + li;
+        const bool oki = i < n;
+        const double* xr_row = phr + (long)(off + (oki ? i : 0)) * M;
+        const double* xi_row = xr_row + NM;
+        d4 accr[NB], acci[NB];
 #pragma unroll
-    for (int s = 0; s < KS; ++s) {
-        const int k = 4 * s + g;
-        kok[s] = k < n;
-        roff[s] = (long)(off + ptab[kok[s] ? k : 0]) * M;
-    }
-    // the inverse operand: element (c, k) of S, zero outside n x n (held in
-    // registers for FP32; re-read from LDS for FP64, which has no room)
-    auto a_op = [&](int cb, int s) -> E2 {
-        const int c = cb * 16 + li, k = 4 * s + g;
-        const E2 v = S[(c < n ? c : 0) * SP + (kok[s] ? k : 0)];
-        const bool ok = c < n && kok[s];
-        return (E2){ok ? v[0] : (ET)0, ok ? v[1] : (ET)0};
-    };
-    constexpr bool HOLD = sizeof(ET) == 4;
-    E2 a_h[HOLD ? NB : 1][HOLD ? KS : 1];
-    if constexpr (HOLD) {
+        for (int b = 0; b < NB; ++b) accr[b] = acci[b] = (d4){0, 0, 0, 0};
+        for (int k0 = 0; k0 < M; k0 += 16) {
+            const int m = k0 + 4 * g;
+            double xr[4], xi[4];
+            row4(xr_row, m, M, oki, xr);
+            row4(xi_row, m, M, oki, xi);
 #pragma unroll
-        for (int cb = 0; cb < NB; ++cb)
+            for (int b = 0; b < NB; ++b) {
+                if (b >= nbn) break;
+                const int j = b * 16 + li;
+                const double* yr_row = phr + (long)(off + (j < n ? j : 0)) * M;
+                double yr[4], yi[4];
+                row4(yr_row, m, M, j < n, yr);
+                row4(yr_row + NM, m, M, j < n, yi);
 #pragma unroll
-            for (int s = 0; s < KS; ++s) a_h[cb][s] = a_op(cb, s);
-    }
-    TO* tr_ = theta + (long)w * 2 * NM;
-    TO* ti_ = tr_ + NM;
-    const int nmb = (M + 15) >> 4;
-    // the Phi operand of the next column block is loaded while the current
-    // one is on the matrix cores
-    double xr[KS], xi[KS];
-    auto load_b = [&](int mb_) {
-        const int mm = mb_ * 16 + li;
-        const int mc = mm < M ? mm : M - 1;
-#pragma unroll
-        for (int s = 0; s < KS; ++s) {
-            xr[s] = phr[roff[s] + mc];
-            xi[s] = phm[roff[s] + mc];
-        }
-    };
-    load_b(0);
-    for (int mb = 0; mb < nmb; ++mb) {
-        const int m = mb * 16 + li;
-        const bool mok = m < M;
-        ET br[KS], bi[KS];
-#pragma unroll
-        for (int s = 0; s < KS; ++s) {
-            br[s] = (kok[s] && mok) ? (ET)xr[s] : (ET)0;
-            bi[s] = (kok[s] && mok) ? (ET)xi[s] : (ET)0;
-        }
-        load_b(mb + 1 < nmb ? mb + 1 : mb);
-#pragma unroll
-        for (int cb = 0; cb < NB; ++cb) {
-            if (cb < nbn) {
-                EV cr = {0, 0, 0, 0}, ci = {0, 0, 0, 0};
-#pragma unroll
-                for (int s = 0; s < KS; ++s) {
-                    E2 a;
-                    if constexpr (HOLD)
-                        a = a_h[cb][s];
-                    else
-                        a = a_op(cb, s);
-                    cr = mma1(a[0], br[s], cr);
-                    cr = mma1(-a[1], bi[s], cr);
-                    ci = mma1(a[0], bi[s], ci);
-                    ci = mma1(a[1], br[s], ci);
-                }
-                if (mok) {
-#pragma unroll
-                    for (int r = 0; r < 4; ++r) {
-                        const int row = cb * 16 + acc_row<ET>(lane, r);
-                        if (row < n) {
-                            const long o = (long)(off + row) * M + m;
-                            store_theta<TO>(tr_ + o, cr[r]);
-                            store_theta<TO>(ti_ + o, ci[r]);
-                        }
-                    }
+                for (int q = 0; q < 4; ++q) {
+                    accr[b] = __builtin_amdgcn_mfma_f64_16x16x4f64(xr[q], yr[q], accr[b], 0, 0, 0);
+                    accr[b] = __builtin_amdgcn_mfma_f64_16x16x4f64(xi[q], yi[q], accr[b], 0, 0, 0);
+                    acci[b] = __builtin_amdgcn_mfma_f64_16x16x4f64(xr[q], yi[q], acci[b], 0, 0, 0);
+                    acci[b] = __builtin_amdgcn_mfma_f64_16x16x4f64(-xi[q], yr[q], acci[b], 0, 0, 0);
                 }
             }
         }
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+            const int j = b * 16 + li;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int ir = ib * 16 + g + 4 * r;
+                if (b < nbn && ir < n && j < n) out[(long)ir * nmax + j] = (d2){accr[b][r], acci[b][r]};
+            }
+        }
     }
+}
+
+template <int NC>
+__global__ __launch_bounds__(64, NC <= 40 ? 2 : 1) void k_cholqr(double* phi,
+                                                                 const d2* __restrict__ ovl,
+                                                                 const uint8_t* __restrict__ live,
+                                                                 int M, int N, int na, int nb,
+                                                                 int nmax) {
+    constexpr int SP = NC + 1;
+    typedef double __attribute__((ext_vector_type(2))) E2;
+    __shared__ __align__(16) E2 S[NC * SP];
+    __shared__ double dv[NC];
+    __shared__ int ident[NC];
+    const int w = blockIdx.x, spin = blockIdx.y;
+    const int off = spin ? na : 0, n = spin ? nb : na;
+    if (n == 0 || !live[w]) return;
+    const int lane = threadIdx.x;
+    const long NM = (long)N * M;
+    double* phr = phi + (long)w * 2 * NM;
+    double* phm = phr + NM;
+    double ar[NC], ai[NC];
+    {
+        const d2* row = ovl + ((long)w * 2 + spin) * nmax * nmax + (long)(lane < n ? lane : 0) * nmax;
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            const d2 v = row[c < n ? c : 0];
+            const bool ok = lane < n && c < n;
+            ar[c] = ok ? v[0] : 0.0;
+            ai[c] = ok ? v[1] : 0.0;
+        }
+    }
+    if (lane < NC) ident[lane] = lane;
+    for (int k = 0; k < n; ++k) {
+        const double pr = rdlane(ar[0], k), pi = rdlane(ai[0], k);
+        const double rden = 1.0 / (pr * pr + pi * pi);
+        const double qr = pr * rden, qi = -pi * rden;  // 1 / pivot
+        const bool below = lane > k;
+        const double mr = below ? ar[0] * qr - ai[0] * qi : 0.0;
+        const double mi = below ? ar[0] * qi + ai[0] * qr : 0.0;
+        if (lane == k) dv[k] = pr;
+#pragma unroll
+        for (int c = 1; c < NC; ++c) {
+            const double sr = rdlane(ar[c], k), si = rdlane(ai[c], k);
+            ar[c - 1] = ar[c] - (mr * sr - mi * si);
+            ai[c - 1] = ai[c] - (mr * si + mi * sr);
+            if ((c & 7) == 0) __builtin_amdgcn_sched_barrier(0);
+        }
+        ar[NC - 1] = lane == k ? 1.0 : -mr;
+        ai[NC - 1] = -mi;
+    }
+    __syncthreads();
+    // S[i][k] = D_i^{-1/2} conj(L^{-1}[i][k]): R^{-1} transposed, by rows i
+    if (lane < n) {
+        const double sc = 1.0 / sqrt(dv[lane]);
+#pragma unroll
+        for (int c = 0; c < NC; ++c)
+            if (c >= NC - n) S[lane * SP + c - (NC - n)] = (E2){sc * ar[c], -sc * ai[c]};
+    }
+    __syncthreads();
+    rows_times_phi<NC, double>(S, ident, n, phr, phm, M, off, phr, phm);
 }
 
 __global__ void k_weights(const double* __restrict__ lnd, const double* __restrict__ s_imp,
@@ -1092,10 +1233,32 @@ hipError_t weights(const double* lnd, const double* s_imp, double* lnov, double*
     return hipGetLastError();
 }
 
-hipError_t mgs(double* phi, const uint8_t* live, int nw, int M, int N, int na, int nb,
+template <int NC>
+hipError_t cholqr_nc(double* phi, const uint8_t* live, int nw, int M, int N, int na, int nb,
+                     void* ws, hipStream_t s) {
+    const dim3 grid(nw, 2), blk(64);
+    const int nmax = na > nb ? na : nb;
+    hipLaunchKernelGGL((k_gram<(NC + 15) / 16>), grid, blk, 0, s, phi, (d2*)ws, live, M, N, na,
+                       nb, nmax);
+    hipLaunchKernelGGL((k_cholqr<NC>), grid, blk, 0, s, phi, (const d2*)ws, live, M, N, na, nb,
+                       nmax);
+    return hipGetLastError();
+}
+
+hipError_t mgs(double* phi, const uint8_t* live, int nw, int M, int N, int na, int nb, void* ws,
                hipStream_t s) {
     if (nw <= 0) return hipSuccess;
     const int nmax = na > nb ? na : nb;
+#define AFQ_QR(NC) \
+    if (nmax <= NC) return cholqr_nc<NC>(phi, live, nw, M, N, na, nb, ws, s);
+    AFQ_QR(8)
+    AFQ_QR(16)
+    AFQ_QR(24)
+    AFQ_QR(32)
+    AFQ_QR(40)
+    AFQ_QR(48)
+#undef AFQ_QR
+    // larger blocks: Gram-Schmidt column by column in one workgroup
     const size_t shm = (size_t)2 * nmax * M * sizeof(double);
     if (shm <= 128 * 1024) {
         static bool attr = false;

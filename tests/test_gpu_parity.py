@@ -151,7 +151,8 @@ def test_parity_ragged(lib, torch_mod, dims):
 # per product, averaged over the contractions) leave about 1e-6 relative in
 # the energies over 40 steps; the bound 1e-5 keeps a 10x margin and still
 # fails on a dropped split term (plain BF16 products: about 4e-4).
-@pytest.mark.parametrize("dims", [(37, 75, 7, 6, 7, 5, 37), (64, 130, 16, 16, 16, 15, 16)])
+@pytest.mark.parametrize("dims", [(37, 75, 7, 6, 7, 5, 37), (64, 130, 16, 16, 16, 15, 16),
+                                  (40, 120, 20, 20, 20, 19, 16), (60, 90, 44, 33, 44, 32, 6)])
 @pytest.mark.parametrize("prec,tol", [("fp32", 1e-5), ("bf16", 1e-5), ("bf16x3", 1e-5),
                                       ("bf16_plain", 5e-3)])
 def test_reduced_precision_close_to_oracle(lib, torch_mod, dims, prec, tol):
