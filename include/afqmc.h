@@ -183,14 +183,14 @@ afqmc_status afqmc_adjoint_forward(afqmc_sys sys, const double* V, uint64_t seed
 afqmc_status afqmc_adjoint_backward(afqmc_sys sys, double* dE_dlambda);
 
 /* Launch-shape autotuner.  Times every candidate launch shape of the
- * force-bias and field-sum GEMMs (64 x 64 or 128 x 128 tiles) and of the
+ * force-bias and field-sum GEMMs (64 x 64, 128 x 128 or 256 x 128 tiles) and of the
  * fused propagation (waves per workgroup x column blocks per wave, B
  * prefetch or not) on this system's own buffers and keeps the fastest per
  * problem shape in a process-wide table, so tuning another system of the
  * same shape costs nothing.  All candidates sum in the same order, so tuning
  * never changes a result bit.  The walker state is left unchanged.  choice
  * (optional, host, 3 ints): the chosen force-bias tile and field-sum tile
- * (1: 64 x 64, 2: 128 x 128) and the propagation shape index.
+ * (1: 64 x 64, 2: 128 x 128, 3: 256 x 128) and the propagation shape index.
  * Synchronises. */
 afqmc_status afqmc_autotune(afqmc_sys sys, int* choice);
 

@@ -83,7 +83,7 @@ hipError_t pick(const ShapeKey& key, const std::vector<int>& cands, F run, hipSt
 
 hipError_t tune_gemm(int role, Gemm g, DType compute, hipStream_t st, int* out) {
     const ShapeKey key{role, g.m, g.n, g.k, g.ta, g.tb, g.tc, compute};
-    return pick(key, {1, 2},
+    return pick(key, {1, 2, 3},
                 [&](int c) {
                     g.tile = c;
                     return gemm(g, compute, st);

@@ -58,6 +58,8 @@ const char* const kPhaseNames[PH_COUNT] = {
     "det_theta",       "weights", "mgs",            "exchange", "energy"};
 
 
+int fb_ksplit(int k) { return std::max(1, std::min(8, k / 4000)); }
+
 Gemm force_bias_gemm(afqmc_sys s) {
     // F[(w,p), g] = sum_(i,m) Theta[(w,p),(i,m)] L^half[g,(i,m)], g <= n_chol
     Gemm g{};
@@ -76,6 +78,9 @@ Gemm force_bias_gemm(afqmc_sys s) {
     g.k = (int)s->NM();
     g.batch = 1;
     g.tile = s->tile_fb;
+    // long K (= N M): fixed K ranges so that large tiles still fill the chip
+    g.ksplit = fb_ksplit(g.k);
+    g.ws = s->d_kws.p;
     return g;
 }
 
@@ -392,6 +397,7 @@ afqmc_status afqmc_init_walkers(afqmc_ham ham, int n_alpha, int n_beta, const do
         {&s->d_Af, (size_t)nw * 2 * M * M * dt_size(s->tp)},
         {&s->d_lnd, (size_t)nw * 4 * 8},
         {&s->d_ovl, lu_theta_ws_bytes(nw, n_alpha, n_beta)},
+        {&s->d_kws, gemm_ws_bytes(2 * nw, nc + 1, fb_ksplit((int)NM), s->tc)},
         {&s->d_exch, (size_t)nw * 2 * s->n_gt * 2 * 8},
         {&s->d_el, (size_t)nw * 2 * 8},
         {&s->d_sums, 8 * 8},
@@ -591,7 +597,7 @@ void afqmc_free_sys(afqmc_sys s) {
     for (DevBuf* b : {&s->d_trialT, &s->d_P, &s->d_Plp, &s->d_a, &s->d_lhx, &s->d_lhx_lp,
                       &s->d_phi, &s->d_phinew, &s->d_theta, &s->d_theta_lp, &s->d_w, &s->d_lnov,
                       &s->d_alive, &s->d_F, &s->d_X, &s->d_simp, &s->d_Apk, &s->d_Af,
-                      &s->d_lnd, &s->d_ovl, &s->d_exch, &s->d_el, &s->d_sums})
+                      &s->d_lnd, &s->d_ovl, &s->d_kws, &s->d_exch, &s->d_el, &s->d_sums})
         b->release();
     drop_batch_plans(s->id);
     free_adjoint(s);

@@ -15,16 +15,56 @@ namespace {
 
 using namespace dev;
 
+// K range length of a split GEMM: ceil(k / ksplit) rounded up to 32, so the
+// ranges start on vector boundaries and do not depend on the tile shape.
+__host__ __device__ inline int gemm_kchunk_dev(int k, int ksplit) {
+    const int c = (k + ksplit - 1) / ksplit;
+    return (c + 31) / 32 * 32;
+}
+
+// C = alpha sum_z ws[z] (+ beta C; C2 = alpha sum), z in order, in FP64.
+template <typename AccS, typename TO>
+__global__ __launch_bounds__(256) void k_ksum(Gemm g) {
+    const long idx = (long)blockIdx.x * 256 + threadIdx.x;
+    if (idx >= (long)g.m * g.n) return;
+    const long i = idx / g.n, j = idx % g.n;
+    const AccS* w = (const AccS*)g.ws;
+    double v = 0.0;
+    for (int z = 0; z < g.ksplit; ++z) v += (double)w[(long)z * g.m * g.n + idx];
+    v *= g.alpha;
+    const long ro = rowmap(g.rc, i);
+    TO* out = (TO*)g.C;
+    if (g.C2) ((TO*)g.C2)[ro + j] = (TO)v;
+    if (g.beta != 0.0) v += g.beta * (double)out[ro + j];
+    out[ro + j] = (TO)v;
+}
+
 template <typename TA, typename TB, typename TC, typename TO, int BM, int BN, int BK, int WGM,
           int WGN, int VA, int VB, bool AL>
-__global__ __launch_bounds__(64 * WGM * WGN) void k_gemm(Gemm g) {
+__global__ __launch_bounds__(64 * WGM * WGN) void k_gemm(Gemm g, int ntn, int ntm) {
     typedef Core<TA, TB, TC, BM, BN, BK, WGM, WGN, VA, VB, AL> C;
     __shared__ __attribute__((aligned(16))) typename C::LT As[C::LDS_A];
     __shared__ __attribute__((aligned(16))) typename C::LT Bs[C::LDS_B];
-    const int b = blockIdx.z;
-    const long row0 = (long)blockIdx.y * BM, col0 = (long)blockIdx.x * BN;
-    const TA* A = (const TA*)g.A + (long)b * g.a_bs;
-    const TB* B = (const TB*)g.B + (long)b * g.b_bs;
+    // XCD-aware order: workgroups are dealt to the eight XCDs in turn, so
+    // logical tile L = (id mod 8) per + id / 8 gives each XCD a contiguous
+    // run of tiles (column tiles fastest): the column tiles of one row block
+    // share its A rows in one L2
+    const int ks = g.ksplit > 1 ? g.ksplit : 1;
+    const long nt = (long)ntn * ntm * ks * g.batch;
+    const long per = (nt + 7) / 8;
+    const long L = (long)(blockIdx.x % 8) * per + blockIdx.x / 8;
+    if (L >= nt) return;
+    const long tpk = (long)ntn * ntm;
+    const int b = (int)(L / (tpk * ks));
+    const int kz = (int)((L / tpk) % ks);
+    const long rem = L % tpk;
+    const long row0 = (rem / ntn) * BM, col0 = (rem % ntn) * BN;
+    // K range of this workgroup (whole K without split)
+    const int kc = ks > 1 ? gemm_kchunk_dev(g.k, ks) : g.k;
+    const int k_lo = kz * kc;
+    const int k_len = k_lo < g.k ? (g.k - k_lo < kc ? g.k - k_lo : kc) : 0;
+    const TA* A = (const TA*)g.A + (long)b * g.a_bs + k_lo;
+    const TB* B = (const TB*)g.B + (long)b * g.b_bs + k_lo;
     const int tid = threadIdx.x;
     long aoff[C::LA], boff[C::LB];
 #pragma unroll
@@ -38,13 +78,30 @@ __global__ __launch_bounds__(64 * WGM * WGN) void k_gemm(Gemm g) {
         boff[j] = r < g.n ? rowmap(g.rb, r) : -1;
     }
     typename C::accv acc[C::TM][C::TN];
-    C::run(A, aoff, B, boff, g.k, As, Bs, acc);
+    C::run(A, aoff, B, boff, k_len, As, Bs, acc);
 
     const int lane = tid & 63, wave = tid >> 6;
     const int wm = wave / WGN, wn = wave % WGN;
     TO* out = (TO*)g.C + (long)b * g.c_bs;
     TO* out2 = g.C2 ? (TO*)g.C2 + (long)b * g.c_bs : nullptr;
     typedef typename std::conditional<std::is_same<TC, double>::value, double, float>::type AccS;
+    if (ks > 1) {
+        // partial sums of this K range
+        AccS* wsp = (AccS*)g.ws + (long)kz * g.m * g.n;
+#pragma unroll
+        for (int a = 0; a < C::TM; ++a)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const long i = row0 + wm * C::TM * 16 + a * 16 + acc_row<AccS>(lane, r);
+                if (i >= g.m) continue;
+#pragma unroll
+                for (int bb = 0; bb < C::TN; ++bb) {
+                    const long j = col0 + wn * C::TN * 16 + bb * 16 + (lane & 15);
+                    if (j < g.n) wsp[i * g.n + j] = acc[a][bb][r];
+                }
+            }
+        return;
+    }
 #pragma unroll
     for (int a = 0; a < C::TM; ++a) {
 #pragma unroll
@@ -78,16 +135,18 @@ bool rows_aligned(const void* p, const RowMap& r, long bs, int batch, int v, siz
 template <typename TA, typename TB, typename TC, typename TO, int BM, int BN, int BK, int WGM,
           int WGN>
 hipError_t launch_tile(const Gemm& g, hipStream_t s) {
-    dim3 grid((g.n + BN - 1) / BN, (g.m + BM - 1) / BM, g.batch);
+    const int ntn = (g.n + BN - 1) / BN, ntm = (g.m + BM - 1) / BM;
+    const long nt = (long)ntn * ntm * g.batch * (g.ksplit > 1 ? g.ksplit : 1);
+    const dim3 grid((unsigned)(((nt + 7) / 8) * 8));
     constexpr int VA = VW<TA>::v, VB = VW<TB>::v;
     const bool al = rows_aligned(g.A, g.ra, g.a_bs, g.batch, VA, sizeof(TA)) &&
                     rows_aligned(g.B, g.rb, g.b_bs, g.batch, VB, sizeof(TB));
     if (al)
         hipLaunchKernelGGL((k_gemm<TA, TB, TC, TO, BM, BN, BK, WGM, WGN, VA, VB, true>), grid,
-                           dim3(64 * WGM * WGN), 0, s, g);
+                           dim3(64 * WGM * WGN), 0, s, g, ntn, ntm);
     else
         hipLaunchKernelGGL((k_gemm<TA, TB, TC, TO, BM, BN, BK, WGM, WGN, 1, 1, false>), grid,
-                           dim3(64 * WGM * WGN), 0, s, g);
+                           dim3(64 * WGM * WGN), 0, s, g, ntn, ntm);
     return hipGetLastError();
 }
 
@@ -96,8 +155,18 @@ hipError_t launch_gemm(const Gemm& g, hipStream_t s) {
     const long tiles128 = ((long)(g.m + 127) / 128) * ((g.n + 127) / 128) * g.batch;
     constexpr int BK = Info<TC>::KM == 4 ? 16 : 32;
     const bool big = g.tile ? g.tile == 2 : (g.m >= 96 && g.n >= 96 && tiles128 >= 512);
-    if (big) return launch_tile<TA, TB, TC, TO, 128, 128, BK, 2, 2>(g, s);
-    return launch_tile<TA, TB, TC, TO, 64, 64, BK, 2, 2>(g, s);
+    hipError_t e;
+    if (g.tile == 3)
+        e = launch_tile<TA, TB, TC, TO, 256, 128, BK, 4, 2>(g, s);
+    else if (big)
+        e = launch_tile<TA, TB, TC, TO, 128, 128, BK, 2, 2>(g, s);
+    else
+        e = launch_tile<TA, TB, TC, TO, 64, 64, BK, 2, 2>(g, s);
+    if (e != hipSuccess || g.ksplit <= 1) return e;
+    typedef typename std::conditional<std::is_same<TC, double>::value, double, float>::type AccS;
+    const long n = (long)g.m * g.n;
+    hipLaunchKernelGGL((k_ksum<AccS, TO>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, g);
+    return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------
@@ -382,8 +451,17 @@ hipError_t launch_exchange_blk(const void* lhalf, const void* theta, double* out
 
 }  // namespace
 
+int gemm_kchunk(int k, int ksplit) { return gemm_kchunk_dev(k, ksplit); }
+
+size_t gemm_ws_bytes(int m, int n, int ksplit, DType compute) {
+    if (ksplit <= 1) return 0;
+    return (size_t)ksplit * m * n * (compute == DT_F64 ? 8 : 4);
+}
+
 hipError_t gemm(const Gemm& g, DType compute, hipStream_t s) {
     if (g.m <= 0 || g.n <= 0 || g.batch <= 0) return hipSuccess;
+    if (g.ksplit > 1 && (g.batch != 1 || !g.ws || g.k <= 0))
+        return hipErrorInvalidValue;
 #define AFQ_G(TA_, TB_, TC_, TO_)                                                       \
     if (g.ta == dt_of<TA_>() && g.tb == dt_of<TB_>() && g.tc == dt_of<TO_>() &&         \
         compute == dt_of<TC_>())                                                         \

@@ -156,6 +156,7 @@ struct afqmc_sys_s {
     // step scratch
     afq::host::DevBuf d_F, d_X, d_simp, d_Apk, d_Af, d_lnd, d_exch, d_el, d_sums;
     afq::host::DevBuf d_ovl;  // overlap matrices of the determinant kernels
+    afq::host::DevBuf d_kws;  // split-K partial sums of the force-bias GEMM
     int n_gt_a = 0, n_gt_b = 0, n_gt = 0;
     // launch shapes (autotuned; 0 = size heuristic): GEMM tiles of the force
     // bias and the field sum, and the propagation workgroup shape
@@ -210,6 +211,7 @@ struct PhaseTimer {
 
 // GEMM descriptors of the contraction phases (their tile from the system's
 // tuned shapes).
+int fb_ksplit(int k);
 Gemm force_bias_gemm(afqmc_sys s);
 Gemm field_sum_gemm(afqmc_sys s);
 

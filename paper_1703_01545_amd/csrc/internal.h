@@ -52,12 +52,19 @@ struct Gemm {
     double alpha;
     double beta;
     int m, n, k, batch;
-    int tile;  // 0: size heuristic; 1: 64 x 64 tiles; 2: 128 x 128 tiles
+    int tile;  // 0: size heuristic; 1: 64 x 64 tiles; 2: 128 x 128; 3: 256 x 128
+    // ksplit > 1: K cut into ksplit ranges of gemm_kchunk(k, ksplit) (the same
+    // for every tile shape), partial sums (FP32; FP64 for FP64 compute) into
+    // ws[ksplit][m][n] (batch 1), then summed in range order into C
+    int ksplit;
+    void* ws;
 };
 
 // Compute precision of a GEMM (the MFMA input type; accumulation is FP64 for
 // DT_F64 and FP32 otherwise).
 hipError_t gemm(const Gemm& g, DType compute, hipStream_t s);
+int gemm_kchunk(int k, int ksplit);
+size_t gemm_ws_bytes(int m, int n, int ksplit, DType compute);
 
 // Packed upper triangle (P = M(M+1)/2 per plane) -> full symmetric M x M,
 // for `planes` consecutive planes (types DT_F64 / DT_F32; DT_SPLIT: FP32
