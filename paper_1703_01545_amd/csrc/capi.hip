@@ -338,6 +338,11 @@ afqmc_status afqmc_init_walkers(afqmc_ham ham, int n_alpha, int n_beta, const do
     if (n_walkers <= 0) return fail(AFQMC_E_INVALID, "n_walkers must be > 0");
     if (!(par->dt > 0.0) || par->taylor_order < 1 || par->ortho_every < 0 || par->measure_every < 0)
         return fail(AFQMC_E_INVALID, "bad params (dt > 0, taylor_order >= 1, periods >= 0)");
+    static bool unpack_ready = false;  // kernel attribute, set once outside any capture
+    if (!unpack_ready) {
+        if (unpack_prepare() != hipSuccess) return fail(AFQMC_E_DEVICE, "unpack kernel attribute");
+        unpack_ready = true;
+    }
     if (par->contract_prec < AFQMC_FP64 || par->contract_prec > AFQMC_BF16X3)
         return fail(AFQMC_E_INVALID, "bad contract_prec");
     if (par->mode != AFQMC_PHASELESS && par->mode != AFQMC_FREE)

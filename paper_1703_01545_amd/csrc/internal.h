@@ -70,6 +70,10 @@ size_t gemm_ws_bytes(int m, int n, int ksplit, DType compute);
 // for `planes` consecutive planes (types DT_F64 / DT_F32; DT_SPLIT: FP32
 // input, hi/lo BF16 output planes [plane][hi, lo][M][M]).
 hipError_t unpack_sym(const void* pk, void* full, int M, int planes, DType t, hipStream_t s);
+// LDS limit of the one-plane split unpack; unpack_prepare raises the kernel's
+// dynamic LDS limit to it (call once, outside graph capture).
+constexpr size_t kUnpackLds = 128 * 1024;
+hipError_t unpack_prepare();
 // FP32 planes of n elements -> hi/lo BF16 planes [plane][hi, lo][n].
 hipError_t split_planes(const float* in, void* out, long n, long planes, hipStream_t s);
 

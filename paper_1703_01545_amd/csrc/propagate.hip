@@ -942,6 +942,49 @@ __global__ __launch_bounds__(256) void k_unpack_split(const float* __restrict__ 
     }
 }
 
+// One workgroup per walker plane: the packed upper triangle is staged whole
+// in LDS, then every thread writes runs of 8 consecutive elements of a row
+// of the full matrix (A_ij from the packed row min(i, j)) as one 16-byte hi
+// store and one 16-byte lo store.  Needs M % 8 == 0 and the triangle in LDS.
+__global__ __launch_bounds__(256) void k_unpack_split_plane(const float* __restrict__ pk,
+                                                            bf16_t* __restrict__ full, int M) {
+    extern __shared__ float tri[];
+    const long P = (long)M * (M + 1) / 2;
+    const long plane = blockIdx.x;
+    const float* src = pk + plane * P;
+    // eight loads in flight per thread
+    for (long e0 = threadIdx.x; e0 < P; e0 += 8 * 256) {
+        float v[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const long e = e0 + q * 256;
+            v[q] = src[e < P ? e : 0];
+        }
+#pragma unroll
+        for (int q = 0; q < 8; ++q)
+            if (e0 + q * 256 < P) tri[e0 + q * 256] = v[q];
+    }
+    __syncthreads();
+    bf16_t* hi = full + plane * 2 * (long)M * M;
+    bf16_t* lo = hi + (long)M * M;
+    const int rr = M / 8;  // runs per row
+    for (int r = threadIdx.x; r < M * rr; r += 256) {
+        const int i = r / rr, j0 = (r % rr) * 8;
+        bf8 h, l;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            const int j = j0 + e;
+            const int a = i < j ? i : j, b = i < j ? j : i;
+            const float v = tri[(long)a * (2 * M - a + 1) / 2 + (b - a)];
+            const bf16_t x = to_bf(v);
+            h[e] = x;
+            l[e] = to_bf(v - (float)x);
+        }
+        *reinterpret_cast<bf8*>(hi + (long)i * M + j0) = h;
+        *reinterpret_cast<bf8*>(lo + (long)i * M + j0) = l;
+    }
+}
+
 template <typename T, int NWAVE, int MAXB, bool PF>
 hipError_t launch_prop(const double* phi, double* phi_out, const void* Pm, const void* Af,
                        const uint8_t* live, int nw, int M, int N, int K, hipStream_t s) {
@@ -963,6 +1006,11 @@ hipError_t split_planes(const float* in, void* out, long n, long planes, hipStre
     return hipGetLastError();
 }
 
+hipError_t unpack_prepare() {
+    return hipFuncSetAttribute((const void*)k_unpack_split_plane,
+                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)kUnpackLds);
+}
+
 hipError_t unpack_sym(const void* pk, void* full, int M, int planes, DType t, hipStream_t s) {
     if (planes <= 0) return hipSuccess;
     dim3 grid((M + 31) / 32, planes);
@@ -972,6 +1020,9 @@ hipError_t unpack_sym(const void* pk, void* full, int M, int planes, DType t, hi
     else if (t == DT_F32)
         hipLaunchKernelGGL(k_unpack<float>, grid, dim3(256), 0, s, (const float*)pk, (float*)full,
                            M);
+    else if (t == DT_SPLIT && M % 8 == 0 && (size_t)M * (M + 1) / 2 * 4 <= kUnpackLds)
+        hipLaunchKernelGGL(k_unpack_split_plane, dim3(planes), dim3(256),
+                           (size_t)M * (M + 1) / 2 * 4, s, (const float*)pk, (bf16_t*)full, M);
     else if (t == DT_SPLIT)
         hipLaunchKernelGGL(k_unpack_split, grid, dim3(256), 0, s, (const float*)pk,
                            (bf16_t*)full, M);
