@@ -52,11 +52,12 @@ def phase_flops(name, M, nc, na, nb, nw, taylor_order=6):
     }.get(name)
 
 
-def phase_dtype(name, prec):
-    """Matrix-core input type of a phase under a precision plan."""
+def phase_dtype(name, prec, M):
+    """Matrix-core input type of a phase under a precision plan (split-BF16
+    propagator products need M % 8 == 0, FP32 otherwise)."""
     contract = {"fp64": "fp64", "fp32": "fp32", "bf16": "bf16", "bf16_plain": "bf16",
                 "bf16x3": "bf16"}[prec]
-    prop = {"fp64": "fp64", "bf16x3": "fp32+bf16x3"}.get(prec, "fp32")
+    prop = "fp64" if prec == "fp64" else ("bf16" if prec == "bf16x3" and M % 8 == 0 else "fp32")
     return {"force_bias_gemm": contract, "field_sum_gemm": contract, "exchange": contract,
             "propagate": prop}.get(name)
 
@@ -123,19 +124,11 @@ def _roofline(prof_a, prof_b, steps, cfg, prec):
     n_a, n_b = prof_a[dom][1], prof_b[dom][1]
     tot_s = (prof_a[dom][0] + prof_b[dom][0]) * 1e-3
     achieved = (fl_a * n_a + fl_b * n_b) / tot_s / 1e12
-    dtype = phase_dtype(dom, prec)
+    dtype = phase_dtype(dom, prec, cfg.M)
     # split BF16 issues three BF16 products per algorithmic product
-    split = prec in ("bf16", "bf16x3") and dtype in ("bf16", "fp32+bf16x3")
-    if dtype == "fp32+bf16x3":
-        # P halves on the FP32 matrix cores, Taylor terms on the BF16 ones: the
-        # published peaks weighted by the two parts' algorithmic FLOPs
-        K = cfg.taylor_order
-        peak = (2 * 4.0 + K * 8.0) / (2 * 4.0 / PEAK_TFLOPS["fp32"] + K * 8.0 / PEAK_TFLOPS["bf16"])
-        peak_issued = (2 * 4.0 + K * 8.0) / (2 * 4.0 / PEAK_TFLOPS["fp32"]
-                                             + 3 * K * 8.0 / PEAK_TFLOPS["bf16"])
-    else:
-        peak = PEAK_TFLOPS[dtype]
-        peak_issued = peak / 3 if split else peak
+    split = prec in ("bf16", "bf16x3") and dtype == "bf16"
+    peak = PEAK_TFLOPS[dtype]
+    peak_issued = peak / 3 if split else peak
     roof = {"bound": "mfma", "kernel": dom, "kernel_dtype": dtype,
             "flops_per_launch": (fl_a * n_a + fl_b * n_b) / max(n_a + n_b, 1),
             "avg_launch_ms": tot_s * 1e3 / max(n_a + n_b, 1),

@@ -50,9 +50,12 @@ typedef enum {
  *   products (one-body halves and Taylor terms) in FP32.
  * AFQMC_BF16_PLAIN: L, L^half, Theta and the field coefficients stored as
  *   single BF16 values, one BF16 product per pair (fastest, least accurate).
- * AFQMC_BF16X3: as AFQMC_BF16, and the Taylor terms of the propagator also
- *   in split BF16 (A_w carried as hi + lo planes); the one-body halves P stay
- *   FP32.  Needs M % 8 == 0 for the split Taylor terms (FP32 otherwise).
+ * AFQMC_BF16X3: as AFQMC_BF16, and the propagator products also in split
+ *   BF16: the Taylor terms (A_w carried as hi + lo planes) and the one-body
+ *   halves, applied as P y = y + Q y with Q = P - I (formed in FP64, carried
+ *   as hi + lo planes) so that the identity part is added exactly in FP32
+ *   and the rounding of the product scales with |Q|.  Needs M % 8 == 0 for
+ *   the split propagator products (FP32 products otherwise).
  * In every mode the walker determinants, overlaps, determinants,
  * Gram-Schmidt, weights and phases stay FP64. */
 typedef enum {
@@ -242,8 +245,8 @@ afqmc_status afqmc_selftest_gemm(afqmc_prec prec, int m, int n, int k, const dou
 
 /* Kernel self-test of the fused propagation: out[w] = P T_K(A_w) P phi[w]
  * (Eq. 3 and Eq. 11, T_K the order-K Taylor polynomial of exp) with the
- * products in precision `prec` (AFQMC_FP64; AFQMC_BF16X3: Taylor terms in
- * split BF16 and P in FP32; else FP32), workgroup shape `variant` (waves x
+ * products in precision `prec` (AFQMC_FP64; AFQMC_BF16X3: Taylor terms and
+ * P - I in split BF16, the identity part of P added in FP32; else FP32), workgroup shape `variant` (waves x
  * column blocks per wave: 0: 8 x 2, 1: 4 x 2, 2: 4 x 1, 3: 2 x 2, with the
  * next chunk of the matrix operand prefetched; 4..7: the same shapes without
  * the prefetch, FP32 and split BF16 only; 8: 16 x 1, 9: 8 x 1, 10: 8 x 2 and

@@ -526,10 +526,26 @@ afqmc_status afqmc_init_walkers(afqmc_ham ham, int n_alpha, int n_beta, const do
         std::vector<double> X(ht.size()), Pm;
         for (size_t i = 0; i < X.size(); ++i) X[i] = -0.5 * par->dt * ht[i];
         expm_host(X, M, Pm);
+        // split products carry Q = P - I (formed in FP64) as hi/lo BF16 planes
         std::vector<float> Pf(Pm.begin(), Pm.end());
-        if (hipMemcpy(s->d_P.p, Pm.data(), Pm.size() * 8, hipMemcpyHostToDevice) != hipSuccess ||
-            hipMemcpy(s->d_Plp.p, Pf.data(), Pf.size() * 4, hipMemcpyHostToDevice) != hipSuccess)
+        if (s->ta == DT_SPLIT)
+            for (int i = 0; i < M; ++i)
+                for (int j = 0; j < M; ++j)
+                    Pf[(size_t)i * M + j] = (float)(Pm[(size_t)i * M + j] - (i == j ? 1.0 : 0.0));
+        if (hipMemcpy(s->d_P.p, Pm.data(), Pm.size() * 8, hipMemcpyHostToDevice) != hipSuccess)
             return bail(fail(AFQMC_E_DEVICE, "upload P"));
+        if (s->ta == DT_SPLIT) {
+            DevBuf q32;
+            if (q32.alloc(Pf.size() * 4) != hipSuccess)
+                return bail(fail(AFQMC_E_NOMEM, "Q staging"));
+            if (hipMemcpy(q32.p, Pf.data(), Pf.size() * 4, hipMemcpyHostToDevice) != hipSuccess ||
+                split_planes(q32.as<float>(), s->d_Plp.p, (long)Pf.size(), 1, st) != hipSuccess ||
+                hipStreamSynchronize(st) != hipSuccess)
+                return bail(fail(AFQMC_E_DEVICE, "upload Q"));
+        } else if (hipMemcpy(s->d_Plp.p, Pf.data(), Pf.size() * 4, hipMemcpyHostToDevice) !=
+                   hipSuccess) {
+            return bail(fail(AFQMC_E_DEVICE, "upload P"));
+        }
     }
     // low-precision copies of the contraction operands
     if (s->ts != DT_F64 &&
@@ -866,7 +882,17 @@ afqmc_status afqmc_selftest_propagate(afqmc_prec prec, int M, int N, int nw, int
     HIPCHK(hipMemcpy(dP64.p, P, nP * 8, hipMemcpyHostToDevice));
     HIPCHK(hipMemcpy(dA64.p, A, nA * 8, hipMemcpyHostToDevice));
     HIPCHK(hipMemset(dlive.p, 1, nw));
-    HIPCHK(convert(dP64.as<double>(), dP.p, t, (long)nP, nullptr));
+    if (ta == DT_SPLIT) {  // Q = P - I as hi/lo BF16 planes
+        std::vector<float> q(P, P + nP);
+        for (int i = 0; i < M; ++i) q[(size_t)i * M + i] = (float)(P[(size_t)i * M + i] - 1.0);
+        DevBuf dq;
+        HIPCHK(dq.alloc(nP * 4));
+        HIPCHK(hipMemcpy(dq.p, q.data(), nP * 4, hipMemcpyHostToDevice));
+        HIPCHK(split_planes(dq.as<float>(), dP.p, (long)nP, 1, nullptr));
+        HIPCHK(hipDeviceSynchronize());
+    } else {
+        HIPCHK(convert(dP64.as<double>(), dP.p, t, (long)nP, nullptr));
+    }
     if (ta == DT_SPLIT) {
         HIPCHK(dA32.alloc(nA * 4));
         HIPCHK(convert(dA64.as<double>(), dA32.p, DT_F32, (long)nA, nullptr));

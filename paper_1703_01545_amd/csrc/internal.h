@@ -82,8 +82,9 @@ hipError_t split_planes(const float* in, void* out, long n, long planes, hipStre
 // phi, phi_out: FP64 walker blocks [w][plane][N][M]; Pm: M x M real
 // symmetric, Af: [w][plane][M][M] complex symmetric, both in type t
 // (DT_F64 or DT_F32, the product precision).  ta: type of Af, equal to t,
-// or DT_SPLIT with t == DT_F32 (Taylor terms in split BF16, Af as hi/lo
-// planes [w][plane][hi, lo][M][M], M % 8 == 0).  Frozen walkers (live == 0)
+// or DT_SPLIT with t == DT_F32: every product in split BF16, Af as hi/lo
+// planes [w][plane][hi, lo][M][M] and Pm holding Q = P - I as hi/lo planes
+// [hi, lo][M][M] (P y computed as y + Q y), M % 8 == 0.  Frozen walkers (live == 0)
 // are copied unchanged.  M <= 256.  `variant` selects the workgroup shape
 // (waves per workgroup x column blocks per wave, with or without B prefetch,
 // one or two row blocks per workgroup; see kPropShapes); every variant gives

@@ -316,11 +316,14 @@ __global__ __launch_bounds__(64 * NWAVE, 2) void k_propagate(
 }
 
 // ---------------------------------------------------------------------------
-// Split-BF16 Taylor terms.  A_w is stored as hi/lo BF16 planes
+// Split-BF16 propagation.  A_w is stored as hi/lo BF16 planes
 // ([w][re, im][hi, lo][M][M]) and the state S as four BF16 planes (re hi,
 // re lo, im hi, im lo); each real product is three BF16 MFMAs 16x16x32
-// (hi hi + hi lo + lo hi) with FP32 accumulation.  The one-body halves P
-// stay FP32 (P is close to the identity, so its rounding is not scaled down).
+// (hi hi + hi lo + lo hi) with FP32 accumulation.  The one-body halves are
+// applied as P y = y + Q y with Q = P - I held as hi/lo BF16 planes
+// ([hi, lo][M][M]): P is close to the identity, so splitting Q instead of P
+// scales the rounding of the product down by |Q|, and the identity part is
+// added exactly (in FP32) by starting the accumulators at y.
 
 typedef unsigned int u4v __attribute__((ext_vector_type(4)));
 
@@ -331,12 +334,15 @@ __device__ __forceinline__ bf8 bload8(__amdgpu_buffer_rsrc_t r, int off) {
     return __builtin_bit_cast(bf8, __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0));
 }
 
-// acc[s] = S x A_w^T for this wave's column blocks; K in chunks of 32, lane
-// group g supplying k = k0 + 8 g + e (e < 8) for both operands.
-template <int MAXB, bool PF, int SPB>
+// CX (complex operand A_w, four planes): acc[s] = S x A_w^T from zero.
+// !CX (real operand Q, two planes): acc[s] += S x Q^T, each part of S
+// against Q.  This wave's column blocks; K in chunks of 32, lane group g
+// supplying k = k0 + 8 g + e (e < 8) for both operands.
+template <int MAXB, bool PF, int SPB, bool CX>
 __device__ __forceinline__ void pass_split(__amdgpu_buffer_rsrc_t rb, int M, int Mp, int MB,
                                            const bf16_t* Sb, const int* cb,
                                            f4 (&acc)[MAXB][2]) {
+    constexpr int NP = CX ? 4 : 2;  // operand planes: re hi, re lo (, im hi, im lo)
     const int lane = threadIdx.x & 63;
     const int g = lane >> 4, li = lane & 15;
     const int hl_b = M * M * 2;      // hi -> lo plane, bytes
@@ -348,81 +354,93 @@ __device__ __forceinline__ void pass_split(__amdgpu_buffer_rsrc_t rb, int M, int
     for (int s = 0; s < MAXB; ++s) {
         const int m = cb[s] * 16 + li;
         boff[s] = m < M ? (m * M + 8 * g) * 2 : kOutOfRange;
-        acc[s][0] = acc[s][1] = f4{0, 0, 0, 0};
+        if constexpr (CX) acc[s][0] = acc[s][1] = f4{0, 0, 0, 0};
     }
-    bf8 bc[MAXB][4], bn[MAXB][4];  // re hi, re lo, im hi, im lo
+    bf8 bc[MAXB][NP], bn[MAXB][NP];
     // unconditional loads and the PF choice as in pass()
     if constexpr (PF) {
 #pragma unroll
-        for (int s = 0; s < MAXB; ++s) {
-            bc[s][0] = bload8(rb, boff[s]);
-            bc[s][1] = bload8(rb, boff[s] + hl_b);
-            bc[s][2] = bload8(rb, boff[s] + pl_b);
-            bc[s][3] = bload8(rb, boff[s] + pl_b + hl_b);
-        }
+        for (int s = 0; s < MAXB; ++s)
+#pragma unroll
+            for (int p = 0; p < NP; ++p)
+                bc[s][p] = bload8(rb, boff[s] + (p & 1) * hl_b + (p >> 1) * pl_b);
     }
     for (int k0 = 0; k0 < Mp; k0 += 32) {
         const int kb = (k0 + (PF ? 32 : 0)) * 2;
 #pragma unroll
         for (int s = 0; s < MAXB; ++s) {
             bf8* d = PF ? bn[s] : bc[s];
-            d[0] = bload8(rb, boff[s] + kb);
-            d[1] = bload8(rb, boff[s] + kb + hl_b);
-            d[2] = bload8(rb, boff[s] + kb + pl_b);
-            d[3] = bload8(rb, boff[s] + kb + pl_b + hl_b);
+#pragma unroll
+            for (int p = 0; p < NP; ++p)
+                d[p] = bload8(rb, boff[s] + kb + (p & 1) * hl_b + (p >> 1) * pl_b);
         }
         const bf8 rh = *reinterpret_cast<const bf8*>(s0 + k0);
         const bf8 rl = *reinterpret_cast<const bf8*>(s0 + spl + k0);
         const bf8 ih = *reinterpret_cast<const bf8*>(s0 + 2 * spl + k0);
         const bf8 il = *reinterpret_cast<const bf8*>(s0 + 3 * spl + k0);
-        const bf8 nh = neg8(ih), nl = neg8(il);
+        if constexpr (CX) {
+            const bf8 nh = neg8(ih), nl = neg8(il);
 #pragma unroll
-        for (int s = 0; s < MAXB; ++s) {
-            if (cb[s] >= MB) continue;  // wave-uniform
-            f4 ar = acc[s][0], ai = acc[s][1];
-            // re += Sr Ar - Si Ai
-            ar = mma8(rl, bc[s][0], ar);
-            ar = mma8(rh, bc[s][1], ar);
-            ar = mma8(rh, bc[s][0], ar);
-            ar = mma8(nl, bc[s][2], ar);
-            ar = mma8(nh, bc[s][3], ar);
-            ar = mma8(nh, bc[s][2], ar);
-            // im += Sr Ai + Si Ar
-            ai = mma8(rl, bc[s][2], ai);
-            ai = mma8(rh, bc[s][3], ai);
-            ai = mma8(rh, bc[s][2], ai);
-            ai = mma8(il, bc[s][0], ai);
-            ai = mma8(ih, bc[s][1], ai);
-            ai = mma8(ih, bc[s][0], ai);
-            acc[s][0] = ar;
-            acc[s][1] = ai;
+            for (int s = 0; s < MAXB; ++s) {
+                if (cb[s] >= MB) continue;  // wave-uniform
+                f4 ar = acc[s][0], ai = acc[s][1];
+                // re += Sr Ar - Si Ai
+                ar = mma8(rl, bc[s][0], ar);
+                ar = mma8(rh, bc[s][1], ar);
+                ar = mma8(rh, bc[s][0], ar);
+                ar = mma8(nl, bc[s][2], ar);
+                ar = mma8(nh, bc[s][3], ar);
+                ar = mma8(nh, bc[s][2], ar);
+                // im += Sr Ai + Si Ar
+                ai = mma8(rl, bc[s][2], ai);
+                ai = mma8(rh, bc[s][3], ai);
+                ai = mma8(rh, bc[s][2], ai);
+                ai = mma8(il, bc[s][0], ai);
+                ai = mma8(ih, bc[s][1], ai);
+                ai = mma8(ih, bc[s][0], ai);
+                acc[s][0] = ar;
+                acc[s][1] = ai;
+            }
+        } else {
+#pragma unroll
+            for (int s = 0; s < MAXB; ++s) {
+                if (cb[s] >= MB) continue;  // wave-uniform
+                f4 ar = acc[s][0], ai = acc[s][1];
+                ar = mma8(rl, bc[s][0], ar);
+                ar = mma8(rh, bc[s][1], ar);
+                ar = mma8(rh, bc[s][0], ar);
+                ai = mma8(il, bc[s][0], ai);
+                ai = mma8(ih, bc[s][1], ai);
+                ai = mma8(ih, bc[s][0], ai);
+                acc[s][0] = ar;
+                acc[s][1] = ai;
+            }
         }
         if constexpr (PF) {
 #pragma unroll
             for (int s = 0; s < MAXB; ++s)
 #pragma unroll
-                for (int q = 0; q < 4; ++q) bc[s][q] = bn[s][q];
+                for (int p = 0; p < NP; ++p) bc[s][p] = bn[s][p];
         }
     }
 }
 
-// As k_propagate (FP32 products) with the Taylor terms in split BF16.  The
-// FP32 state (for the P halves) and the BF16 planes (for the Taylor terms)
-// share the LDS buffer; Mp is M rounded up to 32, and columns >= M of both
-// views are kept zero.
+// As k_propagate (FP32 accumulation) with every product in split BF16: the
+// four BF16 planes of the state are the only copy of it in LDS (Mp is M
+// rounded up to 32; columns >= M stay zero), the identity parts of the
+// one-body halves and the running Taylor sum are FP32 registers.
 template <int NWAVE, int MAXB, bool PF>
 __global__ __launch_bounds__(64 * NWAVE, 2) void k_propagate_split(
-    const double* __restrict__ phi, double* __restrict__ phi_out, const float* __restrict__ Pm,
+    const double* __restrict__ phi, double* __restrict__ phi_out, const bf16_t* __restrict__ Qs,
     const bf16_t* __restrict__ Af, const uint8_t* __restrict__ live, int nw, int M, int N, int K,
     int nrb) {
     extern __shared__ __attribute__((aligned(16))) char smem_raw[];
-    float* S = reinterpret_cast<float*>(smem_raw);
     bf16_t* Sb = reinterpret_cast<bf16_t*>(smem_raw);
     constexpr int NT = 64 * NWAVE;
     const int Mp = (M + 31) / 32 * 32;
     const int MB = (M + 15) / 16;
-    constexpr int SPT = kPitchF, SPB = kPitchB;  // fixed pitches (M <= 256)
-    constexpr long splane = 16L * SPT, bplane = 16L * SPB;
+    constexpr int SPB = kPitchB;  // fixed pitch (M <= 256)
+    constexpr long bplane = 16L * SPB;
     const long nblk = (long)nw * nrb;
     const long per = (nblk + 7) / 8;
     const long L = (long)(blockIdx.x % 8) * per + blockIdx.x / 8;
@@ -443,38 +461,22 @@ __global__ __launch_bounds__(64 * NWAVE, 2) void k_propagate_split(
         }
         return;
     }
-    for (int e = tid; e < 2 * 16 * Mp; e += NT) {
-        const int p = e / (16 * Mp), rem = e % (16 * Mp);
-        const int r = rem / Mp, m = rem % Mp;
-        double v = 0.0;
-        if (r < nrow && m < M) v = src[p * NM + (long)(row0 + r) * M + m];
-        S[p * splane + r * SPT + m] = (float)v;
-    }
     const int vw = (wave + (int)(L % NWAVE)) % NWAVE;
     int cb[MAXB];
 #pragma unroll
     for (int s = 0; s < MAXB; ++s) cb[s] = vw + s * NWAVE;
-    __syncthreads();
-    f4 acc[MAXB][2], z[MAXB][2];
     const long Aplane = (long)M * M;
-    const __amdgpu_buffer_rsrc_t rP = make_rsrc(Pm, Aplane);
+    const __amdgpu_buffer_rsrc_t rQ = make_rsrc(Qs, 2 * Aplane);
     const __amdgpu_buffer_rsrc_t rA = make_rsrc(Af + (long)w * 4 * Aplane, 4 * Aplane);
     const int li = lane & 15;
-    // zero the BF16 view's columns no block writes (MB * 16 .. Mp)
-    auto zero_b = [&]() {
+    // the columns no block writes (MB * 16 .. Mp) stay zero throughout
+    {
         const int pad = Mp - MB * 16;
         for (int e = tid; e < 4 * 16 * pad; e += NT) {
             const int q = e / (16 * pad), rem = e % (16 * pad);
             Sb[q * bplane + (rem / pad) * SPB + MB * 16 + rem % pad] = (bf16_t)0.0f;
         }
-    };
-    auto zero_f = [&]() {
-        const int pad = Mp - MB * 16;
-        for (int e = tid; e < 2 * 16 * pad; e += NT) {
-            const int q = e / (16 * pad), rem = e % (16 * pad);
-            S[q * splane + (rem / pad) * SPT + MB * 16 + rem % pad] = 0.0f;
-        }
-    };
+    }
     auto put_b = [&](int s, const f4& vr, const f4& vi) {
         const int col = cb[s] * 16 + li;
         const bool ok = col < M;
@@ -489,19 +491,27 @@ __global__ __launch_bounds__(64 * NWAVE, 2) void k_propagate_split(
             Sb[3 * bplane + off] = to_bf(xi - (float)hi);
         }
     };
-    auto put_f = [&](int s, const f4& vr, const f4& vi) {
+    // the walker's block in the accumulator layout (zero past the orbitals
+    // and past column M), loaded unconditionally from clamped offsets
+    f4 acc[MAXB][2], z[MAXB][2];
+#pragma unroll
+    for (int s = 0; s < MAXB; ++s) {
         const int col = cb[s] * 16 + li;
-        const bool ok = col < M;
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-            const int off = acc_row<float>(lane, r) * SPT + col;
-            S[off] = ok ? vr[r] : 0.0f;
-            S[splane + off] = ok ? vi[r] : 0.0f;
+            const int row = acc_row<float>(lane, r);
+            const bool ok = cb[s] < MB && row < nrow && col < M;
+            const long o = ok ? (long)(row0 + row) * M + col : 0;
+            const double xr = src[o], xi = src[NM + o];
+            acc[s][0][r] = ok ? (float)xr : 0.0f;
+            acc[s][1][r] = ok ? (float)xi : 0.0f;
         }
-    };
-    pass<float, MAXB, 1, PF, SPT>(rP, M, Mp, MB, S, cb, acc);
+        if (cb[s] < MB) put_b(s, acc[s][0], acc[s][1]);
+    }
     __syncthreads();
-    zero_b();
+    // first one-body half: y = x + Q x
+    pass_split<MAXB, PF, SPB, false>(rQ, M, Mp, MB, Sb, cb, acc);
+    __syncthreads();
 #pragma unroll
     for (int s = 0; s < MAXB; ++s) {
         z[s][0] = acc[s][0];
@@ -510,31 +520,29 @@ __global__ __launch_bounds__(64 * NWAVE, 2) void k_propagate_split(
     }
     __syncthreads();
     for (int n = 1; n <= K; ++n) {
-        pass_split<MAXB, PF, SPB>(rA, M, Mp, MB, Sb, cb, acc);
+        pass_split<MAXB, PF, SPB, true>(rA, M, Mp, MB, Sb, cb, acc);
         __syncthreads();
         const float inv = inv_n_f(n);
-        if (n == K) zero_f();
 #pragma unroll
         for (int s = 0; s < MAXB; ++s) {
             term_update(acc[s][0], z[s][0], inv);
             term_update(acc[s][1], z[s][1], inv);
             if (cb[s] < MB) {
                 if (n == K)
-                    put_f(s, z[s][0], z[s][1]);
+                    put_b(s, z[s][0], z[s][1]);
                 else
                     put_b(s, acc[s][0], acc[s][1]);
             }
         }
         __syncthreads();
     }
-    if (K == 0) {  // no Taylor terms: back to the FP32 view
-        zero_f();
+    // second one-body half on the Taylor sum (the BF16 view holds z)
 #pragma unroll
-        for (int s = 0; s < MAXB; ++s)
-            if (cb[s] < MB) put_f(s, z[s][0], z[s][1]);
-        __syncthreads();
+    for (int s = 0; s < MAXB; ++s) {
+        acc[s][0] = z[s][0];
+        acc[s][1] = z[s][1];
     }
-    pass<float, MAXB, 1, PF, SPT>(rP, M, Mp, MB, S, cb, acc);
+    pass_split<MAXB, PF, SPB, false>(rQ, M, Mp, MB, Sb, cb, acc);
 #pragma unroll
     for (int s = 0; s < MAXB; ++s) {
         const int col = cb[s] * 16 + li;
@@ -553,51 +561,16 @@ __global__ __launch_bounds__(64 * NWAVE, 2) void k_propagate_split(
 
 // ---------------------------------------------------------------------------
 // RB row blocks per workgroup (16 RB orbitals of one walker): every operand
-// fragment of A_w or P a wave loads serves RB row blocks, so the loads per
+// fragment of A_w or Q a wave loads serves RB row blocks, so the loads per
 // matrix-core product drop by RB.  Operands are loaded chunk by chunk (no
-// prefetch); row blocks past the walker's last orbital are skipped.
-
-template <int MAXB, int RB>
-__device__ __forceinline__ void pass_rb(__amdgpu_buffer_rsrc_t rb, int M, int Mp, int MB, int nrbv,
-                                        const float* S, int SPT, const int* cb,
-                                        f4 (&acc)[RB][MAXB][2]) {
-    const int lane = threadIdx.x & 63;
-    const int g = lane >> 4, li = lane & 15;
-    const long splane = 16L * RB * SPT;
-    int boff[MAXB];
-#pragma unroll
-    for (int s = 0; s < MAXB; ++s) {
-        const int m = cb[s] * 16 + li;
-        boff[s] = m < M ? (m * M + 4 * g) * 4 : kOutOfRange;
-#pragma unroll
-        for (int r = 0; r < RB; ++r) acc[r][s][0] = acc[r][s][1] = f4{0, 0, 0, 0};
-    }
-    for (int k0 = 0; k0 < Mp; k0 += 16) {
-        float bc[MAXB][4];
-#pragma unroll
-        for (int s = 0; s < MAXB; ++s) bload4(rb, boff[s] + k0 * 4, bc[s]);
-#pragma unroll
-        for (int r = 0; r < RB; ++r) {
-            if (r >= nrbv) continue;  // wave-uniform
-            const float* sr_ = S + (r * 16 + li) * SPT + 4 * g + k0;
-            const f4 xr = *reinterpret_cast<const f4*>(sr_);
-            const f4 xi = *reinterpret_cast<const f4*>(sr_ + splane);
-#pragma unroll
-            for (int j = 0; j < 4; ++j)
-#pragma unroll
-                for (int s = 0; s < MAXB; ++s) {
-                    if (cb[s] >= MB) continue;  // wave-uniform
-                    acc[r][s][0] = mma1(xr[j], bc[s][j], acc[r][s][0]);
-                    acc[r][s][1] = mma1(xi[j], bc[s][j], acc[r][s][1]);
-                }
-        }
-    }
-}
-
-template <int MAXB, int RB>
+// prefetch); row blocks past the walker's last orbital are skipped.  CX and
+// the accumulation as in pass_split, with the same product order per
+// accumulator.
+template <int MAXB, int RB, bool CX>
 __device__ __forceinline__ void pass_split_rb(__amdgpu_buffer_rsrc_t rb, int M, int Mp, int MB,
                                               int nrbv, const bf16_t* Sb, int SPB, const int* cb,
                                               f4 (&acc)[RB][MAXB][2]) {
+    constexpr int NP = CX ? 4 : 2;
     const int lane = threadIdx.x & 63;
     const int g = lane >> 4, li = lane & 15;
     const int hl_b = M * M * 2;
@@ -608,19 +581,18 @@ __device__ __forceinline__ void pass_split_rb(__amdgpu_buffer_rsrc_t rb, int M, 
     for (int s = 0; s < MAXB; ++s) {
         const int m = cb[s] * 16 + li;
         boff[s] = m < M ? (m * M + 8 * g) * 2 : kOutOfRange;
+        if constexpr (CX) {
 #pragma unroll
-        for (int r = 0; r < RB; ++r) acc[r][s][0] = acc[r][s][1] = f4{0, 0, 0, 0};
+            for (int r = 0; r < RB; ++r) acc[r][s][0] = acc[r][s][1] = f4{0, 0, 0, 0};
+        }
     }
     for (int k0 = 0; k0 < Mp; k0 += 32) {
-        bf8 bc[MAXB][4];  // re hi, re lo, im hi, im lo
+        bf8 bc[MAXB][NP];  // re hi, re lo (, im hi, im lo)
 #pragma unroll
-        for (int s = 0; s < MAXB; ++s) {
-            const int o = boff[s] + k0 * 2;
-            bc[s][0] = bload8(rb, o);
-            bc[s][1] = bload8(rb, o + hl_b);
-            bc[s][2] = bload8(rb, o + pl_b);
-            bc[s][3] = bload8(rb, o + pl_b + hl_b);
-        }
+        for (int s = 0; s < MAXB; ++s)
+#pragma unroll
+            for (int p = 0; p < NP; ++p)
+                bc[s][p] = bload8(rb, boff[s] + k0 * 2 + (p & 1) * hl_b + (p >> 1) * pl_b);
 #pragma unroll
         for (int r = 0; r < RB; ++r) {
             if (r >= nrbv) continue;  // wave-uniform
@@ -632,31 +604,46 @@ __device__ __forceinline__ void pass_split_rb(__amdgpu_buffer_rsrc_t rb, int M, 
 #pragma unroll
             for (int s = 0; s < MAXB; ++s) {
                 if (cb[s] >= MB) continue;  // wave-uniform
-                f4 ar = acc[r][s][0], ai = acc[r][s][1];
+                f4 ar = acc[r][s][0];
                 ar = mma8(rl, bc[s][0], ar);
                 ar = mma8(rh, bc[s][1], ar);
                 ar = mma8(rh, bc[s][0], ar);
-                ai = mma8(rl, bc[s][2], ai);
-                ai = mma8(rh, bc[s][3], ai);
-                ai = mma8(rh, bc[s][2], ai);
+                if constexpr (CX) {
+                    f4 ai = acc[r][s][1];
+                    ai = mma8(rl, bc[s][2], ai);
+                    ai = mma8(rh, bc[s][3], ai);
+                    ai = mma8(rh, bc[s][2], ai);
+                    acc[r][s][1] = ai;
+                }
                 acc[r][s][0] = ar;
-                acc[r][s][1] = ai;
             }
             const bf8 ih = *reinterpret_cast<const bf8*>(s0 + 2 * spl);
             const bf8 il = *reinterpret_cast<const bf8*>(s0 + 3 * spl);
-            const bf8 nh = neg8(ih), nl = neg8(il);
+            if constexpr (CX) {
+                const bf8 nh = neg8(ih), nl = neg8(il);
 #pragma unroll
-            for (int s = 0; s < MAXB; ++s) {
-                if (cb[s] >= MB) continue;  // wave-uniform
-                f4 ar = acc[r][s][0], ai = acc[r][s][1];
-                ar = mma8(nl, bc[s][2], ar);
-                ar = mma8(nh, bc[s][3], ar);
-                ar = mma8(nh, bc[s][2], ar);
-                ai = mma8(il, bc[s][0], ai);
-                ai = mma8(ih, bc[s][1], ai);
-                ai = mma8(ih, bc[s][0], ai);
-                acc[r][s][0] = ar;
-                acc[r][s][1] = ai;
+                for (int s = 0; s < MAXB; ++s) {
+                    if (cb[s] >= MB) continue;  // wave-uniform
+                    f4 ar = acc[r][s][0], ai = acc[r][s][1];
+                    ar = mma8(nl, bc[s][2], ar);
+                    ar = mma8(nh, bc[s][3], ar);
+                    ar = mma8(nh, bc[s][2], ar);
+                    ai = mma8(il, bc[s][0], ai);
+                    ai = mma8(ih, bc[s][1], ai);
+                    ai = mma8(ih, bc[s][0], ai);
+                    acc[r][s][0] = ar;
+                    acc[r][s][1] = ai;
+                }
+            } else {
+#pragma unroll
+                for (int s = 0; s < MAXB; ++s) {
+                    if (cb[s] >= MB) continue;  // wave-uniform
+                    f4 ai = acc[r][s][1];
+                    ai = mma8(il, bc[s][0], ai);
+                    ai = mma8(ih, bc[s][1], ai);
+                    ai = mma8(ih, bc[s][0], ai);
+                    acc[r][s][1] = ai;
+                }
             }
             // keep each row block's operand fragments from being hoisted
             // together (register budget of the 16-wave shape)
@@ -668,7 +655,7 @@ __device__ __forceinline__ void pass_split_rb(__amdgpu_buffer_rsrc_t rb, int M, 
 // ZREG: the running Taylor sum in registers (else in LDS beside the state).
 template <int NWAVE, int MAXB, int RB, bool ZREG>
 __global__ __launch_bounds__(64 * NWAVE, 1) void k_propagate_split_rb(
-    const double* __restrict__ phi, double* __restrict__ phi_out, const float* __restrict__ Pm,
+    const double* __restrict__ phi, double* __restrict__ phi_out, const bf16_t* __restrict__ Qs,
     const bf16_t* __restrict__ Af, const uint8_t* __restrict__ live, int nw, int M, int N, int K,
     int nrb) {
     extern __shared__ __attribute__((aligned(16))) char smem_raw[];
@@ -679,10 +666,9 @@ __global__ __launch_bounds__(64 * NWAVE, 1) void k_propagate_split_rb(
     // fixed row pitches (M <= 256): LDS offsets become instruction immediates
     constexpr int SPT = kPitchF, SPB = kPitchB;
     constexpr long splane = (long)ROWS * SPT, bplane = (long)ROWS * SPB;
-    float* S = reinterpret_cast<float*>(smem_raw);
     bf16_t* Sb = reinterpret_cast<bf16_t*>(smem_raw);
-    // running Taylor sum, FP32, same layout as the FP32 view (own elements
-    // only: no barrier needed for its updates)
+    // running Taylor sum, FP32, rows of pitch SPT (own elements only: no
+    // barrier needed for its updates)
     float* Zs = reinterpret_cast<float*>(smem_raw + 4 * bplane * sizeof(bf16_t));
     const long nblk = (long)nw * nrb;
     const long per = (nblk + 7) / 8;
@@ -705,37 +691,24 @@ __global__ __launch_bounds__(64 * NWAVE, 1) void k_propagate_split_rb(
         }
         return;
     }
-    for (int e = tid; e < 2 * ROWS * Mp; e += NT) {
-        const int p = e / (ROWS * Mp), rem = e % (ROWS * Mp);
-        const int r = rem / Mp, m = rem % Mp;
-        double v = 0.0;
-        if (r < nrow && m < M) v = src[p * NM + (long)(row0 + r) * M + m];
-        S[p * splane + r * SPT + m] = (float)v;
-    }
     const int vw = (wave + (int)(L % NWAVE)) % NWAVE;
     int cb[MAXB];
 #pragma unroll
     for (int s = 0; s < MAXB; ++s) cb[s] = vw + s * NWAVE;
-    __syncthreads();
     f4 acc[RB][MAXB][2];
     f4 zr[ZREG ? RB : 1][MAXB][2];
     const long Aplane = (long)M * M;
-    const __amdgpu_buffer_rsrc_t rP = make_rsrc(Pm, Aplane);
+    const __amdgpu_buffer_rsrc_t rQ = make_rsrc(Qs, 2 * Aplane);
     const __amdgpu_buffer_rsrc_t rA = make_rsrc(Af + (long)w * 4 * Aplane, 4 * Aplane);
     const int li = lane & 15;
-    const int pad = Mp - MB * 16;
-    auto zero_b = [&]() {
+    // the columns no block writes (MB * 16 .. Mp) stay zero throughout
+    {
+        const int pad = Mp - MB * 16;
         for (int e = tid; e < 4 * ROWS * pad; e += NT) {
             const int q = e / (ROWS * pad), rem = e % (ROWS * pad);
             Sb[q * bplane + (rem / pad) * SPB + MB * 16 + rem % pad] = (bf16_t)0.0f;
         }
-    };
-    auto zero_f = [&]() {
-        for (int e = tid; e < 2 * ROWS * pad; e += NT) {
-            const int q = e / (ROWS * pad), rem = e % (ROWS * pad);
-            S[q * splane + (rem / pad) * SPT + MB * 16 + rem % pad] = 0.0f;
-        }
-    };
+    }
     auto put_b = [&](int r, int s, const f4& vr, const f4& vi) {
         const int col = cb[s] * 16 + li;
         const bool ok = col < M;
@@ -748,16 +721,6 @@ __global__ __launch_bounds__(64 * NWAVE, 1) void k_propagate_split_rb(
             Sb[bplane + off] = to_bf(xr - (float)hr);
             Sb[2 * bplane + off] = hi;
             Sb[3 * bplane + off] = to_bf(xi - (float)hi);
-        }
-    };
-    auto put_f = [&](int r, int s, const f4& vr, const f4& vi) {
-        const int col = cb[s] * 16 + li;
-        const bool ok = col < M;
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const int off = (r * 16 + acc_row<float>(lane, q)) * SPT + col;
-            S[off] = ok ? vr[q] : 0.0f;
-            S[splane + off] = ok ? vi[q] : 0.0f;
         }
     };
     // z (this thread's elements) <- v, or += v
@@ -785,11 +748,29 @@ __global__ __launch_bounds__(64 * NWAVE, 1) void k_propagate_split_rb(
             }
         }
     };
-    // rows past the walker's orbitals (r >= nrbv) are never read: their S
-    // rows stay as loaded (zeros) and their accumulators are not stored
-    pass_rb<MAXB, RB>(rP, M, Mp, MB, nrbv, S, SPT, cb, acc);
+    // the walker's rows in the accumulator layout (zero past the orbitals
+    // and past column M); row blocks past the orbitals (r >= nrbv) are never
+    // read or stored
+#pragma unroll
+    for (int r = 0; r < RB; ++r)
+#pragma unroll
+        for (int s = 0; s < MAXB; ++s) {
+            const int col = cb[s] * 16 + li;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int row = r * 16 + acc_row<float>(lane, q);
+                const bool ok = cb[s] < MB && row < nrow && col < M;
+                const long o = ok ? (long)(row0 + row) * M + col : 0;
+                const double xr = src[o], xi = src[NM + o];
+                acc[r][s][0][q] = ok ? (float)xr : 0.0f;
+                acc[r][s][1][q] = ok ? (float)xi : 0.0f;
+            }
+            if (r < nrbv && cb[s] < MB) put_b(r, s, acc[r][s][0], acc[r][s][1]);
+        }
     __syncthreads();
-    zero_b();
+    // first one-body half: y = x + Q x
+    pass_split_rb<MAXB, RB, false>(rQ, M, Mp, MB, nrbv, Sb, SPB, cb, acc);
+    __syncthreads();
 #pragma unroll
     for (int r = 0; r < RB; ++r)
 #pragma unroll
@@ -800,10 +781,9 @@ __global__ __launch_bounds__(64 * NWAVE, 1) void k_propagate_split_rb(
             }
     __syncthreads();
     for (int n = 1; n <= K; ++n) {
-        pass_split_rb<MAXB, RB>(rA, M, Mp, MB, nrbv, Sb, SPB, cb, acc);
+        pass_split_rb<MAXB, RB, true>(rA, M, Mp, MB, nrbv, Sb, SPB, cb, acc);
         __syncthreads();
         const float inv = inv_n_f(n);
-        if (n == K) zero_f();
 #pragma unroll
         for (int r = 0; r < RB; ++r)
 #pragma unroll
@@ -816,7 +796,7 @@ __global__ __launch_bounds__(64 * NWAVE, 1) void k_propagate_split_rb(
                 }
                 if (n == K) {
                     zacc(r, s, acc[r][s][0], acc[r][s][1], false);  // acc <- z
-                    put_f(r, s, acc[r][s][0], acc[r][s][1]);
+                    put_b(r, s, acc[r][s][0], acc[r][s][1]);
                 } else {
                     put_b(r, s, acc[r][s][0], acc[r][s][1]);
                     f4 tr = acc[r][s][0], ti = acc[r][s][1];
@@ -825,20 +805,9 @@ __global__ __launch_bounds__(64 * NWAVE, 1) void k_propagate_split_rb(
             }
         __syncthreads();
     }
-    if (K == 0) {
-        zero_f();
-#pragma unroll
-        for (int r = 0; r < RB; ++r)
-#pragma unroll
-            for (int s = 0; s < MAXB; ++s)
-                if (r < nrbv && cb[s] < MB) {
-                    f4 tr = f4{0, 0, 0, 0}, ti = f4{0, 0, 0, 0};
-                    zacc(r, s, tr, ti, false);
-                    put_f(r, s, tr, ti);
-                }
-        __syncthreads();
-    }
-    pass_rb<MAXB, RB>(rP, M, Mp, MB, nrbv, S, SPT, cb, acc);
+    // second one-body half on the Taylor sum: acc and the BF16 view hold z
+    // (with K = 0 both still hold y)
+    pass_split_rb<MAXB, RB, false>(rQ, M, Mp, MB, nrbv, Sb, SPB, cb, acc);
 #pragma unroll
     for (int r = 0; r < RB; ++r)
 #pragma unroll
@@ -858,11 +827,9 @@ __global__ __launch_bounds__(64 * NWAVE, 1) void k_propagate_split_rb(
 }
 
 template <int NWAVE, int MAXB, int RB, bool ZREG>
-hipError_t launch_prop_split_rb(const double* phi, double* phi_out, const void* Pm, const void* Af,
+hipError_t launch_prop_split_rb(const double* phi, double* phi_out, const void* Qs, const void* Af,
                                 const uint8_t* live, int nw, int M, int N, int K, hipStream_t s) {
-    const int Mp = (M + 31) / 32 * 32;
-    // BF16 view (>= the FP32 view) + the FP32 running sum
-    (void)Mp;
+    // the BF16 state + the FP32 running sum when it is not in registers
     const size_t shm = 4 * 16 * RB * (size_t)kPitchB * sizeof(bf16_t) +
                        (ZREG ? 0 : 2 * 16 * RB * (size_t)kPitchF * sizeof(float));
     const int nrb = (N + 16 * RB - 1) / (16 * RB);
@@ -875,20 +842,21 @@ hipError_t launch_prop_split_rb(const double* phi, double* phi_out, const void* 
         if (e != hipSuccess) return e;
         attr = true;
     }
-    hipLaunchKernelGGL((k_propagate_split_rb<NWAVE, MAXB, RB, ZREG>), dim3(grid), dim3(64 * NWAVE), shm,
-                       s, phi, phi_out, (const float*)Pm, (const bf16_t*)Af, live, nw, M, N, K, nrb);
+    hipLaunchKernelGGL((k_propagate_split_rb<NWAVE, MAXB, RB, ZREG>), dim3(grid), dim3(64 * NWAVE),
+                       shm, s, phi, phi_out, (const bf16_t*)Qs, (const bf16_t*)Af, live, nw, M, N,
+                       K, nrb);
     return hipGetLastError();
 }
 
 template <int NWAVE, int MAXB, bool PF>
-hipError_t launch_prop_split(const double* phi, double* phi_out, const void* Pm, const void* Af,
+hipError_t launch_prop_split(const double* phi, double* phi_out, const void* Qs, const void* Af,
                              const uint8_t* live, int nw, int M, int N, int K, hipStream_t s) {
-    const size_t shm = 4 * 16 * (size_t)kPitchB * sizeof(bf16_t);  // >= the FP32 view
+    const size_t shm = 4 * 16 * (size_t)kPitchB * sizeof(bf16_t);
     const int nrb = (N + 15) / 16;
     const long nblk = (long)nw * nrb;
     const long grid = ((nblk + 7) / 8) * 8;
     hipLaunchKernelGGL((k_propagate_split<NWAVE, MAXB, PF>), dim3(grid), dim3(64 * NWAVE), shm, s,
-                       phi, phi_out, (const float*)Pm, (const bf16_t*)Af, live, nw, M, N, K, nrb);
+                       phi, phi_out, (const bf16_t*)Qs, (const bf16_t*)Af, live, nw, M, N, K, nrb);
     return hipGetLastError();
 }
 
