@@ -43,8 +43,11 @@ template <typename TA, typename TB, typename TC, typename TO, int BM, int BN, in
           int WGN, int VA, int VB, bool AL>
 __global__ __launch_bounds__(64 * WGM * WGN) void k_gemm(Gemm g, int ntn, int ntm) {
     typedef Core<TA, TB, TC, BM, BN, BK, WGM, WGN, VA, VB, AL> C;
-    __shared__ __attribute__((aligned(16))) typename C::LT As[C::LDS_A];
-    __shared__ __attribute__((aligned(16))) typename C::LT Bs[C::LDS_B];
+    // split-BF16 tiles of 128 rows or more: two LDS buffers (the split and
+    // stores of the next K tile overlap the products); the others: one
+    constexpr bool DB = std::is_same<TC, Split>::value && AL && BM >= 128;
+    __shared__ __attribute__((aligned(16))) typename C::LT As[(DB ? 2 : 1) * C::LDS_A];
+    __shared__ __attribute__((aligned(16))) typename C::LT Bs[(DB ? 2 : 1) * C::LDS_B];
     // XCD-aware order: workgroups are dealt to the eight XCDs in turn, so
     // logical tile L = (id mod 8) per + id / 8 gives each XCD a contiguous
     // run of tiles (column tiles fastest): the column tiles of one row block
@@ -78,7 +81,7 @@ __global__ __launch_bounds__(64 * WGM * WGN) void k_gemm(Gemm g, int ntn, int nt
         boff[j] = r < g.n ? rowmap(g.rb, r) : -1;
     }
     typename C::accv acc[C::TM][C::TN];
-    C::run(A, aoff, B, boff, k_len, As, Bs, acc);
+    C::template run<DB>(A, aoff, B, boff, k_len, As, Bs, acc);
 
     const int lane = tid & 63, wave = tid >> 6;
     const int wm = wave / WGN, wn = wave % WGN;

@@ -162,8 +162,9 @@ __device__ __forceinline__ void gload_run(const TS* __restrict__ row, int kg, in
 // ---------------------------------------------------------------------------
 // GEMM core.  C[i, j] = sum_k A(i, k) B(j, k), both operands K-contiguous
 // rows resolved once per thread (aoff/boff; -1 = row out of range, reads
-// zero).  BM x BK and BN x BK tiles are staged through LDS with one register
-// prefetch of the next K tile; each of the NT/64 waves accumulates TM x TN
+// zero).  BM x BK and BN x BK tiles are staged through LDS (one buffer, or
+// two with the next tile's stores overlapping the products) with one
+// register prefetch of the next K tile; each of the NT/64 waves accumulates TM x TN
 // MFMA blocks of a (BM/WGM) x (BN/WGN) sub-tile.  V*: elements per global
 // load of each operand (1 = scalar, else one 16-byte vector load).
 template <typename TA, typename TB, typename TC, int BM, int BN, int BK, int WGM, int WGN, int VA,
@@ -190,13 +191,78 @@ struct Core {
     static __device__ __forceinline__ int arow(int j) { return threadIdx.x / TPRA + j * RPA; }
     static __device__ __forceinline__ int brow(int j) { return threadIdx.x / TPRB + j * RPB; }
 
+    // acc += the products of one staged K tile (As, Bs: one buffer)
+    static __device__ __forceinline__ void compute(const LT* As, const LT* Bs,
+                                                   accv (&acc)[TM][TN]) {
+        const int lane = threadIdx.x & 63;
+        const int wave = threadIdx.x >> 6;
+        const int wm = wave / WGN, wn = wave % WGN;
+        if constexpr (Info<TC>::KM == 4) {
+#pragma unroll
+            for (int ks = 0; ks < BK; ks += 4) {
+                LT af[TM], bfr[TN];
+#pragma unroll
+                for (int a = 0; a < TM; ++a)
+                    af[a] = As[(wm * TM * 16 + a * 16 + (lane & 15)) * PK + ks + (lane >> 4)];
+#pragma unroll
+                for (int b = 0; b < TN; ++b)
+                    bfr[b] = Bs[(wn * TN * 16 + b * 16 + (lane & 15)) * PK + ks + (lane >> 4)];
+#pragma unroll
+                for (int a = 0; a < TM; ++a)
+#pragma unroll
+                    for (int b = 0; b < TN; ++b) acc[a][b] = mma1(af[a], bfr[b], acc[a][b]);
+            }
+        } else {
+#pragma unroll
+            for (int ks = 0; ks < BK; ks += 32) {
+                bf8 ah[TM], bh[TN];
+#pragma unroll
+                for (int a = 0; a < TM; ++a)
+                    ah[a] = *reinterpret_cast<const bf8*>(
+                        &As[(wm * TM * 16 + a * 16 + (lane & 15)) * PK + ks + 8 * (lane >> 4)]);
+#pragma unroll
+                for (int b = 0; b < TN; ++b)
+                    bh[b] = *reinterpret_cast<const bf8*>(
+                        &Bs[(wn * TN * 16 + b * 16 + (lane & 15)) * PK + ks + 8 * (lane >> 4)]);
+                if constexpr (PL == 2) {
+                    bf8 al[TM], bl[TN];
+#pragma unroll
+                    for (int a = 0; a < TM; ++a)
+                        al[a] = *reinterpret_cast<const bf8*>(
+                            &As[BM * PK + (wm * TM * 16 + a * 16 + (lane & 15)) * PK + ks +
+                                8 * (lane >> 4)]);
+#pragma unroll
+                    for (int b = 0; b < TN; ++b)
+                        bl[b] = *reinterpret_cast<const bf8*>(
+                            &Bs[BN * PK + (wn * TN * 16 + b * 16 + (lane & 15)) * PK + ks +
+                                8 * (lane >> 4)]);
+#pragma unroll
+                    for (int a = 0; a < TM; ++a)
+#pragma unroll
+                        for (int b = 0; b < TN; ++b) {
+                            acc[a][b] = mma8(al[a], bh[b], acc[a][b]);
+                            acc[a][b] = mma8(ah[a], bl[b], acc[a][b]);
+                            acc[a][b] = mma8(ah[a], bh[b], acc[a][b]);
+                        }
+                } else {
+#pragma unroll
+                    for (int a = 0; a < TM; ++a)
+#pragma unroll
+                        for (int b = 0; b < TN; ++b) acc[a][b] = mma8(ah[a], bh[b], acc[a][b]);
+                }
+            }
+        }
+    }
+
+    // DB = false: one LDS buffer, two barriers per K tile.  DB = true: As and
+    // Bs hold two buffers each; tile t + 1 is split and stored into the other
+    // buffer right after the products of tile t are issued, one barrier per
+    // K tile.  The products and their order per accumulator are the same.
+    template <bool DB = false>
     static __device__ __forceinline__ void run(const TA* __restrict__ A, const long* aoff,
                                                const TB* __restrict__ B, const long* boff, int K,
                                                LT* As, LT* Bs, accv (&acc)[TM][TN]) {
         const int tid = threadIdx.x;
-        const int lane = tid & 63;
-        const int wave = tid >> 6;
-        const int wm = wave / WGN, wn = wave % WGN;
         const int ka = (tid % TPRA) * VA, kb = (tid % TPRB) * VB;
         ST ra[LA][VA], rb[LB][VB];
 #pragma unroll
@@ -223,82 +289,43 @@ struct Core {
                     for (int e = 0; e < VB; ++e) rb[j][e] = (ST)0;
             }
         };
-        auto sstore = [&]() {
+        auto sstore = [&](LT* Ad, LT* Bd) {
 #pragma unroll
             for (int j = 0; j < LA; ++j)
 #pragma unroll
-                for (int e = 0; e < VA; ++e) lds_put<TC>(As, BM * PK, arow(j) * PK + ka + e, ra[j][e]);
+                for (int e = 0; e < VA; ++e) lds_put<TC>(Ad, BM * PK, arow(j) * PK + ka + e, ra[j][e]);
 #pragma unroll
             for (int j = 0; j < LB; ++j)
 #pragma unroll
-                for (int e = 0; e < VB; ++e) lds_put<TC>(Bs, BN * PK, brow(j) * PK + kb + e, rb[j][e]);
+                for (int e = 0; e < VB; ++e) lds_put<TC>(Bd, BN * PK, brow(j) * PK + kb + e, rb[j][e]);
         };
 
         gload(0);
-        sstore();
-        __syncthreads();
-        for (int k0 = 0; k0 < K; k0 += BK) {
-            const bool more = k0 + BK < K;
-            if (more) gload(k0 + BK);
-            if constexpr (Info<TC>::KM == 4) {
-#pragma unroll
-                for (int ks = 0; ks < BK; ks += 4) {
-                    LT af[TM], bfr[TN];
-#pragma unroll
-                    for (int a = 0; a < TM; ++a)
-                        af[a] = As[(wm * TM * 16 + a * 16 + (lane & 15)) * PK + ks + (lane >> 4)];
-#pragma unroll
-                    for (int b = 0; b < TN; ++b)
-                        bfr[b] = Bs[(wn * TN * 16 + b * 16 + (lane & 15)) * PK + ks + (lane >> 4)];
-#pragma unroll
-                    for (int a = 0; a < TM; ++a)
-#pragma unroll
-                        for (int b = 0; b < TN; ++b) acc[a][b] = mma1(af[a], bfr[b], acc[a][b]);
-                }
-            } else {
-#pragma unroll
-                for (int ks = 0; ks < BK; ks += 32) {
-                    bf8 ah[TM], bh[TN];
-#pragma unroll
-                    for (int a = 0; a < TM; ++a)
-                        ah[a] = *reinterpret_cast<const bf8*>(
-                            &As[(wm * TM * 16 + a * 16 + (lane & 15)) * PK + ks + 8 * (lane >> 4)]);
-#pragma unroll
-                    for (int b = 0; b < TN; ++b)
-                        bh[b] = *reinterpret_cast<const bf8*>(
-                            &Bs[(wn * TN * 16 + b * 16 + (lane & 15)) * PK + ks + 8 * (lane >> 4)]);
-                    if constexpr (PL == 2) {
-                        bf8 al[TM], bl[TN];
-#pragma unroll
-                        for (int a = 0; a < TM; ++a)
-                            al[a] = *reinterpret_cast<const bf8*>(
-                                &As[BM * PK + (wm * TM * 16 + a * 16 + (lane & 15)) * PK + ks +
-                                    8 * (lane >> 4)]);
-#pragma unroll
-                        for (int b = 0; b < TN; ++b)
-                            bl[b] = *reinterpret_cast<const bf8*>(
-                                &Bs[BN * PK + (wn * TN * 16 + b * 16 + (lane & 15)) * PK + ks +
-                                    8 * (lane >> 4)]);
-#pragma unroll
-                        for (int a = 0; a < TM; ++a)
-#pragma unroll
-                            for (int b = 0; b < TN; ++b) {
-                                acc[a][b] = mma8(al[a], bh[b], acc[a][b]);
-                                acc[a][b] = mma8(ah[a], bl[b], acc[a][b]);
-                                acc[a][b] = mma8(ah[a], bh[b], acc[a][b]);
-                            }
-                    } else {
-#pragma unroll
-                        for (int a = 0; a < TM; ++a)
-#pragma unroll
-                            for (int b = 0; b < TN; ++b) acc[a][b] = mma8(ah[a], bh[b], acc[a][b]);
-                    }
-                }
-            }
+        sstore(As, Bs);
+        if constexpr (DB) {
+            if (BK < K) gload(BK);
             __syncthreads();
-            if (more) {
-                sstore();
+            int cur = 0;
+            for (int k0 = 0; k0 < K; k0 += BK) {
+                compute(As + cur * LDS_A, Bs + cur * LDS_B, acc);
+                if (k0 + BK < K) {
+                    sstore(As + (cur ^ 1) * LDS_A, Bs + (cur ^ 1) * LDS_B);
+                    if (k0 + 2 * BK < K) gload(k0 + 2 * BK);
+                }
                 __syncthreads();
+                cur ^= 1;
+            }
+        } else {
+            __syncthreads();
+            for (int k0 = 0; k0 < K; k0 += BK) {
+                const bool more = k0 + BK < K;
+                if (more) gload(k0 + BK);
+                compute(As, Bs, acc);
+                __syncthreads();
+                if (more) {
+                    sstore(As, Bs);
+                    __syncthreads();
+                }
             }
         }
     }
