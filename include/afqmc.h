@@ -188,7 +188,7 @@ afqmc_status afqmc_adjoint_backward(afqmc_sys sys, double* dE_dlambda);
 /* Launch-shape autotuner.  Times every candidate launch shape of the
  * force-bias and field-sum GEMMs (64 x 64, 128 x 128 or 256 x 128 tiles) and of the
  * fused propagation (waves per workgroup x column blocks per wave, B
- * prefetch or not) on this system's own buffers and keeps the fastest per
+ * prefetch or not, orbitals per workgroup) on this system's own buffers and keeps the fastest per
  * problem shape in a process-wide table, so tuning another system of the
  * same shape costs nothing.  All candidates sum in the same order, so tuning
  * never changes a result bit.  The walker state is left unchanged.  choice
@@ -251,8 +251,10 @@ afqmc_status afqmc_selftest_gemm(afqmc_prec prec, int m, int n, int k, const dou
  * next chunk of the matrix operand prefetched; 4..7: the same shapes without
  * the prefetch, FP32 and split BF16 only; 8: 16 x 1, 9: 8 x 1, 10: 8 x 2 and
  * 11: 4 x 2 with two row blocks (32 orbitals) per workgroup, split BF16
- * only (8, 9 keep the running Taylor sum in LDS); a shape serves
- * M <= 16 waves blocks; split BF16 needs M % 8 == 0; E_SHAPE otherwise).
+ * only (8, 9 keep the running Taylor sum in LDS); 12: 8 x 2 with five row
+ * blocks (80 orbitals) per workgroup, split BF16 and M rounded up to 32 at
+ * most 224 only; a shape serves M <= 16 waves blocks; split BF16 needs
+ * M % 8 == 0; E_SHAPE otherwise).
  * phi, out:
  * nw x 2 x N x M (plane 0 real, plane 1 imaginary of orbital columns); P:
  * M x M real symmetric; A: nw x 2 x M x M complex symmetric.  Host float64

@@ -87,9 +87,9 @@ hipError_t split_planes(const float* in, void* out, long n, long planes, hipStre
 // [hi, lo][M][M] (P y computed as y + Q y), M % 8 == 0.  Frozen walkers (live == 0)
 // are copied unchanged.  M <= 256.  `variant` selects the workgroup shape
 // (waves per workgroup x column blocks per wave, with or without B prefetch,
-// one or two row blocks per workgroup; see kPropShapes); every variant gives
+// one, two or five row blocks per workgroup; see kPropShapes); every variant gives
 // bitwise the same result, 0 is the default.
-constexpr int kPropVariants = 12;
+constexpr int kPropVariants = 13;
 bool propagate_variant_ok(int variant, int M, DType t, DType ta);
 hipError_t propagate(const double* phi, double* phi_out, const void* Pm, const void* Af,
                      const uint8_t* live, int nw, int M, int N, int K, DType t, DType ta,

@@ -65,6 +65,9 @@ __global__ __launch_bounds__(256) void k_unpack(const T* __restrict__ pk, T* __r
 // LDS row pitches of the propagation state for M <= 256 (elements): 16-byte
 // aligned rows whose starts step across the banks.
 constexpr int kPitchF = 260, kPitchB = 264;
+// BF16 row pitch of the five-row-block shape (M <= 224): 80 rows fit in LDS
+constexpr int kPitchB5 = 232;
+constexpr int rb_pitch(int rb) { return rb == 5 ? kPitchB5 : kPitchB; }
 
 constexpr int kBufFlags = 0x00020000;  // gfx9-family raw buffer descriptor word 3
 constexpr int kOutOfRange = 0x40000000;
@@ -664,7 +667,7 @@ __global__ __launch_bounds__(64 * NWAVE, 1) void k_propagate_split_rb(
     const int Mp = (M + 31) / 32 * 32;
     const int MB = (M + 15) / 16;
     // fixed row pitches (M <= 256): LDS offsets become instruction immediates
-    constexpr int SPT = kPitchF, SPB = kPitchB;
+    constexpr int SPT = kPitchF, SPB = rb_pitch(RB);
     constexpr long splane = (long)ROWS * SPT, bplane = (long)ROWS * SPB;
     bf16_t* Sb = reinterpret_cast<bf16_t*>(smem_raw);
     // running Taylor sum, FP32, rows of pitch SPT (own elements only: no
@@ -830,7 +833,7 @@ template <int NWAVE, int MAXB, int RB, bool ZREG>
 hipError_t launch_prop_split_rb(const double* phi, double* phi_out, const void* Qs, const void* Af,
                                 const uint8_t* live, int nw, int M, int N, int K, hipStream_t s) {
     // the BF16 state + the FP32 running sum when it is not in registers
-    const size_t shm = 4 * 16 * RB * (size_t)kPitchB * sizeof(bf16_t) +
+    const size_t shm = 4 * 16 * RB * (size_t)rb_pitch(RB) * sizeof(bf16_t) +
                        (ZREG ? 0 : 2 * 16 * RB * (size_t)kPitchF * sizeof(float));
     const int nrb = (N + 16 * RB - 1) / (16 * RB);
     const long nblk = (long)nw * nrb;
@@ -1012,7 +1015,8 @@ struct PropShape {
 constexpr PropShape kPropShapes[kPropVariants] = {
     {8, 2, true, 1},   {4, 2, true, 1},   {4, 1, true, 1}, {2, 2, true, 1},
     {8, 2, false, 1},  {4, 2, false, 1},  {4, 1, false, 1}, {2, 2, false, 1},
-    {16, 1, false, 2}, {8, 1, false, 2},  {8, 2, false, 2}, {4, 2, false, 2}};
+    {16, 1, false, 2}, {8, 1, false, 2},  {8, 2, false, 2}, {4, 2, false, 2},
+    {8, 2, false, 5}};
 }  // namespace
 
 bool propagate_variant_ok(int v, int M, DType t, DType ta) {
@@ -1022,6 +1026,7 @@ bool propagate_variant_ok(int v, int M, DType t, DType ta) {
     const PropShape p = kPropShapes[v];
     if (t == DT_F64 && !p.pf) return false;  // the FP64 path keeps the prefetching shapes
     if (p.rows > 1 && ta != DT_SPLIT) return false;
+    if (p.rows == 5 && (M + 31) / 32 * 32 > kPitchB5 - 8) return false;  // 80 rows in LDS
     return (M + 15) / 16 <= p.waves * p.blocks;
 }
 
@@ -1060,6 +1065,8 @@ hipError_t propagate(const double* phi, double* phi_out, const void* Pm, const v
             return launch_prop_split_rb<8, 2, 2, true>(phi, phi_out, Pm, Af, live, nw, M, N, K, s);
         if (variant == 11)
             return launch_prop_split_rb<4, 2, 2, true>(phi, phi_out, Pm, Af, live, nw, M, N, K, s);
+        if (variant == 12)
+            return launch_prop_split_rb<8, 2, 5, true>(phi, phi_out, Pm, Af, live, nw, M, N, K, s);
     } else {
         AFQ_P(0, float, 8, 2, true)
         AFQ_P(1, float, 4, 2, true)

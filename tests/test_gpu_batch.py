@@ -94,7 +94,7 @@ def test_autotune_keeps_results(lib):
             for s in (a, b):
                 ch = lib.autotune(s)
                 assert ch[0] in (1, 2, 3) and ch[1] in (1, 2, 3)
-                assert 0 <= ch[2] < 12
+                assert 0 <= ch[2] < 13
         outs.append((lib.pair_step(a, b, 12, seed=3), _state(a), _state(b)))
     assert np.array_equal(outs[0][0], outs[1][0])
     for u, v in zip(outs[0][1] + outs[0][2], outs[1][1] + outs[1][2]):

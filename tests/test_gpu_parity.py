@@ -308,7 +308,7 @@ def test_propagation_kernel(lib, dims, prec):
 
 
 @pytest.mark.parametrize("dims", [(12, 6, 3), (37, 13, 5), (130, 40, 3), (200, 80, 2), (64, 17, 2),
-                                  (128, 24, 2)])
+                                  (128, 24, 2), (224, 100, 2), (232, 20, 1)])
 @pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3"])
 def test_propagation_shapes_bitwise(lib, dims, prec):
     """Every workgroup shape the autotuner may pick gives bitwise the result
@@ -327,11 +327,12 @@ def test_propagation_shapes_bitwise(lib, dims, prec):
     # variant: (waves, column blocks per wave, prefetch, row blocks per workgroup)
     shapes = {0: (8, 2, 1, 1), 1: (4, 2, 1, 1), 2: (4, 1, 1, 1), 3: (2, 2, 1, 1), 4: (8, 2, 0, 1),
               5: (4, 2, 0, 1), 6: (4, 1, 0, 1), 7: (2, 2, 0, 1), 8: (16, 1, 0, 2), 9: (8, 1, 0, 2),
-              10: (8, 2, 0, 2), 11: (4, 2, 0, 2)}
+              10: (8, 2, 0, 2), 11: (4, 2, 0, 2), 12: (8, 2, 0, 5)}
     ran = 0
     for v, (waves, blocks, pf, rows) in shapes.items():
         ok = ((M + 15) // 16 <= waves * blocks and not (prec == "fp64" and not pf)
-              and not (rows > 1 and prec != "bf16x3"))
+              and not (rows > 1 and prec != "bf16x3")
+              and not (rows == 5 and (M + 31) // 32 * 32 > 224))
         if not ok:
             with pytest.raises(lib.AfqmcError):
                 lib.selftest_propagate(phi, P, A, 6, prec, variant=v)
