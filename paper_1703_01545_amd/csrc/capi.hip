@@ -384,7 +384,7 @@ afqmc_status afqmc_init_walkers(afqmc_ham ham, int n_alpha, int n_beta, const do
     } allocs[] = {
         {&s->d_trialT, (size_t)NM * 8},
         {&s->d_P, (size_t)M * M * 8},
-        {&s->d_Plp, (size_t)M * M * 4},
+        {&s->d_Plp, s->ta == DT_SPLIT ? (size_t)split_tile_elems(M) * 2 * 2 : (size_t)M * M * 4},
         {&s->d_a, (size_t)std::max(nc, 1) * 8},
         {&s->d_lhx, (size_t)(nc + 1) * NM * 8},
         {&s->d_lhx_lp, s->ts == DT_F64 ? 0 : (size_t)(nc + 1) * NM * dt_size(s->ts)},
@@ -399,7 +399,8 @@ afqmc_status afqmc_init_walkers(afqmc_ham ham, int n_alpha, int n_beta, const do
         {&s->d_X, (size_t)nw * 2 * std::max(nc, 1) * dt_size(s->ts)},
         {&s->d_simp, (size_t)nw * 4 * 8},
         {&s->d_Apk, (size_t)nw * 2 * P * dt_size(s->tp)},
-        {&s->d_Af, (size_t)nw * 2 * M * M * dt_size(s->tp)},
+        {&s->d_Af, s->ta == DT_SPLIT ? (size_t)nw * 4 * split_tile_elems(M) * 2
+                                     : (size_t)nw * 2 * M * M * dt_size(s->tp)},
         {&s->d_lnd, (size_t)nw * 4 * 8},
         {&s->d_ovl, lu_theta_ws_bytes(nw, n_alpha, n_beta)},
         {&s->d_kws, gemm_ws_bytes(2 * nw, nc + 1, fb_ksplit((int)NM), s->tc)},
@@ -527,11 +528,15 @@ afqmc_status afqmc_init_walkers(afqmc_ham ham, int n_alpha, int n_beta, const do
         for (size_t i = 0; i < X.size(); ++i) X[i] = -0.5 * par->dt * ht[i];
         expm_host(X, M, Pm);
         // split products carry Q = P - I (formed in FP64) as hi/lo BF16 planes
+        // in the fragment-tiled layout
         std::vector<float> Pf(Pm.begin(), Pm.end());
-        if (s->ta == DT_SPLIT)
+        if (s->ta == DT_SPLIT) {
+            Pf.assign((size_t)split_tile_elems(M), 0.0f);
             for (int i = 0; i < M; ++i)
                 for (int j = 0; j < M; ++j)
-                    Pf[(size_t)i * M + j] = (float)(Pm[(size_t)i * M + j] - (i == j ? 1.0 : 0.0));
+                    Pf[split_tile_index(M, i, j)] =
+                        (float)(Pm[(size_t)i * M + j] - (i == j ? 1.0 : 0.0));
+        }
         if (hipMemcpy(s->d_P.p, Pm.data(), Pm.size() * 8, hipMemcpyHostToDevice) != hipSuccess)
             return bail(fail(AFQMC_E_DEVICE, "upload P"));
         if (s->ta == DT_SPLIT) {
@@ -870,33 +875,42 @@ afqmc_status afqmc_selftest_propagate(afqmc_prec prec, int M, int N, int nw, int
     if (!propagate_variant_ok(variant, M, t, ta))
         return fail(AFQMC_E_SHAPE, "workgroup shape or precision does not serve this M");
     const size_t nphi = (size_t)nw * 2 * N * M, nA = (size_t)nw * 2 * M * M, nP = (size_t)M * M;
+    const size_t nT = ta == DT_SPLIT ? (size_t)split_tile_elems(M) : nP;  // one operand plane
     DevBuf dphi, dout, dP, dA, dA32, dP64, dA64, dlive;
     HIPCHK(dphi.alloc(nphi * 8));
     HIPCHK(dout.alloc(nphi * 8));
     HIPCHK(dP64.alloc(nP * 8));
     HIPCHK(dA64.alloc(nA * 8));
-    HIPCHK(dP.alloc(nP * dt_size(t)));
-    HIPCHK(dA.alloc(nA * dt_size(t)));
+    HIPCHK(dP.alloc(nT * dt_size(t)));
+    HIPCHK(dA.alloc((size_t)nw * 2 * nT * dt_size(t)));
     HIPCHK(dlive.alloc(nw));
     HIPCHK(hipMemcpy(dphi.p, phi, nphi * 8, hipMemcpyHostToDevice));
     HIPCHK(hipMemcpy(dP64.p, P, nP * 8, hipMemcpyHostToDevice));
     HIPCHK(hipMemcpy(dA64.p, A, nA * 8, hipMemcpyHostToDevice));
     HIPCHK(hipMemset(dlive.p, 1, nw));
-    if (ta == DT_SPLIT) {  // Q = P - I as hi/lo BF16 planes
-        std::vector<float> q(P, P + nP);
-        for (int i = 0; i < M; ++i) q[(size_t)i * M + i] = (float)(P[(size_t)i * M + i] - 1.0);
+    if (ta == DT_SPLIT) {  // Q = P - I as fragment-tiled hi/lo BF16 planes
+        std::vector<float> q(nT, 0.0f);
+        for (int i = 0; i < M; ++i)
+            for (int j = 0; j < M; ++j)
+                q[split_tile_index(M, i, j)] =
+                    (float)(P[(size_t)i * M + j] - (i == j ? 1.0 : 0.0));
         DevBuf dq;
-        HIPCHK(dq.alloc(nP * 4));
-        HIPCHK(hipMemcpy(dq.p, q.data(), nP * 4, hipMemcpyHostToDevice));
-        HIPCHK(split_planes(dq.as<float>(), dP.p, (long)nP, 1, nullptr));
+        HIPCHK(dq.alloc(nT * 4));
+        HIPCHK(hipMemcpy(dq.p, q.data(), nT * 4, hipMemcpyHostToDevice));
+        HIPCHK(split_planes(dq.as<float>(), dP.p, (long)nT, 1, nullptr));
         HIPCHK(hipDeviceSynchronize());
     } else {
         HIPCHK(convert(dP64.as<double>(), dP.p, t, (long)nP, nullptr));
     }
-    if (ta == DT_SPLIT) {
-        HIPCHK(dA32.alloc(nA * 4));
-        HIPCHK(convert(dA64.as<double>(), dA32.p, DT_F32, (long)nA, nullptr));
-        HIPCHK(split_planes(dA32.as<float>(), dA.p, (long)nP, 2L * nw, nullptr));
+    if (ta == DT_SPLIT) {  // each walker plane fragment-tiled, then split
+        std::vector<float> at((size_t)nw * 2 * nT, 0.0f);
+        for (size_t pl = 0; pl < (size_t)nw * 2; ++pl)
+            for (int i = 0; i < M; ++i)
+                for (int j = 0; j < M; ++j)
+                    at[pl * nT + split_tile_index(M, i, j)] = (float)A[pl * nP + (size_t)i * M + j];
+        HIPCHK(dA32.alloc(at.size() * 4));
+        HIPCHK(hipMemcpy(dA32.p, at.data(), at.size() * 4, hipMemcpyHostToDevice));
+        HIPCHK(split_planes(dA32.as<float>(), dA.p, (long)nT, 2L * nw, nullptr));
     } else {
         HIPCHK(convert(dA64.as<double>(), dA.p, t, (long)nA, nullptr));
     }

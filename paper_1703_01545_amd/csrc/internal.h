@@ -66,13 +66,30 @@ hipError_t gemm(const Gemm& g, DType compute, hipStream_t s);
 int gemm_kchunk(int k, int ksplit);
 size_t gemm_ws_bytes(int m, int n, int ksplit, DType compute);
 
+// Fragment-tiled layout of an M x M operand of the split-BF16 propagation:
+// rows padded to 16 (MT), columns to 32 (MP), stored as 1 KB tiles of 16 rows
+// x 32 columns ordered [row block][column chunk], inside a tile element
+// (16 rows, 8 column runs) at ((c % 32) / 8 * 16 + r % 16) * 8 + c % 8, so
+// that lane l of a wave reads row l % 16, columns 8 (l / 16) .. + 7 of a
+// chunk with one 16-byte load and a wave's load is 1 KB contiguous.
+// Padding elements are zero.
+__host__ __device__ inline long split_tile_elems(int M) {
+    return (long)((M + 15) / 16 * 16) * ((M + 31) / 32 * 32);
+}
+__host__ __device__ inline long split_tile_index(int M, int r, int c) {
+    const long kc = (M + 31) / 32;
+    return ((r / 16 * kc + c / 32) * 64 + (c % 32) / 8 * 16 + r % 16) * 8 + c % 8;
+}
+
 // Packed upper triangle (P = M(M+1)/2 per plane) -> full symmetric M x M,
-// for `planes` consecutive planes (types DT_F64 / DT_F32; DT_SPLIT: FP32
-// input, hi/lo BF16 output planes [plane][hi, lo][M][M]).
+// for `planes` consecutive planes (types DT_F64 / DT_F32 row-major;
+// DT_SPLIT: FP32 input, hi/lo BF16 output planes [plane][hi, lo][tiles] in
+// the fragment-tiled layout, M % 8 == 0, M <= 256).
 hipError_t unpack_sym(const void* pk, void* full, int M, int planes, DType t, hipStream_t s);
-// LDS limit of the one-plane split unpack; unpack_prepare raises the kernel's
-// dynamic LDS limit to it (call once, outside graph capture).
-constexpr size_t kUnpackLds = 128 * 1024;
+// LDS limit of the one-plane split unpack (the packed triangle of M = 256);
+// unpack_prepare raises the kernel's dynamic LDS limit to it (call once,
+// outside graph capture).
+constexpr size_t kUnpackLds = 160 * 1024;
 hipError_t unpack_prepare();
 // FP32 planes of n elements -> hi/lo BF16 planes [plane][hi, lo][n].
 hipError_t split_planes(const float* in, void* out, long n, long planes, hipStream_t s);
@@ -83,8 +100,9 @@ hipError_t split_planes(const float* in, void* out, long n, long planes, hipStre
 // symmetric, Af: [w][plane][M][M] complex symmetric, both in type t
 // (DT_F64 or DT_F32, the product precision).  ta: type of Af, equal to t,
 // or DT_SPLIT with t == DT_F32: every product in split BF16, Af as hi/lo
-// planes [w][plane][hi, lo][M][M] and Pm holding Q = P - I as hi/lo planes
-// [hi, lo][M][M] (P y computed as y + Q y), M % 8 == 0.  Frozen walkers (live == 0)
+// planes [w][plane][hi, lo][tiles] and Pm holding Q = P - I as hi/lo planes
+// [hi, lo][tiles], both in the fragment-tiled layout (P y computed as
+// y + Q y), M % 8 == 0.  Frozen walkers (live == 0)
 // are copied unchanged.  M <= 256.  `variant` selects the workgroup shape
 // (waves per workgroup x column blocks per wave, with or without B prefetch,
 // one, two or five row blocks per workgroup; see kPropShapes); every variant gives

@@ -348,15 +348,15 @@ __device__ __forceinline__ void pass_split(__amdgpu_buffer_rsrc_t rb, int M, int
     constexpr int NP = CX ? 4 : 2;  // operand planes: re hi, re lo (, im hi, im lo)
     const int lane = threadIdx.x & 63;
     const int g = lane >> 4, li = lane & 15;
-    const int hl_b = M * M * 2;      // hi -> lo plane, bytes
-    const int pl_b = 2 * hl_b;       // re -> im plane
+    const int hl_b = (int)split_tile_elems(M) * 2;  // hi -> lo plane, bytes
+    const int pl_b = 2 * hl_b;                        // re -> im plane
+    const int kc = Mp / 32;
     const long spl = 16L * SPB;
     const bf16_t* s0 = Sb + li * SPB + 8 * g;
-    int boff[MAXB];
+    int boff[MAXB];  // this lane's 16 bytes of chunk 0 of each column block
 #pragma unroll
     for (int s = 0; s < MAXB; ++s) {
-        const int m = cb[s] * 16 + li;
-        boff[s] = m < M ? (m * M + 8 * g) * 2 : kOutOfRange;
+        boff[s] = cb[s] < MB ? (cb[s] * kc * 64 + lane) * 16 : kOutOfRange;
         if constexpr (CX) acc[s][0] = acc[s][1] = f4{0, 0, 0, 0};
     }
     bf8 bc[MAXB][NP], bn[MAXB][NP];
@@ -369,7 +369,7 @@ __device__ __forceinline__ void pass_split(__amdgpu_buffer_rsrc_t rb, int M, int
                 bc[s][p] = bload8(rb, boff[s] + (p & 1) * hl_b + (p >> 1) * pl_b);
     }
     for (int k0 = 0; k0 < Mp; k0 += 32) {
-        const int kb = (k0 + (PF ? 32 : 0)) * 2;
+        const int kb = (k0 + (PF ? 32 : 0)) * 32;  // 1 KB per chunk
 #pragma unroll
         for (int s = 0; s < MAXB; ++s) {
             bf8* d = PF ? bn[s] : bc[s];
@@ -468,7 +468,7 @@ __global__ __launch_bounds__(64 * NWAVE, 2) void k_propagate_split(
     int cb[MAXB];
 #pragma unroll
     for (int s = 0; s < MAXB; ++s) cb[s] = vw + s * NWAVE;
-    const long Aplane = (long)M * M;
+    const long Aplane = split_tile_elems(M);  // fragment-tiled operand planes
     const __amdgpu_buffer_rsrc_t rQ = make_rsrc(Qs, 2 * Aplane);
     const __amdgpu_buffer_rsrc_t rA = make_rsrc(Af + (long)w * 4 * Aplane, 4 * Aplane);
     const int li = lane & 15;
@@ -576,14 +576,14 @@ __device__ __forceinline__ void pass_split_rb(__amdgpu_buffer_rsrc_t rb, int M, 
     constexpr int NP = CX ? 4 : 2;
     const int lane = threadIdx.x & 63;
     const int g = lane >> 4, li = lane & 15;
-    const int hl_b = M * M * 2;
+    const int hl_b = (int)split_tile_elems(M) * 2;
     const int pl_b = 2 * hl_b;
+    const int kc = Mp / 32;
     const long spl = 16L * RB * SPB;
     int boff[MAXB];
 #pragma unroll
     for (int s = 0; s < MAXB; ++s) {
-        const int m = cb[s] * 16 + li;
-        boff[s] = m < M ? (m * M + 8 * g) * 2 : kOutOfRange;
+        boff[s] = cb[s] < MB ? (cb[s] * kc * 64 + lane) * 16 : kOutOfRange;
         if constexpr (CX) {
 #pragma unroll
             for (int r = 0; r < RB; ++r) acc[r][s][0] = acc[r][s][1] = f4{0, 0, 0, 0};
@@ -595,7 +595,7 @@ __device__ __forceinline__ void pass_split_rb(__amdgpu_buffer_rsrc_t rb, int M, 
         for (int s = 0; s < MAXB; ++s)
 #pragma unroll
             for (int p = 0; p < NP; ++p)
-                bc[s][p] = bload8(rb, boff[s] + k0 * 2 + (p & 1) * hl_b + (p >> 1) * pl_b);
+                bc[s][p] = bload8(rb, boff[s] + k0 * 32 + (p & 1) * hl_b + (p >> 1) * pl_b);
 #pragma unroll
         for (int r = 0; r < RB; ++r) {
             if (r >= nrbv) continue;  // wave-uniform
@@ -700,7 +700,7 @@ __global__ __launch_bounds__(64 * NWAVE, 1) void k_propagate_split_rb(
     for (int s = 0; s < MAXB; ++s) cb[s] = vw + s * NWAVE;
     f4 acc[RB][MAXB][2];
     f4 zr[ZREG ? RB : 1][MAXB][2];
-    const long Aplane = (long)M * M;
+    const long Aplane = split_tile_elems(M);  // fragment-tiled operand planes
     const __amdgpu_buffer_rsrc_t rQ = make_rsrc(Qs, 2 * Aplane);
     const __amdgpu_buffer_rsrc_t rA = make_rsrc(Af + (long)w * 4 * Aplane, 4 * Aplane);
     const int li = lane & 15;
@@ -875,48 +875,12 @@ __global__ void k_split_planes(const float* __restrict__ in, bf16_t* __restrict_
     out[pl * 2 * n + n + i] = to_bf(v - (float)h);
 }
 
-// Packed upper triangle (FP32) -> full symmetric M x M as hi/lo BF16 planes
-// ([plane][hi, lo][M][M]).
-__global__ __launch_bounds__(256) void k_unpack_split(const float* __restrict__ pk,
-                                                      bf16_t* __restrict__ full, int M) {
-    __shared__ float tile[32][33];
-    const long P = (long)M * (M + 1) / 2;
-    const long plane = blockIdx.y;
-    const int ti = blockIdx.x;
-    const float* src = pk + plane * P;
-    bf16_t* hi = full + plane * 2 * (long)M * M;
-    bf16_t* lo = hi + (long)M * M;
-    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
-    const int nt = (M + 31) / 32;
-    auto put = [&](long o, float v) {
-        const bf16_t h = to_bf(v);
-        hi[o] = h;
-        lo[o] = to_bf(v - (float)h);
-    };
-    for (int tj = ti; tj < nt; ++tj) {
-        for (int r = ty; r < 32; r += 8) {
-            const int i = ti * 32 + r, j = tj * 32 + tx;
-            float v = 0.0f;
-            if (i < M && j < M && j >= i) v = src[(long)i * (2 * M - i + 1) / 2 + (j - i)];
-            tile[r][tx] = v;
-        }
-        __syncthreads();
-        for (int r = ty; r < 32; r += 8) {
-            const int i = ti * 32 + r, j = tj * 32 + tx;
-            if (i < M && j < M) put((long)i * M + j, (j >= i) ? tile[r][tx] : tile[tx][r]);
-            if (tj != ti) {
-                const int jm = tj * 32 + r, im = ti * 32 + tx;
-                if (jm < M && im < M) put((long)jm * M + im, tile[tx][r]);
-            }
-        }
-        __syncthreads();
-    }
-}
-
-// One workgroup per walker plane: the packed upper triangle is staged whole
-// in LDS, then every thread writes runs of 8 consecutive elements of a row
-// of the full matrix (A_ij from the packed row min(i, j)) as one 16-byte hi
-// store and one 16-byte lo store.  Needs M % 8 == 0 and the triangle in LDS.
+// One workgroup per walker plane: the packed upper triangle (FP32) is staged
+// whole in LDS, then every thread writes one 8-element run of the
+// fragment-tiled hi/lo BF16 planes of the full symmetric matrix (A_ij from
+// the packed row min(i, j); zero past M) as one 16-byte hi store and one
+// 16-byte lo store; consecutive threads write consecutive runs.  Needs
+// M % 8 == 0 and the triangle in LDS (M <= 256).
 __global__ __launch_bounds__(256) void k_unpack_split_plane(const float* __restrict__ pk,
                                                             bf16_t* __restrict__ full, int M) {
     extern __shared__ float tri[];
@@ -936,23 +900,29 @@ __global__ __launch_bounds__(256) void k_unpack_split_plane(const float* __restr
             if (e0 + q * 256 < P) tri[e0 + q * 256] = v[q];
     }
     __syncthreads();
-    bf16_t* hi = full + plane * 2 * (long)M * M;
-    bf16_t* lo = hi + (long)M * M;
-    const int rr = M / 8;  // runs per row
-    for (int r = threadIdx.x; r < M * rr; r += 256) {
-        const int i = r / rr, j0 = (r % rr) * 8;
-        bf8 h, l;
+    const long TE = split_tile_elems(M);
+    bf16_t* hi = full + plane * 2 * TE;
+    bf16_t* lo = hi + TE;
+    const int kc = (M + 31) / 32;
+    const int nrun = (int)(TE / 8);
+    for (int u = threadIdx.x; u < nrun; u += 256) {
+        // run u: tile u / 64, lane slot u % 64 (row r % 16, column run)
+        const int t = u >> 6, l = u & 63;
+        const int i = (t / kc) * 16 + (l & 15);
+        const int j0 = (t % kc) * 32 + (l >> 4) * 8;
+        bf8 h, lw;
 #pragma unroll
         for (int e = 0; e < 8; ++e) {
             const int j = j0 + e;
             const int a = i < j ? i : j, b = i < j ? j : i;
-            const float v = tri[(long)a * (2 * M - a + 1) / 2 + (b - a)];
+            const bool in = i < M && j < M;
+            const float v = in ? tri[(long)a * (2 * M - a + 1) / 2 + (b - a)] : 0.0f;
             const bf16_t x = to_bf(v);
             h[e] = x;
-            l[e] = to_bf(v - (float)x);
+            lw[e] = to_bf(v - (float)x);
         }
-        *reinterpret_cast<bf8*>(hi + (long)i * M + j0) = h;
-        *reinterpret_cast<bf8*>(lo + (long)i * M + j0) = l;
+        *reinterpret_cast<bf8*>(hi + (long)u * 8) = h;
+        *reinterpret_cast<bf8*>(lo + (long)u * 8) = lw;
     }
 }
 
@@ -994,9 +964,6 @@ hipError_t unpack_sym(const void* pk, void* full, int M, int planes, DType t, hi
     else if (t == DT_SPLIT && M % 8 == 0 && (size_t)M * (M + 1) / 2 * 4 <= kUnpackLds)
         hipLaunchKernelGGL(k_unpack_split_plane, dim3(planes), dim3(256),
                            (size_t)M * (M + 1) / 2 * 4, s, (const float*)pk, (bf16_t*)full, M);
-    else if (t == DT_SPLIT)
-        hipLaunchKernelGGL(k_unpack_split, grid, dim3(256), 0, s, (const float*)pk,
-                           (bf16_t*)full, M);
     else
         return hipErrorInvalidValue;
     return hipGetLastError();
