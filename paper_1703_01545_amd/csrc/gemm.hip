@@ -350,12 +350,16 @@ __global__ __launch_bounds__(256, 2) void k_exchange_blk(const float* __restrict
     // the tile column-major (column = plane, j; row = gamma, i), four rows per
     // 16-byte store; pairs (i, j = i + d mod NB), d = 0 .. NB / 2, cover each
     // unordered pair once (weight 2; the diagonal and d = NB / 2 weight 1),
-    // and both reads of a pair walk the lanes with the odd stride P + 1
+    // and both reads of a pair walk the lanes with the odd stride P + 1.
+    // Two tiles fit in LDS: in round r waves (r, 0) and (r, 1) store theirs,
+    // then all four waves reduce them, each tile's pair terms split in two
+    // halves; the halves' sums are added in fixed order.
     constexpr int D = NB / 2 + 1;
-    float fr = 0.0f, fi = 0.0f;
+    constexpr int NE = G * D * NB, HE = (NE + 1) / 2;
+    __shared__ double red[2][2][2][2];  // [round][tile][half][re, im]
     for (int round = 0; round < 2; ++round) {
-        float* Sx = S + (wave & 1) * C * P;
         if ((wave >> 1) == round) {
+            float* Sx = S + (wave & 1) * C * P;
 #pragma unroll
             for (int a = 0; a < Cr::TM; ++a)
 #pragma unroll
@@ -364,32 +368,49 @@ __global__ __launch_bounds__(256, 2) void k_exchange_blk(const float* __restrict
                                                4 * (lane >> 4)]) = acc[a][b];
         }
         __syncthreads();
-        if ((wave >> 1) == round) {
-            for (int e = lane; e < G * D * NB; e += 64) {
-                const int gl = e / (D * NB), q = e % (D * NB);
-                const int d = q / NB, i = q % NB;
-                const int j = i + d < NB ? i + d : i + d - NB;
-                const float wgt = (d == 0 || 2 * d == NB) ? 1.0f : 2.0f;
-                const int r0 = gl * NB;
-                const float a_ij = Sx[j * P + r0 + i], b_ij = Sx[(NB + j) * P + r0 + i];
-                const float a_ji = Sx[i * P + r0 + j], b_ji = Sx[(NB + i) * P + r0 + j];
-                fr += wgt * (a_ij * a_ji - b_ij * b_ji);
-                fi += wgt * (a_ij * b_ji + b_ij * a_ji);
+        const float* Sx = S + (wave & 1) * C * P;
+        const int half = wave >> 1;
+        const int e0 = half * HE + lane, e1 = half ? NE : HE;
+        // (gl, d, i) of term e, advanced by 64 terms per iteration
+        int gl = e0 / (D * NB), d = (e0 % (D * NB)) / NB, i = e0 % NB;
+        constexpr int STEP_D = 64 / NB, STEP_I = 64 % NB;
+        float fr = 0.0f, fi = 0.0f;
+        for (int e = e0; e < e1; e += 64) {
+            const int j = i + d < NB ? i + d : i + d - NB;
+            const float wgt = (d == 0 || 2 * d == NB) ? 1.0f : 2.0f;
+            const int r0 = gl * NB;
+            const float a_ij = Sx[j * P + r0 + i], b_ij = Sx[(NB + j) * P + r0 + i];
+            const float a_ji = Sx[i * P + r0 + j], b_ji = Sx[(NB + i) * P + r0 + j];
+            fr += wgt * (a_ij * a_ji - b_ij * b_ji);
+            fi += wgt * (a_ij * b_ji + b_ij * a_ji);
+            i += STEP_I;
+            d += STEP_D;
+            if (i >= NB) {
+                i -= NB;
+                d += 1;
+            }
+            if (d >= D) {
+                d -= D;
+                gl += 1;
             }
         }
-        __syncthreads();
-    }
-    double sr = fr, si = fi;
+        double sr = fr, si = fi;
 #pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) {
-        sr += __shfl_xor(sr, o, 64);
-        si += __shfl_xor(si, o, 64);
+        for (int o = 32; o >= 1; o >>= 1) {
+            sr += __shfl_xor(sr, o, 64);
+            si += __shfl_xor(si, o, 64);
+        }
+        if (lane == 0) {
+            red[round][wave & 1][half][0] = sr;
+            red[round][wave & 1][half][1] = si;
+        }
+        __syncthreads();
     }
     const int w = w0 + wn, gg = gt * 2 + wm;
     if (lane == 0 && w < nw && gg < n_gt) {
         double* o = out + ((long)(w * 2 + spin) * n_gt + gg) * 2;
-        o[0] = sr;
-        o[1] = si;
+        o[0] = red[wm][wn][0][0] + red[wm][wn][1][0];
+        o[1] = red[wm][wn][0][1] + red[wm][wn][1][1];
     }
 }
 
