@@ -880,24 +880,26 @@ __global__ void k_split_planes(const float* __restrict__ in, bf16_t* __restrict_
 // fragment-tiled hi/lo BF16 planes of the full symmetric matrix (A_ij from
 // the packed row min(i, j); zero past M) as one 16-byte hi store and one
 // 16-byte lo store; consecutive threads write consecutive runs.  Needs
-// M % 8 == 0 and the triangle in LDS (M <= 256).
-__global__ __launch_bounds__(256) void k_unpack_split_plane(const float* __restrict__ pk,
-                                                            bf16_t* __restrict__ full, int M) {
+// M % 8 == 0 and the triangle in LDS (M <= 256); 512 threads (two workgroups
+// per CU by LDS, eight waves each).
+constexpr int kUnpackThreads = 512;
+__global__ __launch_bounds__(kUnpackThreads) void k_unpack_split_plane(
+    const float* __restrict__ pk, bf16_t* __restrict__ full, int M) {
     extern __shared__ float tri[];
     const long P = (long)M * (M + 1) / 2;
     const long plane = blockIdx.x;
     const float* src = pk + plane * P;
     // eight loads in flight per thread
-    for (long e0 = threadIdx.x; e0 < P; e0 += 8 * 256) {
+    for (long e0 = threadIdx.x; e0 < P; e0 += 8 * kUnpackThreads) {
         float v[8];
 #pragma unroll
         for (int q = 0; q < 8; ++q) {
-            const long e = e0 + q * 256;
+            const long e = e0 + q * kUnpackThreads;
             v[q] = src[e < P ? e : 0];
         }
 #pragma unroll
         for (int q = 0; q < 8; ++q)
-            if (e0 + q * 256 < P) tri[e0 + q * 256] = v[q];
+            if (e0 + q * kUnpackThreads < P) tri[e0 + q * kUnpackThreads] = v[q];
     }
     __syncthreads();
     const long TE = split_tile_elems(M);
@@ -905,7 +907,7 @@ __global__ __launch_bounds__(256) void k_unpack_split_plane(const float* __restr
     bf16_t* lo = hi + TE;
     const int kc = (M + 31) / 32;
     const int nrun = (int)(TE / 8);
-    for (int u = threadIdx.x; u < nrun; u += 256) {
+    for (int u = threadIdx.x; u < nrun; u += kUnpackThreads) {
         // run u: tile u / 64, lane slot u % 64 (row r % 16, column run)
         const int t = u >> 6, l = u & 63;
         const int i = (t / kc) * 16 + (l & 15);
@@ -962,7 +964,7 @@ hipError_t unpack_sym(const void* pk, void* full, int M, int planes, DType t, hi
         hipLaunchKernelGGL(k_unpack<float>, grid, dim3(256), 0, s, (const float*)pk, (float*)full,
                            M);
     else if (t == DT_SPLIT && M % 8 == 0 && (size_t)M * (M + 1) / 2 * 4 <= kUnpackLds)
-        hipLaunchKernelGGL(k_unpack_split_plane, dim3(planes), dim3(256),
+        hipLaunchKernelGGL(k_unpack_split_plane, dim3(planes), dim3(kUnpackThreads),
                            (size_t)M * (M + 1) / 2 * 4, s, (const float*)pk, (bf16_t*)full, M);
     else
         return hipErrorInvalidValue;
