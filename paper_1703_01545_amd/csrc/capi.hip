@@ -58,7 +58,21 @@ const char* const kPhaseNames[PH_COUNT] = {
     "det_theta",       "weights", "mgs",            "exchange", "energy"};
 
 
-int fb_ksplit(int k) { return std::max(1, std::min(8, k / 4000)); }
+int fb_ksplit(int m, int n, int k, int cus) {
+    if (k < 8000 || cus <= 0) return std::max(1, std::min(8, k / 4000));
+    const long tiles = (long)((m + 255) / 256) * ((n + 127) / 128);
+    int best = 4;
+    long best_num = 0, best_den = 1;  // fill fraction as a ratio
+    for (int ks = 4; ks <= 12; ++ks) {
+        const long wg = tiles * ks, den = (long)cus * ((wg + cus - 1) / cus);
+        if (wg * best_den > best_num * den) {
+            best = ks;
+            best_num = wg;
+            best_den = den;
+        }
+    }
+    return best;
+}
 
 Gemm force_bias_gemm(afqmc_sys s) {
     // F[(w,p), g] = sum_(i,m) Theta[(w,p),(i,m)] L^half[g,(i,m)], g <= n_chol
@@ -79,7 +93,7 @@ Gemm force_bias_gemm(afqmc_sys s) {
     g.batch = 1;
     g.tile = s->tile_fb;
     // long K (= N M): fixed K ranges so that large tiles still fill the chip
-    g.ksplit = fb_ksplit(g.k);
+    g.ksplit = s->fb_ks;
     g.ws = s->d_kws.p;
     return g;
 }
@@ -378,6 +392,13 @@ afqmc_status afqmc_init_walkers(afqmc_ham ham, int n_alpha, int n_beta, const do
     s->n_gt_a = exchange_gtiles(nc, s->na, M, s->tc);
     s->n_gt_b = exchange_gtiles(nc, s->nb, M, s->tc);  // tiles depend on the compute type
     s->n_gt = std::max(1, std::max(s->n_gt_a, s->n_gt_b));
+    {
+        int dev = 0, cus = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+            return bail(fail(AFQMC_E_DEVICE, "device attributes"));
+        s->fb_ks = fb_ksplit(2 * nw, nc + 1, (int)NM, cus);
+    }
     struct A_ {
         DevBuf* b;
         size_t bytes;
@@ -403,7 +424,7 @@ afqmc_status afqmc_init_walkers(afqmc_ham ham, int n_alpha, int n_beta, const do
                                      : (size_t)nw * 2 * M * M * dt_size(s->tp)},
         {&s->d_lnd, (size_t)nw * 4 * 8},
         {&s->d_ovl, lu_theta_ws_bytes(nw, n_alpha, n_beta)},
-        {&s->d_kws, gemm_ws_bytes(2 * nw, nc + 1, fb_ksplit((int)NM), s->tc)},
+        {&s->d_kws, gemm_ws_bytes(2 * nw, nc + 1, s->fb_ks, s->tc)},
         {&s->d_exch, (size_t)nw * 2 * s->n_gt * 2 * 8},
         {&s->d_el, (size_t)nw * 2 * 8},
         {&s->d_sums, 8 * 8},

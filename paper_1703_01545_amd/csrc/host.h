@@ -163,6 +163,7 @@ struct afqmc_sys_s {
     // launch shapes (autotuned; 0 = size heuristic): GEMM tiles of the force
     // bias and the field sum, and the propagation workgroup shape
     int tile_fb = 0, tile_fs = 0, prop_var = 0;
+    int fb_ks = 1;  // K ranges of the force-bias GEMM (fb_ksplit at creation)
     // graph capture: the Philox step word is read from *t_dev (plus the
     // step's offset t - t_base) instead of being baked into the launch
     const int64_t* t_dev = nullptr;
@@ -213,7 +214,12 @@ struct PhaseTimer {
 
 // GEMM descriptors of the contraction phases (their tile from the system's
 // tuned shapes).
-int fb_ksplit(int k);
+// K ranges of the force-bias GEMM (m x n output, K = k) on a device of `cus`
+// compute units: 1 below K = 8000; else the count in 4..12 whose workgroups
+// of the largest tile (256 x 128, one per CU) best fill the last round,
+// fewest on ties.  It does not depend on the tile the autotuner picks, so
+// every tile shape sums the same K ranges in the same order.
+int fb_ksplit(int m, int n, int k, int cus);
 Gemm force_bias_gemm(afqmc_sys s);
 Gemm field_sum_gemm(afqmc_sys s);
 
