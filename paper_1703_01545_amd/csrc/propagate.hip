@@ -6,8 +6,9 @@
 // propagation: the orbitals never couple (every factor multiplies from the
 // left), so the R x M complex state stays resident in LDS across the
 // 2 + K dense products and only P, A_w and the walker itself stream from
-// HBM/L2.  The running sum Z of the Taylor terms lives in registers.  The
-// products run on the matrix cores (FP32 or FP64 MFMA 16x16x4).
+// HBM/L2.  The running sum Z of the Taylor terms lives in registers (in LDS
+// for two of the shapes).  The products run on the matrix cores: FP64 or
+// FP32 MFMA 16x16x4, or split BF16 (MFMA 16x16x32, three per product).
 #include "mfma.h"
 
 // No contraction of a multiply and an add into one fused operation anywhere
@@ -971,10 +972,13 @@ hipError_t unpack_sym(const void* pk, void* full, int M, int planes, DType t, hi
     return hipGetLastError();
 }
 
-// Workgroup shapes (waves, column blocks per wave, B prefetch): a shape
-// serves M up to 16 * waves * blocks.  Fewer waves per workgroup leave no
-// idle waves at small M; more waves shorten each wave's share at large M;
-// without the prefetch a wave holds fewer registers and more waves fit.
+// Workgroup shapes (waves, column blocks per wave, B prefetch, 16-orbital
+// row blocks): a shape serves M up to 16 * waves * blocks.  Fewer waves per
+// workgroup leave no idle waves at small M; more waves shorten each wave's
+// share at large M; without the prefetch a wave holds fewer registers and
+// more waves fit; more row blocks let each operand fragment a wave loads
+// serve more orbitals (five, all 80 orbitals at N = 80, need M <= 224 for
+// the state to fit LDS).
 namespace {
 struct PropShape {
     int waves, blocks;
