@@ -188,6 +188,57 @@ def test_parity_m100_sampled_walkers(lib, torch_mod):
     assert rel(el_a[sub], ref_el) < TOL
 
 
+def test_bench_config_sampled_walkers(lib, torch_mod):
+    """The timed workload as bench.py runs it: the M=200 pair (40/40 vs 40/39,
+    n_chol = 800) at its full 2048 walkers per system, autotuned shapes,
+    graph-replayed batch path, device Philox fields, in the split-BF16 plan
+    and in FP64.  The FP64 oracle recomputes three walkers one by one: the
+    FP64 run must match them to 1e-10, the split-BF16 run within the bound
+    below; the pair's energy difference of the split-BF16 run must meet the
+    0.05 kcal/mol target against the FP64 run on the same fields.
+
+    Bound of the split-BF16 run: each split-BF16 product carries a relative
+    error of a few 2^-17 (< 3e-5), and a step applies ten dense products to a
+    walker (force bias, field sum, two one-body halves, six Taylor terms), so
+    20 steps bound the relative error of a walker's orbitals and of its
+    weight (a product of 20 overlap ratios) by 20 x 10 x 3e-5 = 6e-3; the
+    local energy of a walker, formed from its orbitals by two more split
+    contractions, is checked at the same bound."""
+    cfg = config(2)
+    n_steps, seed = 20, 9
+    banner(f"bench workload M={cfg.M} Nw={cfg.n_walkers}, sampled walkers")
+    ham = cfg.hamiltonian()
+    trials = (cfg.trial_a(), cfg.trial_b())
+    spins = ((cfg.na_a, cfg.nb_a), (cfg.na_b, cfg.nb_b))
+    sub = np.array([0, 777, cfg.n_walkers - 1])
+    osys = [O.System(ham.h, ham.chol, ham.e_core, t, na, nb, cfg.dt,
+                     taylor_order=cfg.taylor_order) for t, (na, nb) in zip(trials, spins)]
+    wa, wb = (O.init_walkers(s, len(sub)) for s in osys)
+    O.run_pair(osys[0], osys[1], wa, wb, O.PhiloxFields(seed, 0, cfg.n_chol, walkers=sub),
+               n_steps, cfg.ortho_every, cfg.measure_every)
+    ref_el = [O.local_energy(s, wk.theta) for s, wk in zip(osys, (wa, wb))]
+    traces = {}
+    for prec, tol in (("fp64", TOL), ("bf16x3", 6e-3)):
+        H = lib.Hamiltonian(ham.h, ham.chol, ham.e_core)
+        kw = dict(taylor_order=cfg.taylor_order, ortho_every=cfg.ortho_every,
+                  measure_every=cfg.measure_every, precision=prec)
+        ga, gb = (lib.System(H, na, nb, t, cfg.n_walkers, cfg.dt, **kw)
+                  for t, (na, nb) in zip(trials, spins))
+        traces[prec] = lib.pair_batch_step([(ga, gb)], [seed], n_steps, lanes=1)[0]
+        for g, wk, ref in zip((ga, gb), (wa, wb), ref_el):
+            w = g.walkers()
+            el = g.local_energy()[0][sub]
+            banner(f"  {prec}: weight {rel(w['weight'][sub], wk.weight):.2e}  phi "
+                   f"{max(rel(w['phi'][k], wk.phi[i]) for i, k in enumerate(sub)):.2e}  "
+                   f"local energy {rel(el, ref):.2e}")
+            _compare_walkers(g, wk, sub, tol=tol)
+            assert rel(el, ref) < tol
+    err = np.abs(traces["bf16x3"][:, 2] - traces["fp64"][:, 2]) * 627.5095
+    banner(f"  dE split-BF16 vs FP64 (kcal/mol) {np.max(err):.2e}")
+    assert traces["fp64"].shape[0] == n_steps // cfg.measure_every
+    assert np.max(err) < 0.05
+
+
 def test_identical_pair_exact_zero(lib):
     banner("identical pair")
     wl = Workload(20, 40, 4, 4, 4, 4, 32, 0.01, ham_seed=2)
