@@ -167,6 +167,24 @@ def test_reduced_precision_close_to_oracle(lib, torch_mod, dims, prec, tol):
         assert err <= tol * scale, (key, err, scale)
 
 
+# The largest basis the split plan serves (M = 256: the one-plane unpack holds
+# a 131 KB triangle in LDS, the 32-orbital propagation shapes) and the largest
+# the 80-orbital shape serves (M = 224), as whole pairs against the oracle at
+# the bound above; Philox fields, one measurement after 10 steps.
+@pytest.mark.parametrize("dims", [(256, 384, 12, 12, 12, 11, 6), (224, 448, 40, 40, 40, 39, 3)])
+def test_split_plan_largest_bases(lib, torch_mod, dims):
+    M, nc, a1, b1, a2, b2, nw = dims
+    banner(f"bf16x3 vs oracle, large basis {dims}")
+    wl = Workload(M, nc, a1, b1, a2, b2, nw, 0.005, ham_seed=5)
+    ref, tr, _, (ga, gb), _ = _run_pair_both(lib, torch_mod, wl, 10, 5, 10, philox_seed=3,
+                                             precision="bf16x3")
+    assert tr.shape == (1, 3)
+    scale = max(np.max(np.abs(ref["EA"])), np.max(np.abs(ref["EB"])))
+    for col, key in enumerate(("EA", "EB", "dE")):
+        err = np.max(np.abs(tr[:, col] - np.asarray(ref[key])))
+        assert err <= 1e-5 * scale, (key, err, scale)
+
+
 def test_parity_m100_sampled_walkers(lib, torch_mod):
     """M=100 pair at its full walker count (1024), device Philox fields; the
     oracle recomputes a sample of walkers one by one (walkers are independent
