@@ -575,6 +575,9 @@ struct AdjState {
     // scratch
     DevBuf xc, simp_s, apk, A, x, tA, tB, y, tT, tbT, ybar, Abar, Abpk, G, Fbar, thbar, phibar,
         phibar2, wbar, wbar2, mode, lnrb, lnib, th_s, y_s, z, acc, ebuf, scale, Tb, U, vd, cp, part;
+    // K ranges of G = <L_g, A_bar> (K = M(M+1)/2 is long, the output small)
+    int g_ks = 1;
+    DevBuf gws;
 };
 
 namespace {
@@ -735,6 +738,8 @@ afqmc_status adj_setup(afqmc_sys s, AdjState* a, hipStream_t st) {
         {&a->vd, (size_t)nw * 2 * 8}, {&a->cp, rowb}, {&a->part, (size_t)nw * 8},
     };
     for (auto& b : bufs) HIPCHK(b.b->alloc(b.n));
+    a->g_ks = P >= 512 ? (int)std::min(8L, P / 256) : 1;
+    if (a->g_ks > 1) HIPCHK(a->gws.alloc(gemm_ws_bytes(2 * nw, std::max(nc, 1), a->g_ks, a->prec)));
     const int nmax = std::max(s->na, s->nb);
     HIPCHK(a->Tb.alloc((size_t)nw * 2 * std::max(nc, 1) * nmax * nmax * 8));
     return AFQMC_OK;
@@ -979,6 +984,10 @@ afqmc_status reverse_step(afqmc_sys s, AdjState* a, int j, const double* phi_nex
         g.n = nc;
         g.k = (int)P;
         g.batch = 1;
+        if (a->g_ks > 1) {
+            g.ksplit = a->g_ks;
+            g.ws = a->gws.p;
+        }
         if (nc > 0) HIPCHK(gemm(g, pr, st));
     }
     hipLaunchKernelGGL(k_adj_fbar, dim3(nblk((long)nw * (nc + 1), 256)), dim3(256), 0, st,

@@ -151,7 +151,7 @@ struct afqmc_sys_s {
     afq::host::AdjState* adj = nullptr;  // reverse-mode tape (adjoint.hip)
     // constant per-system data
     // d_Plp: P in FP32, or with ta == DT_SPLIT Q = P - I as hi/lo BF16 planes
-    // (the same M * M * 4 bytes)
+    // in the fragment-tiled layout (split_tile_elems(M) * 4 bytes)
     afq::host::DevBuf d_trialT, d_P, d_Plp, d_a, d_lhx, d_lhx_lp;
     // walker state
     afq::host::DevBuf d_phi, d_phinew, d_theta, d_theta_lp, d_w, d_lnov, d_alive;
