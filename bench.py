@@ -5,11 +5,14 @@ Default workload: the M = 200 pair (n_chol = 800, neutral 40/40 vs ion
 40/39 electrons, 2048 walkers per system, dt = 0.005, Taylor order 6,
 modified Gram-Schmidt every 10 steps, mixed energy every 20 steps), Cholesky
 contractions in split BF16 (hi + lo products) with FP32 accumulation,
-propagator products in FP32, determinants / Gram-Schmidt / weights in FP64.
-One "step" is one pair-step: both systems advanced one dt, with the periodic
-Gram-Schmidt and energy measurement amortised in (steps are a multiple of the
-measurement period).  The timed steps are replayed from a HIP graph; a
-following profiled pass of direct launches gives the per-kernel times.
+propagator products (Taylor terms and one-body halves) in split BF16,
+determinants / Gram-Schmidt / weights in FP64.  One "step" is one pair-step:
+both systems advanced one dt, with the periodic Gram-Schmidt and energy
+measurement in it where the cadence puts them.  The warm-up is rounded up to
+whole periods of that cadence (20 steps) so the timed window starts on a
+period boundary; exactly --steps steps are timed, replayed from a HIP graph;
+a following profiled pass of direct launches (whole periods) gives the
+per-kernel times.
 
 --workload batch: 64 uneven pairs (M in 40..240, FP32 contractions) stepped
 together from one graph, against the same pairs stepped one at a time.
@@ -23,6 +26,7 @@ from __future__ import annotations
 
 import argparse
 import json
+import math
 import os
 import sys
 import time
@@ -62,29 +66,77 @@ def phase_dtype(name, prec, M):
             "propagate": prop}.get(name)
 
 
-def cpu_baseline(cfg, n_walkers, n_steps):
-    """The FP64 oracle, as it stands, on a bounded sample of the same pair."""
-    import numpy as np
-    from oracle import afqmc as O
+def round_up(n: int, period: int) -> int:
+    return -(-n // period) * period if period > 0 else n
+
+
+def plan_counts(steps: int, warmup: int, profile_steps: int, period: int):
+    """Step counts actually run.  The timed steps are exactly the requested
+    number; the warm-up is rounded up to a whole number of periods of the
+    Gram-Schmidt / measurement cadence so that the timed window starts where
+    a period starts (its first measurement and orthonormalisation fall at
+    the same offsets as in a long run), and the profiled pass is rounded up
+    to whole periods so its per-step phase times carry the amortised
+    measurement."""
+    if steps <= 0 or warmup < 0 or profile_steps < 0:
+        raise ValueError("--steps must be positive; --warmup and --profile-steps non-negative")
+    return steps, round_up(warmup, period), round_up(profile_steps, period)
+
+
+def _cpu_model() -> str:
     try:
-        from threadpoolctl import threadpool_info
-        cores = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+        import subprocess
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        for line in out.splitlines():
+            if line.startswith("Model name:"):
+                return line.split(":", 1)[1].strip()
     except Exception:
-        cores = os.cpu_count() or 1
+        pass
+    return "unknown"
+
+
+def _oracle_rate(cfg, n_walkers, n_steps, threads):
+    """Walker-steps/s of the FP64 oracle on n_walkers walkers per system of the
+    pair cfg over n_steps pair-steps, BLAS limited to `threads` threads."""
+    import numpy as np
+    from threadpoolctl import threadpool_info, threadpool_limits
+
+    from oracle import afqmc as O
     ham = cfg.hamiltonian()
     sa = O.System(ham.h, ham.chol, ham.e_core, cfg.trial_a(), cfg.na_a, cfg.nb_a, cfg.dt)
     sb = O.System(ham.h, ham.chol, ham.e_core, cfg.trial_b(), cfg.na_b, cfg.nb_b, cfg.dt)
     wa, wb = O.init_walkers(sa, n_walkers), O.init_walkers(sb, n_walkers)
-    t0 = time.perf_counter()
-    out = O.run_pair(sa, sb, wa, wb, O.PhiloxFields(cfg.seed, 0, cfg.n_chol), n_steps,
-                     cfg.ortho_every, cfg.measure_every)
-    el = time.perf_counter() - t0
+    with threadpool_limits(limits=threads):
+        used = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+        t0 = time.perf_counter()
+        out = O.run_pair(sa, sb, wa, wb, O.PhiloxFields(cfg.seed, 0, cfg.n_chol), n_steps,
+                         cfg.ortho_every, cfg.measure_every)
+        el = time.perf_counter() - t0
     assert np.all(np.isfinite(out["dE"]))
-    return {"value": 2 * n_walkers * n_steps / el, "unit": "walker-steps/s", "cores": int(cores),
-            "kind": "oracle",
+    return 2 * n_walkers * n_steps / el, int(used), el
+
+
+def cpu_baseline(cfg, cfg_small, n_walkers, n_steps):
+    """The FP64 oracle, as it stands, on bounded samples: the benchmark pair on
+    all host threads (the reported value) and on one thread, and the M = 100
+    pair on all threads.  Walkers are independent without population
+    control, so a walker subset runs at the full batch's per-walker rate."""
+    import numpy as np  # noqa: F401
+    host = os.cpu_count() or 1
+    v_all, used_all, el_all = _oracle_rate(cfg, n_walkers, n_steps, host)
+    v_one, used_one, el_one = _oracle_rate(cfg, n_walkers, n_steps, 1)
+    v_s, used_s, el_s = _oracle_rate(cfg_small, 2 * n_walkers, n_steps, host)
+    return {"value": v_all, "unit": "walker-steps/s", "cores": used_all, "kind": "oracle",
             "sample": f"{n_walkers} walkers per system x {n_steps} pair-steps of the same "
                       f"M={cfg.M} pair (MGS every {cfg.ortho_every}, energy every "
-                      f"{cfg.measure_every}), FP64 numpy, {el:.1f} s"}
+                      f"{cfg.measure_every}), FP64 numpy/scipy, {used_all} BLAS threads, "
+                      f"{el_all:.1f} s",
+            "single_thread": {"value": v_one, "cores": used_one,
+                              "sample": f"same sample on 1 thread, {el_one:.1f} s"},
+            "M100_pair": {"value": v_s, "cores": used_s,
+                          "sample": f"{2 * n_walkers} walkers per system x {n_steps} pair-steps "
+                                    f"of the M={cfg_small.M} pair, {el_s:.1f} s"},
+            "host_cpus": host, "cpu_model": _cpu_model()}
 
 
 def _traffic(roof, cfg, prec, shapes):
@@ -149,10 +201,8 @@ def bench_pair(args):
         cfg = cfg.with_(n_walkers=args.walkers)
     prec = args.precision
     me = cfg.measure_every
-    if args.steps % me or args.warmup % me or args.profile_steps % me:
-        print(f"--steps, --warmup and --profile-steps must be multiples of the measurement "
-              f"period {me}", file=sys.stderr)
-        sys.exit(2)
+    period = math.lcm(cfg.ortho_every, me)
+    steps, warmup, profile_steps = plan_counts(args.steps, args.warmup, args.profile_steps, period)
     ham = cfg.hamiltonian()
     ta, tb = cfg.trial_a(), cfg.trial_b()
     print(f"[bench] M={cfg.M} n_chol={cfg.n_chol} Nw={cfg.n_walkers} precision={prec}",
@@ -179,14 +229,14 @@ def bench_pair(args):
         torch.cuda.synchronize()
         del src, dst
     torch.cuda.synchronize()
-    tr_w = run(ga, gb, args.warmup)
-    print(f"[bench] warmup done ({args.warmup} steps)", file=sys.stderr, flush=True)
+    tr_w = run(ga, gb, warmup)
+    print(f"[bench] warmup done ({warmup} steps)", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    tr_t = run(ga, gb, args.steps)
+    tr_t = run(ga, gb, steps)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
-    print(f"[bench] timed {args.steps} graph-replayed steps in {elapsed:.3f} s", file=sys.stderr,
+    print(f"[bench] timed {steps} graph-replayed steps in {elapsed:.3f} s", file=sys.stderr,
           flush=True)
     # per-kernel HIP events on the launch stream over a profiled pass of the
     # same trajectory (direct launches)
@@ -194,7 +244,7 @@ def bench_pair(args):
     gb.profile(True)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    tr_p = lib.pair_step(ga, gb, args.profile_steps, seed=args.seed)
+    tr_p = lib.pair_step(ga, gb, profile_steps, seed=args.seed)
     torch.cuda.synchronize()
     el_prof = time.perf_counter() - t1
     prof_a, prof_b = ga.profile_read(), gb.profile_read()
@@ -203,15 +253,16 @@ def bench_pair(args):
     alive = (ga.walkers()["alive"].mean(), gb.walkers()["alive"].mean())
     trace = np.concatenate([x for x in (tr_w, tr_t, tr_p) if len(x)])
     tuned = [list(lib.autotune(x)) for x in (ga, gb)]  # cached: the shapes the graph used
-    phases, roofline = _roofline(prof_a, prof_b, args.profile_steps, cfg, prec)
+    phases, roofline = _roofline(prof_a, prof_b, profile_steps, cfg, prec)
     _traffic(roofline, cfg, prec, tuned)
-    roofline["measured_over"] = (f"{args.profile_steps} pair-steps of the same run, direct "
+    roofline["measured_over"] = (f"{profile_steps} pair-steps of the same run, direct "
                                  "launches, HIP events around every launch on its stream")
 
-    ws = 2 * cfg.n_walkers * args.steps / elapsed
+    ws = 2 * cfg.n_walkers * steps / elapsed
     out = {
         "metric": METRIC, "value": ws, "unit": "walker-steps/s", "n_gpus": 1,
-        "steps": args.steps, "warmup": args.warmup, "ms_per_step": elapsed * 1e3 / args.steps,
+        "steps": steps, "warmup": warmup, "warmup_requested": args.warmup,
+        "ms_per_step": elapsed * 1e3 / steps,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": prec,
         "data": "synthetic",
         "config": {"workload": f"correlated pair M={cfg.M} n_chol={cfg.n_chol} "
@@ -223,14 +274,14 @@ def bench_pair(args):
                    "walker_arithmetic": "fp64", "launch": "HIP graph replay",
                    "parallelism": "single GPU"},
         "roofline": roofline,
-        "profiled_ms_per_step": el_prof * 1e3 / args.profile_steps,
+        "profiled_ms_per_step": el_prof * 1e3 / profile_steps,
         "tuned_shapes": {"fb_tile/fs_tile/prop_shape": tuned},
         "phases_ms_per_step": {k: round(v["ms_per_step"], 4) for k, v in phases.items()},
         "alive_fraction": [float(alive[0]), float(alive[1])],
         "dE_trace_Eh": [float(x) for x in trace[:, 2]],
     }
 
-    n_all = args.warmup + args.steps + args.profile_steps
+    n_all = warmup + steps + profile_steps
     if prec != "fp64" and not args.no_fp64_check:
         del ga, gb, H
         H64, fa, fb = make("fp64")
@@ -249,7 +300,7 @@ def bench_pair(args):
 
     if not args.no_cpu_baseline:
         print("[bench] timing the FP64 oracle on a sample", file=sys.stderr, flush=True)
-        out["cpu_baseline"] = cpu_baseline(cfg, args.cpu_walkers, args.cpu_steps)
+        out["cpu_baseline"] = cpu_baseline(cfg, config(1), args.cpu_walkers, args.cpu_steps)
     print(json.dumps(out), flush=True)
 
 
@@ -265,9 +316,8 @@ def bench_batch(args):
     cfgs = pair_batch_configs(n_pairs=args.pairs)
     prec = "fp32" if args.precision == "bf16" else args.precision
     me = cfgs[0].measure_every
-    if args.steps % me or args.warmup % me:
-        print(f"--steps and --warmup must be multiples of {me}", file=sys.stderr)
-        sys.exit(2)
+    steps, warmup, _ = plan_counts(args.steps, args.warmup, 0,
+                                   math.lcm(cfgs[0].ortho_every, me))
     pairs, hams, seeds = [], [], []
     t_gen = time.perf_counter()
     for p, c in enumerate(cfgs):
@@ -290,16 +340,16 @@ def bench_batch(args):
     solo = []
     for (a, b), sd in zip(pairs, seeds):
         t0 = time.perf_counter()
-        lib.pair_step(a, b, args.steps, seed=sd)
+        lib.pair_step(a, b, steps, seed=sd)
         torch.cuda.synchronize()
         solo.append(time.perf_counter() - t0)
     print(f"[bench] standalone pairs: {sum(solo):.2f} s", file=sys.stderr, flush=True)
     # batch: warm-up (autotune + capture), then timed graph replays
-    lib.pair_batch_step(pairs, seeds, args.warmup, lanes=args.lanes)
+    lib.pair_batch_step(pairs, seeds, warmup, lanes=args.lanes)
     torch.cuda.synchronize()
     print("[bench] batch warmup done", file=sys.stderr, flush=True)
     t0 = time.perf_counter()
-    tr = lib.pair_batch_step(pairs, seeds, args.steps, lanes=args.lanes)
+    tr = lib.pair_batch_step(pairs, seeds, steps, lanes=args.lanes)
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
     print(f"[bench] batch: {el:.2f} s", file=sys.stderr, flush=True)
@@ -309,7 +359,7 @@ def bench_batch(args):
             ch = lib.autotune(s)  # cached: returns the shapes the graph uses
             key = f"prop{ch[2]}/fb{ch[0]}/fs{ch[1]}"
             choices[key] = choices.get(key, 0) + 1
-    ws = 2 * walkers * args.steps / el
+    ws = 2 * walkers * steps / el
     fl = 0.0
     for c in cfgs:
         P = c.M * (c.M + 1) // 2
@@ -319,8 +369,8 @@ def bench_batch(args):
                                  + (2 * 4.0 + c.taylor_order * 8.0) * N * c.M * c.M)
     out = {
         "metric": "aggregate walker-steps/s, 64 uneven correlated pairs (batched)",
-        "value": ws, "unit": "walker-steps/s", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": el * 1e3 / args.steps, "higher_is_better": True,
+        "value": ws, "unit": "walker-steps/s", "n_gpus": 1, "steps": steps,
+        "warmup": warmup, "ms_per_step": el * 1e3 / steps, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": prec, "data": "synthetic",
         "config": {"workload": f"{len(cfgs)} pairs, M in [{min(c.M for c in cfgs)}, "
                                f"{max(c.M for c in cfgs)}], n_chol = 4M, N_sigma = M//5, "
@@ -328,7 +378,7 @@ def bench_batch(args):
                    "lanes": args.lanes, "launch": "HIP graph replay, autotuned shapes"},
         "standalone_sum_s": sum(solo), "batch_s": el,
         "batch_over_standalone": el / sum(solo),
-        "contraction_tflops_per_s": fl * args.steps / el / 1e12,
+        "contraction_tflops_per_s": fl * steps / el / 1e12,
         "tuned_shapes": choices,
         "dE_finite": bool(np.all(np.isfinite(tr[:, :, 2]))),
     }
@@ -404,7 +454,7 @@ def bench_adjoint(args):
     print(json.dumps(out), flush=True)
 
 
-def main():
+def make_parser() -> argparse.ArgumentParser:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--workload", default="pair", choices=["pair", "batch", "adjoint"])
@@ -418,15 +468,19 @@ def main():
     ap.add_argument("--lanes", type=int, default=4, help="batch workload: stream lanes")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-walkers", type=int, default=4)
-    ap.add_argument("--cpu-steps", type=int, default=100)
+    ap.add_argument("--cpu-walkers", type=int, default=4,
+                    help="oracle sample: walkers per system (M = 200; twice as many at M = 100)")
+    ap.add_argument("--cpu-steps", type=int, default=40, help="oracle sample: pair-steps")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="copy a buffer of this size once (device to device) before the timed "
                          "steps: the reference kernel for scaling HBM traffic counters")
     ap.add_argument("--no-fp64-check", action="store_true",
                     help="skip the FP64 rerun that measures the energy-difference error")
-    args = ap.parse_args()
+    return ap
 
+
+def main(argv=None):
+    args = make_parser().parse_args(argv)
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (walkers and "
               "pairs are independent; sharding them across GPUs is described in the design "

@@ -52,6 +52,30 @@ def test_normals_moments_and_layout():
     assert np.array_equal(y[:, :250], x[:3])
 
 
+def test_normals_joint_distribution():
+    """Box-Muller must turn each pair of uniforms into two independent standard
+    normals.  Over 4 x 25 600 draws: the covariance of the four draws of one
+    generator call is the identity, each draw is N(0, 1) by a
+    Kolmogorov-Smirnov test, the polar angle of each pair is uniform and its
+    squared radius is exponential with mean 2 (chi-square, 2 degrees of
+    freedom).  Swapping sin for cos, or reusing one uniform for both
+    coordinates, fails here even though the moments of single draws survive."""
+    from scipy import stats
+    x = philox.normals(seed=2024, stream=1, t=3, walkers=np.arange(400), n_chol=256)
+    q = x.reshape(-1, 4)
+    cov = np.cov(q, rowvar=False)
+    assert np.max(np.abs(cov - np.eye(4))) < 0.04
+    for j in range(4):
+        assert stats.kstest(q[:, j], "norm").pvalue > 1e-3
+    for p in (0, 2):
+        z0, z1 = q[:, p], q[:, p + 1]
+        ang = np.mod(np.arctan2(z1, z0), 2 * np.pi) / (2 * np.pi)
+        assert stats.kstest(ang, "uniform").pvalue > 1e-3
+        assert stats.kstest(z0 ** 2 + z1 ** 2, "expon", args=(0, 2.0)).pvalue > 1e-3
+        quad = np.bincount((z0 > 0) * 2 + (z1 > 0), minlength=4) / len(z0)
+        assert np.max(np.abs(quad - 0.25)) < 0.01
+
+
 # -------------------------------------------------- FCI-space pins (P1)
 
 @pytest.fixture(scope="module", params=[(5, 2, 2, 4), (5, 2, 1, 3), (6, 3, 2, 5), (4, 1, 0, 3)])
