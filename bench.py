@@ -57,11 +57,10 @@ def phase_flops(name, M, nc, na, nb, nw, taylor_order=6):
 
 
 def phase_dtype(name, prec, M):
-    """Matrix-core input type of a phase under a precision plan (split-BF16
-    propagator products need M % 8 == 0, FP32 otherwise)."""
+    """Matrix-core input type of a phase under a precision plan."""
     contract = {"fp64": "fp64", "fp32": "fp32", "bf16": "bf16", "bf16_plain": "bf16",
                 "bf16x3": "bf16"}[prec]
-    prop = "fp64" if prec == "fp64" else ("bf16" if prec == "bf16x3" and M % 8 == 0 else "fp32")
+    prop = "fp64" if prec == "fp64" else ("bf16" if prec == "bf16x3" else "fp32")
     return {"force_bias_gemm": contract, "field_sum_gemm": contract, "exchange": contract,
             "propagate": prop}.get(name)
 
@@ -125,7 +124,7 @@ def cpu_baseline(cfg, cfg_small, n_walkers, n_steps):
     host = os.cpu_count() or 1
     v_all, used_all, el_all = _oracle_rate(cfg, n_walkers, n_steps, host)
     v_one, used_one, el_one = _oracle_rate(cfg, n_walkers, n_steps, 1)
-    v_s, used_s, el_s = _oracle_rate(cfg_small, 2 * n_walkers, n_steps, host)
+    v_s, used_s, el_s = _oracle_rate(cfg_small, 8 * n_walkers, n_steps, host)
     return {"value": v_all, "unit": "walker-steps/s", "cores": used_all, "kind": "oracle",
             "sample": f"{n_walkers} walkers per system x {n_steps} pair-steps of the same "
                       f"M={cfg.M} pair (MGS every {cfg.ortho_every}, energy every "
@@ -134,7 +133,7 @@ def cpu_baseline(cfg, cfg_small, n_walkers, n_steps):
             "single_thread": {"value": v_one, "cores": used_one,
                               "sample": f"same sample on 1 thread, {el_one:.1f} s"},
             "M100_pair": {"value": v_s, "cores": used_s,
-                          "sample": f"{2 * n_walkers} walkers per system x {n_steps} pair-steps "
+                          "sample": f"{8 * n_walkers} walkers per system x {n_steps} pair-steps "
                                     f"of the M={cfg_small.M} pair, {el_s:.1f} s"},
             "host_cpus": host, "cpu_model": _cpu_model()}
 
@@ -469,7 +468,7 @@ def make_parser() -> argparse.ArgumentParser:
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-walkers", type=int, default=4,
-                    help="oracle sample: walkers per system (M = 200; twice as many at M = 100)")
+                    help="oracle sample: walkers per system (M = 200; eight times as many at M = 100)")
     ap.add_argument("--cpu-steps", type=int, default=40, help="oracle sample: pair-steps")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="copy a buffer of this size once (device to device) before the timed "

@@ -54,8 +54,8 @@ typedef enum {
  *   BF16: the Taylor terms (A_w carried as hi + lo planes) and the one-body
  *   halves, applied as P y = y + Q y with Q = P - I (formed in FP64, carried
  *   as hi + lo planes) so that the identity part is added exactly in FP32
- *   and the rounding of the product scales with |Q|.  Needs M % 8 == 0 for
- *   the split propagator products (FP32 products otherwise).
+ *   and the rounding of the product scales with |Q|.  Any M: the operand
+ *   tiles are zero-padded to 16 rows and 32 columns.
  * In every mode the walker determinants, overlaps, determinants,
  * Gram-Schmidt, weights and phases stay FP64. */
 typedef enum {
@@ -253,8 +253,7 @@ afqmc_status afqmc_selftest_gemm(afqmc_prec prec, int m, int n, int k, const dou
  * 11: 4 x 2 with two row blocks (32 orbitals) per workgroup, split BF16
  * only (8, 9 keep the running Taylor sum in LDS); 12: 8 x 2 with five row
  * blocks (80 orbitals) per workgroup, split BF16 and M rounded up to 32 at
- * most 224 only; a shape serves M <= 16 waves blocks; split BF16 needs
- * M % 8 == 0; E_SHAPE otherwise).
+ * most 224 only; a shape serves M <= 16 waves blocks; E_SHAPE otherwise).
  * phi, out:
  * nw x 2 x N x M (plane 0 real, plane 1 imaginary of orbital columns); P:
  * M x M real symmetric; A: nw x 2 x M x M complex symmetric.  Host float64

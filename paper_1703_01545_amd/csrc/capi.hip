@@ -382,7 +382,7 @@ afqmc_status afqmc_init_walkers(afqmc_ham ham, int n_alpha, int n_beta, const do
         case AFQMC_BF16X3: s->ts = DT_F32; s->tc = DT_SPLIT; s->tp = DT_F32; break;
         default: s->ts = DT_BF16; s->tc = DT_BF16; s->tp = DT_F32; break;
     }
-    s->ta = (par->contract_prec == AFQMC_BF16X3 && M % 8 == 0) ? DT_SPLIT : s->tp;
+    s->ta = par->contract_prec == AFQMC_BF16X3 ? DT_SPLIT : s->tp;
     auto bail = [&](afqmc_status r) {
         afqmc_free_sys(s);
         return r;

@@ -84,7 +84,7 @@ __host__ __device__ inline long split_tile_index(int M, int r, int c) {
 // Packed upper triangle (P = M(M+1)/2 per plane) -> full symmetric M x M,
 // for `planes` consecutive planes (types DT_F64 / DT_F32 row-major;
 // DT_SPLIT: FP32 input, hi/lo BF16 output planes [plane][hi, lo][tiles] in
-// the fragment-tiled layout, M % 8 == 0, M <= 256).
+// the fragment-tiled layout, M <= 256).
 hipError_t unpack_sym(const void* pk, void* full, int M, int planes, DType t, hipStream_t s);
 // LDS limit of the one-plane split unpack (the packed triangle of M = 256);
 // unpack_prepare raises the kernel's dynamic LDS limit to it (call once,
@@ -102,7 +102,7 @@ hipError_t split_planes(const float* in, void* out, long n, long planes, hipStre
 // or DT_SPLIT with t == DT_F32: every product in split BF16, Af as hi/lo
 // planes [w][plane][hi, lo][tiles] and Pm holding Q = P - I as hi/lo planes
 // [hi, lo][tiles], both in the fragment-tiled layout (P y computed as
-// y + Q y), M % 8 == 0.  Frozen walkers (live == 0)
+// y + Q y).  Frozen walkers (live == 0)
 // are copied unchanged.  M <= 256.  `variant` selects the workgroup shape
 // (waves per workgroup x column blocks per wave, with or without B prefetch,
 // one, two or five row blocks per workgroup; see kPropShapes); every variant gives

@@ -880,9 +880,9 @@ __global__ void k_split_planes(const float* __restrict__ in, bf16_t* __restrict_
 // whole in LDS, then every thread writes one 8-element run of the
 // fragment-tiled hi/lo BF16 planes of the full symmetric matrix (A_ij from
 // the packed row min(i, j); zero past M) as one 16-byte hi store and one
-// 16-byte lo store; consecutive threads write consecutive runs.  Needs
-// M % 8 == 0 and the triangle in LDS (M <= 256); 512 threads (two workgroups
-// per CU by LDS, eight waves each).
+// 16-byte lo store; consecutive threads write consecutive runs (any M: the
+// runs past column M are zero).  Needs the triangle in LDS (M <= 256); 512
+// threads (two workgroups per CU by LDS, eight waves each).
 constexpr int kUnpackThreads = 512;
 __global__ __launch_bounds__(kUnpackThreads) void k_unpack_split_plane(
     const float* __restrict__ pk, bf16_t* __restrict__ full, int M) {
@@ -964,7 +964,7 @@ hipError_t unpack_sym(const void* pk, void* full, int M, int planes, DType t, hi
     else if (t == DT_F32)
         hipLaunchKernelGGL(k_unpack<float>, grid, dim3(256), 0, s, (const float*)pk, (float*)full,
                            M);
-    else if (t == DT_SPLIT && M % 8 == 0 && (size_t)M * (M + 1) / 2 * 4 <= kUnpackLds)
+    else if (t == DT_SPLIT && (size_t)M * (M + 1) / 2 * 4 <= kUnpackLds)
         hipLaunchKernelGGL(k_unpack_split_plane, dim3(planes), dim3(kUnpackThreads),
                            (size_t)M * (M + 1) / 2 * 4, s, (const float*)pk, (bf16_t*)full, M);
     else
@@ -995,7 +995,7 @@ constexpr PropShape kPropShapes[kPropVariants] = {
 bool propagate_variant_ok(int v, int M, DType t, DType ta) {
     if (v < 0 || v >= kPropVariants || M <= 0) return false;
     if (t != DT_F64 && t != DT_F32) return false;
-    if (ta != t && !(t == DT_F32 && ta == DT_SPLIT && M % 8 == 0)) return false;
+    if (ta != t && !(t == DT_F32 && ta == DT_SPLIT)) return false;
     const PropShape p = kPropShapes[v];
     if (t == DT_F64 && !p.pf) return false;  // the FP64 path keeps the prefetching shapes
     if (p.rows > 1 && ta != DT_SPLIT) return false;

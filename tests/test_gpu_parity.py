@@ -354,8 +354,6 @@ def test_errors(lib):
 def test_propagation_kernel(lib, dims, prec):
     """Fused P T_K(A) P kernel vs the same products in numpy (K = 6)."""
     M, N, nw = dims
-    if prec == "bf16x3" and M % 8:
-        pytest.skip("split-BF16 Taylor terms need M % 8 == 0")
     banner(f"propagate kernel {prec} {dims}")
     rng = np.random.default_rng(M + N)
     phi = rng.standard_normal((nw, M, N)) + 1j * rng.standard_normal((nw, M, N))
@@ -383,8 +381,6 @@ def test_propagation_shapes_bitwise(lib, dims, prec):
     """Every workgroup shape the autotuner may pick gives bitwise the result
     of the default shape (same summation order per output element)."""
     M, N, nw = dims
-    if prec == "bf16x3" and M % 8:
-        pytest.skip("split-BF16 Taylor terms need M % 8 == 0")
     banner(f"propagate shapes {prec} {dims}")
     rng = np.random.default_rng(7 * M + N)
     phi = rng.standard_normal((nw, M, N)) + 1j * rng.standard_normal((nw, M, N))
