@@ -18,6 +18,9 @@ per-kernel times.
 together from one graph, against the same pairs stepped one at a time.
 --workload adjoint: dE/dlambda through the last 100 of 500 steps at M = 100
 against correlated finite differences.
+--workload se_study: standard error of the energy difference over 11 repeats,
+correlated against uncorrelated fields, versus basis size and walker count
+(FP64 unless --precision says otherwise).
 
 Prints one JSON line.  value = walker-steps/s (2 systems x walkers x steps /
 wall time of the timed steps, inputs resident in HBM).
@@ -453,10 +456,69 @@ def bench_adjoint(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_se_study(args):
+    """Synthetic analogue of the paper's efficiency study (Sec. II.B, III.C):
+    11 repeats of neutral/ion pairs (n_chol = 4M, N_sigma = M/5, the ion one
+    beta electron short) propagated to tau = 3 with dt = 0.01 (MGS every 0.05,
+    energies every 0.1), fields correlated between the two systems or not.
+    The standard error of the cumulative averages of dE after tau = 1, over
+    the repeats, against the basis size M (at 32 walkers) and against the
+    walker count (at M = 48).  Since the error falls as 1/sqrt(walkers), an
+    uncorrelated run needs (SE_unc / SE_cor)^2 times the walkers, and so that
+    much more time, to reach the correlated error at the same tau."""
+    import numpy as np
+
+    from paper_1703_01545_amd import afqmc as lib
+    from paper_1703_01545_amd import repeats, stats
+    from synth import make_hamiltonian, make_trial
+
+    n_rep, dt, steps, me, oe, j_eq = 11, 0.01, 300, 10, 5, 10
+    rows = []
+    cases = [(24, 32), (48, 32), (96, 32), (48, 8), (48, 128)]
+    t_all = time.perf_counter()
+    for M, nw in cases:
+        ham = make_hamiltonian(M, 4 * M, seed=50 + M)
+        H = lib.Hamiltonian(ham.h, ham.chol, ham.e_core)
+        n = M // 5
+        sa = (n, n, make_trial(ham.h, n, n))
+        sb = (n, n - 1, make_trial(ham.h, n, n - 1))
+        kw = dict(ortho_every=oe, measure_every=me, precision=args.precision)
+        t0 = time.perf_counter()
+        cor = repeats.correlated_repeats(H, sa, sb, nw, n_rep, steps, dt, seed0=args.seed, **kw)
+        unc = repeats.uncorrelated_repeats(H, sa, sb, nw, n_rep, steps, dt, seed0=args.seed,
+                                           **kw)
+        el = time.perf_counter() - t0
+        ec = stats.final_estimate(cor[:, :, 2], j_eq)
+        eu = stats.final_estimate(unc[:, :, 2], j_eq)
+        se_c = stats.mean_and_se(stats.cumulative_averages(cor[:, :, 2], j_eq), axis=0)[1]
+        se_u = stats.mean_and_se(stats.cumulative_averages(unc[:, :, 2], j_eq), axis=0)[1]
+        rows.append({"M": M, "n_chol": 4 * M, "electrons": [n, n, n, n - 1], "walkers": nw,
+                     "dE_correlated": ec.value, "se_correlated": ec.se,
+                     "dE_uncorrelated": eu.value, "se_uncorrelated": eu.se,
+                     "se_at_tau3_correlated": float(se_c[-1]),
+                     "se_at_tau3_uncorrelated": float(se_u[-1]),
+                     "walker_factor_for_equal_error": float((se_u[-1] / se_c[-1]) ** 2),
+                     "seconds": el})
+        print(f"[bench] M={M} Nw={nw}: SE cor {se_c[-1]:.2e} unc {se_u[-1]:.2e} ({el:.1f} s)",
+              file=sys.stderr, flush=True)
+        del H
+    factors = [r["walker_factor_for_equal_error"] for r in rows]
+    out = {"metric": "walker (CPU-time) factor for equal standard error of dE, uncorrelated "
+                     "over correlated sampling, 11 repeats, tau = 3",
+           "value": float(np.median(factors)), "unit": "x", "n_gpus": 1,
+           "higher_is_better": True, "vs_baseline": None, "dtype": args.precision,
+           "data": "synthetic",
+           "config": {"workload": "neutral/ion pairs, n_chol = 4M, N_sigma = M/5, dt = 0.01, "
+                                  "300 steps, 11 repeats, equilibration tau = 1",
+                      "cases": [[M, nw] for M, nw in cases]},
+           "rows": rows, "seconds": time.perf_counter() - t_all}
+    print(json.dumps(out), flush=True)
+
+
 def make_parser() -> argparse.ArgumentParser:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--workload", default="pair", choices=["pair", "batch", "adjoint"])
+    ap.add_argument("--workload", default="pair", choices=["pair", "batch", "adjoint", "se_study"])
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--profile-steps", type=int, default=20)
@@ -492,6 +554,10 @@ def main(argv=None):
         bench_batch(args)
     elif args.workload == "adjoint":
         bench_adjoint(args)
+    elif args.workload == "se_study":
+        if args.precision == "bf16x3":
+            args.precision = "fp64"
+        bench_se_study(args)
     else:
         bench_pair(args)
 

@@ -141,6 +141,30 @@ afqmc_status afqmc_orthonormalize(afqmc_sys sys);
 afqmc_status afqmc_pair_step(afqmc_sys a, afqmc_sys b, uint64_t seed, int n_steps,
                              const double* fields, double* e_trace);
 
+/* Population control by the comb (Sec. II.B: walkers with large weights are
+ * replicated, small ones stochastically removed), for the equilibration of a
+ * primary system; not used between correlated systems.  With C the running
+ * sum of the live weights in walker order and W its last value, new walker j
+ * copies the first walker k with C[k] > (j + xi) W / n_walkers; every new
+ * walker is live with weight W / n_walkers (the total weight is kept).  xi:
+ * one uniform number in [0, 1), drawn by the caller.  Overlaps and Theta are
+ * recomputed for the copies.  Synchronises.  Errors: E_INVALID (xi outside
+ * [0, 1)), E_STATE (free mode, or no walker of positive weight: nothing
+ * changed). */
+afqmc_status afqmc_population_control(afqmc_sys sys, double xi);
+
+/* Preliminary equilibration scheme (Sec. II.B): start the secondary system
+ * from the primary's walkers.  Walker k of `sec` takes walker k's
+ * determinant of `pri` (the first n_alpha and n_beta orbital columns of each
+ * spin block when the secondary has fewer electrons), and its weight becomes
+ * w_pri |r| max(0, cos arg r) with r = <phi_T^sec|phi> / <phi_T^pri|phi> (the
+ * phase of the ratio projected as in the phaseless step; a walker with
+ * cos arg r <= 0 is frozen).  The secondary's step counter is set to the
+ * primary's, so the two continue as a correlated pair.  Synchronises.
+ * Errors: E_SHAPE (different M or walker count, more electrons of a spin
+ * in the secondary, different streams), E_STATE (free mode), E_INVALID. */
+afqmc_status afqmc_init_from_primary(afqmc_sys sec, afqmc_sys pri);
+
 /* Many correlated pairs of uneven size advanced together (the pairs of
  * Sec. II.B, batched).  Pair p (systems a[p], b[p]) runs exactly what
  * afqmc_pair_step(a[p], b[p], seeds[p], n_steps, NULL, ...) runs, bit for
@@ -251,9 +275,10 @@ afqmc_status afqmc_selftest_gemm(afqmc_prec prec, int m, int n, int k, const dou
  * next chunk of the matrix operand prefetched; 4..7: the same shapes without
  * the prefetch, FP32 and split BF16 only; 8: 16 x 1, 9: 8 x 1, 10: 8 x 2 and
  * 11: 4 x 2 with two row blocks (32 orbitals) per workgroup, split BF16
- * only (8, 9 keep the running Taylor sum in LDS); 12: 8 x 2 with five row
- * blocks (80 orbitals) per workgroup, split BF16 and M rounded up to 32 at
- * most 224 only; a shape serves M <= 16 waves blocks; E_SHAPE otherwise).
+ * only (8, 9 keep the running Taylor sum in LDS); 12: 8 x 2 and 13: 16 x 1
+ * with five row blocks (80 orbitals) per workgroup, split BF16 and M rounded
+ * up to 32 at most 224 only; a shape serves M <= 16 waves blocks; E_SHAPE
+ * otherwise).
  * phi, out:
  * nw x 2 x N x M (plane 0 real, plane 1 imaginary of orbital columns); P:
  * M x M real symmetric; A: nw x 2 x M x M complex symmetric.  Host float64

@@ -274,6 +274,55 @@ def mixed_energy(wk: Walkers, e_local: np.ndarray, mode: str = PHASELESS):
     return complex(np.sum(wk.weight * e_local) / np.sum(wk.weight)).real
 
 
+# ------------------------------------------- population control and PES
+
+def comb(wk: Walkers, xi: float) -> Walkers:
+    """Population control by the comb (Sec. II.B: walkers with large weights
+    are replicated, small ones stochastically removed), keeping the walker
+    count: with C the running sum of the live weights in walker order and
+    W = C[-1], the j-th new walker copies the first walker k with
+    C[k] > (j + xi) W / Nw (xi in [0, 1) drawn once per call); every new
+    walker is live with weight W / Nw, so the total weight is kept.  A point
+    that rounding puts at or past W takes the last walker of positive weight.
+    Phaseless mode only."""
+    w = np.where(wk.alive, wk.weight, 0.0)
+    nw = w.shape[0]
+    C = np.cumsum(w)
+    W = C[-1]
+    if not W > 0:
+        raise ValueError("no walker of positive weight")
+    z = (np.arange(nw, dtype=np.float64) + xi) * W / nw
+    sel = np.searchsorted(C, z, side="right")
+    last = int(np.nonzero(w > 0)[0][-1])
+    sel = np.where(sel >= nw, last, sel)
+    wk.phi = wk.phi[sel].copy()
+    wk.lnov = wk.lnov[sel].copy()
+    wk.theta = wk.theta[sel].copy()
+    wk.weight = np.full(nw, W / nw)
+    wk.alive = np.ones(nw, dtype=bool)
+    return wk
+
+
+def init_from_primary(sec: System, pri: System, wk_pri: Walkers) -> Walkers:
+    """Preliminary equilibration scheme (Sec. II.B): the secondary system's
+    walkers start from the primary's determinants (the first N_alpha and
+    N_beta orbital columns of each spin block when the secondary has fewer
+    electrons) with weights scaled by <phi_T^sec|phi>/<phi_T^pri|phi>, the
+    phase of that ratio projected as in the phaseless step:
+    w_sec = w_pri |ratio| max(0, cos arg ratio)."""
+    assert sec.M == pri.M and sec.na <= pri.na and sec.nb <= pri.nb
+    cols = list(range(sec.na)) + [pri.na + j for j in range(sec.nb)]
+    phi = wk_pri.phi[:, :, cols].copy()
+    lnov, theta = overlap(sec, phi)
+    ln_ratio = lnov - wk_pri.lnov
+    w = wk_pri.weight * np.exp(ln_ratio.real) * np.maximum(0.0, np.cos(ln_ratio.imag))
+    alive = wk_pri.alive & (w > 0)
+    w = np.where(alive, w, 0.0)
+    e_t = local_energy(sec, overlap(sec, sec.trial[None].astype(np.complex128))[1])[0].real
+    c0 = sec.e_core - 0.5 * float(np.sum(sec.a * sec.a))
+    return Walkers(phi, w, lnov, theta, alive, wk_pri.t, e_t - c0)
+
+
 # --------------------------------------------------------------------- fields
 
 class ExplicitFields:

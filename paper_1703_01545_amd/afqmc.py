@@ -34,6 +34,7 @@ EXPORTS = [
     "afqmc_last_error", "afqmc_selftest_gemm", "afqmc_selftest_fields", "afqmc_profile_enable",
     "afqmc_profile_read", "afqmc_phase_name", "afqmc_selftest_propagate", "afqmc_autotune",
     "afqmc_adjoint_forward", "afqmc_adjoint_backward",
+    "afqmc_population_control", "afqmc_init_from_primary",
 ]
 
 
@@ -51,6 +52,8 @@ _lib.afqmc_init_walkers.argtypes = [_vp, C.c_int, C.c_int, _dp, _dp, C.c_int, C.
 _lib.afqmc_step.argtypes = [_vp, C.c_uint64, C.c_uint64, C.c_int, _vp]
 _lib.afqmc_local_energy.argtypes = [_vp, _dp, _dp, _dp]
 _lib.afqmc_orthonormalize.argtypes = [_vp]
+_lib.afqmc_population_control.argtypes = [_vp, C.c_double]
+_lib.afqmc_init_from_primary.argtypes = [_vp, _vp]
 _lib.afqmc_pair_step.argtypes = [_vp, _vp, C.c_uint64, C.c_int, _vp, _dp]
 _lib.afqmc_pair_batch_step.argtypes = [C.c_int, C.POINTER(_vp), C.POINTER(_vp),
                                        C.POINTER(C.c_uint64), C.c_int, C.c_int, C.c_int, _dp]
@@ -173,6 +176,14 @@ class System:
 
     def orthonormalize(self):
         _check(_lib.afqmc_orthonormalize(self._s))
+
+    def population_control(self, xi: float):
+        """Comb of the walker population with the uniform number xi in [0, 1)."""
+        _check(_lib.afqmc_population_control(self._s, float(xi)))
+
+    def init_from_primary(self, primary: "System"):
+        """Start this (secondary) system from the primary's walkers (PES)."""
+        _check(_lib.afqmc_init_from_primary(self._s, primary._s))
 
     def local_energy(self):
         el = np.empty((self.nw, 2))

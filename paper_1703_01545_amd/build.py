@@ -14,7 +14,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libafqmc.so")
-SOURCES = ["gemm.hip", "propagate.hip", "walker.hip", "capi.hip", "batch.hip", "adjoint.hip"]
+SOURCES = ["gemm.hip", "propagate.hip", "walker.hip", "capi.hip", "batch.hip", "adjoint.hip",
+           "population.hip"]
 ARCH = os.environ.get("AFQMC_ARCH", "gfx950")
 
 FLAGS = [

@@ -1,6 +1,8 @@
 // C ABI of the correlated-sampling ph-AFQMC walker step (see include/afqmc.h).
 // Host code: handle management, validation, the per-system precompute, and
 // the ordering of the device phases of one step.
+#include <string>
+
 #include "host.h"
 
 using namespace afq;
@@ -223,6 +225,58 @@ afqmc_status measure(afqmc_sys s, hipStream_t st) {
     return AFQMC_OK;
 }
 
+// Validation shared by the pair entry points; *n_meas = measurements among
+// the n_steps.
+afqmc_status pair_check(afqmc_sys a, afqmc_sys b, int n_steps, int* n_meas) {
+    afqmc_status r;
+    if ((r = check_sys(a)) != AFQMC_OK || (r = check_sys(b)) != AFQMC_OK) return r;
+    if (n_steps < 0) return fail(AFQMC_E_INVALID, "n_steps < 0");
+    if (a == b) return fail(AFQMC_E_INVALID, "a pair needs two distinct systems");
+    if (a->M != b->M || a->n_chol != b->n_chol || a->nw != b->nw ||
+        a->ham->chol_hash != b->ham->chol_hash)
+        return fail(AFQMC_E_SHAPE, "pair systems must share M, n_chol, walker count and L");
+    if (a->par.dt != b->par.dt || a->par.ortho_every != b->par.ortho_every ||
+        a->par.measure_every != b->par.measure_every || a->par.mode != b->par.mode)
+        return fail(AFQMC_E_SHAPE, "pair systems must share dt, periods and mode");
+    if (a->t != b->t) return fail(AFQMC_E_STATE, "pair systems are at different steps");
+    if (a->ham->stream != b->ham->stream) return fail(AFQMC_E_SHAPE, "pair systems need one stream");
+    const int me = a->par.measure_every;
+    int n = 0;
+    for (int i = 0; i < n_steps; ++i)
+        if (me > 0 && (a->t + i + 1) % me == 0) ++n;
+    *n_meas = n;
+    return AFQMC_OK;
+}
+
+// The steps of a correlated pair (Sec. II.B); measurement rows go to the
+// device array `trace` (n_meas x 3), then to e_trace on the host.
+afqmc_status pair_run(afqmc_sys a, afqmc_sys b, uint64_t seed, int n_steps,
+                      const double* fields_dev, double* e_trace, double* trace, int n_meas) {
+    afqmc_status r;
+    hipStream_t st = a->ham->stream;
+    const int me = a->par.measure_every, oe = a->par.ortho_every;
+    int slot = 0;
+    for (int i = 0; i < n_steps; ++i) {
+        const double* ext = fields_dev ? fields_dev + (size_t)i * a->nw * a->n_chol : nullptr;
+        if ((r = one_step(a, seed, 0, ext, st)) != AFQMC_OK) return r;
+        if ((r = one_step(b, seed, 0, ext, st)) != AFQMC_OK) return r;
+        if (oe > 0 && a->t % oe == 0) {
+            if ((r = ortho(a, st)) != AFQMC_OK) return r;
+            if ((r = ortho(b, st)) != AFQMC_OK) return r;
+        }
+        if (me > 0 && a->t % me == 0) {
+            if ((r = measure(a, st)) != AFQMC_OK) return r;
+            if ((r = measure(b, st)) != AFQMC_OK) return r;
+            HIPCHK(trace_record(a->d_sums.as<double>(), b->d_sums.as<double>(), trace, slot++,
+                                nullptr, 0, (int)a->par.mode, st));
+        }
+    }
+    HIPCHK(hipStreamSynchronize(st));
+    if (e_trace && n_meas > 0)
+        HIPCHK(hipMemcpy(e_trace, trace, (size_t)n_meas * 3 * 8, hipMemcpyDeviceToHost));
+    return AFQMC_OK;
+}
+
 }  // namespace host
 }  // namespace afq
 
@@ -428,6 +482,7 @@ afqmc_status afqmc_init_walkers(afqmc_ham ham, int n_alpha, int n_beta, const do
         {&s->d_exch, (size_t)nw * 2 * s->n_gt * 2 * 8},
         {&s->d_el, (size_t)nw * 2 * 8},
         {&s->d_sums, 8 * 8},
+        {&s->d_pc, (size_t)nw * 12 + 16},
     };
     for (auto& a : allocs) {
         hipError_t e = a.b->alloc(a.bytes);
@@ -644,7 +699,8 @@ void afqmc_free_sys(afqmc_sys s) {
     for (DevBuf* b : {&s->d_trialT, &s->d_P, &s->d_Plp, &s->d_a, &s->d_lhx, &s->d_lhx_lp,
                       &s->d_phi, &s->d_phinew, &s->d_theta, &s->d_theta_lp, &s->d_w, &s->d_lnov,
                       &s->d_alive, &s->d_F, &s->d_X, &s->d_simp, &s->d_Apk, &s->d_Af,
-                      &s->d_lnd, &s->d_ovl, &s->d_kws, &s->d_exch, &s->d_el, &s->d_sums})
+                      &s->d_lnd, &s->d_ovl, &s->d_kws, &s->d_exch, &s->d_el, &s->d_sums,
+                      &s->d_pc})
         b->release();
     drop_batch_plans(s->id);
     free_adjoint(s);
@@ -697,44 +753,66 @@ afqmc_status afqmc_local_energy(afqmc_sys s, double* e_local, double* weights_ou
 
 afqmc_status afqmc_pair_step(afqmc_sys a, afqmc_sys b, uint64_t seed, int n_steps,
                              const double* fields_dev, double* e_trace) {
-    afqmc_status r;
-    if ((r = check_sys(a)) != AFQMC_OK || (r = check_sys(b)) != AFQMC_OK) return r;
-    if (n_steps < 0) return fail(AFQMC_E_INVALID, "n_steps < 0");
-    if (a == b) return fail(AFQMC_E_INVALID, "a pair needs two distinct systems");
-    if (a->M != b->M || a->n_chol != b->n_chol || a->nw != b->nw ||
-        a->ham->chol_hash != b->ham->chol_hash)
-        return fail(AFQMC_E_SHAPE, "pair systems must share M, n_chol, walker count and L");
-    if (a->par.dt != b->par.dt || a->par.ortho_every != b->par.ortho_every ||
-        a->par.measure_every != b->par.measure_every || a->par.mode != b->par.mode)
-        return fail(AFQMC_E_SHAPE, "pair systems must share dt, periods and mode");
-    if (a->t != b->t) return fail(AFQMC_E_STATE, "pair systems are at different steps");
-    if (a->ham->stream != b->ham->stream) return fail(AFQMC_E_SHAPE, "pair systems need one stream");
-    hipStream_t st = a->ham->stream;
-    const int me = a->par.measure_every, oe = a->par.ortho_every;
     int n_meas = 0;
-    for (int i = 0; i < n_steps; ++i)
-        if (me > 0 && (a->t + i + 1) % me == 0) ++n_meas;
+    afqmc_status r = pair_check(a, b, n_steps, &n_meas);
+    if (r != AFQMC_OK) return r;
     DevBuf trace;
     HIPCHK(trace.alloc((size_t)std::max(1, n_meas) * 3 * 8));
-    int slot = 0;
-    for (int i = 0; i < n_steps; ++i) {
-        const double* ext = fields_dev ? fields_dev + (size_t)i * a->nw * a->n_chol : nullptr;
-        if ((r = one_step(a, seed, 0, ext, st)) != AFQMC_OK) return r;
-        if ((r = one_step(b, seed, 0, ext, st)) != AFQMC_OK) return r;
-        if (oe > 0 && a->t % oe == 0) {
-            if ((r = ortho(a, st)) != AFQMC_OK) return r;
-            if ((r = ortho(b, st)) != AFQMC_OK) return r;
-        }
-        if (me > 0 && a->t % me == 0) {
-            if ((r = measure(a, st)) != AFQMC_OK) return r;
-            if ((r = measure(b, st)) != AFQMC_OK) return r;
-            HIPCHK(trace_record(a->d_sums.as<double>(), b->d_sums.as<double>(),
-                                trace.as<double>(), slot++, nullptr, 0, (int)a->par.mode, st));
-        }
-    }
+    return pair_run(a, b, seed, n_steps, fields_dev, e_trace, trace.as<double>(), n_meas);
+}
+
+afqmc_status afqmc_population_control(afqmc_sys s, double xi) {
+    afqmc_status r = check_sys(s);
+    if (r != AFQMC_OK) return r;
+    if (s->par.mode != AFQMC_PHASELESS)
+        return fail(AFQMC_E_STATE, "population control needs real weights (phaseless mode)");
+    if (!(xi >= 0.0 && xi < 1.0)) return fail(AFQMC_E_INVALID, "xi must lie in [0, 1)");
+    hipStream_t st = s->ham->stream;
+    double* csum = s->d_pc.as<double>();
+    int* sel = (int*)(csum + s->nw);
+    int* status = sel + s->nw;
+    HIPCHK(comb_select(s->d_w.as<double>(), s->d_alive.as<uint8_t>(), s->nw, xi, csum, sel, status,
+                       st));
+    int flag = 0;
+    HIPCHK(hipMemcpyAsync(&flag, status, sizeof(int), hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
-    if (e_trace && n_meas > 0)
-        HIPCHK(hipMemcpy(e_trace, trace.p, (size_t)n_meas * 3 * 8, hipMemcpyDeviceToHost));
+    if (flag) return fail(AFQMC_E_STATE, "population control: no walker has positive weight");
+    HIPCHK(gather_walkers(s->d_phi.as<double>(), s->d_phinew.as<double>(), sel, s->nw,
+                          2 * s->NM(), st));
+    std::swap(s->d_phi.p, s->d_phinew.p);
+    // overlaps and Theta of the copied determinants (the same kernels, so the
+    // same values as the originals')
+    if ((r = overlap_theta(s, s->d_phi.as<double>(), st)) != AFQMC_OK) return r;
+    HIPCHK(weights(s->d_lnd.as<double>(), s->d_simp.as<double>(), s->d_lnov.as<double>(),
+                   s->d_w.as<double>(), s->d_alive.as<uint8_t>(), s->nw, (int)s->par.mode, 0, 0.0,
+                   st));
+    return AFQMC_OK;
+}
+
+afqmc_status afqmc_init_from_primary(afqmc_sys sec, afqmc_sys pri) {
+    afqmc_status r;
+    if ((r = check_sys(sec)) != AFQMC_OK || (r = check_sys(pri)) != AFQMC_OK) return r;
+    if (sec == pri) return fail(AFQMC_E_INVALID, "secondary and primary must differ");
+    if (sec->M != pri->M || sec->nw != pri->nw)
+        return fail(AFQMC_E_SHAPE, "secondary and primary must share M and the walker count");
+    if (sec->na > pri->na || sec->nb > pri->nb)
+        return fail(AFQMC_E_SHAPE, "the secondary may not have more electrons of a spin");
+    if (sec->par.mode != AFQMC_PHASELESS || pri->par.mode != AFQMC_PHASELESS)
+        return fail(AFQMC_E_STATE, "the secondary start needs phaseless systems");
+    if (sec->ham->stream != pri->ham->stream)
+        return fail(AFQMC_E_SHAPE, "secondary and primary need one stream");
+    hipStream_t st = pri->ham->stream;
+    HIPCHK(take_columns(pri->d_phi.as<double>(), sec->d_phi.as<double>(), sec->nw, sec->M, pri->N,
+                        pri->na, sec->N, sec->na, st));
+    HIPCHK(hipMemcpyAsync(sec->d_alive.p, pri->d_alive.p, sec->nw, hipMemcpyDeviceToDevice, st));
+    if ((r = overlap_theta(sec, sec->d_phi.as<double>(), st)) != AFQMC_OK) return r;
+    HIPCHK(weights(sec->d_lnd.as<double>(), sec->d_simp.as<double>(), sec->d_lnov.as<double>(),
+                   sec->d_w.as<double>(), sec->d_alive.as<uint8_t>(), sec->nw, 0, 0, 0.0, st));
+    HIPCHK(secondary_weights(pri->d_w.as<double>(), pri->d_lnov.as<double>(),
+                             sec->d_lnov.as<double>(), sec->d_w.as<double>(),
+                             sec->d_alive.as<uint8_t>(), sec->nw, st));
+    HIPCHK(hipStreamSynchronize(st));
+    sec->t = pri->t;
     return AFQMC_OK;
 }
 

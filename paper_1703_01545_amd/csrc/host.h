@@ -159,6 +159,7 @@ struct afqmc_sys_s {
     afq::host::DevBuf d_F, d_X, d_simp, d_Apk, d_Af, d_lnd, d_exch, d_el, d_sums;
     afq::host::DevBuf d_ovl;  // overlap matrices of the determinant kernels
     afq::host::DevBuf d_kws;  // split-K partial sums of the force-bias GEMM
+    afq::host::DevBuf d_pc;   // comb workspace: running sums, selection, status
     int n_gt_a = 0, n_gt_b = 0, n_gt = 0;
     // launch shapes (autotuned; 0 = size heuristic): GEMM tiles of the force
     // bias and the field sum, and the propagation workgroup shape
@@ -230,6 +231,12 @@ afqmc_status one_step(afqmc_sys s, uint64_t seed, uint64_t stream_id, const doub
                       hipStream_t st);
 afqmc_status ortho(afqmc_sys s, hipStream_t st);
 afqmc_status measure(afqmc_sys s, hipStream_t st);
+// Validation shared by the pair entry points (*n_meas: measurements among
+// the n_steps), and the steps of a correlated pair with the measurement rows
+// staged in the device array `trace` (n_meas x 3), then copied to e_trace.
+afqmc_status pair_check(afqmc_sys a, afqmc_sys b, int n_steps, int* n_meas);
+afqmc_status pair_run(afqmc_sys a, afqmc_sys b, uint64_t seed, int n_steps,
+                      const double* fields_dev, double* e_trace, double* trace, int n_meas);
 
 // Autotuner: fills the system's launch shapes (tile_fb, tile_fs, prop_var) from the process-wide table, timing the candidates of shapes not
 // seen before.  Synchronises st.

@@ -107,7 +107,7 @@ hipError_t split_planes(const float* in, void* out, long n, long planes, hipStre
 // (waves per workgroup x column blocks per wave, with or without B prefetch,
 // one, two or five row blocks per workgroup; see kPropShapes); every variant gives
 // bitwise the same result, 0 is the default.
-constexpr int kPropVariants = 13;
+constexpr int kPropVariants = 14;
 bool propagate_variant_ok(int variant, int M, DType t, DType ta);
 hipError_t propagate(const double* phi, double* phi_out, const void* Pm, const void* Af,
                      const uint8_t* live, int nw, int M, int N, int K, DType t, DType ta,
@@ -184,6 +184,24 @@ hipError_t local_energy(const double* F, int ldf, const double* exch, int n_gt_a
 // mode: out[0..3] = sum W E_L (re, im), sum W (re, im).
 hipError_t mixed_sums(const double* el, const double* w, const uint8_t* alive, int nw, int mode,
                       double* out, hipStream_t s);
+
+// Population control by the comb (one workgroup): csum (nw doubles) and sel
+// (nw ints) are workspaces; w and alive become the new population's weights
+// (W / nw) and flags; sel[j] = walker copied into slot j.  status[0] = 1 when
+// no walker has positive weight (then nothing is changed).
+hipError_t comb_select(double* w, uint8_t* alive, int nw, double xi, double* csum, int* sel,
+                       int* status, hipStream_t s);
+// dst walker j <- src walker sel[j], `per` doubles per walker.
+hipError_t gather_walkers(const double* src, double* dst, const int* sel, int nw, long per,
+                          hipStream_t s);
+// Secondary walkers from primary ones: per walker and plane, rows
+// 0..na_sec-1 from the primary's alpha rows, the rest from its beta rows.
+hipError_t take_columns(const double* pri, double* sec, int nw, int M, int n_pri, int na_pri,
+                        int n_sec, int na_sec, hipStream_t s);
+// w_sec = w_pri |r| max(0, cos arg r), r = exp(lnov_sec - lnov_pri); alive
+// cleared where the result is not positive.
+hipError_t secondary_weights(const double* w_pri, const double* lnov_pri, const double* lnov_sec,
+                             double* w_sec, uint8_t* alive, int nw, hipStream_t s);
 
 // Small helpers.
 hipError_t broadcast(const double* src, double* dst, long n, int copies, hipStream_t s);

@@ -989,7 +989,7 @@ constexpr PropShape kPropShapes[kPropVariants] = {
     {8, 2, true, 1},   {4, 2, true, 1},   {4, 1, true, 1}, {2, 2, true, 1},
     {8, 2, false, 1},  {4, 2, false, 1},  {4, 1, false, 1}, {2, 2, false, 1},
     {16, 1, false, 2}, {8, 1, false, 2},  {8, 2, false, 2}, {4, 2, false, 2},
-    {8, 2, false, 5}};
+    {8, 2, false, 5},  {16, 1, false, 5}};
 }  // namespace
 
 bool propagate_variant_ok(int v, int M, DType t, DType ta) {
@@ -1040,6 +1040,9 @@ hipError_t propagate(const double* phi, double* phi_out, const void* Pm, const v
             return launch_prop_split_rb<4, 2, 2, true>(phi, phi_out, Pm, Af, live, nw, M, N, K, s);
         if (variant == 12)
             return launch_prop_split_rb<8, 2, 5, true>(phi, phi_out, Pm, Af, live, nw, M, N, K, s);
+        if (variant == 13)
+            return launch_prop_split_rb<16, 1, 5, true>(phi, phi_out, Pm, Af, live, nw, M, N, K,
+                                                        s);
     } else {
         AFQ_P(0, float, 8, 2, true)
         AFQ_P(1, float, 4, 2, true)

@@ -392,7 +392,7 @@ def test_propagation_shapes_bitwise(lib, dims, prec):
     # variant: (waves, column blocks per wave, prefetch, row blocks per workgroup)
     shapes = {0: (8, 2, 1, 1), 1: (4, 2, 1, 1), 2: (4, 1, 1, 1), 3: (2, 2, 1, 1), 4: (8, 2, 0, 1),
               5: (4, 2, 0, 1), 6: (4, 1, 0, 1), 7: (2, 2, 0, 1), 8: (16, 1, 0, 2), 9: (8, 1, 0, 2),
-              10: (8, 2, 0, 2), 11: (4, 2, 0, 2), 12: (8, 2, 0, 5)}
+              10: (8, 2, 0, 2), 11: (4, 2, 0, 2), 12: (8, 2, 0, 5), 13: (16, 1, 0, 5)}
     ran = 0
     for v, (waves, blocks, pf, rows) in shapes.items():
         ok = ((M + 15) // 16 <= waves * blocks and not (prec == "fp64" and not pf)
