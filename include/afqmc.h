@@ -165,6 +165,23 @@ afqmc_status afqmc_population_control(afqmc_sys sys, double xi);
  * in the secondary, different streams), E_STATE (free mode), E_INVALID. */
 afqmc_status afqmc_init_from_primary(afqmc_sys sec, afqmc_sys pri);
 
+/* For callers that cannot allocate device memory during the call (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): afqmc_pair_step with the same arguments, results and errors,
+ * bit for bit, except that the device staging rows of the energy trace live
+ * in a fixed array inside the library (one per GPU, held until the process
+ * ends) instead of a buffer allocated per call; the call itself makes no
+ * hipMalloc or hipFree.  At most AFQMC_NOALLOC_MAX_MEASUREMENTS measurement
+ * steps per call (else E_INVALID, nothing run); profiling must be off
+ * (E_STATE: it creates events).  Every call on one GPU shares that array:
+ * calls that overlap on one GPU (different host threads or streams) race on
+ * it.  Each row is written before it is read, so nothing needs clearing
+ * between calls.  The systems themselves are allocated beforehand by
+ * afqmc_init_walkers. */
+#define AFQMC_NOALLOC_MAX_MEASUREMENTS 1024
+afqmc_status afqmc_pair_step_noalloc(afqmc_sys a, afqmc_sys b, uint64_t seed, int n_steps,
+                                     const double* fields, double* e_trace);
+
 /* Many correlated pairs of uneven size advanced together (the pairs of
  * Sec. II.B, batched).  Pair p (systems a[p], b[p]) runs exactly what
  * afqmc_pair_step(a[p], b[p], seeds[p], n_steps, NULL, ...) runs, bit for

@@ -33,7 +33,7 @@ EXPORTS = [
     "afqmc_sys_info", "afqmc_checkpoint", "afqmc_restore", "afqmc_free_sys", "afqmc_free_ham",
     "afqmc_last_error", "afqmc_selftest_gemm", "afqmc_selftest_fields", "afqmc_profile_enable",
     "afqmc_profile_read", "afqmc_phase_name", "afqmc_selftest_propagate", "afqmc_autotune",
-    "afqmc_adjoint_forward", "afqmc_adjoint_backward",
+    "afqmc_adjoint_forward", "afqmc_adjoint_backward", "afqmc_pair_step_noalloc",
     "afqmc_population_control", "afqmc_init_from_primary",
 ]
 
@@ -55,6 +55,7 @@ _lib.afqmc_orthonormalize.argtypes = [_vp]
 _lib.afqmc_population_control.argtypes = [_vp, C.c_double]
 _lib.afqmc_init_from_primary.argtypes = [_vp, _vp]
 _lib.afqmc_pair_step.argtypes = [_vp, _vp, C.c_uint64, C.c_int, _vp, _dp]
+_lib.afqmc_pair_step_noalloc.argtypes = [_vp, _vp, C.c_uint64, C.c_int, _vp, _dp]
 _lib.afqmc_pair_batch_step.argtypes = [C.c_int, C.POINTER(_vp), C.POINTER(_vp),
                                        C.POINTER(C.c_uint64), C.c_int, C.c_int, C.c_int, _dp]
 _lib.afqmc_autotune.argtypes = [_vp, C.POINTER(C.c_int)]
@@ -278,6 +279,23 @@ def pair_step(a: System, b: System, n_steps: int, seed: int = 0, fields=None) ->
     tr = np.zeros((max(n_meas, 1), 3))
     _check(_lib.afqmc_pair_step(a._s, b._s, int(seed), int(n_steps), _dev_ptr(fields), _ptr(tr)))
     return tr[:n_meas]
+
+
+def pair_step_noalloc(a: System, b: System, n_steps: int, seed: int = 0,
+                      fields=None) -> np.ndarray:
+    """pair_step through the entry point that allocates no device memory
+    during the call (its trace staging is a fixed array in the library, at
+    most NOALLOC_MAX_MEASUREMENTS measurements per call)."""
+    me = a.params.measure_every
+    t0 = a.info()["step"]
+    n_meas = sum(1 for i in range(n_steps) if me > 0 and (t0 + i + 1) % me == 0)
+    tr = np.zeros((max(n_meas, 1), 3))
+    _check(_lib.afqmc_pair_step_noalloc(a._s, b._s, int(seed), int(n_steps), _dev_ptr(fields),
+                                        _ptr(tr)))
+    return tr[:n_meas]
+
+
+NOALLOC_MAX_MEASUREMENTS = 1024
 
 
 def pair_batch_step(pairs, seeds, n_steps: int, lanes: int = 0, graph: bool = True) -> np.ndarray:
