@@ -81,6 +81,13 @@ typedef struct {
     int measure_every;    /* mixed-energy period in steps (0: off)          */
     afqmc_prec contract_prec;
     afqmc_mode mode;
+    /* Optional force-bias cap, one of the bounding conditions Sec. II.D
+     * cites without stating.  fb_cap > 0: every step counts the (live
+     * walker, gamma) with |xbar_gamma| > fb_cap (afqmc_cap_events); with
+     * caps_enabled those xbar_gamma are also scaled to modulus fb_cap, phase
+     * kept.  fb_cap = 0 (the default): no cap, nothing counted. */
+    double fb_cap;
+    int caps_enabled;
 } afqmc_params;
 
 /* Load H of Eq. 1: h1 (M x M, symmetric), chol (n_chol x M x M, each
@@ -140,6 +147,11 @@ afqmc_status afqmc_orthonormalize(afqmc_sys sys);
  * dt/ortho_every/measure_every; E_STATE when their step counters differ. */
 afqmc_status afqmc_pair_step(afqmc_sys a, afqmc_sys b, uint64_t seed, int n_steps,
                              const double* fields, double* e_trace);
+
+/* Number of (live walker, step, gamma) whose force bias exceeded fb_cap
+ * since the system was created (counted whether or not the cap is applied;
+ * always 0 with fb_cap = 0).  Synchronises. */
+afqmc_status afqmc_cap_events(afqmc_sys sys, int64_t* count);
 
 /* Population control by the comb (Sec. II.B: walkers with large weights are
  * replicated, small ones stochastically removed), for the equilibration of a
@@ -217,7 +229,8 @@ afqmc_status afqmc_pair_batch_step(int n_pairs, const afqmc_sys* a, const afqmc_
  * local energy; the fields are held fixed (pathwise derivative).
  * afqmc_adjoint_backward recomputes the window one segment at a time from
  * the snapshots and returns dE/dlambda; the system is left in the state after
- * the window.  V: host M x M symmetric, row-major, copied.  prec: AFQMC_FP64
+ * the window.  Systems with an applied force-bias cap are refused (E_STATE):
+ * the reverse pass differentiates the uncapped step.  V: host M x M symmetric, row-major, copied.  prec: AFQMC_FP64
  * or AFQMC_FP32 products in the adjoint's contractions (FP64 storage and
  * small dense algebra).  Errors: E_STATE (free mode; backward without a
  * forward), E_SHAPE (a spin block above 48 orbitals), E_INVALID.

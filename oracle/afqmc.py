@@ -64,7 +64,8 @@ class System:
     """Per-system quantities fixed for a run (the precompute of the step)."""
 
     def __init__(self, h, chol, e_core, trial, n_alpha, n_beta, dt, taylor_order=6,
-                 h_pert: Optional[np.ndarray] = None, lam: float = 0.0):
+                 h_pert: Optional[np.ndarray] = None, lam: float = 0.0, fb_cap: float = 0.0,
+                 cap_apply: bool = False, expansion=None):
         h = np.asarray(h, dtype=np.float64)
         if h_pert is not None:
             h = h + lam * np.asarray(h_pert, dtype=np.float64)
@@ -78,31 +79,64 @@ class System:
         self.n_chol = self.chol.shape[0]
         self.dt = float(dt)
         self.K = int(taylor_order)
+        # optional force-bias cap (a bounding condition the paper cites in
+        # Sec. II.D without stating it): |xbar_g| > fb_cap is counted and,
+        # with cap_apply, scaled to modulus fb_cap keeping its phase
+        self.fb_cap = float(fb_cap)
+        self.cap_apply = bool(cap_apply)
         assert self.trial.shape == (self.M, self.N)
         # spin blocks: (offset, count)
         self.spins = [(0, self.na), (self.na, self.nb)]
-        # Trial density G_T^s = Phi_T (Phi_T^T Phi_T)^{-1} Phi_T^T and
-        # a_g = sum_s Tr(L_g G_T^s): <v_g> = i a_g (Eq. 2, Eq. 9).
-        self.a = np.zeros(self.n_chol)
-        for off, n in self.spins:
-            if n == 0:
-                continue
-            t = self.trial[:, off:off + n]
-            g_t = t @ np.linalg.solve(t.T @ t, t.T)
-            self.a += self.chol.reshape(self.n_chol, self.M * self.M) @ g_t.T.reshape(-1)
+        # Multi-determinant trial (Sec. II.D, the CASSCF trial): expansion =
+        # (coefficients c_i, determinants D_i of shape (M, N)); the trial is
+        # sum_i c_i |D_i>.  Without it the trial is the one determinant `trial`.
+        if expansion is not None:
+            coeffs, dets = expansion
+            self.coeffs = np.asarray(coeffs, dtype=np.float64)
+            self.dets = np.asarray(dets, dtype=np.float64)
+            assert self.dets.shape == (len(self.coeffs), self.M, self.N)
+            self.trial = self.dets[0]
+        else:
+            self.coeffs = np.ones(1)
+            self.dets = self.trial[None]
+        self.n_det = len(self.coeffs)
+        # Half-rotated tensors of every determinant: L^half_{g s} = D^{sT} L_g,
+        # h^half_s = D^{sT} h.
+        self.lhalf_d, self.hhalf_d = [], []
+        for d in self.dets:
+            lh, hh = [], []
+            for off, n in self.spins:
+                t = d[:, off:off + n]
+                lh.append(np.matmul(t.T[None], self.chol))
+                hh.append(t.T @ h)
+            self.lhalf_d.append(lh)
+            self.hhalf_d.append(hh)
+        if self.n_det == 1:
+            # Trial density G_T^s = Phi_T (Phi_T^T Phi_T)^{-1} Phi_T^T and
+            # a_g = sum_s Tr(L_g G_T^s): <v_g> = i a_g (Eq. 2, Eq. 9).
+            self.a = np.zeros(self.n_chol)
+            for off, n in self.spins:
+                if n == 0:
+                    continue
+                t = self.trial[:, off:off + n]
+                g_t = t @ np.linalg.solve(t.T @ t, t.T)
+                self.a += self.chol.reshape(self.n_chol, self.M * self.M) @ g_t.T.reshape(-1)
+        else:
+            # a_g = <phi_T|rho_g|phi_T>/<phi_T|phi_T> = sum_j c_j <phi_T|D_j> f_g(D_j)
+            # / sum_j c_j <phi_T|D_j>, with f_g(D_j) = <phi_T|rho_g|D_j>/<phi_T|D_j>
+            # the mixed estimate at the determinant D_j.
+            lnov_d, theta_d = overlap(self, self.dets.astype(np.complex128))
+            fd = force_bias_f(self, theta_d)
+            wgt = self.coeffs * np.exp(lnov_d - np.max(lnov_d.real))
+            self.a = (np.sum(wgt[:, None] * fd, axis=0) / np.sum(wgt)).real
         # One-body part after mean-field subtraction (Eq. 2).
         M_, G_ = self.M, self.n_chol
         l2 = (np.swapaxes(self.chol, 0, 1).reshape(M_, G_ * M_) @ self.chol.reshape(G_ * M_, M_)
               if G_ else np.zeros((M_, M_)))
         self.htilde = h - 0.5 * l2 + np.einsum("g,gij->ij", self.a, self.chol)
         self.P = scipy.linalg.expm(-0.5 * self.dt * self.htilde)
-        # Half-rotated tensors: L^half_{g s} = Phi_T^{sT} L_g, h^half_s = Phi_T^{sT} h.
-        self.lhalf = []
-        self.hhalf = []
-        for off, n in self.spins:
-            t = self.trial[:, off:off + n]
-            self.lhalf.append(np.matmul(t.T[None], self.chol))
-            self.hhalf.append(t.T @ h)
+        self.lhalf = self.lhalf_d[0]
+        self.hhalf = self.hhalf_d[0]
 
 
 @dataclass
@@ -114,15 +148,72 @@ class Walkers:
     alive: np.ndarray     # (nw,) bool
     t: int = 0            # absolute step counter (feeds the field generator)
     e_shift: float = 0.0  # constant energy shift of the weight factor
+    cap_events: int = 0   # (live walker, step, gamma) with |xbar| above the cap
 
     def copy(self) -> "Walkers":
         return Walkers(self.phi.copy(), self.weight.copy(), self.lnov.copy(),
-                       self.theta.copy(), self.alive.copy(), self.t, self.e_shift)
+                       self.theta.copy(), self.alive.copy(), self.t, self.e_shift,
+                       self.cap_events)
+
+
+class MsdTheta:
+    """Per-walker data of a multi-determinant trial: th[k, i] = Theta of walker
+    k against determinant D_i (Phi^s (D_i^{sT} Phi^s)^{-1} per spin block) and
+    ld[k, i] = ln <D_i|phi_k> (without c_i)."""
+
+    def __init__(self, th: np.ndarray, ld: np.ndarray):
+        self.th, self.ld = th, ld
+
+    def __getitem__(self, idx) -> "MsdTheta":
+        return MsdTheta(self.th[idx], self.ld[idx])
+
+    def __setitem__(self, idx, other: "MsdTheta"):
+        self.th[idx] = other.th
+        self.ld[idx] = other.ld
+
+    def copy(self) -> "MsdTheta":
+        return MsdTheta(self.th.copy(), self.ld.copy())
+
+
+def _det_overlap(trial: np.ndarray, spins, phi: np.ndarray):
+    """ln det(D^{sT} Phi^s) summed over spins, and Theta against one
+    determinant D."""
+    nw = phi.shape[0]
+    lndet = np.zeros(nw, dtype=np.complex128)
+    theta = np.zeros_like(phi)
+    for off, n in spins:
+        if n == 0:
+            continue
+        t = trial[:, off:off + n]
+        ps = phi[:, :, off:off + n]
+        o = np.matmul(t.T[None], ps)
+        sign, logabs = np.linalg.slogdet(o)
+        lndet += logabs + 1j * np.angle(sign)
+        theta[:, :, off:off + n] = np.swapaxes(
+            np.linalg.solve(np.swapaxes(o, 1, 2), np.swapaxes(ps, 1, 2)), 1, 2)
+    return lndet, theta
+
+
+def det_weights(sys: System, ld: np.ndarray):
+    """ln <phi_T|phi> = ln sum_i c_i <D_i|phi> and r_i = c_i <D_i|phi> / <phi_T|phi>
+    from the per-determinant log overlaps ld (nw, n_det)."""
+    top = np.max(ld.real, axis=1, keepdims=True)
+    terms = sys.coeffs[None, :] * np.exp(ld - top)
+    tot = np.sum(terms, axis=1)
+    return np.log(tot) + top[:, 0], terms / tot[:, None]
 
 
 def overlap(sys: System, phi: np.ndarray):
     """ln <phi_T|phi> = sum_s ln det(Phi_T^{sT} Phi^s) by LU with partial
-    pivoting, and Theta^s = Phi^s (Phi_T^{sT} Phi^s)^{-1}."""
+    pivoting, and Theta^s = Phi^s (Phi_T^{sT} Phi^s)^{-1}.  With a
+    multi-determinant trial: ln sum_i c_i <D_i|phi> and an MsdTheta."""
+    if sys.n_det > 1:
+        nw = phi.shape[0]
+        th = np.zeros((nw, sys.n_det) + phi.shape[1:], dtype=np.complex128)
+        ld = np.zeros((nw, sys.n_det), dtype=np.complex128)
+        for i, d in enumerate(sys.dets):
+            ld[:, i], th[:, i] = _det_overlap(d, sys.spins, phi)
+        return det_weights(sys, ld)[0], MsdTheta(th, ld)
     nw = phi.shape[0]
     lndet = np.zeros(nw, dtype=np.complex128)
     theta = np.zeros_like(phi)
@@ -152,21 +243,39 @@ def init_walkers(sys: System, nw: int, init_phi: Optional[np.ndarray] = None,
     return Walkers(phi, w, lnov, theta, np.ones(nw, dtype=bool), 0, e_t - c0)
 
 
-def force_bias_f(sys: System, theta: np.ndarray) -> np.ndarray:
-    """f_g = sum_s Tr(L^half_{g s} Theta^s) = <phi_T|rho_g|phi>/<phi_T|phi>."""
+def force_bias_f(sys: System, theta) -> np.ndarray:
+    """f_g = sum_s Tr(L^half_{g s} Theta^s) = <phi_T|rho_g|phi>/<phi_T|phi>;
+    with a multi-determinant trial sum_i r_i f_g^{(i)}, r_i = c_i <D_i|phi> /
+    <phi_T|phi>."""
+    if isinstance(theta, MsdTheta):
+        r = det_weights(sys, theta.ld)[1]
+        return sum(r[:, i, None] * _det_force_bias(sys.spins, sys.lhalf_d[i], theta.th[:, i],
+                                                     sys.n_chol, sys.M)
+                   for i in range(sys.n_det))
+    return _det_force_bias(sys.spins, sys.lhalf, theta, sys.n_chol, sys.M)
+
+
+def _det_force_bias(spins, lhalf, theta, n_chol, M) -> np.ndarray:
     nw = theta.shape[0]
-    f = np.zeros((nw, sys.n_chol), dtype=np.complex128)
-    for (off, n), lh in zip(sys.spins, sys.lhalf):
+    f = np.zeros((nw, n_chol), dtype=np.complex128)
+    for (off, n), lh in zip(spins, lhalf):
         if n == 0:
             continue
         th = np.swapaxes(theta[:, :, off:off + n], 1, 2).reshape(nw, -1)   # (nw, n*M) as (i, m)
-        f += th @ lh.reshape(sys.n_chol, n * sys.M).T
+        f += th @ lh.reshape(n_chol, n * M).T
     return f
 
 
 def xbar_of(sys: System, f: np.ndarray) -> np.ndarray:
     """Optimal force bias, Eq. 9: xbar = -sqrt(dt) (i f - i a)."""
     return -np.sqrt(sys.dt) * (1j * f - 1j * sys.a[None, :])
+
+
+def cap_xbar(xbar: np.ndarray, cap: float) -> np.ndarray:
+    """Entries with |xbar| > cap scaled to modulus cap, phase kept."""
+    mag = np.abs(xbar)
+    over = mag > cap
+    return np.where(over, xbar * (cap / np.where(over, mag, 1.0)), xbar)
 
 
 def propagate(sys: System, phi: np.ndarray, lnov: np.ndarray, theta: np.ndarray,
@@ -182,6 +291,8 @@ def propagate(sys: System, phi: np.ndarray, lnov: np.ndarray, theta: np.ndarray,
         xbar = np.zeros((nw, sys.n_chol), dtype=np.complex128)
     else:
         xbar = xbar_of(sys, force_bias_f(sys, theta))
+        if sys.fb_cap > 0.0 and sys.cap_apply:
+            xbar = cap_xbar(xbar, sys.fb_cap)
     c = x - xbar
     A = (1j * sq * (c @ sys.chol.reshape(sys.n_chol, sys.M * sys.M))).reshape(nw, sys.M, sys.M)
     s = -1j * sq * (c @ sys.a)
@@ -201,6 +312,9 @@ def propagate(sys: System, phi: np.ndarray, lnov: np.ndarray, theta: np.ndarray,
 def step(sys: System, wk: Walkers, x: np.ndarray, mode: str = PHASELESS) -> Walkers:
     """Advance all live walkers one time step with fields x (nw, n_chol)."""
     live = wk.alive
+    if sys.fb_cap > 0.0 and mode != FREE:
+        raw = xbar_of(sys, force_bias_f(sys, wk.theta))
+        wk.cap_events += int(np.sum((np.abs(raw) > sys.fb_cap) & live[:, None]))
     new_phi, new_lnov, new_theta, lnR, lnI, _ = propagate(sys, wk.phi, wk.lnov, wk.theta, x, mode)
     shift = sys.dt * wk.e_shift
     if mode == PHASELESS:
@@ -248,13 +362,24 @@ def orthonormalize(sys: System, wk: Walkers) -> Walkers:
     return wk
 
 
-def local_energy(sys: System, theta: np.ndarray, chunk: int = 8) -> np.ndarray:
-    """Mixed local energy E_L = <phi_T|H|phi>/<phi_T|phi> (Eq. 7), complex."""
+def local_energy(sys: System, theta, chunk: int = 8) -> np.ndarray:
+    """Mixed local energy E_L = <phi_T|H|phi>/<phi_T|phi> (Eq. 7), complex;
+    with a multi-determinant trial sum_i r_i E_L^{(i)}, E_L^{(i)} the energy
+    against D_i."""
+    if isinstance(theta, MsdTheta):
+        r = det_weights(sys, theta.ld)[1]
+        return sum(r[:, i] * _det_local_energy(sys, sys.lhalf_d[i], sys.hhalf_d[i],
+                                               theta.th[:, i], chunk)
+                   for i in range(sys.n_det))
+    return _det_local_energy(sys, sys.lhalf, sys.hhalf, theta, chunk)
+
+
+def _det_local_energy(sys: System, lhalf, hhalf, theta: np.ndarray, chunk: int) -> np.ndarray:
     nw = theta.shape[0]
-    f = force_bias_f(sys, theta)
+    f = _det_force_bias(sys.spins, lhalf, theta, sys.n_chol, sys.M)
     e1 = np.zeros(nw, dtype=np.complex128)
     exch = np.zeros(nw, dtype=np.complex128)
-    for (off, n), lh, hh in zip(sys.spins, sys.lhalf, sys.hhalf):
+    for (off, n), lh, hh in zip(sys.spins, lhalf, hhalf):
         if n == 0:
             continue
         th = theta[:, :, off:off + n]

@@ -34,13 +34,14 @@ EXPORTS = [
     "afqmc_last_error", "afqmc_selftest_gemm", "afqmc_selftest_fields", "afqmc_profile_enable",
     "afqmc_profile_read", "afqmc_phase_name", "afqmc_selftest_propagate", "afqmc_autotune",
     "afqmc_adjoint_forward", "afqmc_adjoint_backward", "afqmc_pair_step_noalloc",
-    "afqmc_population_control", "afqmc_init_from_primary",
+    "afqmc_population_control", "afqmc_init_from_primary", "afqmc_cap_events",
 ]
 
 
 class Params(C.Structure):
     _fields_ = [("dt", C.c_double), ("taylor_order", C.c_int), ("ortho_every", C.c_int),
-                ("measure_every", C.c_int), ("contract_prec", C.c_int), ("mode", C.c_int)]
+                ("measure_every", C.c_int), ("contract_prec", C.c_int), ("mode", C.c_int),
+                ("fb_cap", C.c_double), ("caps_enabled", C.c_int)]
 
 
 _dp = C.POINTER(C.c_double)
@@ -53,6 +54,7 @@ _lib.afqmc_step.argtypes = [_vp, C.c_uint64, C.c_uint64, C.c_int, _vp]
 _lib.afqmc_local_energy.argtypes = [_vp, _dp, _dp, _dp]
 _lib.afqmc_orthonormalize.argtypes = [_vp]
 _lib.afqmc_population_control.argtypes = [_vp, C.c_double]
+_lib.afqmc_cap_events.argtypes = [_vp, C.POINTER(C.c_int64)]
 _lib.afqmc_init_from_primary.argtypes = [_vp, _vp]
 _lib.afqmc_pair_step.argtypes = [_vp, _vp, C.c_uint64, C.c_int, _vp, _dp]
 _lib.afqmc_pair_step_noalloc.argtypes = [_vp, _vp, C.c_uint64, C.c_int, _vp, _dp]
@@ -154,7 +156,8 @@ class System:
 
     def __init__(self, ham: Hamiltonian, n_alpha: int, n_beta: int, trial, n_walkers: int,
                  dt: float, taylor_order: int = 6, ortho_every: int = 10, measure_every: int = 20,
-                 precision: str = "fp64", mode: str = "phaseless", init_phi=None):
+                 precision: str = "fp64", mode: str = "phaseless", init_phi=None,
+                 fb_cap: float = 0.0, caps_enabled: bool = False):
         self.ham = ham
         self.M, self.n_chol = ham.M, ham.n_chol
         self.na, self.nb = int(n_alpha), int(n_beta)
@@ -165,7 +168,7 @@ class System:
         assert trial.shape == (self.M, self.N)
         init = None if init_phi is None else _f64(init_phi)
         self.params = Params(float(dt), int(taylor_order), int(ortho_every), int(measure_every),
-                             PREC[precision], MODE[mode])
+                             PREC[precision], MODE[mode], float(fb_cap), int(bool(caps_enabled)))
         out = _vp()
         _check(_lib.afqmc_init_walkers(ham._h, self.na, self.nb, _ptr(trial), _ptr(init), self.nw,
                                        C.byref(self.params), C.byref(out)))
@@ -177,6 +180,12 @@ class System:
 
     def orthonormalize(self):
         _check(_lib.afqmc_orthonormalize(self._s))
+
+    def cap_events(self) -> int:
+        """(live walker, step, gamma) events with |xbar| above fb_cap so far."""
+        n = C.c_int64()
+        _check(_lib.afqmc_cap_events(self._s, C.byref(n)))
+        return n.value
 
     def population_control(self, xi: float):
         """Comb of the walker population with the uniform number xi in [0, 1)."""

@@ -159,6 +159,9 @@ afqmc_status one_step(afqmc_sys s, uint64_t seed, uint64_t stream_id, const doub
     f.n_chol = s->n_chol;
     f.sqdt = sqrt(s->par.dt);
     f.free_proj = s->par.mode == AFQMC_FREE;
+    f.fb_cap = s->par.mode == AFQMC_FREE ? 0.0 : s->par.fb_cap;
+    f.cap_apply = s->par.caps_enabled;
+    f.cap_count = s->d_capcount.as<int64_t>();
     {
         PhaseTimer pt(s, PH_FIELDS, st);
         HIPCHK(fields(f, st));
@@ -406,6 +409,7 @@ afqmc_status afqmc_init_walkers(afqmc_ham ham, int n_alpha, int n_beta, const do
     if (n_walkers <= 0) return fail(AFQMC_E_INVALID, "n_walkers must be > 0");
     if (!(par->dt > 0.0) || par->taylor_order < 1 || par->ortho_every < 0 || par->measure_every < 0)
         return fail(AFQMC_E_INVALID, "bad params (dt > 0, taylor_order >= 1, periods >= 0)");
+    if (!(par->fb_cap >= 0.0)) return fail(AFQMC_E_INVALID, "fb_cap must be >= 0");
     static bool unpack_ready = false;  // kernel attribute, set once outside any capture
     if (!unpack_ready) {
         if (unpack_prepare() != hipSuccess) return fail(AFQMC_E_DEVICE, "unpack kernel attribute");
@@ -483,6 +487,7 @@ afqmc_status afqmc_init_walkers(afqmc_ham ham, int n_alpha, int n_beta, const do
         {&s->d_el, (size_t)nw * 2 * 8},
         {&s->d_sums, 8 * 8},
         {&s->d_pc, (size_t)nw * 12 + 16},
+        {&s->d_capcount, (size_t)nw * 8},
     };
     for (auto& a : allocs) {
         hipError_t e = a.b->alloc(a.bytes);
@@ -490,7 +495,8 @@ afqmc_status afqmc_init_walkers(afqmc_ham ham, int n_alpha, int n_beta, const do
             return bail(fail(AFQMC_E_NOMEM, std::string("hipMalloc: ") + hipGetErrorString(e)));
     }
     // zero buffers read before first written (theta padding, F one-body row)
-    for (DevBuf* b : {&s->d_theta, &s->d_theta_lp, &s->d_lhx, &s->d_exch, &s->d_simp}) {
+    for (DevBuf* b : {&s->d_theta, &s->d_theta_lp, &s->d_lhx, &s->d_exch, &s->d_simp,
+                      &s->d_capcount}) {
         hipError_t e = hipMemsetAsync(b->p, 0, b->n, st);
         if (e != hipSuccess) return bail(fail(AFQMC_E_DEVICE, hipGetErrorString(e)));
     }
@@ -700,7 +706,7 @@ void afqmc_free_sys(afqmc_sys s) {
                       &s->d_phi, &s->d_phinew, &s->d_theta, &s->d_theta_lp, &s->d_w, &s->d_lnov,
                       &s->d_alive, &s->d_F, &s->d_X, &s->d_simp, &s->d_Apk, &s->d_Af,
                       &s->d_lnd, &s->d_ovl, &s->d_kws, &s->d_exch, &s->d_el, &s->d_sums,
-                      &s->d_pc})
+                      &s->d_pc, &s->d_capcount})
         b->release();
     drop_batch_plans(s->id);
     free_adjoint(s);
@@ -759,6 +765,19 @@ afqmc_status afqmc_pair_step(afqmc_sys a, afqmc_sys b, uint64_t seed, int n_step
     DevBuf trace;
     HIPCHK(trace.alloc((size_t)std::max(1, n_meas) * 3 * 8));
     return pair_run(a, b, seed, n_steps, fields_dev, e_trace, trace.as<double>(), n_meas);
+}
+
+afqmc_status afqmc_cap_events(afqmc_sys s, int64_t* count) {
+    afqmc_status r = check_sys(s);
+    if (r != AFQMC_OK) return r;
+    if (!count) return fail(AFQMC_E_INVALID, "count is null");
+    std::vector<int64_t> c((size_t)s->nw);
+    HIPCHK(hipStreamSynchronize(s->ham->stream));
+    HIPCHK(hipMemcpy(c.data(), s->d_capcount.p, c.size() * 8, hipMemcpyDeviceToHost));
+    int64_t n = 0;
+    for (int64_t v : c) n += v;
+    *count = n;
+    return AFQMC_OK;
 }
 
 afqmc_status afqmc_population_control(afqmc_sys s, double xi) {

@@ -160,6 +160,7 @@ struct afqmc_sys_s {
     afq::host::DevBuf d_ovl;  // overlap matrices of the determinant kernels
     afq::host::DevBuf d_kws;  // split-K partial sums of the force-bias GEMM
     afq::host::DevBuf d_pc;   // comb workspace: running sums, selection, status
+    afq::host::DevBuf d_capcount;  // force-bias cap events per walker (int64)
     int n_gt_a = 0, n_gt_b = 0, n_gt = 0;
     // launch shapes (autotuned; 0 = size heuristic): GEMM tiles of the force
     // bias and the field sum, and the propagation workgroup shape

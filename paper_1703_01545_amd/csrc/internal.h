@@ -141,6 +141,13 @@ struct FieldArgs {
     int nw, n_chol;
     double sqdt;
     int free_proj;        // 1: xbar = 0 (free projection)
+    // optional force-bias cap: with fb_cap > 0 every live walker's xbar_g
+    // with |xbar_g| > fb_cap adds one to cap_count[w] (one entry per walker,
+    // owned by its wavefront), and with cap_apply it is scaled to modulus
+    // fb_cap (same phase)
+    double fb_cap;
+    int cap_apply;
+    int64_t* cap_count;
 };
 hipError_t fields(const FieldArgs& f, hipStream_t s);
 

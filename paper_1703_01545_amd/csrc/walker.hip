@@ -84,6 +84,7 @@ __global__ __launch_bounds__(256) void k_fields(FieldArgs f) {
     const double* Fi = Fr + f.ldf;
     const long xr = (long)w * 2 * f.ldx, xi = xr + f.ldx;
     double cia = 0.0, cra = 0.0, ir = 0.0, ii = 0.0;
+    int capped = 0;
     const double sq = f.sqdt;
     const int64_t tstep = f.t_dev ? *f.t_dev + f.t : f.t;
     for (int b = lane; 4 * b < f.n_chol; b += 64) {
@@ -102,8 +103,19 @@ __global__ __launch_bounds__(256) void k_fields(FieldArgs f) {
             const int g = 4 * b + e;
             if (g >= f.n_chol) break;
             const double x = z[e];
-            const double xbr = f.free_proj ? 0.0 : sq * Fi[g];
-            const double xbi = f.free_proj ? 0.0 : -sq * (Fr[g] - f.a[g]);
+            double xbr = f.free_proj ? 0.0 : sq * Fi[g];
+            double xbi = f.free_proj ? 0.0 : -sq * (Fr[g] - f.a[g]);
+            if (f.fb_cap > 0.0) {
+                const double mag = sqrt(xbr * xbr + xbi * xbi);
+                if (mag > f.fb_cap) {
+                    capped += 1;
+                    if (f.cap_apply) {
+                        const double sc = f.fb_cap / mag;
+                        xbr = xbr * sc;
+                        xbi = xbi * sc;
+                    }
+                }
+            }
             const double cr = x - xbr, ci = -xbi;
             put_dt(f.X, f.tx, xr + g, live ? -sq * ci : 0.0);
             put_dt(f.X, f.tx, xi + g, live ? sq * cr : 0.0);
@@ -117,6 +129,11 @@ __global__ __launch_bounds__(256) void k_fields(FieldArgs f) {
     cra = wave_sum(cra);
     ir = wave_sum(ir);
     ii = wave_sum(ii);
+    if (f.fb_cap > 0.0) {
+#pragma unroll
+        for (int o = 32; o >= 1; o >>= 1) capped += __shfl_xor(capped, o, 64);
+        if (lane == 0 && live && f.cap_count) f.cap_count[w] += capped;
+    }
     if (lane == 0) {
         double* o = f.s_imp + (long)w * 4;
         o[0] = sq * cia;

@@ -12,6 +12,7 @@ from .configs import (  # noqa: F401
     config,
     gaussian_fields,
     make_hamiltonian,
+    make_expansion,
     make_trial,
     pair_batch_configs,
     perturbation,

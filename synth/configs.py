@@ -73,6 +73,45 @@ def make_trial(h: np.ndarray, n_alpha: int, n_beta: int) -> np.ndarray:
     return np.ascontiguousarray(np.concatenate([vec[:, :n_alpha], vec[:, :n_beta]], axis=1))
 
 
+def make_expansion(h: np.ndarray, n_alpha: int, n_beta: int, n_det: int, seed: int = 0,
+                   n_act: int = 3, scale: float = 0.25):
+    """Synthetic multi-determinant trial in the form of a truncated CASSCF
+    expansion: the orbitals are the eigenvectors of h (signs as in
+    make_trial); determinant 0 occupies the lowest n_alpha / n_beta of them;
+    the others are distinct single and double excitations, per spin, from
+    the highest n_act occupied into the lowest n_act virtual orbitals, with
+    coefficients scale * N(0, 1) (determinant 0 has coefficient 1).  Returns
+    (coeffs (n_det,), dets (n_det, M, n_alpha + n_beta)), alpha columns first."""
+    M = h.shape[0]
+    vec = make_trial(h, M, 0)  # all eigenvectors, ascending, sign-fixed
+    rng = np.random.default_rng(seed)
+
+    def excite(n):
+        occ = list(range(n))
+        holes = occ[max(0, n - n_act):]
+        parts = list(range(n, min(M, n + n_act)))
+        k = int(rng.integers(1, 3)) if holes and parts else 0
+        k = min(k, len(holes), len(parts))
+        h_ = sorted(rng.choice(holes, size=k, replace=False).tolist()) if k else []
+        p_ = sorted(rng.choice(parts, size=k, replace=False).tolist()) if k else []
+        return tuple(sorted([o for o in occ if o not in h_] + p_))
+
+    seen = {(tuple(range(n_alpha)), tuple(range(n_beta)))}
+    occs = [next(iter(seen))]
+    tries = 0
+    while len(occs) < n_det and tries < 10000:
+        tries += 1
+        cand = (excite(n_alpha), excite(n_beta))
+        if cand not in seen:
+            seen.add(cand)
+            occs.append(cand)
+    if len(occs) < n_det:
+        raise ValueError("active space too small for the requested number of determinants")
+    coeffs = np.concatenate([[1.0], scale * rng.standard_normal(n_det - 1)])
+    dets = np.stack([np.concatenate([vec[:, list(a)], vec[:, list(b)]], axis=1) for a, b in occs])
+    return coeffs, np.ascontiguousarray(dets)
+
+
 def perturbation(M: int, seed: int = 3, scale: float = 0.1) -> np.ndarray:
     """Random symmetric one-body perturbation V with entries N(0,1)*scale."""
     rng = np.random.default_rng(seed)

@@ -313,3 +313,38 @@ def test_explicit_fields_drive_one_walker_across_the_phase_projection(lib):
     for k in range(nw):
         # a frozen walker keeps the determinant it had when it was frozen
         assert rel(got["phi"][k], wk.phi[k]) < TOL
+
+
+# ------------------------------------------------------------- force-bias cap
+
+def test_force_bias_cap_counts_and_applies_like_the_oracle(lib):
+    """fb_cap = 0.03 on the M = 12 pair (about a tenth of the |xbar| lie
+    above it): counting alone leaves every bit of the run unchanged and counts
+    what the oracle counts; the applied cap matches the oracle's capped run."""
+    c = config(0)
+    nw, n_steps, seed = 16, 30, 3
+    banner("force-bias cap vs oracle")
+    wl = Workload(c.M, c.n_chol, c.na_a, c.nb_a, c.na_b, c.nb_b, nw, c.dt)
+    H = lib.Hamiltonian(wl.ham.h, wl.ham.chol, wl.ham.e_core)
+    out = {}
+    for name, cap, apply in (("off", 0.0, False), ("count", 0.03, False), ("apply", 0.03, True)):
+        g = lib.System(H, c.na_a, c.nb_a, wl.trials[0], nw, c.dt, ortho_every=5,
+                       measure_every=0, fb_cap=cap, caps_enabled=apply)
+        g.step(n_steps, seed=seed)
+        out[name] = (g.walkers(), g.cap_events())
+        s = O.System(wl.ham.h, wl.ham.chol, wl.ham.e_core, wl.trials[0], c.na_a, c.nb_a, c.dt,
+                     fb_cap=cap, cap_apply=apply)
+        wk = O.init_walkers(s, nw)
+        f = O.PhiloxFields(seed, 0, c.n_chol)
+        for _ in range(n_steps):
+            O.step(s, wk, f(wk.t, nw))
+            if wk.t % 5 == 0:
+                O.orthonormalize(s, wk)
+        assert out[name][1] == wk.cap_events, (name, out[name][1], wk.cap_events)
+        got = out[name][0]
+        assert np.array_equal(got["alive"], wk.alive)
+        assert rel(got["weight"][wk.alive], wk.weight[wk.alive]) < TOL
+    assert out["count"][1] > 0 and out["off"][1] == 0
+    for k in ("phi", "weight", "lnov", "alive"):
+        assert np.array_equal(out["count"][0][k], out["off"][0][k]), k
+    assert not np.array_equal(out["apply"][0]["weight"], out["off"][0]["weight"])

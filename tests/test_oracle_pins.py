@@ -417,3 +417,39 @@ def test_oracle_rounding_floor_cfg0_shape():
     for k in ("EA", "EB"):
         a, b = np.array(out1[k]), np.array(out2[k])
         assert np.max(np.abs(a - b) / np.abs(a)) < 1e-12
+
+
+def test_force_bias_cap_definition():
+    """The optional force-bias cap (a bounding condition the paper cites
+    without stating; parity unpinned beyond this definition): a threshold above
+    every |xbar| changes nothing; an applied cap leaves every |xbar| at most
+    the cap with its phase unchanged and counts exactly the entries above it;
+    counting alone changes nothing."""
+    c_ham = make_hamiltonian(12, 36, seed=0)
+    trial = make_trial(c_ham.h, 3, 3)
+    f = O.PhiloxFields(3, 0, 36)
+    runs = {}
+    for name, cap, apply in (("off", 0.0, False), ("huge", 1e3, True), ("count", 0.03, False),
+                             ("apply", 0.03, True)):
+        s = O.System(c_ham.h, c_ham.chol, 0.0, trial, 3, 3, 0.01, fb_cap=cap, cap_apply=apply)
+        wk = O.init_walkers(s, 16)
+        raw_over = 0
+        for _ in range(20):
+            raw = O.xbar_of(s, O.force_bias_f(s, wk.theta))
+            raw_over += int(np.sum((np.abs(raw) > 0.03) & wk.alive[:, None]))
+            used = O.propagate(s, wk.phi, wk.lnov, wk.theta, f(wk.t, 16))[5]
+            if name == "apply":
+                assert np.all(np.abs(used) <= 0.03 * (1 + 1e-15))
+                big = np.abs(raw) > 0.03
+                assert np.allclose(np.angle(used[big]), np.angle(raw[big]), atol=1e-13)
+                assert np.array_equal(used[~big], raw[~big])
+            O.step(s, wk, f(wk.t, 16))
+        runs[name] = (wk, raw_over)
+    base = runs["off"][0]
+    assert runs["off"][0].cap_events == 0 and runs["huge"][0].cap_events == 0
+    for name in ("huge", "count"):
+        assert np.array_equal(runs[name][0].phi, base.phi)
+        assert np.array_equal(runs[name][0].weight, base.weight)
+    assert runs["count"][0].cap_events == runs["count"][1] > 0
+    assert runs["apply"][0].cap_events > 0
+    assert not np.array_equal(runs["apply"][0].weight, base.weight)
