@@ -111,6 +111,26 @@ afqmc_status afqmc_init_walkers(afqmc_ham ham, int n_alpha, int n_beta, const do
                                 const double* init_phi, int n_walkers, const afqmc_params* params,
                                 afqmc_sys* out);
 
+/* As afqmc_init_walkers with a multi-determinant trial (Sec. II.D, the
+ * CASSCF trial): phi_T = sum_i coeffs[i] D_i, dets: n_det determinants of
+ * shape M x (n_alpha + n_beta) (row-major, column j = orbital j, alpha
+ * first), coeffs: n_det real coefficients; walkers start from init_phi or
+ * from D_0.  The overlap <phi_T|phi> = sum_i c_i <D_i|phi>, the force bias
+ * and the mixed local energy are the r_i = c_i <D_i|phi> / <phi_T|phi>
+ * weighted sums of those against each D_i; the mean-field shift is
+ * a_g = <phi_T|rho_g|phi_T> / <phi_T|phi_T> of the whole expansion.  Cost
+ * and memory of the overlaps, force bias and energy grow linearly with
+ * n_det; the propagation is unchanged.  n_det = 1 is afqmc_init_walkers.
+ * Errors: as afqmc_init_walkers; E_INVALID (n_det outside 1..256, null
+ * coefficients); E_SINGULAR also when two determinants have exactly
+ * orthogonal spin blocks (the pair term of a_g is then not formed from
+ * their overlap) or the expansion has zero norm.  The reverse-mode adjoint
+ * refuses such systems (E_STATE). */
+afqmc_status afqmc_init_walkers_msd(afqmc_ham ham, int n_alpha, int n_beta, int n_det,
+                                    const double* coeffs, const double* dets,
+                                    const double* init_phi, int n_walkers,
+                                    const afqmc_params* params, afqmc_sys* out);
+
 /* Advance every live walker n_steps imaginary-time steps (force bias Eq. 8-9,
  * propagator Eq. 11 by Taylor series between one-body halves, overlap ratio
  * and phaseless hybrid weight, Sec. II.A/II.D; modified Gram-Schmidt every
@@ -229,8 +249,9 @@ afqmc_status afqmc_pair_batch_step(int n_pairs, const afqmc_sys* a, const afqmc_
  * local energy; the fields are held fixed (pathwise derivative).
  * afqmc_adjoint_backward recomputes the window one segment at a time from
  * the snapshots and returns dE/dlambda; the system is left in the state after
- * the window.  Systems with an applied force-bias cap are refused (E_STATE):
- * the reverse pass differentiates the uncapped step.  V: host M x M symmetric, row-major, copied.  prec: AFQMC_FP64
+ * the window.  Systems with an applied force-bias cap or a multi-determinant
+ * trial are refused (E_STATE): the reverse pass differentiates the uncapped
+ * single-determinant step.  V: host M x M symmetric, row-major, copied.  prec: AFQMC_FP64
  * or AFQMC_FP32 products in the adjoint's contractions (FP64 storage and
  * small dense algebra).  Errors: E_STATE (free mode; backward without a
  * forward), E_SHAPE (a spin block above 48 orbitals), E_INVALID.

@@ -35,6 +35,7 @@ EXPORTS = [
     "afqmc_profile_read", "afqmc_phase_name", "afqmc_selftest_propagate", "afqmc_autotune",
     "afqmc_adjoint_forward", "afqmc_adjoint_backward", "afqmc_pair_step_noalloc",
     "afqmc_population_control", "afqmc_init_from_primary", "afqmc_cap_events",
+    "afqmc_init_walkers_msd",
 ]
 
 
@@ -50,6 +51,8 @@ _lib.afqmc_last_error.restype = C.c_char_p
 _lib.afqmc_load_hamiltonian.argtypes = [C.c_int, C.c_int, _dp, _dp, C.c_double, _vp, C.POINTER(_vp)]
 _lib.afqmc_init_walkers.argtypes = [_vp, C.c_int, C.c_int, _dp, _dp, C.c_int, C.POINTER(Params),
                                     C.POINTER(_vp)]
+_lib.afqmc_init_walkers_msd.argtypes = [_vp, C.c_int, C.c_int, C.c_int, _dp, _dp, _dp, C.c_int,
+                                        C.POINTER(Params), C.POINTER(_vp)]
 _lib.afqmc_step.argtypes = [_vp, C.c_uint64, C.c_uint64, C.c_int, _vp]
 _lib.afqmc_local_energy.argtypes = [_vp, _dp, _dp, _dp]
 _lib.afqmc_orthonormalize.argtypes = [_vp]
@@ -157,21 +160,30 @@ class System:
     def __init__(self, ham: Hamiltonian, n_alpha: int, n_beta: int, trial, n_walkers: int,
                  dt: float, taylor_order: int = 6, ortho_every: int = 10, measure_every: int = 20,
                  precision: str = "fp64", mode: str = "phaseless", init_phi=None,
-                 fb_cap: float = 0.0, caps_enabled: bool = False):
+                 fb_cap: float = 0.0, caps_enabled: bool = False, expansion=None):
+        """expansion: optional (coefficients (n_det,), determinants (n_det, M, N))
+        of a multi-determinant trial; `trial` is then ignored."""
         self.ham = ham
         self.M, self.n_chol = ham.M, ham.n_chol
         self.na, self.nb = int(n_alpha), int(n_beta)
         self.N = self.na + self.nb
         self.nw = int(n_walkers)
         self.mode = mode
-        trial = _f64(trial)
+        trial = _f64(trial if expansion is None else expansion[1][0])
         assert trial.shape == (self.M, self.N)
         init = None if init_phi is None else _f64(init_phi)
         self.params = Params(float(dt), int(taylor_order), int(ortho_every), int(measure_every),
                              PREC[precision], MODE[mode], float(fb_cap), int(bool(caps_enabled)))
         out = _vp()
-        _check(_lib.afqmc_init_walkers(ham._h, self.na, self.nb, _ptr(trial), _ptr(init), self.nw,
-                                       C.byref(self.params), C.byref(out)))
+        if expansion is None:
+            _check(_lib.afqmc_init_walkers(ham._h, self.na, self.nb, _ptr(trial), _ptr(init),
+                                           self.nw, C.byref(self.params), C.byref(out)))
+        else:
+            coeffs, dets = _f64(expansion[0]), _f64(expansion[1])
+            assert dets.shape == (len(coeffs), self.M, self.N)
+            _check(_lib.afqmc_init_walkers_msd(ham._h, self.na, self.nb, len(coeffs), _ptr(coeffs),
+                                               _ptr(dets), _ptr(init), self.nw,
+                                               C.byref(self.params), C.byref(out)))
         self._s = out
 
     def step(self, n_steps: int = 1, seed: int = 0, stream_id: int = 0, fields=None):

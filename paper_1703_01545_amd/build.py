@@ -15,7 +15,7 @@ CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libafqmc.so")
 SOURCES = ["gemm.hip", "propagate.hip", "walker.hip", "capi.hip", "batch.hip", "adjoint.hip",
-           "population.hip", "noalloc.hip"]
+           "population.hip", "noalloc.hip", "msd.hip"]
 ARCH = os.environ.get("AFQMC_ARCH", "gfx950")
 
 FLAGS = [

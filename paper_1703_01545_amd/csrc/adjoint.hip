@@ -1124,6 +1124,7 @@ afqmc_status afqmc_adjoint_forward(afqmc_sys s, const double* V, uint64_t seed, 
     if (prec != AFQMC_FP64 && prec != AFQMC_FP32)
         return fail(AFQMC_E_INVALID, "adjoint precision is AFQMC_FP64 or AFQMC_FP32");
     if (s->par.mode != AFQMC_PHASELESS) return fail(AFQMC_E_STATE, "adjoint needs phaseless mode");
+    if (s->n_det > 1) return fail(AFQMC_E_STATE, "adjoint with a multi-determinant trial");
     if (s->par.fb_cap > 0.0 && s->par.caps_enabled)
         return fail(AFQMC_E_STATE, "adjoint of a step with an applied force-bias cap");
     if (std::max(s->na, s->nb) > kMaxSpin) return fail(AFQMC_E_SHAPE, "spin block above 48");

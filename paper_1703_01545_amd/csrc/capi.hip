@@ -76,16 +76,16 @@ int fb_ksplit(int m, int n, int k, int cus) {
     return best;
 }
 
-Gemm force_bias_gemm(afqmc_sys s) {
+Gemm force_bias_gemm(afqmc_sys s, int det) {
     // F[(w,p), g] = sum_(i,m) Theta[(w,p),(i,m)] L^half[g,(i,m)], g <= n_chol
     Gemm g{};
-    g.A = lp_or(s->d_theta_lp, s->d_theta, s->ts);
+    g.A = lp_or(det_theta_lp(s, det), det_theta(s, det), s->ts);
     g.ta = s->ts;
     g.ra = rows_strided(s->NM());
-    g.B = lp_or(s->d_lhx_lp, s->d_lhx, s->ts);
+    g.B = lp_or(det_lhx_lp(s, det), det_lhx(s, det), s->ts);
     g.tb = s->ts;
     g.rb = rows_strided(s->NM());
-    g.C = s->d_F.p;
+    g.C = det_F(s, det);
     g.tc = DT_F64;
     g.rc = rows_strided(s->n_chol + 1);
     g.alpha = 1.0;
@@ -101,18 +101,28 @@ Gemm force_bias_gemm(afqmc_sys s) {
 }
 
 afqmc_status force_bias(afqmc_sys s, hipStream_t st) {
-    const Gemm g = force_bias_gemm(s);
     PhaseTimer pt(s, PH_FORCE_BIAS, st);
-    HIPCHK(gemm(g, s->tc, st));
+    for (int i = 0; i < s->n_det; ++i) HIPCHK(gemm(force_bias_gemm(s, i), s->tc, st));
+    if (s->n_det > 1)
+        HIPCHK(msd_combine(s->d_F_all.as<double>(), (long)s->nw * 2 * (s->n_chol + 1),
+                           s->d_rw.as<double>(), s->n_det, s->d_alive.as<uint8_t>(), s->nw,
+                           s->n_chol + 1, s->d_F.as<double>(), st));
     return AFQMC_OK;
 }
 
 afqmc_status overlap_theta(afqmc_sys s, double* phi, hipStream_t st) {
-    // overlap, ln det and Theta in one launch per (walker, spin)
+    // overlap, ln det and Theta in one launch per (walker, spin), per
+    // determinant of the trial; then the expansion's combination
     PhaseTimer pt(s, PH_DET_THETA, st);
-    HIPCHK(lu_theta(phi, s->d_trialT.as<double>(), s->d_theta.as<double>(),
-                    s->ts == DT_F64 ? nullptr : s->d_theta_lp.p, s->ts, s->d_lnd.as<double>(),
-                    s->d_alive.as<uint8_t>(), s->nw, s->M, s->N, s->na, s->nb, s->d_ovl.p, st));
+    for (int i = 0; i < s->n_det; ++i)
+        HIPCHK(lu_theta(phi, det_trialT(s, i).as<double>(), det_theta(s, i).as<double>(),
+                        s->ts == DT_F64 ? nullptr : det_theta_lp(s, i).p, s->ts, det_lnd(s, i),
+                        s->d_alive.as<uint8_t>(), s->nw, s->M, s->N, s->na, s->nb, s->d_ovl.p,
+                        st));
+    if (s->n_det > 1)
+        HIPCHK(msd_overlap(s->d_lnd_all.as<double>(), s->d_coef.as<double>(), s->n_det,
+                           s->d_alive.as<uint8_t>(), s->nw, s->d_lnd.as<double>(),
+                           s->d_rw.as<double>(), st));
     return AFQMC_OK;
 }
 
@@ -211,18 +221,25 @@ afqmc_status ortho(afqmc_sys s, hipStream_t st) {
 afqmc_status measure(afqmc_sys s, hipStream_t st) {
     afqmc_status r = force_bias(s, st);
     if (r != AFQMC_OK) return r;
-    const void* lh = lp_or(s->d_lhx_lp, s->d_lhx, s->ts);
-    const void* th = lp_or(s->d_theta_lp, s->d_theta, s->ts);
-    for (int spin = 0; spin < 2; ++spin) {
-        const int off = spin ? s->na : 0, n = spin ? s->nb : s->na;
-        if (n == 0) continue;
-        PhaseTimer pt(s, PH_EXCHANGE, st);
-        HIPCHK(exchange(lh, th, s->d_exch.as<double>(), s->nw, s->M, s->N, s->n_chol, off, n, spin,
-                        s->n_gt, s->tc, st));
+    for (int i = 0; i < s->n_det; ++i) {
+        const void* lh = lp_or(det_lhx_lp(s, i), det_lhx(s, i), s->ts);
+        const void* th = lp_or(det_theta_lp(s, i), det_theta(s, i), s->ts);
+        for (int spin = 0; spin < 2; ++spin) {
+            const int off = spin ? s->na : 0, n = spin ? s->nb : s->na;
+            if (n == 0) continue;
+            PhaseTimer pt(s, PH_EXCHANGE, st);
+            HIPCHK(exchange(lh, th, det_exch(s, i).as<double>(), s->nw, s->M, s->N, s->n_chol,
+                            off, n, spin, s->n_gt, s->tc, st));
+        }
+        PhaseTimer pt(s, PH_ENERGY, st);
+        HIPCHK(local_energy(det_F(s, i), s->n_chol + 1, det_exch(s, i).as<double>(), s->n_gt_a,
+                            s->n_gt_b, s->nw, s->n_chol, s->ham->e_core, det_el(s, i), st));
     }
     PhaseTimer pt(s, PH_ENERGY, st);
-    HIPCHK(local_energy(s->d_F.as<double>(), s->n_chol + 1, s->d_exch.as<double>(), s->n_gt_a,
-                        s->n_gt_b, s->nw, s->n_chol, s->ham->e_core, s->d_el.as<double>(), st));
+    if (s->n_det > 1)
+        HIPCHK(msd_combine(s->d_el_all.as<double>(), (long)s->nw * 2, s->d_rw.as<double>(),
+                           s->n_det, s->d_alive.as<uint8_t>(), s->nw, 1, s->d_el.as<double>(),
+                           st));
     HIPCHK(mixed_sums(s->d_el.as<double>(), s->d_w.as<double>(), s->d_alive.as<uint8_t>(), s->nw,
                       (int)s->par.mode, s->d_sums.as<double>(), st));
     return AFQMC_OK;
@@ -350,6 +367,62 @@ bool theta_trial(const double* trial, int M, int N, int off, int n, double* out 
     return true;
 }
 
+// Theta_ij = D_j (D_i^T D_j)^{-1} of one spin block (rows: out[c][m]) and
+// ln |det(D_i^T D_j)| with its sign, by Gauss-Jordan with partial pivoting on
+// the host (determinants i, j: M x N row-major, columns off .. off + n - 1).
+// Returns false when a pivot is exactly zero.
+bool theta_pair(const double* Di, const double* Dj, int M, int N, int off, int n, double* out,
+                double* logabs, int* sign) {
+    std::vector<double> O((size_t)n * n), inv((size_t)n * n, 0.0);
+    for (int a = 0; a < n; ++a)
+        for (int b = 0; b < n; ++b) {
+            double v = 0.0;
+            for (int m = 0; m < M; ++m) v += Di[(size_t)m * N + off + a] * Dj[(size_t)m * N + off + b];
+            O[(size_t)a * n + b] = v;
+        }
+    for (int i = 0; i < n; ++i) inv[(size_t)i * n + i] = 1.0;
+    double la = 0.0;
+    int sg = 1;
+    for (int k = 0; k < n; ++k) {
+        int p = k;
+        for (int r = k + 1; r < n; ++r)
+            if (fabs(O[(size_t)r * n + k]) > fabs(O[(size_t)p * n + k])) p = r;
+        if (O[(size_t)p * n + k] == 0.0) return false;
+        if (p != k) {
+            sg = -sg;
+            for (int c = 0; c < n; ++c) {
+                std::swap(O[(size_t)k * n + c], O[(size_t)p * n + c]);
+                std::swap(inv[(size_t)k * n + c], inv[(size_t)p * n + c]);
+            }
+        }
+        const double d = O[(size_t)k * n + k];
+        la += log(fabs(d));
+        if (d < 0) sg = -sg;
+        for (int c = 0; c < n; ++c) {
+            O[(size_t)k * n + c] /= d;
+            inv[(size_t)k * n + c] /= d;
+        }
+        for (int r = 0; r < n; ++r) {
+            if (r == k) continue;
+            const double f = O[(size_t)r * n + k];
+            if (f == 0.0) continue;
+            for (int c = 0; c < n; ++c) {
+                O[(size_t)r * n + c] -= f * O[(size_t)k * n + c];
+                inv[(size_t)r * n + c] -= f * inv[(size_t)k * n + c];
+            }
+        }
+    }
+    for (int c = 0; c < n; ++c)
+        for (int m = 0; m < M; ++m) {
+            double v = 0.0;
+            for (int l = 0; l < n; ++l) v += Dj[(size_t)m * N + off + l] * inv[(size_t)l * n + c];
+            out[(size_t)c * M + m] = v;
+        }
+    *logabs = la;
+    *sign = sg;
+    return true;
+}
+
 // Phases of the step, each one kernel launch (the Taylor phase is one
 // launch per term).  Timed with HIP events on the system's stream when
 
@@ -394,13 +467,21 @@ void afqmc_free_ham(afqmc_ham h) {
     ham_unref(h);
 }
 
-afqmc_status afqmc_init_walkers(afqmc_ham ham, int n_alpha, int n_beta, const double* trial,
-                                const double* init_phi, int n_walkers, const afqmc_params* par,
-                                afqmc_sys* out) {
+}  // extern "C"
+
+namespace {
+
+// One system on `ham` with the trial sum_i coeffs[i] D_i (n_det determinants
+// of shape M x N in `dets`; one determinant: the single-determinant trial).
+afqmc_status init_system(afqmc_ham ham, int n_alpha, int n_beta, int n_det, const double* coeffs,
+                         const double* dets, const double* init_phi, int n_walkers,
+                         const afqmc_params* par, afqmc_sys* out) {
     if (!out) return fail(AFQMC_E_INVALID, "out is null");
     *out = nullptr;
     if (!ham || ham->released) return fail(AFQMC_E_INVALID, "null or freed Hamiltonian");
-    if (!trial || !par) return fail(AFQMC_E_INVALID, "null trial or params");
+    if (!dets || !par || (n_det > 1 && !coeffs)) return fail(AFQMC_E_INVALID, "null trial or params");
+    if (n_det < 1 || n_det > 256) return fail(AFQMC_E_INVALID, "n_det must lie in 1 .. 256");
+    const double* trial = dets;
     const int M = ham->M;
     if (n_alpha < 0 || n_beta < 0 || n_alpha > M || n_beta > M || n_alpha + n_beta == 0)
         return fail(AFQMC_E_SHAPE, "need 0 <= n_alpha, n_beta <= M and n_alpha + n_beta > 0");
@@ -494,22 +575,55 @@ afqmc_status afqmc_init_walkers(afqmc_ham ham, int n_alpha, int n_beta, const do
         if (e != hipSuccess)
             return bail(fail(AFQMC_E_NOMEM, std::string("hipMalloc: ") + hipGetErrorString(e)));
     }
+    s->n_det = n_det;
+    if (n_det > 1) {
+        std::vector<std::pair<DevBuf*, size_t>> more = {
+            {&s->d_coef, (size_t)n_det * 8},
+            {&s->d_lnd_all, (size_t)n_det * nw * 4 * 8},
+            {&s->d_F_all, (size_t)n_det * nw * 2 * (nc + 1) * 8},
+            {&s->d_el_all, (size_t)n_det * nw * 2 * 8},
+            {&s->d_rw, (size_t)n_det * nw * 2 * 8}};
+        for (int i = 1; i < n_det; ++i) {
+            s->xdet.push_back(std::make_unique<afqmc_sys_s::DetBufs>());
+            afqmc_sys_s::DetBufs& d = *s->xdet.back();
+            more.push_back({&d.trialT, (size_t)NM * 8});
+            more.push_back({&d.lhx, (size_t)(nc + 1) * NM * 8});
+            more.push_back({&d.lhx_lp, s->ts == DT_F64 ? 0 : (size_t)(nc + 1) * NM * dt_size(s->ts)});
+            more.push_back({&d.theta, (size_t)nw * 2 * NM * 8});
+            more.push_back({&d.theta_lp, s->ts == DT_F64 ? 0 : (size_t)nw * 2 * NM * dt_size(s->ts)});
+            more.push_back({&d.exch, (size_t)nw * 2 * s->n_gt * 2 * 8});
+        }
+        for (auto& m : more) {
+            hipError_t e = m.first->alloc(m.second);
+            if (e != hipSuccess)
+                return bail(fail(AFQMC_E_NOMEM, std::string("hipMalloc: ") + hipGetErrorString(e)));
+        }
+        for (auto& d : s->xdet)
+            for (DevBuf* b : {&d->theta, &d->theta_lp, &d->lhx, &d->exch}) {
+                hipError_t e = hipMemsetAsync(b->p, 0, b->n, st);
+                if (e != hipSuccess) return bail(fail(AFQMC_E_DEVICE, hipGetErrorString(e)));
+            }
+        if (hipMemcpy(s->d_coef.p, coeffs, (size_t)n_det * 8, hipMemcpyHostToDevice) != hipSuccess)
+            return bail(fail(AFQMC_E_DEVICE, "upload coefficients"));
+    }
     // zero buffers read before first written (theta padding, F one-body row)
     for (DevBuf* b : {&s->d_theta, &s->d_theta_lp, &s->d_lhx, &s->d_exch, &s->d_simp,
                       &s->d_capcount}) {
         hipError_t e = hipMemsetAsync(b->p, 0, b->n, st);
         if (e != hipSuccess) return bail(fail(AFQMC_E_DEVICE, hipGetErrorString(e)));
     }
-    // trial^T (rows = orbitals)
-    std::vector<double> trialT((size_t)NM);
-    for (int i = 0; i < N; ++i)
-        for (int m = 0; m < M; ++m) trialT[(size_t)i * M + m] = trial[(size_t)m * N + i];
-    if (hipMemcpy(s->d_trialT.p, trialT.data(), NM * 8, hipMemcpyHostToDevice) != hipSuccess)
-        return bail(fail(AFQMC_E_DEVICE, "upload trial"));
-    // L^half_g[i][n] = sum_m trial[m][i] L_g[n][m]; row n_chol holds h^half.
-    {
+    for (int di = 0; di < n_det; ++di) {
+        const double* D = dets + (size_t)di * M * N;
+        // D^T (rows = orbitals)
+        std::vector<double> trialT((size_t)NM);
+        for (int i = 0; i < N; ++i)
+            for (int m = 0; m < M; ++m) trialT[(size_t)i * M + m] = D[(size_t)m * N + i];
+        if (hipMemcpy(det_trialT(s, di).p, trialT.data(), NM * 8, hipMemcpyHostToDevice) !=
+            hipSuccess)
+            return bail(fail(AFQMC_E_DEVICE, "upload trial"));
+        // L^half_g[i][n] = sum_m D[m][i] L_g[n][m]; row n_chol holds h^half.
         Gemm g{};
-        g.A = s->d_trialT.p;
+        g.A = det_trialT(s, di).p;
         g.ta = DT_F64;
         g.ra = rows_strided(M);
         g.a_bs = 0;
@@ -517,7 +631,7 @@ afqmc_status afqmc_init_walkers(afqmc_ham ham, int n_alpha, int n_beta, const do
         g.tb = DT_F64;
         g.rb = rows_strided(M);
         g.b_bs = (long)M * M;
-        g.C = s->d_lhx.p;
+        g.C = det_lhx(s, di).p;
         g.tc = DT_F64;
         g.rc = rows_strided(M);
         g.c_bs = NM;
@@ -530,42 +644,92 @@ afqmc_status afqmc_init_walkers(afqmc_ham ham, int n_alpha, int n_beta, const do
             return bail(fail(AFQMC_E_DEVICE, "L^half GEMM"));
         g.B = ham->d_h.p;
         g.b_bs = 0;
-        g.C = s->d_lhx.as<double>() + (size_t)nc * NM;
+        g.C = det_lhx(s, di).as<double>() + (size_t)nc * NM;
         g.batch = 1;
         if (gemm(g, DT_F64, st) != hipSuccess) return bail(fail(AFQMC_E_DEVICE, "h^half GEMM"));
     }
-    // a_g = sum_s Tr(L^half_gs Theta_T^s): the force-bias trace of the trial.
-    std::vector<double> thT((size_t)2 * NM, 0.0);
-    if (s->na && !theta_trial(trial, M, N, 0, s->na, thT.data()))
-        return bail(fail(AFQMC_E_SINGULAR, "trial alpha block is singular"));
-    if (s->nb && !theta_trial(trial, M, N, s->na, s->nb, thT.data() + (size_t)s->na * M))
-        return bail(fail(AFQMC_E_SINGULAR, "trial beta block is singular"));
-    std::vector<double> Ftrial((size_t)2 * (nc + 1));
+    // a_g = <phi_T|rho_g|phi_T> / <phi_T|phi_T> (Eq. 2, 9).  With the determinant
+    // pairs (i, j): sum_ij c_i c_j <D_i|D_j> f^(i)_g(D_j) / sum_ij c_i c_j <D_i|D_j>,
+    // f^(i)_g(D_j) = sum_s Tr(L^half_{i,gs} Theta_ij^s), Theta_ij = D_j (D_i^T D_j)^{-1};
+    // one determinant: the force-bias trace of the trial.
+    std::vector<double> Ftrial((size_t)2 * (nc + 1), 0.0);
     {
+        const int nd = n_det;
+        std::vector<double> thT((size_t)nd * 2 * NM, 0.0), lw((size_t)nd * nd);
+        std::vector<int> sgn((size_t)nd * nd);
         DevBuf dth, dF;
-        if (dth.alloc(2 * NM * 8) != hipSuccess || dF.alloc(2 * (nc + 1) * 8) != hipSuccess)
+        if (dth.alloc((size_t)nd * 2 * NM * 8) != hipSuccess ||
+            dF.alloc((size_t)nd * 2 * (nc + 1) * 8) != hipSuccess)
             return bail(fail(AFQMC_E_NOMEM, "scratch"));
-        if (hipMemcpy(dth.p, thT.data(), 2 * NM * 8, hipMemcpyHostToDevice) != hipSuccess)
-            return bail(fail(AFQMC_E_DEVICE, "upload"));
-        Gemm g{};
-        g.A = dth.p;
-        g.ta = DT_F64;
-        g.ra = rows_strided(NM);
-        g.B = s->d_lhx.p;
-        g.tb = DT_F64;
-        g.rb = rows_strided(NM);
-        g.C = dF.p;
-        g.tc = DT_F64;
-        g.rc = rows_strided(nc + 1);
-        g.alpha = 1.0;
-        g.m = 2;
-        g.n = nc + 1;
-        g.k = (int)NM;
-        g.batch = 1;
-        if (gemm(g, DT_F64, st) != hipSuccess) return bail(fail(AFQMC_E_DEVICE, "a GEMM"));
-        if (hipStreamSynchronize(st) != hipSuccess ||
-            hipMemcpy(Ftrial.data(), dF.p, Ftrial.size() * 8, hipMemcpyDeviceToHost) != hipSuccess)
-            return bail(fail(AFQMC_E_DEVICE, "a download"));
+        std::vector<double> Fij((size_t)nd * nd * (nc + 1));
+        for (int i = 0; i < nd; ++i) {
+            const double* Di = dets + (size_t)i * M * N;
+            for (int j = 0; j < nd; ++j) {
+                const double* Dj = dets + (size_t)j * M * N;
+                double la = 0.0, l1 = 0.0;
+                int sg = 1, s1 = 1;
+                double* th = thT.data() + (size_t)j * 2 * NM;
+                if (s->na && !theta_pair(Di, Dj, M, N, 0, s->na, th, &l1, &s1))
+                    return bail(fail(AFQMC_E_SINGULAR, "alpha blocks of trial determinants " +
+                                                           std::to_string(i) + " and " +
+                                                           std::to_string(j) + " are orthogonal"));
+                la += l1;
+                sg *= s1;
+                if (s->nb && !theta_pair(Di, Dj, M, N, s->na, s->nb, th + (size_t)s->na * M, &l1,
+                                         &s1))
+                    return bail(fail(AFQMC_E_SINGULAR, "beta blocks of trial determinants " +
+                                                           std::to_string(i) + " and " +
+                                                           std::to_string(j) + " are orthogonal"));
+                la += l1;
+                sg *= s1;
+                lw[(size_t)i * nd + j] = la;
+                sgn[(size_t)i * nd + j] = sg;
+            }
+            if (hipMemcpy(dth.p, thT.data(), (size_t)nd * 2 * NM * 8, hipMemcpyHostToDevice) !=
+                hipSuccess)
+                return bail(fail(AFQMC_E_DEVICE, "upload"));
+            Gemm g{};
+            g.A = dth.p;
+            g.ta = DT_F64;
+            g.ra = rows_strided(NM);
+            g.B = det_lhx(s, i).p;
+            g.tb = DT_F64;
+            g.rb = rows_strided(NM);
+            g.C = dF.p;
+            g.tc = DT_F64;
+            g.rc = rows_strided(nc + 1);
+            g.alpha = 1.0;
+            g.m = 2 * nd;
+            g.n = nc + 1;
+            g.k = (int)NM;
+            g.batch = 1;
+            if (gemm(g, DT_F64, st) != hipSuccess) return bail(fail(AFQMC_E_DEVICE, "a GEMM"));
+            std::vector<double> Fd((size_t)nd * 2 * (nc + 1));
+            if (hipStreamSynchronize(st) != hipSuccess ||
+                hipMemcpy(Fd.data(), dF.p, Fd.size() * 8, hipMemcpyDeviceToHost) != hipSuccess)
+                return bail(fail(AFQMC_E_DEVICE, "a download"));
+            for (int j = 0; j < nd; ++j)  // real part: row 2 j of the GEMM
+                std::copy(Fd.begin() + (size_t)j * 2 * (nc + 1),
+                          Fd.begin() + (size_t)j * 2 * (nc + 1) + nc + 1,
+                          Fij.begin() + ((size_t)i * nd + j) * (nc + 1));
+        }
+        if (nd == 1) {
+            std::copy(Fij.begin(), Fij.end(), Ftrial.begin());
+        } else {
+            double top = -INFINITY;
+            for (double v : lw) top = std::max(top, v);
+            double den = 0.0;
+            std::vector<double> num((size_t)nc + 1, 0.0);
+            for (int i = 0; i < nd; ++i)
+                for (int j = 0; j < nd; ++j) {
+                    const double wt = coeffs[i] * coeffs[j] * sgn[(size_t)i * nd + j] *
+                                      exp(lw[(size_t)i * nd + j] - top);
+                    den += wt;
+                    for (int g = 0; g <= nc; ++g) num[g] += wt * Fij[((size_t)i * nd + j) * (nc + 1) + g];
+                }
+            if (!(den != 0.0)) return bail(fail(AFQMC_E_SINGULAR, "the trial expansion has zero norm"));
+            for (int g = 0; g <= nc; ++g) Ftrial[g] = num[g] / den;
+        }
     }
     s->a_host.assign(Ftrial.begin(), Ftrial.begin() + nc);
     if (nc > 0 && hipMemcpy(s->d_a.p, s->a_host.data(), nc * 8, hipMemcpyHostToDevice) != hipSuccess)
@@ -635,9 +799,11 @@ afqmc_status afqmc_init_walkers(afqmc_ham ham, int n_alpha, int n_beta, const do
         }
     }
     // low-precision copies of the contraction operands
-    if (s->ts != DT_F64 &&
-        convert(s->d_lhx.as<double>(), s->d_lhx_lp.p, s->ts, (long)(nc + 1) * NM, st) != hipSuccess)
-        return bail(fail(AFQMC_E_DEVICE, "convert L^half"));
+    for (int di = 0; di < n_det; ++di)
+        if (s->ts != DT_F64 &&
+            convert(det_lhx(s, di).as<double>(), (void*)det_lhx_lp(s, di).p, s->ts,
+                    (long)(nc + 1) * NM, st) != hipSuccess)
+            return bail(fail(AFQMC_E_DEVICE, "convert L^half"));
     if (!ham->d_lp[s->ts].p) {
         if (ham->d_lp[s->ts].alloc((size_t)P * std::max(nc, 1) * dt_size(s->ts)) != hipSuccess)
             return bail(fail(AFQMC_E_NOMEM, "packed L"));
@@ -696,6 +862,25 @@ afqmc_status afqmc_init_walkers(afqmc_ham ham, int n_alpha, int n_beta, const do
     return AFQMC_OK;
 }
 
+}  // namespace
+
+extern "C" {
+
+afqmc_status afqmc_init_walkers(afqmc_ham ham, int n_alpha, int n_beta, const double* trial,
+                                const double* init_phi, int n_walkers, const afqmc_params* par,
+                                afqmc_sys* out) {
+    const double one = 1.0;
+    return init_system(ham, n_alpha, n_beta, 1, &one, trial, init_phi, n_walkers, par, out);
+}
+
+afqmc_status afqmc_init_walkers_msd(afqmc_ham ham, int n_alpha, int n_beta, int n_det,
+                                    const double* coeffs, const double* dets,
+                                    const double* init_phi, int n_walkers,
+                                    const afqmc_params* par, afqmc_sys* out) {
+    if (!coeffs) return fail(AFQMC_E_INVALID, "null coefficients");
+    return init_system(ham, n_alpha, n_beta, n_det, coeffs, dets, init_phi, n_walkers, par, out);
+}
+
 void afqmc_free_sys(afqmc_sys s) {
     if (!s || s->dead) return;
     s->dead = true;
@@ -706,8 +891,10 @@ void afqmc_free_sys(afqmc_sys s) {
                       &s->d_phi, &s->d_phinew, &s->d_theta, &s->d_theta_lp, &s->d_w, &s->d_lnov,
                       &s->d_alive, &s->d_F, &s->d_X, &s->d_simp, &s->d_Apk, &s->d_Af,
                       &s->d_lnd, &s->d_ovl, &s->d_kws, &s->d_exch, &s->d_el, &s->d_sums,
-                      &s->d_pc, &s->d_capcount})
+                      &s->d_pc, &s->d_capcount, &s->d_coef, &s->d_lnd_all, &s->d_F_all,
+                      &s->d_el_all, &s->d_rw})
         b->release();
+    s->xdet.clear();
     drop_batch_plans(s->id);
     free_adjoint(s);
     s->ham = nullptr;
@@ -920,7 +1107,13 @@ afqmc_status afqmc_restore(afqmc_sys s, const void* src, size_t bytes) {
     HIPCHK(hipMemcpy(s->d_lnov.p, p, s->d_lnov.n, hipMemcpyHostToDevice));
     p += s->d_lnov.n;
     HIPCHK(hipMemcpy(s->d_alive.p, p, s->nw, hipMemcpyHostToDevice));
-
+    if (s->n_det > 1) {
+        // Theta and ln det against every determinant of the expansion, and the
+        // weights r_i, from the restored determinants (the same kernels, so
+        // the same values as before the snapshot)
+        if ((r = overlap_theta(s, s->d_phi.as<double>(), st)) != AFQMC_OK) return r;
+        HIPCHK(hipStreamSynchronize(st));
+    }
     s->t = hdr[1];
     return AFQMC_OK;
 }

@@ -7,6 +7,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <memory>
 #include <string>
 #include <vector>
 
@@ -161,6 +162,18 @@ struct afqmc_sys_s {
     afq::host::DevBuf d_kws;  // split-K partial sums of the force-bias GEMM
     afq::host::DevBuf d_pc;   // comb workspace: running sums, selection, status
     afq::host::DevBuf d_capcount;  // force-bias cap events per walker (int64)
+    // Multi-determinant trial (Sec. II.D): determinant 0 uses d_trialT, d_lhx,
+    // d_lhx_lp, d_theta, d_theta_lp and d_exch; determinants 1.. their own
+    // buffers in xdet.  With n_det > 1 the per-determinant ln dets, force-bias
+    // traces and local energies go to d_lnd_all, d_F_all and d_el_all, and
+    // d_lnd, d_F, d_el hold the combined values the step reads; d_rw holds
+    // r_i = c_i <D_i|phi> / <phi_T|phi> per walker.
+    int n_det = 1;
+    struct DetBufs {
+        afq::host::DevBuf trialT, lhx, lhx_lp, theta, theta_lp, exch;
+    };
+    std::vector<std::unique_ptr<DetBufs>> xdet;
+    afq::host::DevBuf d_coef, d_lnd_all, d_F_all, d_el_all, d_rw;
     int n_gt_a = 0, n_gt_b = 0, n_gt = 0;
     // launch shapes (autotuned; 0 = size heuristic): GEMM tiles of the force
     // bias and the field sum, and the propagation workgroup shape
@@ -190,6 +203,26 @@ inline void ham_unref(afqmc_ham h) {
 }
 
 inline const void* lp_or(const DevBuf& lp, const DevBuf& hi, DType t) { return t == DT_F64 ? hi.p : lp.p; }  // by storage type
+
+// Per-determinant buffers of the trial expansion (determinant 0: the
+// system's own).
+inline const DevBuf& det_trialT(afqmc_sys s, int i) { return i ? s->xdet[i - 1]->trialT : s->d_trialT; }
+inline const DevBuf& det_lhx(afqmc_sys s, int i) { return i ? s->xdet[i - 1]->lhx : s->d_lhx; }
+inline const DevBuf& det_lhx_lp(afqmc_sys s, int i) { return i ? s->xdet[i - 1]->lhx_lp : s->d_lhx_lp; }
+inline const DevBuf& det_theta(afqmc_sys s, int i) { return i ? s->xdet[i - 1]->theta : s->d_theta; }
+inline const DevBuf& det_theta_lp(afqmc_sys s, int i) { return i ? s->xdet[i - 1]->theta_lp : s->d_theta_lp; }
+inline const DevBuf& det_exch(afqmc_sys s, int i) { return i ? s->xdet[i - 1]->exch : s->d_exch; }
+// where determinant i's ln dets, force-bias traces and local energies go
+inline double* det_lnd(afqmc_sys s, int i) {
+    return s->n_det > 1 ? s->d_lnd_all.as<double>() + (size_t)i * s->nw * 4 : s->d_lnd.as<double>();
+}
+inline double* det_F(afqmc_sys s, int i) {
+    return s->n_det > 1 ? s->d_F_all.as<double>() + (size_t)i * s->nw * 2 * (s->n_chol + 1)
+                        : s->d_F.as<double>();
+}
+inline double* det_el(afqmc_sys s, int i) {
+    return s->n_det > 1 ? s->d_el_all.as<double>() + (size_t)i * s->nw * 2 : s->d_el.as<double>();
+}
 
 // Brackets one phase with a pair of HIP events when profiling is on.
 struct PhaseTimer {
@@ -222,7 +255,7 @@ struct PhaseTimer {
 // fewest on ties.  It does not depend on the tile the autotuner picks, so
 // every tile shape sums the same K ranges in the same order.
 int fb_ksplit(int m, int n, int k, int cus);
-Gemm force_bias_gemm(afqmc_sys s);
+Gemm force_bias_gemm(afqmc_sys s, int det = 0);
 Gemm field_sum_gemm(afqmc_sys s);
 
 // Device phases of one step of one system on stream st (Sec. II.A, II.D).

@@ -210,6 +210,16 @@ hipError_t take_columns(const double* pri, double* sec, int nw, int M, int n_pri
 hipError_t secondary_weights(const double* w_pri, const double* lnov_pri, const double* lnov_sec,
                              double* w_sec, uint8_t* alive, int nw, hipStream_t s);
 
+// Multi-determinant trial: per walker, the combined ln <phi_T|phi> =
+// ln sum_i c_i exp(ln det_i) into lnd_out[w][0..1] (zeros in [2..3]) and the
+// weights r_i = c_i <D_i|phi> / <phi_T|phi> into rw[w][i][re, im], from the
+// per-determinant, per-spin ln dets lnd_all[i][w][4] (frozen walkers skipped).
+hipError_t msd_overlap(const double* lnd_all, const double* coef, int n_det, const uint8_t* alive,
+                       int nw, double* lnd_out, double* rw, hipStream_t s);
+// out[w][re, im][j] = sum_i r_i in_i[w][re, im][j], in_i = in_all + i det_stride.
+hipError_t msd_combine(const double* in_all, long det_stride, const double* rw, int n_det,
+                       const uint8_t* alive, int nw, int ld, double* out, hipStream_t s);
+
 // Small helpers.
 hipError_t broadcast(const double* src, double* dst, long n, int copies, hipStream_t s);
 hipError_t convert(const double* src, void* dst, DType t, long n, hipStream_t s);
