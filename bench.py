@@ -14,8 +14,9 @@ period boundary; exactly --steps steps are timed, replayed from a HIP graph;
 a following profiled pass of direct launches (whole periods) gives the
 per-kernel times.
 
---workload batch: 64 uneven pairs (M in 40..240, FP32 contractions) stepped
-together from one graph, against the same pairs stepped one at a time.
+--workload batch: 64 uneven pairs (M in 40..240, FP32 contractions unless
+--precision says otherwise) stepped together from one graph, against the
+same pairs stepped one at a time.
 --workload adjoint: dE/dlambda through the last 100 of 500 steps at M = 100
 against correlated finite differences.
 --workload se_study: standard error of the energy difference over 11 repeats,
@@ -316,7 +317,7 @@ def bench_batch(args):
     from synth import pair_batch_configs
 
     cfgs = pair_batch_configs(n_pairs=args.pairs)
-    prec = "fp32" if args.precision == "bf16" else args.precision
+    prec = args.precision
     me = cfgs[0].measure_every
     steps, warmup, _ = plan_counts(args.steps, args.warmup, 0,
                                    math.lcm(cfgs[0].ortho_every, me))
@@ -522,8 +523,10 @@ def make_parser() -> argparse.ArgumentParser:
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--profile-steps", type=int, default=20)
-    ap.add_argument("--precision", default="bf16x3",
-                    choices=["bf16", "bf16x3", "fp32", "fp64", "bf16_plain"])
+    ap.add_argument("--precision", default=None,
+                    choices=["bf16", "bf16x3", "fp32", "fp64", "bf16_plain"],
+                    help="precision plan (default: bf16x3 for the pair, fp32 contractions for the "
+                         "batch as its configuration states, fp64 for the SE study)")
     ap.add_argument("--walkers", type=int, default=None, help="override walkers per system")
     ap.add_argument("--pairs", type=int, default=64, help="batch workload: number of pairs")
     ap.add_argument("--lanes", type=int, default=4, help="batch workload: stream lanes")
@@ -550,13 +553,13 @@ def main(argv=None):
     import torch
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
+    if args.precision is None:
+        args.precision = {"batch": "fp32", "se_study": "fp64"}.get(args.workload, "bf16x3")
     if args.workload == "batch":
         bench_batch(args)
     elif args.workload == "adjoint":
         bench_adjoint(args)
     elif args.workload == "se_study":
-        if args.precision == "bf16x3":
-            args.precision = "fp64"
         bench_se_study(args)
     else:
         bench_pair(args)

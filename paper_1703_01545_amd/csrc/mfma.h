@@ -128,6 +128,22 @@ __device__ __forceinline__ void lds_put(typename Info<TC>::LT* p, long plane, in
     }
 }
 
+// Four consecutive staged values (idx a multiple of 4) into the BF16 LDS
+// plane(s) of compute type TC with one 8-byte store per plane; the same
+// values as four lds_put calls.
+typedef __bf16 bf4 __attribute__((ext_vector_type(4)));
+template <typename TC>
+__device__ __forceinline__ void lds_put4(bf16_t* p, long plane, int idx, const float* v) {
+    bf4 hi, lo;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        hi[e] = to_bf(v[e]);
+        lo[e] = to_bf(v[e] - (float)hi[e]);
+    }
+    *reinterpret_cast<bf4*>(p + idx) = hi;
+    if constexpr (std::is_same<TC, Split>::value) *reinterpret_cast<bf4*>(p + plane + idx) = lo;
+}
+
 // Vector width (elements) of one 16-byte global load of storage type TS.
 template <typename TS>
 struct VW {
@@ -290,14 +306,31 @@ struct Core {
             }
         };
         auto sstore = [&](LT* Ad, LT* Bd) {
+            if constexpr (sizeof(LT) == 2 && VA % 4 == 0 && VB % 4 == 0) {
+                // BF16 planes: each thread's run of V consecutive k goes out as
+                // 8-byte stores (4 elements per plane), rows 16-byte aligned
 #pragma unroll
-            for (int j = 0; j < LA; ++j)
+                for (int j = 0; j < LA; ++j)
 #pragma unroll
-                for (int e = 0; e < VA; ++e) lds_put<TC>(Ad, BM * PK, arow(j) * PK + ka + e, ra[j][e]);
+                    for (int e = 0; e < VA; e += 4)
+                        lds_put4<TC>(Ad, BM * PK, arow(j) * PK + ka + e, &ra[j][e]);
 #pragma unroll
-            for (int j = 0; j < LB; ++j)
+                for (int j = 0; j < LB; ++j)
 #pragma unroll
-                for (int e = 0; e < VB; ++e) lds_put<TC>(Bd, BN * PK, brow(j) * PK + kb + e, rb[j][e]);
+                    for (int e = 0; e < VB; e += 4)
+                        lds_put4<TC>(Bd, BN * PK, brow(j) * PK + kb + e, &rb[j][e]);
+            } else {
+#pragma unroll
+                for (int j = 0; j < LA; ++j)
+#pragma unroll
+                    for (int e = 0; e < VA; ++e)
+                        lds_put<TC>(Ad, BM * PK, arow(j) * PK + ka + e, ra[j][e]);
+#pragma unroll
+                for (int j = 0; j < LB; ++j)
+#pragma unroll
+                    for (int e = 0; e < VB; ++e)
+                        lds_put<TC>(Bd, BN * PK, brow(j) * PK + kb + e, rb[j][e]);
+            }
         };
 
         gload(0);
