@@ -60,20 +60,14 @@ const char* const kPhaseNames[PH_COUNT] = {
     "det_theta",       "weights", "mgs",            "exchange", "energy"};
 
 
-int fb_ksplit(int m, int n, int k, int cus) {
-    if (k < 8000 || cus <= 0) return std::max(1, std::min(8, k / 4000));
-    const long tiles = (long)((m + 255) / 256) * ((n + 127) / 128);
-    int best = 4;
-    long best_num = 0, best_den = 1;  // fill fraction as a ratio
-    for (int ks = 4; ks <= 12; ++ks) {
-        const long wg = tiles * ks, den = (long)cus * ((wg + cus - 1) / cus);
-        if (wg * best_den > best_num * den) {
-            best = ks;
-            best_num = wg;
-            best_den = den;
-        }
-    }
-    return best;
+int fb_ksplit(int k) {
+    // a function of K = N M alone: the same K ranges, and so the same bits for
+    // every walker, whatever the walker count, the batch a walker runs in or
+    // the device; about 1800 K per range above K = 8000 (9 ranges at the
+    // benchmark's K = 16000, which with 256 x 128 tiles fill 1008 workgroups
+    // on 256 CUs)
+    if (k < 8000) return std::max(1, std::min(8, k / 4000));
+    return std::max(4, std::min(12, (k + 900) / 1800));
 }
 
 Gemm force_bias_gemm(afqmc_sys s, int det) {
@@ -531,13 +525,7 @@ afqmc_status init_system(afqmc_ham ham, int n_alpha, int n_beta, int n_det, cons
     s->n_gt_a = exchange_gtiles(nc, s->na, M, s->tc);
     s->n_gt_b = exchange_gtiles(nc, s->nb, M, s->tc);  // tiles depend on the compute type
     s->n_gt = std::max(1, std::max(s->n_gt_a, s->n_gt_b));
-    {
-        int dev = 0, cus = 0;
-        if (hipGetDevice(&dev) != hipSuccess ||
-            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
-            return bail(fail(AFQMC_E_DEVICE, "device attributes"));
-        s->fb_ks = fb_ksplit(2 * nw, nc + 1, (int)NM, cus);
-    }
+    s->fb_ks = fb_ksplit((int)NM);
     struct A_ {
         DevBuf* b;
         size_t bytes;

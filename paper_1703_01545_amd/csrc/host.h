@@ -249,12 +249,11 @@ struct PhaseTimer {
 
 // GEMM descriptors of the contraction phases (their tile from the system's
 // tuned shapes).
-// K ranges of the force-bias GEMM (m x n output, K = k) on a device of `cus`
-// compute units: 1 below K = 8000; else the count in 4..12 whose workgroups
-// of the largest tile (256 x 128, one per CU) best fill the last round,
-// fewest on ties.  It does not depend on the tile the autotuner picks, so
-// every tile shape sums the same K ranges in the same order.
-int fb_ksplit(int m, int n, int k, int cus);
+// K ranges of the force-bias GEMM for K = k: 1 below K = 8000 (K / 4000 up to
+// 8 between), else about one per 1800 K, 4..12.  It depends on K alone, so a
+// walker's force bias has the same bits whatever the walker count, the batch
+// or the device, and it does not depend on the tile the autotuner picks.
+int fb_ksplit(int k);
 Gemm force_bias_gemm(afqmc_sys s, int det = 0);
 Gemm field_sum_gemm(afqmc_sys s);
 

@@ -348,3 +348,32 @@ def test_force_bias_cap_counts_and_applies_like_the_oracle(lib):
     for k in ("phi", "weight", "lnov", "alive"):
         assert np.array_equal(out["count"][0][k], out["off"][0][k]), k
     assert not np.array_equal(out["apply"][0]["weight"], out["off"][0]["weight"])
+
+
+# ------------------------------------------------------- walker-subset identity
+
+@pytest.mark.parametrize("precision", ["fp64", "bf16x3"])
+def test_walker_subset_is_bitwise_the_same_walkers(lib, precision):
+    """Walker k's fields depend only on (seed, step, k), and no kernel mixes
+    walkers, so the first 16 walkers of a 96-walker run are bit for bit a
+    16-walker run: weights, ln overlaps and determinants after 20 steps with
+    Gram-Schmidt every 10.  K = N M = 8640 here, so the force bias runs in K
+    ranges (their count depends on K alone) and the autotuner picks launch
+    shapes for each walker count separately."""
+    M, nc, na, nb = 120, 240, 36, 36
+    banner(f"walker subset identity M={M} {precision}")
+    wl = Workload(M, nc, na, nb, na, nb - 1, 96, 0.005, ham_seed=12)
+    H = lib.Hamiltonian(wl.ham.h, wl.ham.chol, wl.ham.e_core)
+    runs = []
+    for nw in (96, 16):
+        a = lib.System(H, na, nb, wl.trials[0], nw, 0.005, ortho_every=10, measure_every=10,
+                       precision=precision)
+        b = lib.System(H, na, nb - 1, wl.trials[1], nw, 0.005, ortho_every=10, measure_every=10,
+                       precision=precision)
+        lib.pair_batch_step([(a, b)], [21], 20, lanes=1)
+        runs.append((a.walkers(), b.walkers()))
+    for s in range(2):
+        big, small = runs[0][s], runs[1][s]
+        assert small["alive"].all()
+        for k in ("phi", "weight", "lnov", "alive"):
+            assert np.array_equal(big[k][:16], small[k]), (s, k)

@@ -183,6 +183,10 @@ def test_split_plan_largest_bases(lib, torch_mod, dims):
     for col, key in enumerate(("EA", "EB", "dE")):
         err = np.max(np.abs(tr[:, col] - np.asarray(ref[key])))
         assert err <= 1e-5 * scale, (key, err, scale)
+    # the energy difference against the oracle in the target's unit
+    err_kcal = abs(tr[0, 2] - ref["dE"][0]) * 627.5095
+    banner(f"  dE split-BF16 vs FP64 oracle: {err_kcal:.2e} kcal/mol")
+    assert err_kcal <= 0.05
 
 
 def test_parity_m100_sampled_walkers(lib, torch_mod):
