@@ -390,10 +390,13 @@ def bench_batch(args):
 
 def bench_adjoint(args):
     """dE/dlambda for h -> h + lambda V at M = 100 (512 walkers): 400 steps at
-    lambda = 0, then the reverse pass through the last 100 steps (snapshots
-    every 10), FP64 and FP32, against correlated finite differences at
-    lambda = +-1e-3 on the same fields (the last 100 steps, and the whole
-    500-step run for the truncation bias of the window)."""
+    lambda = 0, then the reverse pass through the last 100 steps, FP64 and
+    FP32, against correlated finite differences at lambda = +-1e-3 on the same
+    fields (the last 100 steps, and the whole 500-step run for the truncation
+    bias of the window).  Timed two ways, each after one untimed pass:
+    snapshots every 10 steps (each segment recorded again in reverse), and the
+    whole window recorded in the forward pass (3.6 GB here; nothing
+    recomputed); both give bitwise the same derivative."""
     import torch
 
     from paper_1703_01545_amd import afqmc as lib
@@ -416,13 +419,25 @@ def bench_adjoint(args):
         s.step(window, seed=args.seed)
         torch.cuda.synchronize()
         t_fwd = time.perf_counter() - t0
-        s.restore(snap)
-        t0 = time.perf_counter()
-        E = s.adjoint_forward(V, window, seed=args.seed, checkpoint_every=every, precision=prec)
-        t_af = time.perf_counter() - t0
-        t0 = time.perf_counter()
-        dE = s.adjoint_backward()
-        t_ab = time.perf_counter() - t0
+        # each mode once untimed (buffer and tape allocation), then timed:
+        # snapshots every `every` steps (segments recorded again in reverse) and
+        # the whole window recorded in the forward pass (nothing recomputed)
+        modes = {}
+        for name, ce in (("snapshots", every), ("tape", window)):
+            for rep in range(2):
+                s.restore(snap)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                E = s.adjoint_forward(V, window, seed=args.seed, checkpoint_every=ce,
+                                      precision=prec)
+                t_af = time.perf_counter() - t0
+                t0 = time.perf_counter()
+                dE = s.adjoint_backward()
+                t_ab = time.perf_counter() - t0
+            modes[name] = (E, dE, t_af, t_ab)
+        assert modes["tape"][:2] == modes["snapshots"][:2], modes
+        E, dE, t_af, t_ab = modes["snapshots"]
+        _, _, t_af2, t_ab2 = modes["tape"]
         fd = {}
         for name, steps_pert in (("window", window), ("full", burn + window)):
             e = []
@@ -442,7 +457,9 @@ def bench_adjoint(args):
                      "rel_err_vs_fd_window": abs(dE - fd["window"]) / abs(fd["window"]),
                      "forward_window_s": t_fwd, "adjoint_forward_s": t_af,
                      "adjoint_backward_s": t_ab,
-                     "adjoint_cost_over_forward": (t_af + t_ab) / t_fwd}
+                     "adjoint_cost_over_forward": (t_af + t_ab) / t_fwd,
+                     "tape_adjoint_forward_s": t_af2, "tape_adjoint_backward_s": t_ab2,
+                     "tape_adjoint_cost_over_forward": (t_af2 + t_ab2) / t_fwd}
         print(f"[bench] adjoint {prec}: dE={dE:.10g} fd={fd['window']:.10g}", file=sys.stderr,
               flush=True)
     out = {"metric": "dE_mixed/dlambda through the last 100 steps (reverse mode) vs correlated FD",

@@ -249,12 +249,15 @@ afqmc_status afqmc_pair_batch_step(int n_pairs, const afqmc_sys* a, const afqmc_
  * local energy; the fields are held fixed (pathwise derivative).
  * afqmc_adjoint_backward recomputes the window one segment at a time from
  * the snapshots and returns dE/dlambda; the system is left in the state after
- * the window.  Systems with an applied force-bias cap or a multi-determinant
+ * the window.  With checkpoint_every >= n_steps (one segment) the forward
+ * pass records every step instead (device memory of about
+ * n_steps (1 + 1/ortho_every) walker blocks of nw 2 N M doubles) and the
+ * backward pass recomputes nothing; the result is bitwise the same.  Systems with an applied force-bias cap or a multi-determinant
  * trial are refused (E_STATE): the reverse pass differentiates the uncapped
  * single-determinant step.  V: host M x M symmetric, row-major, copied.  prec: AFQMC_FP64
  * or AFQMC_FP32 products in the adjoint's contractions (FP64 storage and
  * small dense algebra).  Errors: E_STATE (free mode; backward without a
- * forward), E_SHAPE (a spin block above 48 orbitals), E_INVALID.
+ * forward), E_SHAPE (a spin block above 64 orbitals), E_INVALID.
  * Synchronises. */
 afqmc_status afqmc_adjoint_forward(afqmc_sys sys, const double* V, uint64_t seed, int n_steps,
                                    int checkpoint_every, afqmc_prec prec, double* energy);

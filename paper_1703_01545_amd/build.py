@@ -15,7 +15,8 @@ CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libafqmc.so")
 SOURCES = ["gemm.hip", "propagate.hip", "walker.hip", "capi.hip", "batch.hip", "adjoint.hip",
-           "population.hip", "noalloc.hip", "msd.hip"]
+           "population.hip", "noalloc.hip", "msd.hip", "taylor_adj.hip",
+           "detadj.hip"]
 ARCH = os.environ.get("AFQMC_ARCH", "gfx950")
 
 FLAGS = [

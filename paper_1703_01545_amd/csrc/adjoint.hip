@@ -34,7 +34,7 @@ namespace afq {
 namespace host {
 namespace {
 
-constexpr int kMaxSpin = 48;  // largest spin block of the small dense kernels
+constexpr int kMaxSpin = 64;  // largest spin block of the dense adjoint kernels
 constexpr uint8_t ACTIVE = 1;
 
 inline int nblk(long n, int b) { return (int)((n + b - 1) / b); }
@@ -175,260 +175,13 @@ __global__ void k_adj_pack(const double* __restrict__ Af, double* __restrict__ A
     Apk[e] = i == j ? A[(long)i * M + i] : A[(long)i * M + j] + A[(long)j * M + i];
 }
 
-// Per (walker, spin): Phi_bar += Y + Phi_T (coef O^{-H} - Theta^H Y), with
-// O = Phi_T^T Phi, Theta = Phi O^{-1}, Y = Theta_bar O^{-H} (Theta_bar may be
-// NULL: Y = 0), coef = cscale * coef[w] (NULL: 0).  th_s / y_s: scratch in the
-// walker layout.  Row layout [w][2][N][M] throughout.
-__device__ void gj_inverse(double* aug, int n, int tid, int nt, double* fac, int* flag) {
-    // aug: n x 2n complex, [row][col][2]; on return columns n..2n-1 hold O^{-1}
-    const int W = 2 * n;
-    for (int k = 0; k < n; ++k) {
-        if (tid == 0) {
-            int p = k;
-            double best = -1.0;
-            for (int r = k; r < n; ++r) {
-                const double v = fabs(aug[(r * W + k) * 2]) + fabs(aug[(r * W + k) * 2 + 1]);
-                if (v > best) {
-                    best = v;
-                    p = r;
-                }
-            }
-            if (!(best > 0.0)) *flag = 1;
-            fac[2 * n] = p;
-        }
-        __syncthreads();
-        const int p = (int)fac[2 * n];
-        if (p != k)
-            for (int c = tid; c < W; c += nt)
-                for (int h = 0; h < 2; ++h) {
-                    const double t = aug[(k * W + c) * 2 + h];
-                    aug[(k * W + c) * 2 + h] = aug[(p * W + c) * 2 + h];
-                    aug[(p * W + c) * 2 + h] = t;
-                }
-        __syncthreads();
-        if (*flag) return;
-        const double pr = aug[(k * W + k) * 2], pi = aug[(k * W + k) * 2 + 1];
-        const double den = pr * pr + pi * pi;
-        const double ir = pr / den, ii = -pi / den;
-        __syncthreads();
-        for (int c = tid; c < W; c += nt) {
-            const double ar = aug[(k * W + c) * 2], ai = aug[(k * W + c) * 2 + 1];
-            aug[(k * W + c) * 2] = ar * ir - ai * ii;
-            aug[(k * W + c) * 2 + 1] = ar * ii + ai * ir;
-        }
-        __syncthreads();
-        for (int r = tid; r < n; r += nt) {
-            fac[2 * r] = aug[(r * W + k) * 2];
-            fac[2 * r + 1] = aug[(r * W + k) * 2 + 1];
-        }
-        __syncthreads();
-        for (int e = tid; e < n * W; e += nt) {
-            const int r = e / W, c = e % W;
-            if (r == k) continue;
-            const double fr = fac[2 * r], fi = fac[2 * r + 1];
-            const double br = aug[(k * W + c) * 2], bi = aug[(k * W + c) * 2 + 1];
-            aug[(r * W + c) * 2] -= fr * br - fi * bi;
-            aug[(r * W + c) * 2 + 1] -= fr * bi + fi * br;
-        }
-        __syncthreads();
-    }
-}
-
-// O[a][b] = sum_m T[off + a][m] Phi[off + b][m] into aug (left half), identity
-// in the right half.
-__device__ void build_overlap(const double* trialT, const double* phr, const double* phi_i,
-                              int M, int off, int n, double* aug, int tid, int nt) {
-    const int W = 2 * n;
-    for (int e = tid; e < n * n; e += nt) {
-        const int a = e / n, b = e % n;
-        const double* t = trialT + (long)(off + a) * M;
-        const double* r = phr + (long)(off + b) * M;
-        const double* i = phi_i + (long)(off + b) * M;
-        double sr = 0.0, si = 0.0;
-        for (int m = 0; m < M; ++m) {
-            sr += t[m] * r[m];
-            si += t[m] * i[m];
-        }
-        aug[(a * W + b) * 2] = sr;
-        aug[(a * W + b) * 2 + 1] = si;
-        aug[(a * W + n + b) * 2] = a == b ? 1.0 : 0.0;
-        aug[(a * W + n + b) * 2 + 1] = 0.0;
-    }
-}
-
-__global__ __launch_bounds__(256) void k_det_adj(
-    const double* __restrict__ phi, const double* __restrict__ trialT, const double* thbar,
-    const double* coef, double cscale, const uint8_t* __restrict__ mode, double* phibar,
-    double* th_s, double* y_s, int M, int N, int na, int nb) {
-    extern __shared__ double sm[];
-    const int w = blockIdx.x, spin = blockIdx.y;
-    const int off = spin ? na : 0, n = spin ? nb : na;
-    if (n == 0 || mode[w] != ACTIVE) return;
-    const int tid = threadIdx.x, nt = blockDim.x;
-    const int W = 2 * n;
-    double* aug = sm;                      // n x 2n complex
-    double* Wm = aug + 2 * n * W;          // n x n complex
-    double* fac = Wm + 2 * n * n;          // 2n + 1
-    __shared__ int flag;
-    if (tid == 0) flag = 0;
-    const long NM = (long)N * M;
-    const double* pr = phi + (long)w * 2 * NM;
-    const double* pi = pr + NM;
-    __syncthreads();
-    build_overlap(trialT, pr, pi, M, off, n, aug, tid, nt);
-    __syncthreads();
-    gj_inverse(aug, n, tid, nt, fac, &flag);
-    if (flag) return;  // singular overlap: the forward froze such a walker
-    // Oinv[a][b] = aug[a][n + b]
-#define OI_R(a, b) aug[((a) * W + n + (b)) * 2]
-#define OI_I(a, b) aug[((a) * W + n + (b)) * 2 + 1]
-    double* thr = th_s + (long)w * 2 * NM;
-    double* thi = thr + NM;
-    double* yr = y_s + (long)w * 2 * NM;
-    double* yi = yr + NM;
-    const double* tbr = thbar ? thbar + (long)w * 2 * NM : nullptr;
-    const double* tbi = thbar ? tbr + NM : nullptr;
-    // Theta rows c = sum_b Phi rows b Oinv[b][c]; Y rows c = sum_b Theta_bar rows b conj(Oinv[c][b])
-    for (int e = tid; e < n * M; e += nt) {
-        const int c = e / M, m = e % M;
-        double sr = 0.0, si = 0.0, ur = 0.0, ui = 0.0;
-        for (int b = 0; b < n; ++b) {
-            const double xr = pr[(long)(off + b) * M + m], xi = pi[(long)(off + b) * M + m];
-            const double orr = OI_R(b, c), oii = OI_I(b, c);
-            sr += xr * orr - xi * oii;
-            si += xr * oii + xi * orr;
-            if (thbar) {
-                const double gr = tbr[(long)(off + b) * M + m], gi = tbi[(long)(off + b) * M + m];
-                const double qr = OI_R(c, b), qi = -OI_I(c, b);
-                ur += gr * qr - gi * qi;
-                ui += gr * qi + gi * qr;
-            }
-        }
-        thr[(long)(off + c) * M + m] = sr;
-        thi[(long)(off + c) * M + m] = si;
-        yr[(long)(off + c) * M + m] = ur;
-        yi[(long)(off + c) * M + m] = ui;
-    }
-    __syncthreads();
-    // W = Theta^H Y, Z = coef O^{-H} - W (kept in Wm)
-    double cr = 0.0, ci = 0.0;
-    if (coef) {
-        cr = cscale * coef[2 * w];
-        ci = cscale * coef[2 * w + 1];
-    }
-    for (int e = tid; e < n * n; e += nt) {
-        const int a = e / n, c = e % n;
-        double sr = 0.0, si = 0.0;
-        if (thbar)
-            for (int m = 0; m < M; ++m) {
-                const double ar = thr[(long)(off + a) * M + m], ai = -thi[(long)(off + a) * M + m];
-                const double br = yr[(long)(off + c) * M + m], bi = yi[(long)(off + c) * M + m];
-                sr += ar * br - ai * bi;
-                si += ar * bi + ai * br;
-            }
-        const double hr = OI_R(c, a), hi = -OI_I(c, a);  // (O^{-H})[a][c]
-        Wm[2 * e] = cr * hr - ci * hi - sr;
-        Wm[2 * e + 1] = cr * hi + ci * hr - si;
-    }
-    __syncthreads();
-    double* gr_ = phibar + (long)w * 2 * NM;
-    double* gi_ = gr_ + NM;
-    for (int e = tid; e < n * M; e += nt) {
-        const int c = e / M, m = e % M;
-        double sr = yr[(long)(off + c) * M + m], si = yi[(long)(off + c) * M + m];
-        for (int a = 0; a < n; ++a) {
-            const double t = trialT[(long)(off + a) * M + m];
-            sr += t * Wm[2 * (a * n + c)];
-            si += t * Wm[2 * (a * n + c) + 1];
-        }
-        gr_[(long)(off + c) * M + m] += sr;
-        gi_[(long)(off + c) * M + m] += si;
-    }
-#undef OI_R
-#undef OI_I
-}
-
-// Gram-Schmidt adjoint per (walker, spin) of walkers alive after it:
-// Phi_bar <- Phi_bar S^H, S = O(Phi_pre)^{-1} O(Q).  cp: scratch copy.
-__global__ __launch_bounds__(256) void k_mgs_adj(const double* __restrict__ pre,
-                                                 const double* __restrict__ q,
-                                                 const double* __restrict__ trialT,
-                                                 const uint8_t* __restrict__ alive,
-                                                 double* phibar, double* cp, int M, int N, int na,
-                                                 int nb) {
-    extern __shared__ double sm[];
-    const int w = blockIdx.x, spin = blockIdx.y;
-    const int off = spin ? na : 0, n = spin ? nb : na;
-    if (n == 0 || !alive[w]) return;
-    const int tid = threadIdx.x, nt = blockDim.x;
-    const int W = 2 * n;
-    double* aug = sm;
-    double* S = aug + 2 * n * W;   // n x n complex; first O(Q), then S
-    double* fac = S + 2 * n * n;
-    __shared__ int flag;
-    if (tid == 0) flag = 0;
-    const long NM = (long)N * M;
-    const double* pr = pre + (long)w * 2 * NM;
-    const double* qr = q + (long)w * 2 * NM;
-    __syncthreads();
-    build_overlap(trialT, pr, pr + NM, M, off, n, aug, tid, nt);
-    for (int e = tid; e < n * n; e += nt) {
-        const int a = e / n, b = e % n;
-        const double* t = trialT + (long)(off + a) * M;
-        const double* r = qr + (long)(off + b) * M;
-        const double* i = qr + NM + (long)(off + b) * M;
-        double sr = 0.0, si = 0.0;
-        for (int m = 0; m < M; ++m) {
-            sr += t[m] * r[m];
-            si += t[m] * i[m];
-        }
-        S[2 * e] = sr;
-        S[2 * e + 1] = si;
-    }
-    __syncthreads();
-    gj_inverse(aug, n, tid, nt, fac, &flag);
-    if (flag) return;
-    // S = Oinv_pre O_Q, written over the left half of aug (no longer needed)
-    for (int e = tid; e < n * n; e += nt) {
-        const int a = e / n, c = e % n;
-        double sr = 0.0, si = 0.0;
-        for (int b = 0; b < n; ++b) {
-            const double xr = aug[(a * W + n + b) * 2], xi = aug[(a * W + n + b) * 2 + 1];
-            const double yr = S[2 * (b * n + c)], yi = S[2 * (b * n + c) + 1];
-            sr += xr * yr - xi * yi;
-            si += xr * yi + xi * yr;
-        }
-        aug[(a * W + c) * 2] = sr;
-        aug[(a * W + c) * 2 + 1] = si;
-    }
-    double* gr = phibar + (long)w * 2 * NM;
-    double* gi = gr + NM;
-    double* cr = cp + (long)w * 2 * NM;
-    double* ci = cr + NM;
-    for (int e = tid; e < n * M; e += nt) {
-        const long o = (long)(off + e / M) * M + e % M;
-        cr[o] = gr[o];
-        ci[o] = gi[o];
-    }
-    __syncthreads();
-    for (int e = tid; e < n * M; e += nt) {
-        const int c = e / M, m = e % M;
-        double sr = 0.0, si = 0.0;
-        for (int b = 0; b < n; ++b) {
-            const double xr = cr[(long)(off + b) * M + m], xi = ci[(long)(off + b) * M + m];
-            const double sr_ = aug[(c * W + b) * 2], si_ = -aug[(c * W + b) * 2 + 1];  // conj S[c][b]
-            sr += xr * sr_ - xi * si_;
-            si += xr * si_ + xi * sr_;
-        }
-        gr[(long)(off + c) * M + m] = sr;
-        gi[(long)(off + c) * M + m] = si;
-    }
-}
-
-// y += x over n elements
-__global__ void k_axpy(double* __restrict__ y, const double* __restrict__ x, long n) {
-    const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) y[i] += x[i];
+// dst[w][r] = scale * src[w][r], r < per (walker strides sbs, dbs)
+__global__ void k_scale_copy(const double* __restrict__ src, long sbs, double* __restrict__ dst,
+                             long dbs, long per, int nw, double scale) {
+    const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= per * nw) return;
+    const long w = e / per, r = e % per;
+    dst[w * dbs + r] = scale * src[w * sbs + r];
 }
 
 // Zero the walker blocks of walkers that are not ACTIVE.
@@ -561,6 +314,7 @@ struct AdjState {
     uint64_t seed = 0;
     DType prec = DT_F64;
     bool ready = false;  // a forward pass is on the tape
+    bool taped = false;  // the forward pass recorded every step (one segment)
     double E = 0.0;
     std::vector<double> V;
     // constants
@@ -573,8 +327,8 @@ struct AdjState {
     std::vector<bool> t_mgs;
     std::vector<int64_t> t_t;
     // scratch
-    DevBuf xc, simp_s, apk, A, x, tA, tB, y, tT, tbT, ybar, Abar, Abpk, G, Fbar, thbar, phibar,
-        phibar2, wbar, wbar2, mode, lnrb, lnib, th_s, y_s, z, acc, ebuf, scale, Tb, U, vd, cp, part;
+    DevBuf xc, simp_s, apk, A, x, tA, y, tT, tbT, ybar, Abar, Abpk, G, Fbar, thbar, phibar,
+        phibar2, wbar, wbar2, mode, lnrb, lnib, z, acc, ebuf, scale, Tb, U, vd, part;
     // K ranges of G = <L_g, A_bar> (K = M(M+1)/2 is long, the output small)
     int g_ks = 1;
     DevBuf gws;
@@ -612,46 +366,15 @@ afqmc_status snap_restore(afqmc_sys s, const Snap& c, hipStream_t st) {
     return AFQMC_OK;
 }
 
-// C[w] (rows i, [w][2][N][M]) (+)= alpha * op(A_w) B[w], A_w complex symmetric
-// [w][2][M][M]; op = conj when conjA.  beta applies to the first product of
-// each output plane.
-hipError_t cgemm(const double* A, const double* B, double* C, double alpha, double beta, bool conjA,
-                 int nw, int M, int N, DType prec, hipStream_t st) {
-    const long NM = (long)N * M, MM = (long)M * M;
-    auto one = [&](int pa, int pb, int pc, double al, double be) {
-        Gemm g{};
-        g.A = B + pb * NM;
-        g.ta = DT_F64;
-        g.ra = rows_strided(M);
-        g.a_bs = 2 * NM;
-        g.B = A + pa * MM;
-        g.tb = DT_F64;
-        g.rb = rows_strided(M);
-        g.b_bs = 2 * MM;
-        g.C = C + pc * NM;
-        g.tc = DT_F64;
-        g.rc = rows_strided(M);
-        g.c_bs = 2 * NM;
-        g.alpha = al;
-        g.beta = be;
-        g.m = N;
-        g.n = M;
-        g.k = M;
-        g.batch = nw;
-        return gemm(g, prec, st);
-    };
-    const double sg = conjA ? -1.0 : 1.0;
-    hipError_t e;
-    // re: Ar Br - sg Ai Bi;  im: Ar Bi + sg Ai Br
-    if ((e = one(0, 0, 0, alpha, beta)) != hipSuccess) return e;
-    if ((e = one(1, 1, 0, -sg * alpha, 1.0)) != hipSuccess) return e;
-    if ((e = one(0, 1, 1, alpha, beta)) != hipSuccess) return e;
-    return one(1, 0, 1, sg * alpha, 1.0);
-}
-
-// rows (w, p, i) times a shared real symmetric M x M matrix
+// rows (w, p, i) times a shared real symmetric M x M matrix (output rows at rc)
+hipError_t rgemm(const double* R, const double* B, double* C, long rows, int M, DType prec,
+                 hipStream_t st, RowMap rc);
 hipError_t rgemm(const double* R, const double* B, double* C, long rows, int M, DType prec,
                  hipStream_t st) {
+    return rgemm(R, B, C, rows, M, prec, st, rows_strided(M));
+}
+hipError_t rgemm(const double* R, const double* B, double* C, long rows, int M, DType prec,
+                 hipStream_t st, RowMap rc) {
     Gemm g{};
     g.A = B;
     g.ta = DT_F64;
@@ -661,7 +384,7 @@ hipError_t rgemm(const double* R, const double* B, double* C, long rows, int M, 
     g.rb = rows_strided(M);
     g.C = C;
     g.tc = DT_F64;
-    g.rc = rows_strided(M);
+    g.rc = rc;
     g.alpha = 1.0;
     g.m = (int)rows;
     g.n = M;
@@ -703,6 +426,11 @@ afqmc_status adj_setup(afqmc_sys s, AdjState* a, hipStream_t st) {
         HIPCHK(a->vhalf.alloc(vh.size() * 8));
         HIPCHK(hipMemcpy(a->vhalf.p, vh.data(), vh.size() * 8, hipMemcpyHostToDevice));
     }
+    static bool lds_ready = false;  // process-wide kernel attribute
+    if (!lds_ready) {
+        HIPCHK(dense_adj_prepare());
+        lds_ready = true;
+    }
     if (a->lht.p) return AFQMC_OK;  // shape-dependent buffers already there
     const size_t rowb = (size_t)nw * 2 * NM * 8;
     HIPCHK(a->lht.alloc((size_t)NM * (nc + 1) * 8));
@@ -727,15 +455,15 @@ afqmc_status adj_setup(afqmc_sys s, AdjState* a, hipStream_t st) {
     } bufs[] = {
         {&a->xc, (size_t)nw * 2 * std::max(nc, 1) * 8}, {&a->simp_s, (size_t)nw * 4 * 8},
         {&a->apk, (size_t)nw * 2 * P * 8},   {&a->A, (size_t)nw * 2 * M * M * 8},
-        {&a->x, (size_t)nw * std::max(nc, 1) * 8}, {&a->tA, rowb}, {&a->tB, rowb}, {&a->y, rowb},
+        {&a->x, (size_t)nw * std::max(nc, 1) * 8}, {&a->tA, rowb}, {&a->y, rowb},
         {&a->tT, (size_t)nw * 2 * M * K * N * 8}, {&a->tbT, (size_t)nw * 2 * M * K * N * 8},
         {&a->ybar, rowb}, {&a->Abar, (size_t)nw * 2 * M * M * 8}, {&a->Abpk, (size_t)nw * 2 * P * 8},
         {&a->G, (size_t)nw * 2 * std::max(nc, 1) * 8}, {&a->Fbar, (size_t)nw * 2 * (nc + 1) * 8},
         {&a->thbar, rowb}, {&a->phibar, rowb}, {&a->phibar2, rowb}, {&a->wbar, (size_t)nw * 8},
         {&a->wbar2, (size_t)nw * 8}, {&a->mode, (size_t)nw}, {&a->lnrb, (size_t)nw * 16},
-        {&a->lnib, (size_t)nw * 8}, {&a->th_s, rowb}, {&a->y_s, rowb}, {&a->z, rowb},
+        {&a->lnib, (size_t)nw * 8}, {&a->z, rowb},
         {&a->acc, 64 * 8}, {&a->ebuf, 16}, {&a->scale, (size_t)nw * 8}, {&a->U, rowb},
-        {&a->vd, (size_t)nw * 2 * 8}, {&a->cp, rowb}, {&a->part, (size_t)nw * 8},
+        {&a->vd, (size_t)nw * 2 * 8}, {&a->part, (size_t)nw * 8},
     };
     for (auto& b : bufs) HIPCHK(b.b->alloc(b.n));
     a->g_ks = P >= 512 ? (int)std::min(8L, P / 256) : 1;
@@ -785,25 +513,40 @@ afqmc_status taped_step(afqmc_sys s, AdjState* a, int j, hipStream_t st) {
     return AFQMC_OK;
 }
 
-size_t det_shm(int n) { return (size_t)(2 * n * 2 * n + 2 * n * n + 2 * n + 1) * 8; }
+// Tape slots 0..n (n steps and the state after them).
+void tape_resize(AdjState* a, int n) {
+    for (auto* v : {&a->t_phi, &a->t_pre, &a->t_F, &a->t_lnov, &a->t_w, &a->t_alive, &a->t_simp,
+                    &a->t_lnd, &a->t_wout, &a->t_aout})
+        if ((int)v->size() < n + 1) v->resize(n + 1);
+    a->t_mgs.assign(n + 1, false);
+    a->t_t.assign(n + 1, 0);
+}
 
-afqmc_status det_adj(afqmc_sys s, AdjState* a, const double* phi, const double* thbar,
-                     const double* coef, double cscale, const uint8_t* mode, double* phibar,
-                     hipStream_t st) {
-    const int nmax = std::max(s->na, s->nb);
-    const size_t shm = det_shm(nmax);
-    static size_t allowed = 65536;
-    if (shm > allowed) {
-        HIPCHK(hipFuncSetAttribute((const void*)k_det_adj,
-                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm));
-        HIPCHK(hipFuncSetAttribute((const void*)k_mgs_adj,
-                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm));
-        allowed = shm;
-    }
-    hipLaunchKernelGGL(k_det_adj, dim3(s->nw, 2), dim3(256), shm, st, phi,
-                       s->d_trialT.as<double>(), thbar, coef, cscale, mode, phibar,
-                       a->th_s.as<double>(), a->y_s.as<double>(), s->M, s->N, s->na, s->nb);
-    HIPCHK(hipGetLastError());
+// The state after the last of n recorded steps into tape slot n.
+afqmc_status tape_end(afqmc_sys s, AdjState* a, int n, hipStream_t st) {
+    const size_t nphi = (size_t)s->nw * 2 * s->NM() * 8;
+    if (!a->t_phi[n].p) HIPCHK(a->t_phi[n].alloc(nphi));
+    HIPCHK(hipMemcpyAsync(a->t_phi[n].p, s->d_phi.p, nphi, hipMemcpyDeviceToDevice, st));
+    return AFQMC_OK;
+}
+
+afqmc_status det_adj(afqmc_sys s, const double* phi, const double* thbar, const double* coef,
+                     double cscale, const uint8_t* mode, double* phibar, hipStream_t st) {
+    DetAdj d{};
+    d.phi = phi;
+    d.trialT = s->d_trialT.as<double>();
+    d.thbar = thbar;
+    d.coef = coef;
+    d.cscale = cscale;
+    d.mode = mode;
+    d.active = ACTIVE;
+    d.phibar = phibar;
+    d.nw = s->nw;
+    d.M = s->M;
+    d.N = s->N;
+    d.na = s->na;
+    d.nb = s->nb;
+    HIPCHK(det_adjoint(d, st));
     return AFQMC_OK;
 }
 
@@ -840,13 +583,20 @@ afqmc_status reverse_step(afqmc_sys s, AdjState* a, int j, const double* phi_nex
     const double* phi_in = a->t_phi[j].as<double>();
     const double* phi_out = a->t_mgs[j] ? a->t_pre[j].as<double>() : phi_next;
     uint8_t* mode = a->mode.as<uint8_t>();
-    const int nmax = std::max(s->na, s->nb);
     // Gram-Schmidt after the step
     if (a->t_mgs[j]) {
-        hipLaunchKernelGGL(k_mgs_adj, dim3(nw, 2), dim3(256), det_shm(nmax), st, phi_out, phi_next,
-                           s->d_trialT.as<double>(), a->t_aout[j].as<uint8_t>(), pb,
-                           a->cp.as<double>(), M, N, s->na, s->nb);
-        HIPCHK(hipGetLastError());
+        MgsAdj g{};
+        g.pre = phi_out;
+        g.q = phi_next;
+        g.trialT = s->d_trialT.as<double>();
+        g.alive = a->t_aout[j].as<uint8_t>();
+        g.phibar = pb;
+        g.nw = nw;
+        g.M = M;
+        g.N = N;
+        g.na = s->na;
+        g.nb = s->nb;
+        HIPCHK(mgs_adjoint(g, st));
     }
     // weight update
     hipLaunchKernelGGL(k_adj_scalars, dim3(nblk(nw, 256)), dim3(256), 0, st,
@@ -858,7 +608,7 @@ afqmc_status reverse_step(afqmc_sys s, AdjState* a, int j, const double* phi_nex
     HIPCHK(hipGetLastError());
     hipLaunchKernelGGL(k_mask, dim3(nblk(nel, 256)), dim3(256), 0, st, pb, mode, 2 * NM, nw);
     // ln <phi_T|phi'> receives ln R_bar
-    afqmc_status r = det_adj(s, a, phi_out, nullptr, a->lnrb.as<double>(), 1.0, mode, pb, st);
+    afqmc_status r = det_adj(s, phi_out, nullptr, a->lnrb.as<double>(), 1.0, mode, pb, st);
     if (r != AFQMC_OK) return r;
     // A of the step (FP64), from the recorded force bias and the regenerated fields
     {
@@ -902,67 +652,72 @@ afqmc_status reverse_step(afqmc_sys s, AdjState* a, int j, const double* phi_nex
         HIPCHK(unpack_sym(a->apk.p, a->A.p, M, 2 * nw, DT_F64, st));
     }
     const double* A = a->A.as<double>();
-    const long KN = (long)K * N;
-    // forward terms: t_0 = P phi_in; t_n = A t_{n-1} / n; y = sum t_n
-    double* tp = a->tA.as<double>();
-    double* tc = a->tB.as<double>();
+    // Taylor tapes, one walker's K terms contiguous: [w][n][2][N][M]
+    const long TS = 2 * NM, KTS = (long)K * TS;
+    double* tt = a->tT.as<double>();   // t_n, n < K
+    double* tb = a->tbT.as<double>();  // t_bar_{n+1} / (n + 1), n < K
     double* y = a->y.as<double>();
-    HIPCHK(rgemm(s->d_P.as<double>(), phi_in, tp, rows, M, pr, st));
-    HIPCHK(hipMemcpyAsync(y, tp, nel * 8, hipMemcpyDeviceToDevice, st));
-    transpose(tp, a->tT.as<double>(), 2 * nw, N, M, KN, 0, 1.0, st);
+    // forward terms: t_0 = P phi_in; t_n = A t_{n-1} / n; y = sum_{n <= K} t_n
+    HIPCHK(rgemm(s->d_P.as<double>(), phi_in, tt, rows, M, pr, st, rows_2level(2 * N, M, KTS)));
     for (int n = 1; n <= K; ++n) {
-        HIPCHK(cgemm(A, tp, tc, 1.0 / n, 0.0, false, nw, M, N, pr, st));
-        hipLaunchKernelGGL(k_axpy, dim3(nblk(nel, 256)), dim3(256), 0, st, y, tc, nel);
-        if (n < K) transpose(tc, a->tT.as<double>(), 2 * nw, N, M, KN, (long)n * N, 1.0, st);
-        std::swap(tp, tc);
+        CTerm c{};
+        c.in = tt + (long)(n - 1) * TS;
+        c.in_bs = KTS;
+        c.A = A;
+        c.out = n < K ? tt + (long)n * TS : nullptr;
+        c.out_bs = KTS;
+        c.acc_in = n == 1 ? tt : y;
+        c.acc_in_bs = n == 1 ? KTS : TS;
+        c.acc_out = y;
+        c.acc_out_bs = TS;
+        c.alpha = 1.0 / n;
+        c.oscale = 1.0;
+        c.nw = nw;
+        c.M = M;
+        c.N = N;
+        HIPCHK(cterm(c, pr, st));
     }
     // dE/dlambda += <phi_bar', dP y>
     HIPCHK(rgemm(a->dP.as<double>(), y, a->z.as<double>(), rows, M, pr, st));
     dot_acc(pb, a->z.as<double>(), mode, 2 * NM, nw, a->part.as<double>(), a->acc.as<double>(),
             0, st);
-    // y_bar = P phi_bar'; Taylor terms backwards
+    // y_bar = P phi_bar'; t_bar_K = y_bar; t_bar_{n-1} = y_bar + conj(A) t_bar_n / n, with
+    // t_bar_n / n kept on the tape for A_bar and u_bar = t_bar_0
     double* yb = a->ybar.as<double>();
+    double* ub = a->tA.as<double>();
     HIPCHK(rgemm(s->d_P.as<double>(), pb, yb, rows, M, pr, st));
-    double* bp = a->tA.as<double>();  // t_bar_n
-    double* bc = a->tB.as<double>();  // t_bar_{n-1}
-    HIPCHK(hipMemcpyAsync(bp, yb, nel * 8, hipMemcpyDeviceToDevice, st));
+    hipLaunchKernelGGL(k_scale_copy, dim3(nblk((long)nw * TS, 256)), dim3(256), 0, st, yb, TS,
+                       tb + (long)(K - 1) * TS, KTS, TS, nw, 1.0 / K);
+    HIPCHK(hipGetLastError());
     for (int n = K; n >= 1; --n) {
-        transpose(bp, a->tbT.as<double>(), 2 * nw, N, M, KN, (long)(n - 1) * N, 1.0 / n, st);
-        HIPCHK(hipMemcpyAsync(bc, yb, nel * 8, hipMemcpyDeviceToDevice, st));
-        HIPCHK(cgemm(A, bp, bc, 1.0 / n, 1.0, true, nw, M, N, pr, st));
-        std::swap(bp, bc);
+        CTerm c{};
+        c.in = tb + (long)(n - 1) * TS;
+        c.in_bs = KTS;
+        c.A = A;
+        c.conj = 1;
+        c.base = yb;
+        c.base_bs = TS;
+        c.out = n >= 2 ? tb + (long)(n - 2) * TS : ub;
+        c.out_bs = n >= 2 ? KTS : TS;
+        c.alpha = 1.0;
+        c.oscale = n >= 2 ? 1.0 / (n - 1) : 1.0;
+        c.nw = nw;
+        c.M = M;
+        c.N = N;
+        HIPCHK(cterm(c, pr, st));
     }
-    double* ub = bp;  // u_bar = t_bar_0
-    // A_bar = sum_n (t_bar_n / n) t_{n-1}^H over the concatenated (n, i) index
+    // A_bar = sum_n (t_bar_n / n) t_{n-1}^H
     {
-        const long MM = (long)M * M, TS = (long)M * KN;
-        auto ag = [&](int pa, int pb_, int pc, double al, double be) {
-            Gemm g{};
-            g.A = a->tbT.as<double>() + pa * TS;
-            g.ta = DT_F64;
-            g.ra = rows_strided(KN);
-            g.a_bs = 2 * TS;
-            g.B = a->tT.as<double>() + pb_ * TS;
-            g.tb = DT_F64;
-            g.rb = rows_strided(KN);
-            g.b_bs = 2 * TS;
-            g.C = a->Abar.as<double>() + pc * MM;
-            g.tc = DT_F64;
-            g.rc = rows_strided(M);
-            g.c_bs = 2 * MM;
-            g.alpha = al;
-            g.beta = be;
-            g.m = M;
-            g.n = M;
-            g.k = (int)KN;
-            g.batch = nw;
-            return gemm(g, pr, st);
-        };
-        // re: tbr tr + tbi ti;  im: tbi tr - tbr ti
-        HIPCHK(ag(0, 0, 0, 1.0, 0.0));
-        HIPCHK(ag(1, 1, 0, 1.0, 1.0));
-        HIPCHK(ag(1, 0, 1, 1.0, 0.0));
-        HIPCHK(ag(0, 1, 1, -1.0, 1.0));
+        CAbar c{};
+        c.S = tb;
+        c.T = tt;
+        c.bs = KTS;
+        c.nq = K;
+        c.Abar = a->Abar.as<double>();
+        c.nw = nw;
+        c.M = M;
+        c.N = N;
+        HIPCHK(cabar(c, pr, st));
     }
     // G = <L_g, A_bar> through the packed upper triangle
     {
@@ -1002,7 +757,7 @@ afqmc_status reverse_step(afqmc_sys s, AdjState* a, int j, const double* phi_nex
     HIPCHK(rgemm(a->dP.as<double>(), phi_in, a->z.as<double>(), rows, M, pr, st));
     dot_acc(ub, a->z.as<double>(), mode, 2 * NM, nw, a->part.as<double>(), a->acc.as<double>(),
             0, st);
-    r = det_adj(s, a, phi_in, a->thbar.as<double>(), a->lnrb.as<double>(), -1.0, mode, pn, st);
+    r = det_adj(s, phi_in, a->thbar.as<double>(), a->lnrb.as<double>(), -1.0, mode, pn, st);
     if (r != AFQMC_OK) return r;
     hipLaunchKernelGGL(k_mask, dim3(nblk(nel, 256)), dim3(256), 0, st, pn, mode, 2 * NM, nw);
     std::swap(a->phibar.p, a->phibar2.p);
@@ -1077,7 +832,7 @@ afqmc_status energy_adjoint(afqmc_sys s, AdjState* a, hipStream_t st) {
         hipLaunchKernelGGL(k_exch_combine, dim3(nblk(2 * NM * nw, 256)), dim3(256), 0, st,
                            a->thbar.as<double>(), a->U.as<double>(), a->scale.as<double>(), NM, nw);
     HIPCHK(hipMemsetAsync(a->phibar.p, 0, a->phibar.n, st));
-    r = det_adj(s, a, s->d_phi.as<double>(), a->thbar.as<double>(), nullptr, 0.0,
+    r = det_adj(s, s->d_phi.as<double>(), a->thbar.as<double>(), nullptr, 0.0,
                 a->mode.as<uint8_t>(), a->phibar.as<double>(), st);
     if (r != AFQMC_OK) return r;
     // explicit term: sum_w (w/W) Re sum_s Tr(V^half_s Theta_s)
@@ -1127,7 +882,7 @@ afqmc_status afqmc_adjoint_forward(afqmc_sys s, const double* V, uint64_t seed, 
     if (s->n_det > 1) return fail(AFQMC_E_STATE, "adjoint with a multi-determinant trial");
     if (s->par.fb_cap > 0.0 && s->par.caps_enabled)
         return fail(AFQMC_E_STATE, "adjoint of a step with an applied force-bias cap");
-    if (std::max(s->na, s->nb) > kMaxSpin) return fail(AFQMC_E_SHAPE, "spin block above 48");
+    if (std::max(s->na, s->nb) > kMaxSpin) return fail(AFQMC_E_SHAPE, "spin block above 64");
     hipStream_t st = s->ham->stream;
     if (!s->adj) s->adj = new AdjState();
     AdjState* a = s->adj;
@@ -1140,14 +895,23 @@ afqmc_status afqmc_adjoint_forward(afqmc_sys s, const double* V, uint64_t seed, 
     a->V.assign(V, V + (size_t)s->M * s->M);
     if ((r = adj_setup(s, a, st)) != AFQMC_OK) return r;
     if ((int)a->ck.size() < a->n_seg) a->ck.resize(a->n_seg);
+    // one segment: the window is recorded now and the reverse pass recomputes
+    // nothing; otherwise snapshots only, each segment recorded again in reverse
+    a->taped = a->n_seg == 1;
+    if (a->taped) tape_resize(a, n_steps);
     for (int sg = 0; sg < a->n_seg; ++sg) {
         if ((r = snap_take(s, a->ck[sg], st)) != AFQMC_OK) return r;
         const int n = std::min(checkpoint_every, n_steps - sg * checkpoint_every);
         for (int i = 0; i < n; ++i) {
+            if (a->taped) {
+                if ((r = taped_step(s, a, i, st)) != AFQMC_OK) return r;
+                continue;
+            }
             if ((r = one_step(s, seed, 0, nullptr, st)) != AFQMC_OK) return r;
             if (s->par.ortho_every > 0 && s->t % s->par.ortho_every == 0)
                 if ((r = ortho(s, st)) != AFQMC_OK) return r;
         }
+        if (a->taped && (r = tape_end(s, a, n, st)) != AFQMC_OK) return r;
     }
     if ((r = snap_take(s, a->fin, st)) != AFQMC_OK) return r;
     if ((r = measure(s, st)) != AFQMC_OK) return r;
@@ -1168,24 +932,19 @@ afqmc_status afqmc_adjoint_backward(afqmc_sys s, double* dE) {
     if (!dE) return fail(AFQMC_E_INVALID, "dE is null");
     hipStream_t st = s->ham->stream;
     const int k = a->every;
-    for (auto* v : {&a->t_phi, &a->t_pre, &a->t_F, &a->t_lnov, &a->t_w, &a->t_alive, &a->t_simp,
-                    &a->t_lnd, &a->t_wout, &a->t_aout})
-        if ((int)v->size() < k + 1) v->resize(k + 1);
-    a->t_mgs.assign(k + 1, false);
-    a->t_t.assign(k + 1, 0);
+    if (!a->taped) tape_resize(a, k);
     HIPCHK(hipMemsetAsync(a->acc.p, 0, a->acc.n, st));
     // the end state: restore and take the energy adjoint
     if ((r = snap_restore(s, a->fin, st)) != AFQMC_OK) return r;
     if ((r = energy_adjoint(s, a, st)) != AFQMC_OK) return r;
     for (int sg = a->n_seg - 1; sg >= 0; --sg) {
         const int n = std::min(k, a->n_steps - sg * k);
-        if ((r = snap_restore(s, a->ck[sg], st)) != AFQMC_OK) return r;
-        for (int j = 0; j < n; ++j)
-            if ((r = taped_step(s, a, j, st)) != AFQMC_OK) return r;
-        // the state after the last step of the segment
-        if (!a->t_phi[n].p) HIPCHK(a->t_phi[n].alloc((size_t)s->nw * 2 * s->NM() * 8));
-        HIPCHK(hipMemcpyAsync(a->t_phi[n].p, s->d_phi.p, (size_t)s->nw * 2 * s->NM() * 8,
-                              hipMemcpyDeviceToDevice, st));
+        if (!a->taped) {
+            if ((r = snap_restore(s, a->ck[sg], st)) != AFQMC_OK) return r;
+            for (int j = 0; j < n; ++j)
+                if ((r = taped_step(s, a, j, st)) != AFQMC_OK) return r;
+            if ((r = tape_end(s, a, n, st)) != AFQMC_OK) return r;
+        }
         for (int j = n - 1; j >= 0; --j)
             if ((r = reverse_step(s, a, j, a->t_phi[j + 1].as<double>(), st)) != AFQMC_OK)
                 return r;

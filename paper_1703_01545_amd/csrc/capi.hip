@@ -63,10 +63,12 @@ const char* const kPhaseNames[PH_COUNT] = {
 int fb_ksplit(int k) {
     // a function of K = N M alone: the same K ranges, and so the same bits for
     // every walker, whatever the walker count, the batch a walker runs in or
-    // the device; about 1800 K per range above K = 8000 (9 ranges at the
-    // benchmark's K = 16000, which with 256 x 128 tiles fill 1008 workgroups
-    // on 256 CUs)
-    if (k < 8000) return std::max(1, std::min(8, k / 4000));
+    // the device; about 1000 K per range below K = 8000 (where the output is
+    // small and takes 64 x 64 tiles: 4 ranges at K = 4000 give 448 workgroups
+    // for 512 walkers and 401 columns, not 112), about 1800 K per range above
+    // (9 ranges at K = 16000, which with 256 x 128 tiles fill 1008 workgroups
+    // for 2048 walkers and 801 columns on 256 CUs)
+    if (k < 8000) return std::max(1, std::min(7, k / 1000));
     return std::max(4, std::min(12, (k + 900) / 1800));
 }
 

@@ -34,9 +34,28 @@ inline afqmc_status fail(afqmc_status s, const std::string& msg) {
 
 inline size_t dt_size(DType t) { return t == DT_F64 ? 8 : (t == DT_F32 ? 4 : 2); }
 
+// Owning device allocation: move-only, so that containers that grow (the
+// tape and snapshot vectors) move buffers instead of freeing copies of them.
 struct DevBuf {
     void* p = nullptr;
     size_t n = 0;
+    DevBuf() = default;
+    DevBuf(const DevBuf&) = delete;
+    DevBuf& operator=(const DevBuf&) = delete;
+    DevBuf(DevBuf&& o) noexcept : p(o.p), n(o.n) {
+        o.p = nullptr;
+        o.n = 0;
+    }
+    DevBuf& operator=(DevBuf&& o) noexcept {
+        if (this != &o) {
+            release();
+            p = o.p;
+            n = o.n;
+            o.p = nullptr;
+            o.n = 0;
+        }
+        return *this;
+    }
     ~DevBuf() { release(); }
     void release() {
         if (p) (void)hipFree(p);

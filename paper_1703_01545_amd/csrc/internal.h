@@ -66,6 +66,76 @@ hipError_t gemm(const Gemm& g, DType compute, hipStream_t s);
 int gemm_kchunk(int k, int ksplit);
 size_t gemm_ws_bytes(int m, int n, int ksplit, DType compute);
 
+// One complex Taylor term per walker on walker rows (planes [2][N][M], FP64
+// storage): C = in op(A)^T, op(A) = A or conj(A) (A complex symmetric,
+// [w][2][M][M]), o = (base + alpha C) oscale written to out, and
+// acc_out = acc_in + o (acc_in may equal acc_out).  base, out and acc_* are
+// optional (NULL; acc_in is required with acc_out); *_bs are walker strides in
+// doubles.
+struct CTerm {
+    const double* in;
+    long in_bs;
+    const double* A;
+    const double* base;
+    long base_bs;
+    double* out;
+    long out_bs;
+    const double* acc_in;
+    long acc_in_bs;
+    double* acc_out;
+    long acc_out_bs;
+    double alpha, oscale;
+    int conj;
+    int nw, M, N;
+};
+hipError_t cterm(const CTerm& c, DType compute, hipStream_t s);
+
+// A_bar[w] = sum_{q < nq} S_q^T conj(T_q): S, T tapes [w][q][2][N][M] (walker
+// stride bs), A_bar [w][2][M][M], overwritten.
+struct CAbar {
+    const double* S;
+    const double* T;
+    long bs;
+    int nq;
+    double* Abar;
+    int nw, M, N;
+};
+hipError_t cabar(const CAbar& c, DType compute, hipStream_t s);
+
+// Dense per-(walker, spin) adjoint kernels of spin blocks of up to 64
+// orbitals (walker rows [w][2][N][M], trialT [N][M]).
+// det_adjoint, for walkers with mode[w] == active:
+//   phibar += Y + Phi_T Z,  Z = coef O^{-H} - O^{-H} (Phi^H Theta_bar) O^{-H},
+//   Y = Theta_bar O^{-H},  O = Phi_T^T Phi,  coef = cscale coef[w] (complex)
+// (thbar NULL: Y = 0, no Theta_bar term; coef NULL: 0).  A walker whose
+// overlap has a zero pivot is left unchanged.
+struct DetAdj {
+    const double* phi;
+    const double* trialT;
+    const double* thbar;
+    const double* coef;
+    double cscale;
+    const uint8_t* mode;
+    uint8_t active;
+    double* phibar;
+    int nw, M, N, na, nb;
+};
+hipError_t det_adjoint(const DetAdj& a, hipStream_t s);
+// mgs_adjoint, for walkers with alive[w]: phibar <- phibar S^H,
+// S = O(pre)^{-1} O(q), O(X) = Phi_T^T X.
+struct MgsAdj {
+    const double* pre;
+    const double* q;
+    const double* trialT;
+    const uint8_t* alive;
+    double* phibar;
+    int nw, M, N, na, nb;
+};
+hipError_t mgs_adjoint(const MgsAdj& a, hipStream_t s);
+// Raise both kernels' LDS limit to what 64-orbital blocks need (once, outside
+// graph capture).
+hipError_t dense_adj_prepare();
+
 // Fragment-tiled layout of an M x M operand of the split-BF16 propagation:
 // rows padded to 16 (MT), columns to 32 (MP), stored as 1 KB tiles of 16 rows
 // x 32 columns ordered [row block][column chunk], inside a tile element

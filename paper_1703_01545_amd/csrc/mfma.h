@@ -52,6 +52,38 @@ __device__ __forceinline__ f4 mma8(bf8 a, bf8 b, f4 c) {
     return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
 }
 
+// Double held by lane l (wave-uniform result).
+__device__ __forceinline__ double rdlane(double v, int l) {
+    const unsigned long long x = __builtin_bit_cast(unsigned long long, v);
+    const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)x, l);
+    const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(x >> 32), l);
+    return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
+}
+
+// Maximum of a 64-bit key over the wavefront: DPP prefix maxima within rows
+// of 16 lanes (row_shr 1, 2, 4, 8), then across rows (row_bcast 15 into rows
+// 1 and 3, row_bcast 31 into rows 2 and 3); lane 63 ends with the maximum.
+template <int CTRL, int ROWS>
+__device__ __forceinline__ unsigned long long dpp_max_step(unsigned long long x) {
+    const int lo = (int)(unsigned)x, hi = (int)(unsigned)(x >> 32);
+    const unsigned l2 = (unsigned)__builtin_amdgcn_update_dpp(lo, lo, CTRL, ROWS, 0xF, false);
+    const unsigned h2 = (unsigned)__builtin_amdgcn_update_dpp(hi, hi, CTRL, ROWS, 0xF, false);
+    const unsigned long long y = ((unsigned long long)h2 << 32) | l2;
+    return y > x ? y : x;
+}
+
+__device__ __forceinline__ unsigned long long wave_max_u64(unsigned long long x) {
+    x = dpp_max_step<0x111, 0xF>(x);
+    x = dpp_max_step<0x112, 0xF>(x);
+    x = dpp_max_step<0x114, 0xF>(x);
+    x = dpp_max_step<0x118, 0xF>(x);
+    x = dpp_max_step<0x142, 0xA>(x);
+    x = dpp_max_step<0x143, 0xC>(x);
+    const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)x, 63);
+    const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(x >> 32), 63);
+    return ((unsigned long long)hi << 32) | lo;
+}
+
 // Row of accumulator element r held by lane l (see the layout note above).
 template <typename TC>
 __device__ __forceinline__ int acc_row(int lane, int r) {

@@ -39,7 +39,9 @@ def _oracle(ham, trial, na, nb, dt, nw, V, seed, burn, window, oe):
 
 
 @pytest.mark.parametrize("dims,every", [((12, 36, 3, 3, 16), 10), ((12, 36, 3, 2, 16), 7),
-                                        ((37, 75, 7, 6, 37), 6)])
+                                        ((37, 75, 7, 6, 37), 6), ((12, 36, 3, 2, 16), 20),
+                                        ((37, 75, 7, 6, 37), 25), ((60, 40, 40, 38, 8), 20),
+                                        ((70, 40, 50, 49, 8), 6), ((70, 40, 64, 33, 5), 7)])
 def test_adjoint_matches_oracle_tangent(lib, dims, every):
     M, nc, na, nb, nw = dims
     dt, oe, seed, burn, window = 0.01, 5, 21, 15, 20
@@ -81,6 +83,36 @@ def test_adjoint_matches_gpu_correlated_fd(lib):
         ep.append(sl.local_energy()[2])
     fd = (ep[0] - ep[1]) / (2 * eps)
     assert abs(dE - fd) <= 1e-6 * abs(fd), (dE, fd, E)
+
+
+def test_whole_window_tape_equals_segments(lib):
+    """checkpoint_every >= the window records every step in the forward pass,
+    and the reverse pass recomputes nothing; the energy and the derivative are
+    bitwise those of the segmented passes (the same kernels replay the same
+    trajectory), in both precisions.  One system runs every mode in turn, so
+    its tape grows and shrinks between passes; a fresh system gives the same."""
+    M, nc, na, nb, nw = 24, 72, 5, 4, 48
+    banner("adjoint whole-window tape vs segments")
+    ham, trial = _setup(M, nc, na, nb, hs=2)
+    V = perturbation(M, seed=3, scale=0.1)
+    H = lib.Hamiltonian(ham.h, ham.chol, ham.e_core)
+    for prec in ("fp64", "fp32"):
+        s = lib.System(H, na, nb, trial, nw, 0.01, ortho_every=5, measure_every=0,
+                       precision=prec)
+        s.step(10, seed=4)
+        snap = s.checkpoint()
+        out = []
+        for every in (7, 20, 50, 3, 20):
+            s.restore(snap)
+            E = s.adjoint_forward(V, 20, seed=4, checkpoint_every=every, precision=prec)
+            out.append((E, s.adjoint_backward(), s.adjoint_backward()))
+            assert s.info()["step"] == 30
+        f = lib.System(H, na, nb, trial, nw, 0.01, ortho_every=5, measure_every=0,
+                       precision=prec)
+        f.step(10, seed=4)
+        E = f.adjoint_forward(V, 20, seed=4, checkpoint_every=20, precision=prec)
+        out.append((E, f.adjoint_backward(), f.adjoint_backward()))
+        assert all(o == out[0] for o in out), out
 
 
 def test_adjoint_fp32_close_to_fp64(lib):
