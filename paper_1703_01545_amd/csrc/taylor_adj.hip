@@ -6,9 +6,11 @@
 // Each complex product is one kernel on the matrix cores (v_mfma_f64_16x16x4
 // for FP64 compute, v_mfma_f32_16x16x4 otherwise, both accumulating in their
 // own type): the real and imaginary planes of both operands are staged once
-// through LDS and the four real products accumulate side by side, so no
-// operand is fetched once per real product, the terms stay in the walker row
-// layout (no transpose), and the sums over terms happen in the epilogue.
+// through LDS and a complex product takes three real ones (Gauss's
+// (a + b)(c + d) - ac - bd for the imaginary part), accumulated side by side,
+// so no operand is fetched once per real product, the terms stay in the
+// walker row layout (no transpose), and the sums over terms happen in the
+// epilogue.
 #include "mfma.h"
 
 namespace afq {
@@ -101,12 +103,11 @@ __global__ __launch_bounds__(256, 3) void k_cterm(CTerm c, int ncb, int nrb) {
             ra[u] = ld_pair<AL>(A + a_p[u] * MM + (long)k * M + j, ok && j < M, ok && j + 1 < M);
         }
     };
-    accv acc_r[RT], acc_i[RT];
+    // three real products per complex one (Gauss): rr = in_r A_r, ii = in_i B_i,
+    // ss = (in_r + in_i)(A_r + B_i), B_i = sgn A_i; C = rr - ii + i (ss - rr - ii)
+    accv acc_rr[RT], acc_ii[RT], acc_ss[RT];
 #pragma unroll
-    for (int t = 0; t < RT; ++t) {
-        acc_r[t] = accv{0, 0, 0, 0};
-        acc_i[t] = accv{0, 0, 0, 0};
-    }
+    for (int t = 0; t < RT; ++t) acc_rr[t] = acc_ii[t] = acc_ss[t] = accv{0, 0, 0, 0};
     fetch(0);
     for (int k0 = 0; k0 < M; k0 += BK) {
 #pragma unroll
@@ -127,14 +128,14 @@ __global__ __launch_bounds__(256, 3) void k_cterm(CTerm c, int ncb, int nrb) {
             const int kk = ks + (lane >> 4);
             const ST br = s_a[0][kk][16 * wv + lr];
             const ST bi = s_a[1][kk][16 * wv + lr];
+            const ST bs = br + bi;
 #pragma unroll
             for (int t = 0; t < RT; ++t) {
                 const ST ar = s_in[0][16 * t + lr][kk];
                 const ST ai = s_in[1][16 * t + lr][kk];
-                acc_r[t] = mma1(ar, br, acc_r[t]);
-                acc_r[t] = mma1(-ai, bi, acc_r[t]);
-                acc_i[t] = mma1(ar, bi, acc_i[t]);
-                acc_i[t] = mma1(ai, br, acc_i[t]);
+                acc_rr[t] = mma1(ar, br, acc_rr[t]);
+                acc_ii[t] = mma1(ai, bi, acc_ii[t]);
+                acc_ss[t] = mma1(ar + ai, bs, acc_ss[t]);
             }
         }
         __syncthreads();  // every wave has read the chunk before it is replaced
@@ -152,7 +153,8 @@ __global__ __launch_bounds__(256, 3) void k_cterm(CTerm c, int ncb, int nrb) {
             const int i = i0 + 16 * t + acc_row<TC>(lane, r);
             if (i >= N) continue;
             const long o = (long)i * M + j;
-            double cr = c.alpha * (double)acc_r[t][r], ci = c.alpha * (double)acc_i[t][r];
+            const double rr = (double)acc_rr[t][r], ii = (double)acc_ii[t][r];
+            double cr = c.alpha * (rr - ii), ci = c.alpha * ((double)acc_ss[t][r] - rr - ii);
             if (base) {
                 cr += base[o];
                 ci += base[NM + o];
@@ -177,7 +179,7 @@ __global__ __launch_bounds__(256, 3) void k_cterm(CTerm c, int ncb, int nrb) {
 // outputs, wave v rows 16 v .. 16 v + 15 and all four column tiles.  Chunks
 // are fetched into registers while the previous one is multiplied.
 template <typename TC, bool AL>
-__global__ __launch_bounds__(256) void k_cabar(CAbar c, int nb1) {
+__global__ __launch_bounds__(256, 2) void k_cabar(CAbar c, int nb1) {
     typedef typename Info<TC>::ST ST;
     typedef typename AccT<TC>::v accv;
     constexpr int BO = 64, PJ = BO + 16;
@@ -217,12 +219,11 @@ __global__ __launch_bounds__(256) void k_cabar(CAbar c, int nb1) {
             rt[u] = ld_pair<AL>(T + ro + m, ok && m < M, ok && m + 1 < M);
         }
     };
-    accv acc_r[4], acc_i[4];
+    // three real products per complex one: rr = S_r T_r, ii = S_i T_i,
+    // ss = (S_r + S_i)(T_r - T_i); A_bar = rr + ii + i (ss - rr + ii)
+    accv acc_rr[4], acc_ii[4], acc_ss[4];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-        acc_r[u] = accv{0, 0, 0, 0};
-        acc_i[u] = accv{0, 0, 0, 0};
-    }
+    for (int u = 0; u < 4; ++u) acc_rr[u] = acc_ii[u] = acc_ss[u] = accv{0, 0, 0, 0};
     if (KC > 0) fetch(0);
     for (int c0 = 0; c0 < KC; c0 += BK) {
 #pragma unroll
@@ -239,14 +240,14 @@ __global__ __launch_bounds__(256) void k_cabar(CAbar c, int nb1) {
             const int kk = ks + (lane >> 4);
             const ST ar = s_s[0][kk][16 * wv + lr];
             const ST ai = s_s[1][kk][16 * wv + lr];
+            const ST as = ar + ai;
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
                 const ST br = s_t[0][kk][16 * u + lr];
                 const ST bi = s_t[1][kk][16 * u + lr];
-                acc_r[u] = mma1(ar, br, acc_r[u]);
-                acc_r[u] = mma1(ai, bi, acc_r[u]);
-                acc_i[u] = mma1(ai, br, acc_i[u]);
-                acc_i[u] = mma1(-ar, bi, acc_i[u]);
+                acc_rr[u] = mma1(ar, br, acc_rr[u]);
+                acc_ii[u] = mma1(ai, bi, acc_ii[u]);
+                acc_ss[u] = mma1(as, br - bi, acc_ss[u]);
             }
         }
         __syncthreads();
@@ -260,8 +261,9 @@ __global__ __launch_bounds__(256) void k_cabar(CAbar c, int nb1) {
         for (int r = 0; r < 4; ++r) {
             const int j = j0 + 16 * wv + acc_row<TC>(lane, r);
             if (j >= M) continue;
-            out[(long)j * M + m] = (double)acc_r[u][r];
-            out[MM + (long)j * M + m] = (double)acc_i[u][r];
+            const double rr = (double)acc_rr[u][r], ii = (double)acc_ii[u][r];
+            out[(long)j * M + m] = rr + ii;
+            out[MM + (long)j * M + m] = (double)acc_ss[u][r] - rr + ii;
         }
     }
 }
