@@ -82,14 +82,23 @@ struct Rows {
 // exchange steps, no row movement): step k pivots on (p_k, k), p_k the row not
 // yet used with the largest |Re| + |Im| in column k (near-ties, 2^-46
 // relative, to the lower row), and afterwards A^{-1}(i, j) = X(p_i, q_j) with
-// q the inverse of k -> p_k.  Thread (wave v, lane j) updates column j of rows
-// v, v + 4, ...; every wave finds the pivot itself, so a step takes two
-// barriers.  Returns false (for every thread) on a zero pivot.
-template <int RW>
+// q the inverse of k -> p_k.  The n^2 entries are dealt to the threads as
+// e = tid + 256 u (row e / n, column e % n, worked out once); every wave
+// finds the pivot itself, so a step takes two barriers.  EPT >= n^2 / 256.
+// Returns false (for every thread) on a zero pivot.
+template <int EPT>
 __device__ bool sweep_inverse(double* X, const Lay& L, int n, int* perm, int* pinv) {
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, j = lane;
+    const int tid = threadIdx.x, lane = tid & 63;
+    int er[EPT], ec[EPT];
+#pragma unroll
+    for (int u = 0; u < EPT; ++u) {
+        const int e = tid + 256 * u;
+        const bool ok = e < n * n;
+        er[u] = ok ? e / n : L.NP - 1;  // out-of-range entries read a padding row
+        ec[u] = ok ? e % n : -1;
+    }
     bool used = false;  // row `lane` has been a pivot row (the same in every wave)
-    double nr[RW], ni[RW];
+    double nr[EPT], ni[EPT];
     for (int k = 0; k < n; ++k) {
         const bool cand = lane < n && !used;
         const double v = cand ? fabs(MRE(X, lane, k)) + fabs(MIM(X, lane, k)) : 0.0;
@@ -101,67 +110,58 @@ __device__ bool sweep_inverse(double* X, const Lay& L, int n, int* perm, int* pi
         if ((kmax >> 6) == 0) return false;
         const int p = 63 - (int)(kmax & 63);
         if (lane == p) used = true;
-        if (threadIdx.x == 0) {
+        if (tid == 0) {
             perm[k] = p;
             pinv[p] = k;
         }
         const double pr = MRE(X, p, k), pi = MIM(X, p, k);
         const double den = pr * pr + pi * pi;
         const double ir = pr / den, ii = -pi / den;
-        double qr = ir, qi = ii;  // the new pivot-row entry of column j
-        if (j < n && j != k) {
-            const double xr = MRE(X, p, j), xi = MIM(X, p, j);
-            qr = xr * ir - xi * ii;
-            qi = xr * ii + xi * ir;
-        }
-        // every read first (clamped into the padded block, results unused
-        // where out of range), then the arithmetic, so the reads overlap
-        const int jc = j < L.NP ? j : L.NP - 1;
-        double fr[RW], fi[RW];
+        // every read first, then the arithmetic, so the reads overlap:
+        //   pivot row p: X(p, j) / piv (j != k), 1 / piv (j == k)
+        //   other rows:  X(r, j) - X(r, k) X(p, j) / piv (j != k), -X(r, k) / piv (j == k)
+        double fr[EPT], fi[EPT], br[EPT], bi[EPT];
 #pragma unroll
-        for (int u = 0; u < RW; ++u) {
-            const int r = wv + 4 * u < L.NP ? wv + 4 * u : L.NP - 1;
-            fr[u] = MRE(X, r, k);
-            fi[u] = MIM(X, r, k);
-            nr[u] = MRE(X, r, jc);
-            ni[u] = MIM(X, r, jc);
+        for (int u = 0; u < EPT; ++u) {
+            const int c = ec[u] < 0 ? 0 : ec[u];
+            fr[u] = MRE(X, er[u], k);
+            fi[u] = MIM(X, er[u], k);
+            nr[u] = MRE(X, er[u], c);
+            ni[u] = MIM(X, er[u], c);
+            br[u] = MRE(X, p, c);
+            bi[u] = MIM(X, p, c);
         }
 #pragma unroll
-        for (int u = 0; u < RW; ++u) {
-            const double gr = j == k ? 0.0 : nr[u], gi = j == k ? 0.0 : ni[u];
-            const double hr = j == k ? ir : qr, hi = j == k ? ii : qi;
-            nr[u] = gr - (fr[u] * hr - fi[u] * hi);
-            ni[u] = gi - (fr[u] * hi + fi[u] * hr);
+        for (int u = 0; u < EPT; ++u) {
+            const bool col_k = ec[u] == k, row_p = er[u] == p;
+            const double bq_r = col_k ? 1.0 : br[u], bq_i = col_k ? 0.0 : bi[u];
+            const double qr = bq_r * ir - bq_i * ii, qi = bq_r * ii + bq_i * ir;  // new pivot-row entry
+            const double gr = col_k ? 0.0 : nr[u], gi = col_k ? 0.0 : ni[u];
+            nr[u] = row_p ? qr : gr - (fr[u] * qr - fi[u] * qi);
+            ni[u] = row_p ? qi : gi - (fr[u] * qi + fi[u] * qr);
         }
         __syncthreads();
 #pragma unroll
-        for (int u = 0; u < RW; ++u) {
-            const int r = wv + 4 * u;
-            if (r < n && j < n) {
-                MRE(X, r, j) = r == p ? qr : nr[u];
-                MIM(X, r, j) = r == p ? qi : ni[u];
+        for (int u = 0; u < EPT; ++u)
+            if (ec[u] >= 0) {
+                MRE(X, er[u], ec[u]) = nr[u];
+                MIM(X, er[u], ec[u]) = ni[u];
             }
-        }
         __syncthreads();
     }
 #pragma unroll
-    for (int u = 0; u < RW; ++u) {
-        const int i = wv + 4 * u;
-        nr[u] = ni[u] = 0.0;
-        if (i < n && j < n) {
-            nr[u] = MRE(X, perm[i], pinv[j]);
-            ni[u] = MIM(X, perm[i], pinv[j]);
-        }
+    for (int u = 0; u < EPT; ++u) {
+        const int c = ec[u] < 0 ? 0 : ec[u];
+        nr[u] = MRE(X, perm[er[u] < n ? er[u] : 0], pinv[c]);
+        ni[u] = MIM(X, perm[er[u] < n ? er[u] : 0], pinv[c]);
     }
     __syncthreads();
 #pragma unroll
-    for (int u = 0; u < RW; ++u) {
-        const int i = wv + 4 * u;
-        if (i < n && j < n) {
-            MRE(X, i, j) = nr[u];
-            MIM(X, i, j) = ni[u];
+    for (int u = 0; u < EPT; ++u)
+        if (ec[u] >= 0) {
+            MRE(X, er[u], ec[u]) = nr[u];
+            MIM(X, er[u], ec[u]) = ni[u];
         }
-    }
     __syncthreads();
     return true;
 }
@@ -335,7 +335,7 @@ __device__ void update_pass(const double* __restrict__ T, const double* __restri
 // largest padded order served; tiles per wave and rows per thread follow).
 template <int NPMAX>
 __global__ __launch_bounds__(256) void k_det_adj(DetAdj a) {
-    constexpr int TPW = (NPMAX / 16) * (NPMAX / 16) / 4, RW = NPMAX / 4;
+    constexpr int TPW = (NPMAX / 16) * (NPMAX / 16) / 4, EPT = NPMAX * NPMAX / 256;
     extern __shared__ double sm[];
     __shared__ int perm[kMaxBlock], pinv[kMaxBlock];
     const int w = blockIdx.x, spin = blockIdx.y;
@@ -354,7 +354,7 @@ __global__ __launch_bounds__(256) void k_det_adj(DetAdj a) {
     put_tiles<TPW>(o, Oi, L);
     if (tb) put_tiles<TPW>(c, Cm, L);
     __syncthreads();
-    if (!sweep_inverse<RW>(Oi, L, n, perm, pinv)) return;  // singular: a frozen walker
+    if (!sweep_inverse<EPT>(Oi, L, n, perm, pinv)) return;  // singular: a frozen walker
     const int NT1 = L.NP / 16, NT = NT1 * NT1;
     double cr = 0.0, ci = 0.0;
     if (a.coef) {
@@ -454,7 +454,7 @@ __global__ __launch_bounds__(256) void k_det_adj(DetAdj a) {
 // Phi_bar <- Phi_bar S^H with S = O(pre)^{-1} O(Q), O(X) = Phi_T^T X.
 template <int NPMAX>
 __global__ __launch_bounds__(256) void k_mgs_adj(MgsAdj a) {
-    constexpr int TPW = (NPMAX / 16) * (NPMAX / 16) / 4, RW = NPMAX / 4;
+    constexpr int TPW = (NPMAX / 16) * (NPMAX / 16) / 4, EPT = NPMAX * NPMAX / 256;
     extern __shared__ double sm[];
     __shared__ int perm[kMaxBlock], pinv[kMaxBlock];
     const int w = blockIdx.x, spin = blockIdx.y;
@@ -473,7 +473,7 @@ __global__ __launch_bounds__(256) void k_mgs_adj(MgsAdj a) {
     put_tiles<TPW>(o, Op, L);
     put_tiles<TPW>(c, Oq, L);
     __syncthreads();
-    if (!sweep_inverse<RW>(Op, L, n, perm, pinv)) return;
+    if (!sweep_inverse<EPT>(Op, L, n, perm, pinv)) return;
     const int NT1 = L.NP / 16, NT = NT1 * NT1;
     // S = O(pre)^{-1} O(Q)
     d4 v[TPW][2];
