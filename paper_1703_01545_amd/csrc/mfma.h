@@ -138,12 +138,25 @@ struct Info<Split> {
     typedef bf16_t LT;
 };
 
-// LDS row pitch in elements: odd word strides for 4/8-byte types, 16-byte
-// aligned rows (+8 elements) for BF16 so fragments load as one 16-byte read.
+// LDS row pitch in elements: odd word strides for 4/8-byte types; BF16 rows
+// unpadded (BK = 32: 64 bytes), their 16-byte granules swizzled (see lds_index).
 template <typename TC, int BK>
 struct Pitch {
-    static constexpr int v = BK + (sizeof(typename Info<TC>::LT) == 2 ? 8 : 1);
+    static constexpr int v = BK + (sizeof(typename Info<TC>::LT) == 2 ? 0 : 1);
 };
+
+// LDS element index of (row r, k) in a tile of pitch PK.  BF16 tiles (PK =
+// 32): granule k / 8 of row r is stored at granule (k / 8) ^ ((r / 4) % 4), so
+// that 16 consecutive rows reading one granule (a fragment load, 16 lanes per
+// LDS cycle) and four consecutive rows written 8 bytes per lane (32 lanes per
+// cycle) each cover the 64 banks once.
+template <typename LT, int PK>
+__device__ __forceinline__ int lds_index(int r, int k) {
+    if constexpr (sizeof(LT) == 2)
+        return r * PK + ((((k >> 3) ^ (r >> 2)) & 3) << 3) + (k & 7);
+    else
+        return r * PK + k;
+}
 
 // Store one staged value into the LDS plane(s) of compute type TC.
 template <typename TC>
@@ -234,6 +247,7 @@ struct Core {
     static_assert(BK % VA == 0 && BK % VB == 0 && NT % TPRA == 0 && NT % TPRB == 0, "loads");
     static_assert(LA >= 1 && LB >= 1 && BM % RPA == 0 && BN % RPB == 0, "loads");
     static_assert(BK % Info<TC>::KM == 0, "bk");
+    static_assert(sizeof(LT) != 2 || BK == 32, "swizzled BF16 tiles hold 32 k");
 
     // per-thread rows: r = tid / TPR + j * RP
     static __device__ __forceinline__ int arow(int j) { return threadIdx.x / TPRA + j * RPA; }
@@ -266,24 +280,22 @@ struct Core {
                 bf8 ah[TM], bh[TN];
 #pragma unroll
                 for (int a = 0; a < TM; ++a)
-                    ah[a] = *reinterpret_cast<const bf8*>(
-                        &As[(wm * TM * 16 + a * 16 + (lane & 15)) * PK + ks + 8 * (lane >> 4)]);
+                    ah[a] = *reinterpret_cast<const bf8*>(&As[lds_index<LT, PK>(
+                        wm * TM * 16 + a * 16 + (lane & 15), ks + 8 * (lane >> 4))]);
 #pragma unroll
                 for (int b = 0; b < TN; ++b)
-                    bh[b] = *reinterpret_cast<const bf8*>(
-                        &Bs[(wn * TN * 16 + b * 16 + (lane & 15)) * PK + ks + 8 * (lane >> 4)]);
+                    bh[b] = *reinterpret_cast<const bf8*>(&Bs[lds_index<LT, PK>(
+                        wn * TN * 16 + b * 16 + (lane & 15), ks + 8 * (lane >> 4))]);
                 if constexpr (PL == 2) {
                     bf8 al[TM], bl[TN];
 #pragma unroll
                     for (int a = 0; a < TM; ++a)
-                        al[a] = *reinterpret_cast<const bf8*>(
-                            &As[BM * PK + (wm * TM * 16 + a * 16 + (lane & 15)) * PK + ks +
-                                8 * (lane >> 4)]);
+                        al[a] = *reinterpret_cast<const bf8*>(&As[BM * PK + lds_index<LT, PK>(
+                            wm * TM * 16 + a * 16 + (lane & 15), ks + 8 * (lane >> 4))]);
 #pragma unroll
                     for (int b = 0; b < TN; ++b)
-                        bl[b] = *reinterpret_cast<const bf8*>(
-                            &Bs[BN * PK + (wn * TN * 16 + b * 16 + (lane & 15)) * PK + ks +
-                                8 * (lane >> 4)]);
+                        bl[b] = *reinterpret_cast<const bf8*>(&Bs[BN * PK + lds_index<LT, PK>(
+                            wn * TN * 16 + b * 16 + (lane & 15), ks + 8 * (lane >> 4))]);
 #pragma unroll
                     for (int a = 0; a < TM; ++a)
 #pragma unroll
@@ -345,23 +357,23 @@ struct Core {
                 for (int j = 0; j < LA; ++j)
 #pragma unroll
                     for (int e = 0; e < VA; e += 4)
-                        lds_put4<TC>(Ad, BM * PK, arow(j) * PK + ka + e, &ra[j][e]);
+                        lds_put4<TC>(Ad, BM * PK, lds_index<LT, PK>(arow(j), ka + e), &ra[j][e]);
 #pragma unroll
                 for (int j = 0; j < LB; ++j)
 #pragma unroll
                     for (int e = 0; e < VB; e += 4)
-                        lds_put4<TC>(Bd, BN * PK, brow(j) * PK + kb + e, &rb[j][e]);
+                        lds_put4<TC>(Bd, BN * PK, lds_index<LT, PK>(brow(j), kb + e), &rb[j][e]);
             } else {
 #pragma unroll
                 for (int j = 0; j < LA; ++j)
 #pragma unroll
                     for (int e = 0; e < VA; ++e)
-                        lds_put<TC>(Ad, BM * PK, arow(j) * PK + ka + e, ra[j][e]);
+                        lds_put<TC>(Ad, BM * PK, lds_index<LT, PK>(arow(j), ka + e), ra[j][e]);
 #pragma unroll
                 for (int j = 0; j < LB; ++j)
 #pragma unroll
                     for (int e = 0; e < VB; ++e)
-                        lds_put<TC>(Bd, BN * PK, brow(j) * PK + kb + e, rb[j][e]);
+                        lds_put<TC>(Bd, BN * PK, lds_index<LT, PK>(brow(j), kb + e), rb[j][e]);
             }
         };
 
