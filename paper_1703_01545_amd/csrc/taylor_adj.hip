@@ -41,12 +41,14 @@ __device__ __forceinline__ d2 ld_pair(const double* __restrict__ p, bool ok0, bo
 // orbital column i): C = in op(A)^T with op(A) = A_r + i sgn A_i (A complex
 // symmetric, sgn = -1 for conj), o = (base + alpha C) oscale -> out, and
 // acc_out = acc_in + o.  Workgroup: 16 RT rows x 64 columns of C; wave v owns
-// columns 16 v .. 16 v + 15 of the block and all RT row tiles.  Each BK chunk
-// of the contraction is fetched into registers while the previous one is
-// multiplied out of LDS; A is staged through its symmetry as rows k (columns
-// j contiguous), so a chunk of it is BK runs of 64 consecutive elements.
+// columns 16 v .. 16 v + 15 of the block and all RT row tiles.  The
+// contraction runs in BK chunks through two LDS buffers: while chunk c is
+// multiplied, chunk c + 1 (fetched into registers during chunk c - 1) is
+// stored into the other buffer and chunk c + 2 is fetched, one barrier per
+// chunk; A is staged through its symmetry as rows k (columns j contiguous),
+// so a chunk of it is BK runs of 64 consecutive elements.
 template <typename TC, int RT, bool AL>
-__global__ __launch_bounds__(256, 3) void k_cterm(CTerm c, int ncb, int nrb) {
+__global__ __launch_bounds__(256, 2) void k_cterm(CTerm c, int ncb, int nrb) {
     typedef typename Info<TC>::ST ST;
     typedef typename AccT<TC>::v accv;
     constexpr int BI = 16 * RT, PK = BK + 1;
@@ -55,8 +57,9 @@ __global__ __launch_bounds__(256, 3) void k_cterm(CTerm c, int ncb, int nrb) {
     constexpr int PJ = BJ + 16;
     constexpr int NIN = RT;  // pairs of the rows chunk per thread (2 BI BK / 2 / 256)
     constexpr int NA = 4;    // pairs of the A chunk per thread (2 BK BJ / 2 / 256)
-    __shared__ ST s_in[2][BI][PK];
-    __shared__ ST s_a[2][BK][PJ];
+    // two LDS buffers: chunk c + 1 is stored while chunk c is multiplied
+    __shared__ ST s_in[2][2][BI][PK];
+    __shared__ ST s_a[2][2][BK][PJ];
     const long nb = (long)ncb * nrb * c.nw;
     const long L = xcd_block(nb);
     if (L >= nb) return;
@@ -108,37 +111,47 @@ __global__ __launch_bounds__(256, 3) void k_cterm(CTerm c, int ncb, int nrb) {
     accv acc_rr[RT], acc_ii[RT], acc_ss[RT];
 #pragma unroll
     for (int t = 0; t < RT; ++t) acc_rr[t] = acc_ii[t] = acc_ss[t] = accv{0, 0, 0, 0};
-    fetch(0);
-    for (int k0 = 0; k0 < M; k0 += BK) {
+    auto stash = [&](int buf) {
 #pragma unroll
         for (int u = 0; u < NIN; ++u) {
-            s_in[in_p[u]][in_r[u]][in_k[u]] = (ST)rin[u][0];
-            s_in[in_p[u]][in_r[u]][in_k[u] + 1] = (ST)rin[u][1];
+            s_in[buf][in_p[u]][in_r[u]][in_k[u]] = (ST)rin[u][0];
+            s_in[buf][in_p[u]][in_r[u]][in_k[u] + 1] = (ST)rin[u][1];
         }
 #pragma unroll
         for (int u = 0; u < NA; ++u) {
             const ST f = a_p[u] ? sgn : (ST)1;
-            s_a[a_p[u]][a_k[u]][a_j[u]] = f * (ST)ra[u][0];
-            s_a[a_p[u]][a_k[u]][a_j[u] + 1] = f * (ST)ra[u][1];
+            s_a[buf][a_p[u]][a_k[u]][a_j[u]] = f * (ST)ra[u][0];
+            s_a[buf][a_p[u]][a_k[u]][a_j[u] + 1] = f * (ST)ra[u][1];
         }
-        __syncthreads();
-        if (k0 + BK < M) fetch(k0 + BK);
+    };
+    fetch(0);
+    stash(0);
+    if (BK < M) fetch(BK);
+    __syncthreads();
+    int cur = 0;
+    for (int k0 = 0; k0 < M; k0 += BK) {
 #pragma unroll
         for (int ks = 0; ks < BK; ks += 4) {
             const int kk = ks + (lane >> 4);
-            const ST br = s_a[0][kk][16 * wv + lr];
-            const ST bi = s_a[1][kk][16 * wv + lr];
+            const ST br = s_a[cur][0][kk][16 * wv + lr];
+            const ST bi = s_a[cur][1][kk][16 * wv + lr];
             const ST bs = br + bi;
 #pragma unroll
             for (int t = 0; t < RT; ++t) {
-                const ST ar = s_in[0][16 * t + lr][kk];
-                const ST ai = s_in[1][16 * t + lr][kk];
+                const ST ar = s_in[cur][0][16 * t + lr][kk];
+                const ST ai = s_in[cur][1][16 * t + lr][kk];
                 acc_rr[t] = mma1(ar, br, acc_rr[t]);
                 acc_ii[t] = mma1(ai, bi, acc_ii[t]);
                 acc_ss[t] = mma1(ar + ai, bs, acc_ss[t]);
             }
         }
-        __syncthreads();  // every wave has read the chunk before it is replaced
+        // the other buffer was last read before the previous barrier
+        if (k0 + BK < M) {
+            stash(cur ^ 1);
+            if (k0 + 2 * BK < M) fetch(k0 + 2 * BK);
+        }
+        __syncthreads();
+        cur ^= 1;
     }
     const int j = j0 + 16 * wv + lr;
     if (j >= M) return;
