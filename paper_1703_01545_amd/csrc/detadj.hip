@@ -305,23 +305,29 @@ __device__ void update_pass(const double* __restrict__ T, const double* __restri
         if (m0 + W2 < M) fetch(m0 + W2);
         for (int t = wv; t < NTU; t += 4) {
             const int c0 = (t / CT) * 16, mc = (t % CT) * 16;
+            const int m = m0 + mc + lr;
+            // the accumulated values are read before the products, so that
+            // their latency overlaps the matrix cores
+            double pr[4], pi[4];
+            bool ok[4];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int row = c0 + acc_row<double>(lane, r);
+                ok[r] = m < M && row < n;
+                pr[r] = pi[r] = 0.0;
+                if (ADD && ok[r]) {
+                    pr[r] = gb[(long)row * M + m];
+                    pi[r] = gb[NM + (long)row * M + m];
+                }
+            }
             d4 dr = {0, 0, 0, 0}, di = {0, 0, 0, 0};
             tile(c0, mc, dr, di);
-            const int m = m0 + mc + lr;
-            if (m < M)
 #pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const int row = c0 + acc_row<double>(lane, r);
-                    if (row < n) {
-                        double* q = gb + (long)row * M + m;
-                        if (ADD) {
-                            q[0] += dr[r];
-                            q[NM] += di[r];
-                        } else {
-                            q[0] = dr[r];
-                            q[NM] = di[r];
-                        }
-                    }
+            for (int r = 0; r < 4; ++r)
+                if (ok[r]) {
+                    double* q = gb + (long)(c0 + acc_row<double>(lane, r)) * M + m;
+                    q[0] = pr[r] + dr[r];
+                    q[NM] = pi[r] + di[r];
                 }
         }
         __syncthreads();
@@ -334,7 +340,7 @@ __device__ void update_pass(const double* __restrict__ T, const double* __restri
 // (Theta_bar NULL: Y = 0 and no C term; coef NULL: 0).  NPMAX: 32 or 64 (the
 // largest padded order served; tiles per wave and rows per thread follow).
 template <int NPMAX>
-__global__ __launch_bounds__(256) void k_det_adj(DetAdj a) {
+__global__ __launch_bounds__(256, NPMAX <= 32 ? 3 : 1) void k_det_adj(DetAdj a) {
     constexpr int TPW = (NPMAX / 16) * (NPMAX / 16) / 4, EPT = NPMAX * NPMAX / 256;
     extern __shared__ double sm[];
     __shared__ int perm[kMaxBlock], pinv[kMaxBlock];
