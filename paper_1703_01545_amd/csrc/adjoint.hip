@@ -157,22 +157,34 @@ __global__ __launch_bounds__(256) void k_adj_fbar(const double* __restrict__ F, 
 }
 
 // Packed symmetric contraction weights of A_bar: q(i <= j) -> A_ij + A_ji
-// (i < j), A_ii.  [w][2][M][M] -> [w][2][P]
-__global__ void k_adj_pack(const double* __restrict__ Af, double* __restrict__ Apk, int M,
-                           long planes) {
+// (i < j), A_ii.  [w][2][M][M] -> [w][2][P].  One workgroup per 32 x 32 tile
+// (bi <= bj) of the upper triangle of one plane: the mirror tile (bj, bi)
+// goes through LDS so that both reads and the packed writes are coalesced.
+__global__ __launch_bounds__(256) void k_adj_pack(const double* __restrict__ Af,
+                                                  double* __restrict__ Apk, int M, int nt) {
+    __shared__ double tt[32][33];
+    const long pl = blockIdx.y;
     const long P = (long)M * (M + 1) / 2;
-    const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= planes * P) return;
-    const long pl = e / P;
-    long q = e % P;
-    int i = 0;
-    while (q >= M - i) {
-        q -= M - i;
-        ++i;
+    int t = blockIdx.x, bi = 0;
+    while (t >= nt - bi) {  // nt <= 8
+        t -= nt - bi;
+        ++bi;
     }
-    const int j = i + (int)q;
+    const int bj = bi + t;
     const double* A = Af + pl * (long)M * M;
-    Apk[e] = i == j ? A[(long)i * M + i] : A[(long)i * M + j] + A[(long)j * M + i];
+    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+    for (int r = ty; r < 32; r += 8) {
+        const int j = bj * 32 + r, i = bi * 32 + tx;
+        tt[r][tx] = (j < M && i < M) ? A[(long)j * M + i] : 0.0;
+    }
+    __syncthreads();
+    for (int r = ty; r < 32; r += 8) {
+        const int i = bi * 32 + r, j = bj * 32 + tx;
+        if (i < M && j < M && i <= j) {
+            const double v = i == j ? A[(long)i * M + i] : A[(long)i * M + j] + tt[tx][r];
+            Apk[pl * P + (long)i * M - (long)i * (i - 1) / 2 + (j - i)] = v;
+        }
+    }
 }
 
 // dst[w][r] = scale * src[w][r], r < per (walker strides sbs, dbs)
@@ -722,8 +734,9 @@ afqmc_status reverse_step(afqmc_sys s, AdjState* a, int j, const double* phi_nex
     // G = <L_g, A_bar> through the packed upper triangle
     {
         const long P = s->P();
-        hipLaunchKernelGGL(k_adj_pack, dim3(nblk(2L * nw * P, 256)), dim3(256), 0, st,
-                           a->Abar.as<double>(), a->Abpk.as<double>(), M, 2L * nw);
+        const int nt = (M + 31) / 32;
+        hipLaunchKernelGGL(k_adj_pack, dim3(nt * (nt + 1) / 2, 2 * nw), dim3(256), 0, st,
+                           a->Abar.as<double>(), a->Abpk.as<double>(), M, nt);
         Gemm g{};
         g.A = a->Abpk.p;
         g.ta = DT_F64;
