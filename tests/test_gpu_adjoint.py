@@ -85,6 +85,33 @@ def test_adjoint_matches_gpu_correlated_fd(lib):
     assert abs(dE - fd) <= 1e-6 * abs(fd), (dE, fd, E)
 
 
+@pytest.mark.parametrize("K,every", [(1, 7), (1, 20), (3, 6), (9, 20)])
+def test_adjoint_taylor_orders(lib, K, every):
+    """Other Taylor orders of the propagator (the tapes hold K terms; K = 1
+    makes the first and last tape slot the same) against the oracle tangent
+    at the same order, segmented and whole-window."""
+    M, nc, na, nb, nw = 12, 36, 3, 2, 16
+    dt, oe, seed, burn, window = 0.01, 5, 21, 15, 20
+    banner(f"adjoint Taylor order {K}, every={every}")
+    ham, trial = _setup(M, nc, na, nb)
+    V = perturbation(M, seed=3, scale=0.1)
+    H = lib.Hamiltonian(ham.h, ham.chol, ham.e_core)
+    s = lib.System(H, na, nb, trial, nw, dt, taylor_order=K, ortho_every=oe, measure_every=0)
+    s.step(burn, seed=seed)
+    E = s.adjoint_forward(V, window, seed=seed, checkpoint_every=every)
+    dE = s.adjoint_backward()
+    sys0 = O.System(ham.h, ham.chol, ham.e_core, trial, na, nb, dt, taylor_order=K)
+    fields = O.PhiloxFields(seed, 0, nc)
+    wk = O.init_walkers(sys0, nw)
+    for _ in range(burn):
+        O.step(sys0, wk, fields(wk.t, nw))
+        if wk.t % oe == 0:
+            O.orthonormalize(sys0, wk)
+    E_o, dE_o, _ = T.window_tangent(sys0, V, wk, fields, window, oe)
+    assert abs(E - E_o) <= 1e-10 * abs(E_o)
+    assert abs(dE - dE_o) <= 1e-9 * abs(dE_o), (dE, dE_o)
+
+
 def test_whole_window_tape_equals_segments(lib):
     """checkpoint_every >= the window records every step in the forward pass,
     and the reverse pass recomputes nothing; the energy and the derivative are
