@@ -187,6 +187,35 @@ __global__ __launch_bounds__(256) void k_adj_pack(const double* __restrict__ Af,
     }
 }
 
+// Up to eight device-to-device copies in one launch: blockIdx.y picks the
+// copy, the x blocks stride over its 8-byte words; block 0 copies the tail
+// bytes.  Buffers are hipMalloc allocations (8-byte aligned).
+struct CopySet {
+    const void* src[8];
+    void* dst[8];
+    long bytes[8];
+};
+__global__ __launch_bounds__(256) void k_copyset(CopySet c) {
+    const int b = blockIdx.y;
+    const long words = c.bytes[b] / 8;
+    const unsigned long long* s8 = (const unsigned long long*)c.src[b];
+    unsigned long long* d8 = (unsigned long long*)c.dst[b];
+    const long stride = (long)gridDim.x * blockDim.x;
+    for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < words; e += stride) d8[e] = s8[e];
+    const long tail = c.bytes[b] - words * 8;
+    if (blockIdx.x == 0 && threadIdx.x < tail)
+        ((uint8_t*)c.dst[b])[words * 8 + threadIdx.x] =
+            ((const uint8_t*)c.src[b])[words * 8 + threadIdx.x];
+}
+
+hipError_t copyset(const CopySet& c, int n, hipStream_t st) {
+    long most = 0;
+    for (int i = 0; i < n; ++i) most = c.bytes[i] > most ? c.bytes[i] : most;
+    const long blocks = std::min(2048L, std::max(1L, (most / 8 + 255) / 256));
+    hipLaunchKernelGGL(k_copyset, dim3((unsigned)blocks, n), dim3(256), 0, st, c);
+    return hipGetLastError();
+}
+
 // dst[w][r] = scale * src[w][r], r < per (walker strides sbs, dbs)
 __global__ void k_scale_copy(const double* __restrict__ src, long sbs, double* __restrict__ dst,
                              long dbs, long per, int nw, double scale) {
@@ -329,6 +358,7 @@ struct AdjState {
     bool taped = false;  // the forward pass recorded every step (one segment)
     double E = 0.0;
     std::vector<double> V;
+    std::vector<double> trial_host;  // Phi_T^T rows (host copy, for V^half)
     // constants
     DevBuf dP, vhalf, lht, lht2[2], lq, lp64;
     // snapshots: segment starts and the end state
@@ -405,38 +435,46 @@ hipError_t rgemm(const double* R, const double* B, double* C, long rows, int M, 
     return gemm(g, prec, st);
 }
 
+// The window's constant operators, on the host: dP = d/dlambda
+// expm(-dt (h~ + lambda V) / 2), the upper-right block of the exponential of
+// [[X, E], [0, X]] (X = -dt h~ / 2, E = -dt V / 2), and V^half = Phi_T^T V
+// (rows = trial orbitals).  Called after the forward steps are queued, so
+// the host work overlaps them (the forward pass needs neither).
+afqmc_status adj_operators(afqmc_sys s, AdjState* a) {
+    const int M = s->M, N = s->N;
+    const long NM = s->NM();
+    std::vector<double> B((size_t)4 * M * M, 0.0), Eb;
+    for (int i = 0; i < M; ++i)
+        for (int j = 0; j < M; ++j) {
+            const double x = -0.5 * s->par.dt * s->htilde[(size_t)i * M + j];
+            B[(size_t)i * 2 * M + j] = x;
+            B[(size_t)(M + i) * 2 * M + M + j] = x;
+            B[(size_t)i * 2 * M + M + j] = -0.5 * s->par.dt * a->V[(size_t)i * M + j];
+        }
+    expm_host(B, 2 * M, Eb);
+    std::vector<double> dP((size_t)M * M);
+    for (int i = 0; i < M; ++i)
+        for (int j = 0; j < M; ++j) dP[(size_t)i * M + j] = Eb[(size_t)i * 2 * M + M + j];
+    HIPCHK(hipMemcpy(a->dP.p, dP.data(), dP.size() * 8, hipMemcpyHostToDevice));
+    std::vector<double> vh((size_t)NM, 0.0);
+    for (int i = 0; i < N; ++i)
+        for (int k = 0; k < M; ++k) {
+            const double t = a->trial_host[(size_t)i * M + k];
+            if (t == 0.0) continue;
+            for (int m = 0; m < M; ++m) vh[(size_t)i * M + m] += t * a->V[(size_t)k * M + m];
+        }
+    HIPCHK(hipMemcpy(a->vhalf.p, vh.data(), vh.size() * 8, hipMemcpyHostToDevice));
+    return AFQMC_OK;
+}
+
 afqmc_status adj_setup(afqmc_sys s, AdjState* a, hipStream_t st) {
     const int M = s->M, N = s->N, nc = s->n_chol, nw = s->nw, K = s->par.taylor_order;
     const long NM = s->NM(), P = s->P();
-    // dP = d/dlambda expm(-dt (h~ + lambda V) / 2): upper-right block of the
-    // exponential of [[X, E], [0, X]], X = -dt h~ / 2, E = -dt V / 2
-    {
-        std::vector<double> B((size_t)4 * M * M, 0.0), Eb;
-        for (int i = 0; i < M; ++i)
-            for (int j = 0; j < M; ++j) {
-                const double x = -0.5 * s->par.dt * s->htilde[(size_t)i * M + j];
-                B[(size_t)i * 2 * M + j] = x;
-                B[(size_t)(M + i) * 2 * M + M + j] = x;
-                B[(size_t)i * 2 * M + M + j] = -0.5 * s->par.dt * a->V[(size_t)i * M + j];
-            }
-        expm_host(B, 2 * M, Eb);
-        std::vector<double> dP((size_t)M * M);
-        for (int i = 0; i < M; ++i)
-            for (int j = 0; j < M; ++j) dP[(size_t)i * M + j] = Eb[(size_t)i * 2 * M + M + j];
-        HIPCHK(a->dP.alloc(dP.size() * 8));
-        HIPCHK(hipMemcpy(a->dP.p, dP.data(), dP.size() * 8, hipMemcpyHostToDevice));
-        // V^half = Phi_T^T V  (rows = trial orbitals)
-        std::vector<double> tr((size_t)NM);
-        HIPCHK(hipMemcpy(tr.data(), s->d_trialT.p, NM * 8, hipMemcpyDeviceToHost));
-        std::vector<double> vh((size_t)NM, 0.0);
-        for (int i = 0; i < N; ++i)
-            for (int k = 0; k < M; ++k) {
-                const double t = tr[(size_t)i * M + k];
-                if (t == 0.0) continue;
-                for (int m = 0; m < M; ++m) vh[(size_t)i * M + m] += t * a->V[(size_t)k * M + m];
-            }
-        HIPCHK(a->vhalf.alloc(vh.size() * 8));
-        HIPCHK(hipMemcpy(a->vhalf.p, vh.data(), vh.size() * 8, hipMemcpyHostToDevice));
+    if (!a->dP.p) {
+        HIPCHK(a->dP.alloc((size_t)M * M * 8));
+        HIPCHK(a->vhalf.alloc((size_t)NM * 8));
+        a->trial_host.resize((size_t)NM);
+        HIPCHK(hipMemcpy(a->trial_host.data(), s->d_trialT.p, NM * 8, hipMemcpyDeviceToHost));
     }
     static bool lds_ready = false;  // process-wide kernel attribute
     if (!lds_ready) {
@@ -502,19 +540,28 @@ afqmc_status taped_step(afqmc_sys s, AdjState* a, int j, hipStream_t st) {
     HIPCHK(ensure(a->t_lnd, (size_t)nw * 32));
     HIPCHK(ensure(a->t_wout, (size_t)nw * 8));
     HIPCHK(ensure(a->t_aout, (size_t)nw));
-    HIPCHK(hipMemcpyAsync(a->t_phi[j].p, s->d_phi.p, nphi, hipMemcpyDeviceToDevice, st));
-    HIPCHK(hipMemcpyAsync(a->t_lnov[j].p, s->d_lnov.p, (size_t)nw * 16, hipMemcpyDeviceToDevice, st));
-    HIPCHK(hipMemcpyAsync(a->t_w[j].p, s->d_w.p, (size_t)nw * 8, hipMemcpyDeviceToDevice, st));
-    HIPCHK(hipMemcpyAsync(a->t_alive[j].p, s->d_alive.p, (size_t)nw, hipMemcpyDeviceToDevice, st));
+    {
+        // the state before the step
+        CopySet c{};
+        c.src[0] = s->d_phi.p, c.dst[0] = a->t_phi[j].p, c.bytes[0] = (long)nphi;
+        c.src[1] = s->d_lnov.p, c.dst[1] = a->t_lnov[j].p, c.bytes[1] = (long)nw * 16;
+        c.src[2] = s->d_w.p, c.dst[2] = a->t_w[j].p, c.bytes[2] = (long)nw * 8;
+        c.src[3] = s->d_alive.p, c.dst[3] = a->t_alive[j].p, c.bytes[3] = nw;
+        HIPCHK(copyset(c, 4, st));
+    }
     a->t_t[j] = s->t;
     afqmc_status r = one_step(s, a->seed, 0, nullptr, st);
     if (r != AFQMC_OK) return r;
-    HIPCHK(hipMemcpyAsync(a->t_F[j].p, s->d_F.p, (size_t)nw * 2 * (s->n_chol + 1) * 8,
-                          hipMemcpyDeviceToDevice, st));
-    HIPCHK(hipMemcpyAsync(a->t_simp[j].p, s->d_simp.p, (size_t)nw * 32, hipMemcpyDeviceToDevice, st));
-    HIPCHK(hipMemcpyAsync(a->t_lnd[j].p, s->d_lnd.p, (size_t)nw * 32, hipMemcpyDeviceToDevice, st));
-    HIPCHK(hipMemcpyAsync(a->t_wout[j].p, s->d_w.p, (size_t)nw * 8, hipMemcpyDeviceToDevice, st));
-    HIPCHK(hipMemcpyAsync(a->t_aout[j].p, s->d_alive.p, (size_t)nw, hipMemcpyDeviceToDevice, st));
+    {
+        // what the step computed
+        CopySet c{};
+        c.src[0] = s->d_F.p, c.dst[0] = a->t_F[j].p, c.bytes[0] = (long)nw * 2 * (s->n_chol + 1) * 8;
+        c.src[1] = s->d_simp.p, c.dst[1] = a->t_simp[j].p, c.bytes[1] = (long)nw * 32;
+        c.src[2] = s->d_lnd.p, c.dst[2] = a->t_lnd[j].p, c.bytes[2] = (long)nw * 32;
+        c.src[3] = s->d_w.p, c.dst[3] = a->t_wout[j].p, c.bytes[3] = (long)nw * 8;
+        c.src[4] = s->d_alive.p, c.dst[4] = a->t_aout[j].p, c.bytes[4] = nw;
+        HIPCHK(copyset(c, 5, st));
+    }
     const int oe = s->par.ortho_every;
     a->t_mgs[j] = oe > 0 && s->t % oe == 0;
     if (a->t_mgs[j]) {
@@ -926,6 +973,7 @@ afqmc_status afqmc_adjoint_forward(afqmc_sys s, const double* V, uint64_t seed, 
         }
         if (a->taped && (r = tape_end(s, a, n, st)) != AFQMC_OK) return r;
     }
+    if ((r = adj_operators(s, a)) != AFQMC_OK) return r;
     if ((r = snap_take(s, a->fin, st)) != AFQMC_OK) return r;
     if ((r = measure(s, st)) != AFQMC_OK) return r;
     double sums[4];
