@@ -367,6 +367,12 @@ struct AdjState {
     // per-step tape of one segment
     std::vector<DevBuf> t_phi, t_pre, t_F, t_lnov, t_w, t_alive, t_simp, t_lnd, t_wout, t_aout;
     std::vector<bool> t_mgs;
+    // Taylor terms t_0 .. t_{K-1} ([w][n][2][N][M]) and y = sum_n t_n of each
+    // recorded step, written by the step's own propagation (FP64 / FP32
+    // products) when device memory allows; t_rec[j]: slot j holds them
+    std::vector<DevBuf> t_terms, t_y;
+    std::vector<bool> t_rec;
+    bool record = false;
     std::vector<int64_t> t_t;
     // scratch
     DevBuf xc, simp_s, apk, A, x, tA, y, tT, tbT, ybar, Abar, Abpk, G, Fbar, thbar, phibar,
@@ -550,8 +556,20 @@ afqmc_status taped_step(afqmc_sys s, AdjState* a, int j, hipStream_t st) {
         HIPCHK(copyset(c, 4, st));
     }
     a->t_t[j] = s->t;
+    a->t_rec[j] = false;
+    if (a->record) {
+        const long TS = 2 * s->NM(), K = s->par.taylor_order;
+        HIPCHK(ensure(a->t_terms, (size_t)nw * K * TS * 8));
+        HIPCHK(ensure(a->t_y, (size_t)nw * TS * 8));
+        s->rec.terms = a->t_terms[j].as<double>();
+        s->rec.bs_walker = K * TS;
+        s->rec.bs_slot = TS;
+        s->rec.y = a->t_y[j].as<double>();
+    }
     afqmc_status r = one_step(s, a->seed, 0, nullptr, st);
+    s->rec = Record();
     if (r != AFQMC_OK) return r;
+    a->t_rec[j] = a->record;
     {
         // what the step computed
         CopySet c{};
@@ -575,10 +593,27 @@ afqmc_status taped_step(afqmc_sys s, AdjState* a, int j, hipStream_t st) {
 // Tape slots 0..n (n steps and the state after them).
 void tape_resize(AdjState* a, int n) {
     for (auto* v : {&a->t_phi, &a->t_pre, &a->t_F, &a->t_lnov, &a->t_w, &a->t_alive, &a->t_simp,
-                    &a->t_lnd, &a->t_wout, &a->t_aout})
+                    &a->t_lnd, &a->t_wout, &a->t_aout, &a->t_terms, &a->t_y})
         if ((int)v->size() < n + 1) v->resize(n + 1);
     a->t_mgs.assign(n + 1, false);
+    a->t_rec.assign(n + 1, false);
     a->t_t.assign(n + 1, 0);
+}
+
+// Record the Taylor terms of the next n taped steps when the propagation
+// computes them in FP64 / FP32 (not split BF16) and the slots still to be
+// allocated fit in 3/4 of the free device memory; otherwise the reverse pass
+// recomputes them.
+void plan_record(afqmc_sys s, AdjState* a, int n) {
+    a->record = false;
+    if (s->ta == DT_SPLIT) return;
+    const size_t slot = (size_t)s->nw * 2 * s->NM() * 8 * (s->par.taylor_order + 1);
+    size_t need = 0;
+    for (int j = 0; j < n; ++j)
+        if (!a->t_terms[j].p) need += slot;
+    size_t free_b = 0, total_b = 0;
+    if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) return;
+    a->record = need <= free_b / 4 * 3;
 }
 
 // The state after the last of n recorded steps into tape slot n.
@@ -713,12 +748,14 @@ afqmc_status reverse_step(afqmc_sys s, AdjState* a, int j, const double* phi_nex
     const double* A = a->A.as<double>();
     // Taylor tapes, one walker's K terms contiguous: [w][n][2][N][M]
     const long TS = 2 * NM, KTS = (long)K * TS;
-    double* tt = a->tT.as<double>();   // t_n, n < K
+    const bool rec = a->t_rec[j];  // the step's propagation recorded them
+    double* tt = rec ? a->t_terms[j].as<double>() : a->tT.as<double>();  // t_n, n < K
     double* tb = a->tbT.as<double>();  // t_bar_{n+1} / (n + 1), n < K
-    double* y = a->y.as<double>();
+    double* y = rec ? a->t_y[j].as<double>() : a->y.as<double>();
     // forward terms: t_0 = P phi_in; t_n = A t_{n-1} / n; y = sum_{n <= K} t_n
-    HIPCHK(rgemm(s->d_P.as<double>(), phi_in, tt, rows, M, pr, st, rows_2level(2 * N, M, KTS)));
-    for (int n = 1; n <= K; ++n) {
+    if (!rec)
+        HIPCHK(rgemm(s->d_P.as<double>(), phi_in, tt, rows, M, pr, st, rows_2level(2 * N, M, KTS)));
+    for (int n = 1; n <= K && !rec; ++n) {
         CTerm c{};
         c.in = tt + (long)(n - 1) * TS;
         c.in_bs = KTS;
@@ -958,7 +995,10 @@ afqmc_status afqmc_adjoint_forward(afqmc_sys s, const double* V, uint64_t seed, 
     // one segment: the window is recorded now and the reverse pass recomputes
     // nothing; otherwise snapshots only, each segment recorded again in reverse
     a->taped = a->n_seg == 1;
-    if (a->taped) tape_resize(a, n_steps);
+    if (a->taped) {
+        tape_resize(a, n_steps);
+        plan_record(s, a, n_steps);
+    }
     for (int sg = 0; sg < a->n_seg; ++sg) {
         if ((r = snap_take(s, a->ck[sg], st)) != AFQMC_OK) return r;
         const int n = std::min(checkpoint_every, n_steps - sg * checkpoint_every);
@@ -1001,6 +1041,7 @@ afqmc_status afqmc_adjoint_backward(afqmc_sys s, double* dE) {
     for (int sg = a->n_seg - 1; sg >= 0; --sg) {
         const int n = std::min(k, a->n_steps - sg * k);
         if (!a->taped) {
+            plan_record(s, a, n);
             if ((r = snap_restore(s, a->ck[sg], st)) != AFQMC_OK) return r;
             for (int j = 0; j < n; ++j)
                 if ((r = taped_step(s, a, j, st)) != AFQMC_OK) return r;

@@ -187,7 +187,7 @@ afqmc_status one_step(afqmc_sys s, uint64_t seed, uint64_t stream_id, const doub
         PhaseTimer pt(s, PH_PROPAGATE, st);
         HIPCHK(propagate(s->d_phi.as<double>(), s->d_phinew.as<double>(), Pm, s->d_Af.p,
                          s->d_alive.as<uint8_t>(), s->nw, s->M, s->N, s->par.taylor_order, s->tp,
-                         s->ta, s->prop_var, st));
+                         s->ta, s->prop_var, st, s->rec));
     }
     if ((r = overlap_theta(s, s->d_phinew.as<double>(), st)) != AFQMC_OK) return r;
     PhaseTimer pt(s, PH_WEIGHTS, st);

@@ -169,6 +169,7 @@ struct afqmc_sys_s {
     std::vector<double> a_host;
     std::vector<double> htilde;  // one-body part after the mean-field subtraction (host copy)
     afq::host::AdjState* adj = nullptr;  // reverse-mode tape (adjoint.hip)
+    afq::Record rec;  // Taylor terms the next propagation records (set only by the adjoint)
     // constant per-system data
     // d_Plp: P in FP32, or with ta == DT_SPLIT Q = P - I as hi/lo BF16 planes
     // in the fragment-tiled layout (split_tile_elems(M) * 4 bytes)

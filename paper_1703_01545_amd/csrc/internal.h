@@ -179,9 +179,19 @@ hipError_t split_planes(const float* in, void* out, long n, long planes, hipStre
 // bitwise the same result, 0 is the default.
 constexpr int kPropVariants = 14;
 bool propagate_variant_ok(int variant, int M, DType t, DType ta);
+// Optional record of the Taylor series (the FP64 / FP32 products only; the
+// split-BF16 propagation refuses it): terms t_0 = P Phi, t_n = A t_{n-1} / n
+// for n < K at terms + w bs_walker + n bs_slot, and y = sum_{n <= K} t_n at
+// y + w 2 N M, all in the walker row layout [2][N][M] (FP64); frozen walkers
+// record zeros.  NULL pointers: nothing recorded.
+struct Record {
+    double* terms = nullptr;
+    long bs_walker = 0, bs_slot = 0;
+    double* y = nullptr;
+};
 hipError_t propagate(const double* phi, double* phi_out, const void* Pm, const void* Af,
                      const uint8_t* live, int nw, int M, int N, int K, DType t, DType ta,
-                     int variant, hipStream_t s);
+                     int variant, hipStream_t s, const Record& rec = Record());
 
 // Exchange partial sums of the mixed local energy:
 //   out[(w * 2 + spin) * n_gtiles + gt] = sum over gamma in tile gt of

@@ -211,11 +211,12 @@ __device__ __forceinline__ void pass(__amdgpu_buffer_rsrc_t rb, int M, int Mp, i
 // walker run back to back on one XCD and A_w streams through its L2; the
 // assignment of column blocks to waves rotates between workgroups so the
 // waves holding an extra block land on different SIMDs.
-template <typename T, int NWAVE, int MAXB, bool PF>
+// REC: also record the Taylor terms and their sum (rec; see Record).
+template <typename T, int NWAVE, int MAXB, bool PF, bool REC>
 __global__ __launch_bounds__(64 * NWAVE, 2) void k_propagate(
     const double* __restrict__ phi, double* __restrict__ phi_out, const T* __restrict__ Pm,
     const T* __restrict__ Af, const uint8_t* __restrict__ live, int nw, int M, int N, int K,
-    int nrb) {
+    int nrb, Record rec) {
     typedef typename AccT<T>::v accv;
     extern __shared__ __attribute__((aligned(16))) char smem_raw[];
     T* S = reinterpret_cast<T*>(smem_raw);
@@ -238,11 +239,18 @@ __global__ __launch_bounds__(64 * NWAVE, 2) void k_propagate(
     double* dst = phi_out + (long)w * 2 * NM;
     const int nrow = min(16, N - row0);
     if (nrow <= 0) return;
-    if (!live[w]) {  // frozen walker: carried over unchanged
+    // recorded terms of this walker: slot n at rt + n rec.bs_slot (planes NM apart)
+    double* rt = REC ? rec.terms + (long)w * rec.bs_walker : nullptr;
+    double* ry = REC ? rec.y + (long)w * 2 * NM : nullptr;
+    if (!live[w]) {  // frozen walker: carried over unchanged (recorded terms zero)
         for (int e = tid; e < 2 * nrow * M; e += NT) {
             const int p = e / (nrow * M), rem = e % (nrow * M);
             const long o = p * NM + (long)(row0 + rem / M) * M + rem % M;
             dst[o] = src[o];
+            if constexpr (REC) {
+                ry[o] = 0.0;
+                for (int n = 0; n < K; ++n) rt[n * rec.bs_slot + o] = 0.0;
+            }
         }
         return;
     }
@@ -273,6 +281,20 @@ __global__ __launch_bounds__(64 * NWAVE, 2) void k_propagate(
             S[splane + off] = ok ? vi[r] : (T)0;
         }
     };
+    // a block of this walker's rows in the walker layout (recording)
+    auto keep = [&](double* base, int s, const accv& vr, const accv& vi) {
+        const int col = cb[s] * 16 + (lane & 15);
+        if (cb[s] >= MB || col >= M) return;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int row = acc_row<T>(lane, r);
+            if (row < nrow) {
+                const long o = (long)(row0 + row) * M + col;
+                base[o] = (double)vr[r];
+                base[NM + o] = (double)vi[r];
+            }
+        }
+    };
     // first one-body half
     pass<T, MAXB, 1, PF, SPT>(rP, M, Mp, MB, S, cb, acc);
     __syncthreads();
@@ -281,6 +303,8 @@ __global__ __launch_bounds__(64 * NWAVE, 2) void k_propagate(
         z[s][0] = acc[s][0];
         z[s][1] = acc[s][1];
         if (cb[s] < MB) put(s, acc[s][0], acc[s][1]);
+        if constexpr (REC)
+            if (K > 0) keep(rt, s, acc[s][0], acc[s][1]);
     }
     __syncthreads();
     // Taylor series of exp(A): term_n = A term_{n-1} / n, z = sum of terms
@@ -297,6 +321,10 @@ __global__ __launch_bounds__(64 * NWAVE, 2) void k_propagate(
                     put(s, z[s][0], z[s][1]);
                 else
                     put(s, acc[s][0], acc[s][1]);
+            }
+            if constexpr (REC) {
+                if (n < K) keep(rt + n * rec.bs_slot, s, acc[s][0], acc[s][1]);
+                if (n == K) keep(ry, s, z[s][0], z[s][1]);
             }
         }
         __syncthreads();
@@ -931,13 +959,20 @@ __global__ __launch_bounds__(kUnpackThreads) void k_unpack_split_plane(
 
 template <typename T, int NWAVE, int MAXB, bool PF>
 hipError_t launch_prop(const double* phi, double* phi_out, const void* Pm, const void* Af,
-                       const uint8_t* live, int nw, int M, int N, int K, hipStream_t s) {
+                       const uint8_t* live, int nw, int M, int N, int K, const Record& rec,
+                       hipStream_t s) {
     const size_t shm = 2 * 16 * (size_t)kPitchF * sizeof(T);
     const int nrb = (N + 15) / 16;
     const long nblk = (long)nw * nrb;
     const long grid = ((nblk + 7) / 8) * 8;
-    hipLaunchKernelGGL((k_propagate<T, NWAVE, MAXB, PF>), dim3(grid), dim3(64 * NWAVE), shm, s, phi,
-                       phi_out, (const T*)Pm, (const T*)Af, live, nw, M, N, K, nrb);
+    if (rec.terms && rec.y)
+        hipLaunchKernelGGL((k_propagate<T, NWAVE, MAXB, PF, true>), dim3(grid), dim3(64 * NWAVE),
+                           shm, s, phi, phi_out, (const T*)Pm, (const T*)Af, live, nw, M, N, K, nrb,
+                           rec);
+    else
+        hipLaunchKernelGGL((k_propagate<T, NWAVE, MAXB, PF, false>), dim3(grid), dim3(64 * NWAVE),
+                           shm, s, phi, phi_out, (const T*)Pm, (const T*)Af, live, nw, M, N, K, nrb,
+                           rec);
     return hipGetLastError();
 }
 
@@ -1005,13 +1040,14 @@ bool propagate_variant_ok(int v, int M, DType t, DType ta) {
 
 hipError_t propagate(const double* phi, double* phi_out, const void* Pm, const void* Af,
                      const uint8_t* live, int nw, int M, int N, int K, DType t, DType ta,
-                     int variant, hipStream_t s) {
+                     int variant, hipStream_t s, const Record& rec) {
     if (nw <= 0) return hipSuccess;
+    if ((rec.terms || rec.y) && ta == DT_SPLIT) return hipErrorNotSupported;
     if (M > 256 || M <= 0 || N <= 0) return hipErrorInvalidValue;
     if (!propagate_variant_ok(variant, M, t, ta)) return hipErrorInvalidValue;
 #define AFQ_P(V, T_, W_, B_, F_)                                                          \
     if (variant == V)                                                                      \
-        return launch_prop<T_, W_, B_, F_>(phi, phi_out, Pm, Af, live, nw, M, N, K, s);
+        return launch_prop<T_, W_, B_, F_>(phi, phi_out, Pm, Af, live, nw, M, N, K, rec, s);
 #define AFQ_S(V, W_, B_, F_)                                                               \
     if (variant == V)                                                                      \
         return launch_prop_split<W_, B_, F_>(phi, phi_out, Pm, Af, live, nw, M, N, K, s);

@@ -116,14 +116,17 @@ def test_whole_window_tape_equals_segments(lib):
     """checkpoint_every >= the window records every step in the forward pass,
     and the reverse pass recomputes nothing; the energy and the derivative are
     bitwise those of the segmented passes (the same kernels replay the same
-    trajectory), in both precisions.  One system runs every mode in turn, so
-    its tape grows and shrinks between passes; a fresh system gives the same."""
+    trajectory), for FP64 and FP32 systems (whose steps record their Taylor
+    terms for the reverse pass) and a split-BF16 one (whose terms the reverse
+    pass recomputes).  One system runs every mode in turn, so its tape grows
+    and shrinks between passes; a fresh system gives the same."""
     M, nc, na, nb, nw = 24, 72, 5, 4, 48
     banner("adjoint whole-window tape vs segments")
     ham, trial = _setup(M, nc, na, nb, hs=2)
     V = perturbation(M, seed=3, scale=0.1)
     H = lib.Hamiltonian(ham.h, ham.chol, ham.e_core)
-    for prec in ("fp64", "fp32"):
+    for prec in ("fp64", "fp32", "bf16x3"):
+        ap = "fp64" if prec == "fp64" else "fp32"  # the adjoint's own products
         s = lib.System(H, na, nb, trial, nw, 0.01, ortho_every=5, measure_every=0,
                        precision=prec)
         s.step(10, seed=4)
@@ -131,13 +134,13 @@ def test_whole_window_tape_equals_segments(lib):
         out = []
         for every in (7, 20, 50, 3, 20):
             s.restore(snap)
-            E = s.adjoint_forward(V, 20, seed=4, checkpoint_every=every, precision=prec)
+            E = s.adjoint_forward(V, 20, seed=4, checkpoint_every=every, precision=ap)
             out.append((E, s.adjoint_backward(), s.adjoint_backward()))
             assert s.info()["step"] == 30
         f = lib.System(H, na, nb, trial, nw, 0.01, ortho_every=5, measure_every=0,
                        precision=prec)
         f.step(10, seed=4)
-        E = f.adjoint_forward(V, 20, seed=4, checkpoint_every=20, precision=prec)
+        E = f.adjoint_forward(V, 20, seed=4, checkpoint_every=20, precision=ap)
         out.append((E, f.adjoint_backward(), f.adjoint_backward()))
         assert all(o == out[0] for o in out), out
 
