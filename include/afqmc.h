@@ -252,9 +252,13 @@ afqmc_status afqmc_pair_batch_step(int n_pairs, const afqmc_sys* a, const afqmc_
  * the window.  With checkpoint_every >= n_steps (one segment) the forward
  * pass records every step instead (device memory of about
  * n_steps (1 + 1/ortho_every) walker blocks of nw 2 N M doubles) and the
- * backward pass recomputes nothing; the result is bitwise the same.  Systems with an applied force-bias cap or a multi-determinant
- * trial are refused (E_STATE): the reverse pass differentiates the uncapped
- * single-determinant step.  V: host M x M symmetric, row-major, copied.  prec: AFQMC_FP64
+ * backward pass recomputes nothing; the result is bitwise the same.  Steps
+ * whose propagation runs FP64 or FP32 products also record their Taylor
+ * terms (taylor_order + 1 more walker blocks per step) when these fit in 3/4
+ * of the free device memory, and the reverse pass starts from them.  Systems
+ * with an applied force-bias cap or a multi-determinant trial are refused
+ * (E_STATE): the reverse pass differentiates the uncapped single-determinant
+ * step.  V: host M x M symmetric, row-major, copied.  prec: AFQMC_FP64
  * or AFQMC_FP32 products in the adjoint's contractions (FP64 storage and
  * small dense algebra).  Errors: E_STATE (free mode; backward without a
  * forward), E_SHAPE (a spin block above 64 orbitals), E_INVALID.
