@@ -69,19 +69,21 @@ __global__ __launch_bounds__(64 * WGM * WGN) void k_gemm(Gemm g, int ntn, int nt
     const TA* A = (const TA*)g.A + (long)b * g.a_bs + k_lo;
     const TB* B = (const TB*)g.B + (long)b * g.b_bs + k_lo;
     const int tid = threadIdx.x;
+    // rows past the operands: with two LDS buffers they repeat the last row
+    // (their products land in outputs that are not stored), else read zero
     long aoff[C::LA], boff[C::LB];
 #pragma unroll
     for (int j = 0; j < C::LA; ++j) {
         const long r = row0 + C::arow(j);
-        aoff[j] = r < g.m ? rowmap(g.ra, r) : -1;
+        aoff[j] = r < g.m ? rowmap(g.ra, r) : DB ? rowmap(g.ra, g.m - 1) : -1;
     }
 #pragma unroll
     for (int j = 0; j < C::LB; ++j) {
         const long r = col0 + C::brow(j);
-        boff[j] = r < g.n ? rowmap(g.rb, r) : -1;
+        boff[j] = r < g.n ? rowmap(g.rb, r) : DB ? rowmap(g.rb, g.n - 1) : -1;
     }
     typename C::accv acc[C::TM][C::TN];
-    C::template run<DB>(A, aoff, B, boff, k_len, As, Bs, acc);
+    C::template run<DB, DB>(A, aoff, B, boff, k_len, As, Bs, acc);
 
     const int lane = tid & 63, wave = tid >> 6;
     const int wm = wave / WGN, wn = wave % WGN;
@@ -295,9 +297,13 @@ template <int NB, int G>
 struct ExchBlk {
     static constexpr int R = G * NB, C = 2 * NB, BM = 2 * R, BN = 2 * C, P = R + 4;
     typedef Core<float, float, Split, BM, BN, 32, 2, 2, 4, 4, true> Cr;
-    static constexpr int OPB = (Cr::LDS_A + Cr::LDS_B) * (int)sizeof(bf16_t);
+    // two operand buffers (the split of the next K tile overlaps the
+    // products; 80 KB at N_s = 40, so two workgroups share a CU's 160 KB),
+    // reused after the K loop for the two tiles and the reduction slots
+    static constexpr int OPB = 2 * (Cr::LDS_A + Cr::LDS_B) * (int)sizeof(bf16_t);
     static constexpr int EPB = 2 * C * P * (int)sizeof(float);
-    static constexpr int SMEM = OPB > EPB ? OPB : EPB;
+    static constexpr int RED = 16 * (int)sizeof(double);
+    static constexpr int SMEM = OPB > EPB + RED ? OPB : EPB + RED;
 };
 
 template <int NB, int G>
@@ -311,8 +317,10 @@ __global__ __launch_bounds__(256, 2) void k_exchange_blk(const float* __restrict
     constexpr int R = E::R, C = E::C, P = E::P;
     __shared__ __attribute__((aligned(16))) char smem[E::SMEM];
     bf16_t* As = reinterpret_cast<bf16_t*>(smem);
-    bf16_t* Bs = As + Cr::LDS_A;
+    bf16_t* Bs = As + 2 * Cr::LDS_A;
     float* S = reinterpret_cast<float*>(smem);
+    // [round][tile][half][re, im]
+    double(*red)[2][2][2] = reinterpret_cast<double(*)[2][2][2]>(smem + E::EPB);
 
     // XCD-aware tile order: each XCD takes a contiguous range of logical
     // tiles, walked in super-tiles of 8 gamma groups x 8 walker pairs, so the
@@ -346,7 +354,7 @@ __global__ __launch_bounds__(256, 2) void k_exchange_blk(const float* __restrict
         boff[j] = (jj < nsig && w < nw) ? (long)(2 * w + p) * NM + (long)(off + jj) * M : -1;
     }
     typename Cr::accv acc[Cr::TM][Cr::TN];
-    Cr::run(lhalf, aoff, theta, boff, M, As, Bs, acc);
+    Cr::template run<true>(lhalf, aoff, theta, boff, M, As, Bs, acc);
     // the tile column-major (column = plane, j; row = gamma, i), four rows per
     // 16-byte store; pairs (i, j = i + d mod NB), d = 0 .. NB / 2, cover each
     // unordered pair once (weight 2; the diagonal and d = NB / 2 weight 1),
@@ -356,7 +364,6 @@ __global__ __launch_bounds__(256, 2) void k_exchange_blk(const float* __restrict
     // halves; the halves' sums are added in fixed order.
     constexpr int D = NB / 2 + 1;
     constexpr int NE = G * D * NB, HE = (NE + 1) / 2;
-    __shared__ double red[2][2][2][2];  // [round][tile][half][re, im]
     for (int round = 0; round < 2; ++round) {
         if ((wave >> 1) == round) {
             float* Sx = S + (wave & 1) * C * P;

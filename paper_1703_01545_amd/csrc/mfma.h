@@ -198,9 +198,10 @@ struct VW {
 // Load V consecutive elements starting at p[kg] into staging registers;
 // vector load when the whole run is in range and aligned, else per element
 // with k >= K reading as zero.
-template <typename ST, typename TS, int V, bool ALIGNED>
+template <typename ST, typename TS, int V, bool ALIGNED, bool FULL = false>
 __device__ __forceinline__ void gload_run(const TS* __restrict__ row, int kg, int K, ST* out) {
-    if (ALIGNED && kg + V <= K) {
+    static_assert(!FULL || ALIGNED, "whole-run loads are vector loads");
+    if (FULL || (ALIGNED && kg + V <= K)) {
         if constexpr (sizeof(TS) == 8) {
             const d2 x = *reinterpret_cast<const d2*>(row + kg);
             out[0] = (ST)x[0];
@@ -318,7 +319,9 @@ struct Core {
     // Bs hold two buffers each; tile t + 1 is split and stored into the other
     // buffer right after the products of tile t are issued, one barrier per
     // K tile.  The products and their order per accumulator are the same.
-    template <bool DB = false>
+    // ROWS_VALID: every aoff / boff names a readable row (rows past the
+    // operand repeat its last row; their results are never stored).
+    template <bool DB = false, bool ROWS_VALID = false>
     static __device__ __forceinline__ void run(const TA* __restrict__ A, const long* aoff,
                                                const TB* __restrict__ B, const long* boff, int K,
                                                LT* As, LT* Bs, accv (&acc)[TM][TN]) {
@@ -331,25 +334,27 @@ struct Core {
             for (int b = 0; b < TN; ++b)
                 for (int e = 0; e < 4; ++e) acc[a][b][e] = 0;
 
-        auto gload = [&](int k0) {
+        // staging sets: registers holding one K tile between its fetch and
+        // its split into LDS
+        auto gload = [&](int k0, ST (&xa)[LA][VA], ST (&xb)[LB][VB]) {
 #pragma unroll
             for (int j = 0; j < LA; ++j) {
                 if (aoff[j] >= 0)
-                    gload_run<ST, TA, VA, AL>(A + aoff[j], k0 + ka, K, ra[j]);
+                    gload_run<ST, TA, VA, AL>(A + aoff[j], k0 + ka, K, xa[j]);
                 else
 #pragma unroll
-                    for (int e = 0; e < VA; ++e) ra[j][e] = (ST)0;
+                    for (int e = 0; e < VA; ++e) xa[j][e] = (ST)0;
             }
 #pragma unroll
             for (int j = 0; j < LB; ++j) {
                 if (boff[j] >= 0)
-                    gload_run<ST, TB, VB, AL>(B + boff[j], k0 + kb, K, rb[j]);
+                    gload_run<ST, TB, VB, AL>(B + boff[j], k0 + kb, K, xb[j]);
                 else
 #pragma unroll
-                    for (int e = 0; e < VB; ++e) rb[j][e] = (ST)0;
+                    for (int e = 0; e < VB; ++e) xb[j][e] = (ST)0;
             }
         };
-        auto sstore = [&](LT* Ad, LT* Bd) {
+        auto sstore = [&](LT* Ad, LT* Bd, ST (&xa)[LA][VA], ST (&xb)[LB][VB]) {
             if constexpr (sizeof(LT) == 2 && VA % 4 == 0 && VB % 4 == 0) {
                 // BF16 planes: each thread's run of V consecutive k goes out as
                 // 8-byte stores (4 elements per plane), rows 16-byte aligned
@@ -357,37 +362,76 @@ struct Core {
                 for (int j = 0; j < LA; ++j)
 #pragma unroll
                     for (int e = 0; e < VA; e += 4)
-                        lds_put4<TC>(Ad, BM * PK, lds_index<LT, PK>(arow(j), ka + e), &ra[j][e]);
+                        lds_put4<TC>(Ad, BM * PK, lds_index<LT, PK>(arow(j), ka + e), &xa[j][e]);
 #pragma unroll
                 for (int j = 0; j < LB; ++j)
 #pragma unroll
                     for (int e = 0; e < VB; e += 4)
-                        lds_put4<TC>(Bd, BN * PK, lds_index<LT, PK>(brow(j), kb + e), &rb[j][e]);
+                        lds_put4<TC>(Bd, BN * PK, lds_index<LT, PK>(brow(j), kb + e), &xb[j][e]);
             } else {
 #pragma unroll
                 for (int j = 0; j < LA; ++j)
 #pragma unroll
                     for (int e = 0; e < VA; ++e)
-                        lds_put<TC>(Ad, BM * PK, lds_index<LT, PK>(arow(j), ka + e), ra[j][e]);
+                        lds_put<TC>(Ad, BM * PK, lds_index<LT, PK>(arow(j), ka + e), xa[j][e]);
 #pragma unroll
                 for (int j = 0; j < LB; ++j)
 #pragma unroll
                     for (int e = 0; e < VB; ++e)
-                        lds_put<TC>(Bd, BN * PK, lds_index<LT, PK>(brow(j), kb + e), rb[j][e]);
+                        lds_put<TC>(Bd, BN * PK, lds_index<LT, PK>(brow(j), kb + e), xb[j][e]);
             }
         };
 
-        gload(0);
-        sstore(As, Bs);
-        if constexpr (DB) {
-            if (BK < K) gload(BK);
+        gload(0, ra, rb);
+        sstore(As, Bs, ra, rb);
+        if (DB && PL == 2 && ROWS_VALID && K % BK == 0) {
+            // Split BF16 over whole K tiles: a second staging set, so that each
+            // tile is fetched two tiles ahead of its split into LDS (the fetch
+            // latency hides behind two tiles of products instead of one).  Tile
+            // t + 1 waits in set (t + 1) & 1 (set 0 = ra/rb, set 1 = sa/sb).
+            // Every step issues the same vector loads and LDS stores (past the
+            // last tile it fetches the last tile again and stores it into the
+            // buffer no later step reads), so the loop body has no branch and
+            // the wait before a split counts only the older set.  Same products
+            // in the same order as the other paths.
+            const int nt = K / BK;
+            ST sa[LA][VA], sb[LB][VB];
+            auto fetch = [&](int t, ST (&xa)[LA][VA], ST (&xb)[LB][VB]) {
+                const int k0 = (t < nt ? t : nt - 1) * BK;
+#pragma unroll
+                for (int j = 0; j < LA; ++j)
+                    gload_run<ST, TA, VA, AL, AL>(A + aoff[j], k0 + ka, K, xa[j]);
+#pragma unroll
+                for (int j = 0; j < LB; ++j)
+                    gload_run<ST, TB, VB, AL, AL>(B + boff[j], k0 + kb, K, xb[j]);
+            };
+            fetch(1, sa, sb);
+            fetch(2, ra, rb);
+            __syncthreads();
+            auto step = [&](int t, ST (&xa)[LA][VA], ST (&xb)[LB][VB]) {
+                compute(As + (t & 1) * LDS_A, Bs + (t & 1) * LDS_B, acc);
+                sstore(As + ((t + 1) & 1) * LDS_A, Bs + ((t + 1) & 1) * LDS_B, xa, xb);
+                fetch(t + 3, xa, xb);
+                __syncthreads();
+                // keep the next step's split of the other set below this
+                // point (hoisted above, it would wait for that set's fetch)
+                __builtin_amdgcn_sched_barrier(0);
+            };
+            int t = 0;
+            for (; t + 1 < nt; t += 2) {
+                step(t, sa, sb);
+                step(t + 1, ra, rb);
+            }
+            if (t < nt) step(t, sa, sb);
+        } else if constexpr (DB) {
+            if (BK < K) gload(BK, ra, rb);
             __syncthreads();
             int cur = 0;
             for (int k0 = 0; k0 < K; k0 += BK) {
                 compute(As + cur * LDS_A, Bs + cur * LDS_B, acc);
                 if (k0 + BK < K) {
-                    sstore(As + (cur ^ 1) * LDS_A, Bs + (cur ^ 1) * LDS_B);
-                    if (k0 + 2 * BK < K) gload(k0 + 2 * BK);
+                    sstore(As + (cur ^ 1) * LDS_A, Bs + (cur ^ 1) * LDS_B, ra, rb);
+                    if (k0 + 2 * BK < K) gload(k0 + 2 * BK, ra, rb);
                 }
                 __syncthreads();
                 cur ^= 1;
@@ -396,11 +440,11 @@ struct Core {
             __syncthreads();
             for (int k0 = 0; k0 < K; k0 += BK) {
                 const bool more = k0 + BK < K;
-                if (more) gload(k0 + BK);
+                if (more) gload(k0 + BK, ra, rb);
                 compute(As, Bs, acc);
                 __syncthreads();
                 if (more) {
-                    sstore(As, Bs);
+                    sstore(As, Bs, ra, rb);
                     __syncthreads();
                 }
             }
