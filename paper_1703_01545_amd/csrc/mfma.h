@@ -384,7 +384,7 @@ struct Core {
 
         gload(0, ra, rb);
         sstore(As, Bs, ra, rb);
-        if (DB && PL == 2 && ROWS_VALID && K % BK == 0) {
+        if (DB && PL == 2 && ROWS_VALID && K > 0 && K % BK == 0) {
             // Split BF16 over whole K tiles: a second staging set, so that each
             // tile is fetched two tiles ahead of its split into LDS (the fetch
             // latency hides behind two tiles of products instead of one).  Tile
