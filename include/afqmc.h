@@ -325,6 +325,18 @@ const char* afqmc_phase_name(int phase);
 afqmc_status afqmc_selftest_gemm(afqmc_prec prec, int m, int n, int k, const double* A,
                                  const double* B, double* C);
 
+/* Kernel self-test with the launch shape fixed: C = A * B^T as above, with
+ * the operands held in the storage the walker step gives its contractions
+ * (FP64 for AFQMC_FP64; FP32 for AFQMC_FP32 and for AFQMC_BF16, which here
+ * selects the split-BF16 products) and an FP64 result.  tile: 0 size
+ * heuristic, 1 64 x 64, 2 128 x 128, 3 256 x 128 workgroup tiles; ksplit
+ * >= 1: K cut into that many ranges whose partial sums are added in range
+ * order.  Every tile shape gives the same bits for the same ksplit.  For the
+ * tests of the GEMM paths the walker step takes.  Errors: E_INVALID.
+ * Synchronises. */
+afqmc_status afqmc_selftest_gemm_shape(afqmc_prec prec, int tile, int ksplit, int m, int n, int k,
+                                       const double* A, const double* B, double* C);
+
 /* Kernel self-test of the fused propagation: out[w] = P T_K(A_w) P phi[w]
  * (Eq. 3 and Eq. 11, T_K the order-K Taylor polynomial of exp) with the
  * products in precision `prec` (AFQMC_FP64; AFQMC_BF16X3: Taylor terms and

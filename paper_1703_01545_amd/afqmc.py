@@ -31,7 +31,7 @@ EXPORTS = [
     "afqmc_load_hamiltonian", "afqmc_init_walkers", "afqmc_step", "afqmc_local_energy",
     "afqmc_orthonormalize", "afqmc_pair_step", "afqmc_pair_batch_step", "afqmc_get_walkers",
     "afqmc_sys_info", "afqmc_checkpoint", "afqmc_restore", "afqmc_free_sys", "afqmc_free_ham",
-    "afqmc_last_error", "afqmc_selftest_gemm", "afqmc_selftest_fields", "afqmc_profile_enable",
+    "afqmc_last_error", "afqmc_selftest_gemm", "afqmc_selftest_gemm_shape", "afqmc_selftest_fields", "afqmc_profile_enable",
     "afqmc_profile_read", "afqmc_phase_name", "afqmc_selftest_propagate", "afqmc_autotune",
     "afqmc_adjoint_forward", "afqmc_adjoint_backward", "afqmc_pair_step_noalloc",
     "afqmc_population_control", "afqmc_init_from_primary", "afqmc_cap_events",
@@ -75,6 +75,8 @@ _lib.afqmc_free_sys.restype = None
 _lib.afqmc_free_ham.argtypes = [_vp]
 _lib.afqmc_free_ham.restype = None
 _lib.afqmc_selftest_gemm.argtypes = [C.c_int, C.c_int, C.c_int, C.c_int, _dp, _dp, _dp]
+_lib.afqmc_selftest_gemm_shape.argtypes = [C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int,
+                                             _dp, _dp, _dp]
 _lib.afqmc_selftest_fields.argtypes = [C.c_uint64, C.c_uint64, C.c_int64, C.c_int, C.c_int, _dp]
 _lib.afqmc_selftest_propagate.argtypes = [C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int,
                                            _dp, _dp, _dp, _dp]
@@ -349,6 +351,19 @@ def selftest_gemm(A, B, precision: str = "fp64") -> np.ndarray:
     n = B.shape[0]
     Cm = np.empty((m, n))
     _check(_lib.afqmc_selftest_gemm(PREC[precision], m, n, k, _ptr(A), _ptr(B), _ptr(Cm)))
+    return Cm
+
+
+def selftest_gemm_shape(A, B, precision: str, tile: int, ksplit: int = 1) -> np.ndarray:
+    """C = A B^T with the workgroup tile (0 heuristic, 1 64x64, 2 128x128,
+    3 256x128) and the number of K ranges fixed; FP32 operand storage for
+    fp32 and bf16 (split-BF16 products)."""
+    A, B = _f64(A), _f64(B)
+    m, k = A.shape
+    n = B.shape[0]
+    Cm = np.empty((m, n))
+    _check(_lib.afqmc_selftest_gemm_shape(PREC[precision], tile, ksplit, m, n, k, _ptr(A), _ptr(B),
+                                          _ptr(Cm)))
     return Cm
 
 

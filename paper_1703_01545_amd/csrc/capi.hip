@@ -3,6 +3,8 @@
 // the ordering of the device phases of one step.
 #include <string>
 
+#include <vector>
+
 #include "host.h"
 
 using namespace afq;
@@ -1159,6 +1161,57 @@ afqmc_status afqmc_selftest_gemm(afqmc_prec prec, int m, int n, int k, const dou
                     : prec == AFQMC_FP32 ? DT_F32
                     : prec == AFQMC_BF16 ? DT_SPLIT
                                          : DT_BF16;
+    HIPCHK(gemm(g, c, nullptr));
+    HIPCHK(hipDeviceSynchronize());
+    HIPCHK(hipMemcpy(C, dC.p, (size_t)m * n * 8, hipMemcpyDeviceToHost));
+    return AFQMC_OK;
+}
+
+afqmc_status afqmc_selftest_gemm_shape(afqmc_prec prec, int tile, int ksplit, int m, int n, int k,
+                                       const double* A, const double* B, double* C) {
+    if (!A || !B || !C || m <= 0 || n <= 0 || k <= 0 || tile < 0 || tile > 3 || ksplit < 1)
+        return fail(AFQMC_E_INVALID, "bad args");
+    if (prec != AFQMC_FP64 && prec != AFQMC_FP32 && prec != AFQMC_BF16)
+        return fail(AFQMC_E_INVALID, "precision: fp64, fp32 or split bf16");
+    const DType st = prec == AFQMC_FP64 ? DT_F64 : DT_F32;  // operand storage
+    const DType c = prec == AFQMC_FP64 ? DT_F64 : prec == AFQMC_FP32 ? DT_F32 : DT_SPLIT;
+    const size_t es = dt_size(st);
+    std::vector<float> a32, b32;
+    const void* ha = A;
+    const void* hb = B;
+    if (st == DT_F32) {
+        a32.assign(A, A + (size_t)m * k);
+        b32.assign(B, B + (size_t)n * k);
+        ha = a32.data();
+        hb = b32.data();
+    }
+    DevBuf dA, dB, dC, dW;
+    HIPCHK(dA.alloc((size_t)m * k * es));
+    HIPCHK(dB.alloc((size_t)n * k * es));
+    HIPCHK(dC.alloc((size_t)m * n * 8));
+    HIPCHK(hipMemcpy(dA.p, ha, (size_t)m * k * es, hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(dB.p, hb, (size_t)n * k * es, hipMemcpyHostToDevice));
+    Gemm g{};
+    g.A = dA.p;
+    g.ta = st;
+    g.ra = rows_strided(k);
+    g.B = dB.p;
+    g.tb = st;
+    g.rb = rows_strided(k);
+    g.C = dC.p;
+    g.tc = DT_F64;
+    g.rc = rows_strided(n);
+    g.alpha = 1.0;
+    g.m = m;
+    g.n = n;
+    g.k = k;
+    g.batch = 1;
+    g.tile = tile;
+    if (ksplit > 1) {
+        g.ksplit = ksplit;
+        HIPCHK(dW.alloc(gemm_ws_bytes(m, n, ksplit, c)));
+        g.ws = dW.p;
+    }
     HIPCHK(gemm(g, c, nullptr));
     HIPCHK(hipDeviceSynchronize());
     HIPCHK(hipMemcpy(C, dC.p, (size_t)m * n * 8, hipMemcpyDeviceToHost));

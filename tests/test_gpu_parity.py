@@ -59,6 +59,35 @@ def test_gemm_kernel(lib, shape, prec):
     assert np.max(np.abs(got - ref) / scale) < tol
 
 
+# Every workgroup tile of the contraction GEMM on operands stored as the walker
+# step stores them (FP32 for the fp32 and split-BF16 products, FP64 for fp64):
+# ragged m and n (rows past the operands), K a whole number of 32-wide tiles
+# (the two-set fetch path of the split products) or not, one or several K
+# ranges, and K ranges left empty (K = 40 in four ranges of 32).  The tile
+# shapes sum in the same order, so they agree bitwise for each number of K
+# ranges; the result matches the product of the stored operands within the
+# rounding of the precision (split BF16: a few 2^-17 per product).
+@pytest.mark.parametrize("shape,ks", [((300, 141, 4096), 3), ((517, 260, 1000), 1),
+                                      ((256, 128, 96), 1), ((700, 333, 2080), 4),
+                                      ((64, 801, 3648), 3), ((150, 70, 40), 4)])
+@pytest.mark.parametrize("prec", ["bf16", "fp32", "fp64"])
+def test_gemm_tile_shapes_agree(lib, prec, shape, ks):
+    banner(f"gemm tiles {prec} {shape} ksplit {ks}")
+    m, n, k = shape
+    rng = np.random.default_rng(m + 3 * n + k)
+    A = rng.standard_normal((m, k))
+    B = rng.standard_normal((n, k))
+    if prec != "fp64":
+        A, B = A.astype(np.float32).astype(np.float64), B.astype(np.float32).astype(np.float64)
+    outs = [lib.selftest_gemm_shape(A, B, prec, tile, ks) for tile in (1, 2, 3)]
+    for o in outs[1:]:
+        assert np.array_equal(o, outs[0])
+    ref = A @ B.T
+    scale = np.abs(A) @ np.abs(B).T
+    tol = {"fp64": 1e-13, "fp32": 1e-5, "bf16": 5e-5}[prec]
+    assert np.max(np.abs(outs[0] - ref) / scale) < tol
+
+
 def test_device_fields_match_oracle_generator(lib):
     banner("philox fields")
     for (seed, stream, t, nw, nc) in [(0, 0, 0, 64, 36), (2 ** 40 + 5, 3, 123457, 33, 401)]:
