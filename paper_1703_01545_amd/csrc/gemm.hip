@@ -289,21 +289,23 @@ __global__ __launch_bounds__(64 * WGM * WGN) void k_exchange(
 // orbitals padded to NB (a multiple of 8).  Wavefront (wm, wn) of the 2 x 2
 // workgroup owns G gamma blocks (rows gamma, i: R = G NB, a multiple of 16)
 // of one walker (columns plane, j: C = 2 NB), so its R x C tile holds whole
-// N_s x N_s blocks and the pairing T_ij T_ji stays inside the wavefront: the
-// tile goes to a private LDS region (odd pitch; two rounds of two
-// wavefronts reuse the operand buffers) and each block's sum is folded by a
-// butterfly.  Output slot: walker, spin, gamma group gg (G blocks each).
+// N_s x N_s blocks and the pairing T_ij T_ji stays inside the wavefront: one
+// gamma block at a time goes row-major to the wavefront's own LDS region, and
+// each lane multiplies its accumulators T_ij (four consecutive i at one j)
+// with the partners T_ji (four consecutive floats of row j, per plane).  The
+// lane sums run over all ordered (i, j) and are folded by a butterfly.
+// Output slot: walker, spin, gamma group gg (G blocks each).
 template <int NB, int G>
 struct ExchBlk {
-    static constexpr int R = G * NB, C = 2 * NB, BM = 2 * R, BN = 2 * C, P = R + 4;
+    static constexpr int R = G * NB, C = 2 * NB, BM = 2 * R, BN = 2 * C;
+    static constexpr int PW = C + 4;  // row pitch of a stored block (floats)
     typedef Core<float, float, Split, BM, BN, 32, 2, 2, 4, 4, true> Cr;
     // two operand buffers (the split of the next K tile overlaps the
     // products; 80 KB at N_s = 40, so two workgroups share a CU's 160 KB),
-    // reused after the K loop for the two tiles and the reduction slots
+    // reused after the K loop for the four wavefronts' block regions
     static constexpr int OPB = 2 * (Cr::LDS_A + Cr::LDS_B) * (int)sizeof(bf16_t);
-    static constexpr int EPB = 2 * C * P * (int)sizeof(float);
-    static constexpr int RED = 16 * (int)sizeof(double);
-    static constexpr int SMEM = OPB > EPB + RED ? OPB : EPB + RED;
+    static constexpr int EPB = 4 * NB * PW * (int)sizeof(float);
+    static constexpr int SMEM = OPB > EPB ? OPB : EPB;
 };
 
 template <int NB, int G>
@@ -314,13 +316,10 @@ __global__ __launch_bounds__(256, 2) void k_exchange_blk(const float* __restrict
                                                       int spin, int n_gt, int n_gtw, int n_wt) {
     typedef ExchBlk<NB, G> E;
     typedef typename E::Cr Cr;
-    constexpr int R = E::R, C = E::C, P = E::P;
     __shared__ __attribute__((aligned(16))) char smem[E::SMEM];
     bf16_t* As = reinterpret_cast<bf16_t*>(smem);
     bf16_t* Bs = As + 2 * Cr::LDS_A;
     float* S = reinterpret_cast<float*>(smem);
-    // [round][tile][half][re, im]
-    double(*red)[2][2][2] = reinterpret_cast<double(*)[2][2][2]>(smem + E::EPB);
 
     // XCD-aware tile order: each XCD takes a contiguous range of logical
     // tiles, walked in super-tiles of 8 gamma groups x 8 walker pairs, so the
@@ -355,69 +354,70 @@ __global__ __launch_bounds__(256, 2) void k_exchange_blk(const float* __restrict
     }
     typename Cr::accv acc[Cr::TM][Cr::TN];
     Cr::template run<true>(lhalf, aoff, theta, boff, M, As, Bs, acc);
-    // the tile column-major (column = plane, j; row = gamma, i), four rows per
-    // 16-byte store; pairs (i, j = i + d mod NB), d = 0 .. NB / 2, cover each
-    // unordered pair once (weight 2; the diagonal and d = NB / 2 weight 1),
-    // and both reads of a pair walk the lanes with the odd stride P + 1.
-    // Two tiles fit in LDS: in round r waves (r, 0) and (r, 1) store theirs,
-    // then all four waves reduce them, each tile's pair terms split in two
-    // halves; the halves' sums are added in fixed order.
-    constexpr int D = NB / 2 + 1;
-    constexpr int NE = G * D * NB, HE = (NE + 1) / 2;
-    for (int round = 0; round < 2; ++round) {
-        if ((wave >> 1) == round) {
-            float* Sx = S + (wave & 1) * C * P;
+    // the operand buffers are free (the K loop ends on a barrier); this
+    // wavefront's block region
+    constexpr int PW = E::PW;
+    float* Sw = S + wave * NB * PW;
+    const int li = lane & 15, rq = 4 * (lane >> 4);
+    float fr = 0.0f, fi = 0.0f;
 #pragma unroll
-            for (int a = 0; a < Cr::TM; ++a)
+    for (int gb = 0; gb < G; ++gb) {
+        // block gb's rows (gamma, i), row-major (columns plane, j)
 #pragma unroll
-                for (int b = 0; b < Cr::TN; ++b)
-                    *reinterpret_cast<f4*>(&Sx[(b * 16 + (lane & 15)) * P + a * 16 +
-                                               4 * (lane >> 4)]) = acc[a][b];
+        for (int a = 0; a < Cr::TM; ++a) {
+            const int r0 = a * 16 + rq;  // four rows r0 .. r0 + 3, one block
+            if (r0 / NB != gb) continue;
+#pragma unroll
+            for (int b = 0; b < Cr::TN; ++b)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) Sw[(r0 - gb * NB + q) * PW + b * 16 + li] = acc[a][b][q];
         }
-        __syncthreads();
-        const float* Sx = S + (wave & 1) * C * P;
-        const int half = wave >> 1;
-        const int e0 = half * HE + lane, e1 = half ? NE : HE;
-        // (gl, d, i) of term e, advanced by 64 terms per iteration
-        int gl = e0 / (D * NB), d = (e0 % (D * NB)) / NB, i = e0 % NB;
-        constexpr int STEP_D = 64 / NB, STEP_I = 64 % NB;
-        float fr = 0.0f, fi = 0.0f;
-        for (int e = e0; e < e1; e += 64) {
-            const int j = i + d < NB ? i + d : i + d - NB;
-            const float wgt = (d == 0 || 2 * d == NB) ? 1.0f : 2.0f;
-            const int r0 = gl * NB;
-            const float a_ij = Sx[j * P + r0 + i], b_ij = Sx[(NB + j) * P + r0 + i];
-            const float a_ji = Sx[i * P + r0 + j], b_ji = Sx[(NB + i) * P + r0 + j];
-            fr += wgt * (a_ij * a_ji - b_ij * b_ji);
-            fi += wgt * (a_ij * b_ji + b_ij * a_ji);
-            i += STEP_I;
-            d += STEP_D;
-            if (i >= NB) {
-                i -= NB;
-                d += 1;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+#pragma unroll
+        for (int a = 0; a < Cr::TM; ++a) {
+            const int r0 = a * 16 + rq;
+            if (r0 / NB != gb) continue;
+            const int i0 = r0 - gb * NB;
+#pragma unroll
+            for (int b = 0; b < Cr::TN; ++b) {
+                const int c = b * 16 + li, p = c / NB, j = c % NB;
+                // partners of T_(i0+q) j: T_j(i0+q) in planes 0 (a) and 1 (b)
+                const f4 pa = *reinterpret_cast<const f4*>(&Sw[j * PW + i0]);
+                const f4 pb = *reinterpret_cast<const f4*>(&Sw[j * PW + NB + i0]);
+                const f4 t = acc[a][b];
+                if (p == 0) {  // t = Re T_ij: Re += a_ij a_ji, Im += a_ij b_ji
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        fr += t[q] * pa[q];
+                        fi += t[q] * pb[q];
+                    }
+                } else {  // t = Im T_ij: Re -= b_ij b_ji, Im += b_ij a_ji
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        fr -= t[q] * pb[q];
+                        fi += t[q] * pa[q];
+                    }
+                }
             }
-            if (d >= D) {
-                d -= D;
-                gl += 1;
-            }
         }
-        double sr = fr, si = fi;
+        // every lane's reads of this block before the next block's stores
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
+    double sr = fr, si = fi;
 #pragma unroll
-        for (int o = 32; o >= 1; o >>= 1) {
-            sr += __shfl_xor(sr, o, 64);
-            si += __shfl_xor(si, o, 64);
-        }
-        if (lane == 0) {
-            red[round][wave & 1][half][0] = sr;
-            red[round][wave & 1][half][1] = si;
-        }
-        __syncthreads();
+    for (int o = 32; o >= 1; o >>= 1) {
+        sr += __shfl_xor(sr, o, 64);
+        si += __shfl_xor(si, o, 64);
     }
     const int w = w0 + wn, gg = gt * 2 + wm;
     if (lane == 0 && w < nw && gg < n_gt) {
         double* o = out + ((long)(w * 2 + spin) * n_gt + gg) * 2;
-        o[0] = red[wm][wn][0][0] + red[wm][wn][1][0];
-        o[1] = red[wm][wn][0][1] + red[wm][wn][1][1];
+        o[0] = sr;
+        o[1] = si;
     }
 }
 
