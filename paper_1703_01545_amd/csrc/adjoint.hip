@@ -163,9 +163,9 @@ __global__ __launch_bounds__(256) void k_adj_fbar(const double* __restrict__ F, 
 __global__ __launch_bounds__(256) void k_adj_pack(const double* __restrict__ Af,
                                                   double* __restrict__ Apk, int M, int nt) {
     __shared__ double tt[32][33];
-    const long pl = blockIdx.y;
+    const long pl = blockIdx.x;  // planes on x (limit 2^31 - 1 blocks)
     const long P = (long)M * (M + 1) / 2;
-    int t = blockIdx.x, bi = 0;
+    int t = blockIdx.y, bi = 0;
     while (t >= nt - bi) {  // nt <= 8
         t -= nt - bi;
         ++bi;
@@ -819,7 +819,7 @@ afqmc_status reverse_step(afqmc_sys s, AdjState* a, int j, const double* phi_nex
     {
         const long P = s->P();
         const int nt = (M + 31) / 32;
-        hipLaunchKernelGGL(k_adj_pack, dim3(nt * (nt + 1) / 2, 2 * nw), dim3(256), 0, st,
+        hipLaunchKernelGGL(k_adj_pack, dim3(2 * nw, nt * (nt + 1) / 2), dim3(256), 0, st,
                            a->Abar.as<double>(), a->Abpk.as<double>(), M, nt);
         Gemm g{};
         g.A = a->Abpk.p;

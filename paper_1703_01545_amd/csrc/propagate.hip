@@ -23,14 +23,15 @@ using namespace dev;
 
 // Packed upper triangle (row-major, P = M(M+1)/2 per plane) -> full
 // symmetric M x M, through a 32 x 33 LDS tile so both the direct and the
-// mirrored writes are coalesced.  grid: (row bands of 32, planes).
+// mirrored writes are coalesced.  grid: (planes, row bands of 32): the plane
+// count (2 per walker) on x, whose limit is 2^31 - 1 blocks.
 template <typename T>
 __global__ __launch_bounds__(256) void k_unpack(const T* __restrict__ pk, T* __restrict__ full,
                                                 int M) {
     __shared__ T tile[32][33];
     const long P = (long)M * (M + 1) / 2;
-    const long plane = blockIdx.y;
-    const int ti = blockIdx.x;
+    const long plane = blockIdx.x;
+    const int ti = blockIdx.y;
     const T* src = pk + plane * P;
     T* dst = full + plane * (long)M * M;
     const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // 32 x 8
@@ -992,7 +993,7 @@ hipError_t unpack_prepare() {
 
 hipError_t unpack_sym(const void* pk, void* full, int M, int planes, DType t, hipStream_t s) {
     if (planes <= 0) return hipSuccess;
-    dim3 grid((M + 31) / 32, planes);
+    dim3 grid(planes, (M + 31) / 32);
     if (t == DT_F64)
         hipLaunchKernelGGL(k_unpack<double>, grid, dim3(256), 0, s, (const double*)pk,
                            (double*)full, M);

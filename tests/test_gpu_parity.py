@@ -239,6 +239,25 @@ def test_parity_m100_sampled_walkers(lib, torch_mod):
     assert rel(el_a[sub], ref_el) < TOL
 
 
+def test_walker_count_beyond_grid_y_limit(lib):
+    """40 000 walkers per system: 80 000 walker planes, more than a launch
+    grid takes in its y or z dimension (65 535 blocks), so every per-plane
+    launch (the FP64 plan's unpack of the field sums among them) must put the
+    planes on x.  Sampled walkers, on both sides of 32 768, match the oracle."""
+    c = config(0)
+    nw = 40000
+    banner(f"walker count {nw} (planes beyond the grid's y limit)")
+    wl = Workload(c.M, c.n_chol, c.na_a, c.nb_a, c.na_b, c.nb_b, nw, c.dt)
+    sub = np.array([0, 32767, 32768, nw - 1])
+    sa, sb = wl.oracle_systems()
+    wa, wb = O.init_walkers(sa, len(sub)), O.init_walkers(sb, len(sub))
+    O.run_pair(sa, sb, wa, wb, O.PhiloxFields(3, 0, c.n_chol, walkers=sub), 10, 5, 5)
+    H, (ga, gb) = wl.gpu_systems(lib, ortho_every=5, measure_every=5)
+    lib.pair_step(ga, gb, 10, seed=3)
+    _compare_walkers(ga, wa, sub)
+    _compare_walkers(gb, wb, sub)
+
+
 def test_bench_config_sampled_walkers(lib, torch_mod):
     """The timed workload as bench.py runs it: the M=200 pair (40/40 vs 40/39,
     n_chol = 800) at its full 2048 walkers per system, autotuned shapes,
