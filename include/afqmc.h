@@ -15,6 +15,11 @@
  * - Every call returns an afqmc_status; on failure a message is available
  *   from afqmc_last_error() (thread-local).  No call aborts, exits or throws
  *   across the ABI.
+ * - Handles are not synchronised internally: calls on one handle, or on
+ *   systems that share a Hamiltonian (and so its stream), must not overlap.
+ *   Calls on unrelated Hamiltonians may come from different host threads;
+ *   the process-wide caches (tuned launch shapes, captured batch graphs)
+ *   are guarded.
  * - A walker whose weight is no longer positive is frozen, not an error
  *   (Sec. II.B of the paper); afqmc_get_walkers reports it through `alive`.
  */

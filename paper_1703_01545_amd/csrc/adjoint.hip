@@ -25,6 +25,8 @@
 //   dE/dlambda += <Phi_bar', dP y> + <u_bar, dP Phi>.
 // Gram-Schmidt Q = Phi R^{-1}: everything after it is unchanged by Q -> Q U,
 // so Phi_bar = Q_bar S^H with S = R^{-1} = O(Phi)^{-1} O(Q).
+#include <atomic>
+
 #include "host.h"
 
 using namespace afq;
@@ -482,7 +484,7 @@ afqmc_status adj_setup(afqmc_sys s, AdjState* a, hipStream_t st) {
         a->trial_host.resize((size_t)NM);
         HIPCHK(hipMemcpy(a->trial_host.data(), s->d_trialT.p, NM * 8, hipMemcpyDeviceToHost));
     }
-    static bool lds_ready = false;  // process-wide kernel attribute
+    static std::atomic<bool> lds_ready{false};  // process-wide kernel attribute
     if (!lds_ready) {
         HIPCHK(dense_adj_prepare());
         lds_ready = true;

@@ -14,6 +14,7 @@
 #include <array>
 #include <map>
 #include <memory>
+#include <mutex>
 
 #include "host.h"
 
@@ -28,6 +29,9 @@ namespace {
 
 typedef std::array<long, 8> ShapeKey;
 std::map<ShapeKey, int> g_tuned;  // problem shape -> fastest candidate
+// Guards the process-wide caches (g_tuned, g_plans): calls on unrelated
+// handles may come from different host threads.
+std::mutex g_cache_mu;
 
 struct EventPair {
     hipEvent_t a = nullptr, b = nullptr;
@@ -60,10 +64,13 @@ hipError_t time_launches(F run, hipStream_t st, int reps, float* ms) {
 template <typename F>
 hipError_t pick(const ShapeKey& key, const std::vector<int>& cands, F run, hipStream_t st,
                 int* out) {
-    auto it = g_tuned.find(key);
-    if (it != g_tuned.end()) {
-        *out = it->second;
-        return hipSuccess;
+    {
+        std::lock_guard<std::mutex> lk(g_cache_mu);
+        auto it = g_tuned.find(key);
+        if (it != g_tuned.end()) {
+            *out = it->second;
+            return hipSuccess;
+        }
     }
     int best = cands.front();
     float best_ms = 1e30f;
@@ -76,7 +83,10 @@ hipError_t pick(const ShapeKey& key, const std::vector<int>& cands, F run, hipSt
             best = c;
         }
     }
-    g_tuned[key] = best;
+    {
+        std::lock_guard<std::mutex> lk(g_cache_mu);
+        g_tuned[key] = best;
+    }
     *out = best;
     return hipSuccess;
 }
@@ -254,6 +264,7 @@ afqmc_status autotune(afqmc_sys s, hipStream_t st) {
 }
 
 void drop_batch_plans(uint64_t id) {
+    std::lock_guard<std::mutex> lk(g_cache_mu);
     for (size_t i = 0; i < g_plans.size();) {
         const auto& ids = g_plans[i]->ids;
         if (std::find(ids.begin(), ids.end(), id) != ids.end())
@@ -354,15 +365,18 @@ afqmc_status afqmc_pair_batch_step(int n_pairs, const afqmc_sys* a, const afqmc_
     for (afqmc_sys z : all) ids.push_back(z->id);
     const bool use_graph = !(flags & 1);
     BatchPlan* plan = nullptr;
-    for (auto& pl : g_plans)
-        if (pl->ids == ids && pl->seeds == sds && pl->lanes == L) plan = pl.get();
-    if (plan) {
-        bool same = true;
-        for (size_t i = 0; i < all.size(); ++i) same = same && plan->phi0[i] == all[i]->d_phi.p;
-        if (!same) {  // odd number of direct steps since capture: capture again
-            for (size_t i = 0; i < g_plans.size(); ++i)
-                if (g_plans[i].get() == plan) g_plans.erase(g_plans.begin() + i);
-            plan = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(g_cache_mu);
+        for (auto& pl : g_plans)
+            if (pl->ids == ids && pl->seeds == sds && pl->lanes == L) plan = pl.get();
+        if (plan) {
+            bool same = true;
+            for (size_t i = 0; i < all.size(); ++i) same = same && plan->phi0[i] == all[i]->d_phi.p;
+            if (!same) {  // odd number of direct steps since capture: capture again
+                for (size_t i = 0; i < g_plans.size(); ++i)
+                    if (g_plans[i].get() == plan) g_plans.erase(g_plans.begin() + i);
+                plan = nullptr;
+            }
         }
     }
     if (!plan) {
@@ -376,6 +390,7 @@ afqmc_status afqmc_pair_batch_step(int n_pairs, const afqmc_sys* a, const afqmc_
         HIPCHK(pl->ln.create(L));
         HIPCHK(pl->ctr.alloc(4 * sizeof(int64_t)));
         plan = pl.get();
+        std::lock_guard<std::mutex> lk(g_cache_mu);
         g_plans.push_back(std::move(pl));
     }
     Lanes& ln = plan->ln;

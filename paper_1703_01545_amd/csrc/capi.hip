@@ -1,8 +1,8 @@
 // C ABI of the correlated-sampling ph-AFQMC walker step (see include/afqmc.h).
 // Host code: handle management, validation, the per-system precompute, and
 // the ordering of the device phases of one step.
+#include <atomic>
 #include <string>
-
 #include <vector>
 
 #include "host.h"
@@ -489,7 +489,7 @@ afqmc_status init_system(afqmc_ham ham, int n_alpha, int n_beta, int n_det, cons
     if (!(par->dt > 0.0) || par->taylor_order < 1 || par->ortho_every < 0 || par->measure_every < 0)
         return fail(AFQMC_E_INVALID, "bad params (dt > 0, taylor_order >= 1, periods >= 0)");
     if (!(par->fb_cap >= 0.0)) return fail(AFQMC_E_INVALID, "fb_cap must be >= 0");
-    static bool unpack_ready = false;  // kernel attribute, set once outside any capture
+    static std::atomic<bool> unpack_ready{false};  // kernel attribute, set outside any capture
     if (!unpack_ready) {
         if (unpack_prepare() != hipSuccess) return fail(AFQMC_E_DEVICE, "unpack kernel attribute");
         unpack_ready = true;
@@ -500,7 +500,7 @@ afqmc_status init_system(afqmc_ham ham, int n_alpha, int n_beta, int n_det, cons
         return fail(AFQMC_E_INVALID, "bad mode");
     hipStream_t st = ham->stream;
     afqmc_sys s = new afqmc_sys_s();
-    static uint64_t next_id = 0;
+    static std::atomic<uint64_t> next_id{0};
     s->id = ++next_id;
     s->ham = ham;
     ham->refs++;

@@ -9,6 +9,8 @@
 // HBM/L2.  The running sum Z of the Taylor terms lives in registers (in LDS
 // for two of the shapes).  The products run on the matrix cores: FP64 or
 // FP32 MFMA 16x16x4, or split BF16 (MFMA 16x16x32, three per product).
+#include <atomic>
+
 #include "mfma.h"
 
 // No contraction of a multiply and an add into one fused operation anywhere
@@ -868,7 +870,7 @@ hipError_t launch_prop_split_rb(const double* phi, double* phi_out, const void* 
     const int nrb = (N + 16 * RB - 1) / (16 * RB);
     const long nblk = (long)nw * nrb;
     const long grid = ((nblk + 7) / 8) * 8;
-    static bool attr = false;
+    static std::atomic<bool> attr{false};  // per kernel; set before any capture
     if (!attr && shm > 65536) {
         hipError_t e = hipFuncSetAttribute((const void*)k_propagate_split_rb<NWAVE, MAXB, RB, ZREG>,
                                            hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);

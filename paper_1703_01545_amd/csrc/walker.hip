@@ -5,6 +5,8 @@
 // sums, so every run is bitwise reproducible.
 #include <math.h>
 
+#include <atomic>
+
 #include "internal.h"
 #include "mfma.h"
 
@@ -1202,7 +1204,7 @@ hipError_t lu_theta(const double* phi, const double* trialT, double* theta, void
     // larger blocks: one workgroup of four wavefronts per block, the matrix in
     // LDS (writes the FP64 Theta and, if requested, the copy)
     const size_t shm = (size_t)2 * 64 * 65 * sizeof(double);
-    static bool attr = false;  // set once, outside graph capture
+    static std::atomic<bool> attr{false};  // set once, outside graph capture
     if (!attr) {
         hipError_t e = hipFuncSetAttribute((const void*)k_lu_theta<16, 16>,
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);

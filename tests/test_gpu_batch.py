@@ -101,6 +101,44 @@ def test_autotune_keeps_results(lib):
         assert np.array_equal(u, v)
 
 
+def test_unrelated_hamiltonians_from_two_host_threads(lib):
+    """Two host threads, each with its own Hamiltonian and pair, autotune and
+    step at the same time (ctypes releases the interpreter lock during a
+    call): the shared cache of tuned launch shapes is guarded, and tuning
+    never changes a bit, so each pair ends bitwise where it ends when the two
+    run one after the other."""
+    import threading
+    banner("two host threads, unrelated Hamiltonians")
+    wls = [Workload(20, 40, 4, 4, 4, 3, 48, 0.01, ham_seed=s) for s in (5, 6)]
+
+    def run(wl, out, i):
+        try:
+            H, (a, b) = wl.gpu_systems(lib, precision="bf16x3", ortho_every=5, measure_every=5)
+            lib.autotune(a)
+            lib.autotune(b)
+            tr = lib.pair_step(a, b, 20, seed=9)
+            out[i] = (tr, a.walkers()["phi"], b.walkers()["weight"])
+        except Exception as e:  # surfaced in the main thread
+            out[i] = e
+
+    seq = [None, None]
+    for i, wl in enumerate(wls):
+        run(wl, seq, i)
+    par = [None, None]
+    th = [threading.Thread(target=run, args=(wl, par, i)) for i, wl in enumerate(wls)]
+    for t in th:
+        t.start()
+    for t in th:
+        t.join(timeout=120)
+    for i in range(2):
+        for r in (seq[i], par[i]):
+            if isinstance(r, Exception):
+                raise r
+            assert r is not None
+        for u, v in zip(seq[i], par[i]):
+            assert np.array_equal(u, v)
+
+
 def test_batch_errors(lib):
     banner("batch errors")
     sys_ = _make(lib, "fp64")
