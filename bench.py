@@ -206,6 +206,11 @@ def bench_pair(args):
     me = cfg.measure_every
     period = math.lcm(cfg.ortho_every, me)
     steps, warmup, profile_steps = plan_counts(args.steps, args.warmup, args.profile_steps, period)
+    if profile_steps == 0:
+        # the phase times and the roofline come from the profiled pass
+        profile_steps = period
+        print(f"[bench] --profile-steps 0: {period} steps profiled (the roofline needs them)",
+              file=sys.stderr, flush=True)
     ham = cfg.hamiltonian()
     ta, tb = cfg.trial_a(), cfg.trial_b()
     print(f"[bench] M={cfg.M} n_chol={cfg.n_chol} Nw={cfg.n_walkers} precision={prec}",
