@@ -178,6 +178,21 @@ afqmc_status afqmc_pair_step(afqmc_sys a, afqmc_sys b, uint64_t seed, int n_step
  * always 0 with fb_cap = 0).  Synchronises. */
 afqmc_status afqmc_cap_events(afqmc_sys sys, int64_t* count);
 
+/* Gram-Schmidt monitor (Sec. II.D: the walker orbitals lose orthogonality
+ * between orthonormalisations).  Every orthonormalisation of a live walker's
+ * spin block records ell = max_k 1/2 ln(S_kk / D_k), with S = Phi^H Phi =
+ * L D L^H over the block's columns (0 for orthogonal columns; about
+ * 2 ell / ln 10 decimal digits of the Gram-matrix factorisation are lost),
+ * and |ln |det R|| = |1/2 sum_k ln D_k| (how far the columns' volume moved
+ * since the previous orthonormalisation); non-finite values count as
+ * infinite.  Returns (each pointer may be NULL) the largest ell and the
+ * largest |ln |det R|| over the walker spin blocks since the system was
+ * created or the last call, and how many blocks had ell > threshold at some
+ * orthonormalisation; then clears the record.  Errors: E_INVALID (threshold
+ * negative or NaN), E_STATE.  Synchronises. */
+afqmc_status afqmc_gs_monitor(afqmc_sys sys, double threshold, double* max_ell,
+                              double* max_lndet, int64_t* trips);
+
 /* Population control by the comb (Sec. II.B: walkers with large weights are
  * replicated, small ones stochastically removed), for the equilibration of a
  * primary system; not used between correlated systems.  With C the running

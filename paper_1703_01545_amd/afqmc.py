@@ -35,7 +35,7 @@ EXPORTS = [
     "afqmc_profile_read", "afqmc_phase_name", "afqmc_selftest_propagate", "afqmc_autotune",
     "afqmc_adjoint_forward", "afqmc_adjoint_backward", "afqmc_pair_step_noalloc",
     "afqmc_population_control", "afqmc_init_from_primary", "afqmc_cap_events",
-    "afqmc_init_walkers_msd",
+    "afqmc_init_walkers_msd", "afqmc_gs_monitor",
 ]
 
 
@@ -75,6 +75,7 @@ _lib.afqmc_free_sys.restype = None
 _lib.afqmc_free_ham.argtypes = [_vp]
 _lib.afqmc_free_ham.restype = None
 _lib.afqmc_selftest_gemm.argtypes = [C.c_int, C.c_int, C.c_int, C.c_int, _dp, _dp, _dp]
+_lib.afqmc_gs_monitor.argtypes = [_vp, C.c_double, _dp, _dp, C.POINTER(C.c_int64)]
 _lib.afqmc_selftest_gemm_shape.argtypes = [C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int,
                                              _dp, _dp, _dp]
 _lib.afqmc_selftest_fields.argtypes = [C.c_uint64, C.c_uint64, C.c_int64, C.c_int, C.c_int, _dp]
@@ -200,6 +201,15 @@ class System:
         n = C.c_int64()
         _check(_lib.afqmc_cap_events(self._s, C.byref(n)))
         return n.value
+
+    def gs_monitor(self, threshold: float = 9.0):
+        """Gram-Schmidt monitor since the last call: (largest loss of
+        orthogonality ell, largest |ln |det R||, spin blocks with ell above
+        threshold); clears the record."""
+        me, ml, n = C.c_double(), C.c_double(), C.c_int64()
+        _check(_lib.afqmc_gs_monitor(self._s, float(threshold), C.byref(me), C.byref(ml),
+                                     C.byref(n)))
+        return me.value, ml.value, n.value
 
     def population_control(self, xi: float):
         """Comb of the walker population with the uniform number xi in [0, 1)."""

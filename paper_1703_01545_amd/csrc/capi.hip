@@ -205,7 +205,7 @@ afqmc_status ortho(afqmc_sys s, hipStream_t st) {
     {
         PhaseTimer pt(s, PH_MGS, st);
         HIPCHK(mgs(s->d_phi.as<double>(), s->d_alive.as<uint8_t>(), s->nw, s->M, s->N, s->na, s->nb,
-                   s->d_ovl.p, st));
+                   s->d_ovl.p, s->d_gsmon.as<double>(), st));
     }
     afqmc_status r = overlap_theta(s, s->d_phi.as<double>(), st);
     if (r != AFQMC_OK) return r;
@@ -561,6 +561,7 @@ afqmc_status init_system(afqmc_ham ham, int n_alpha, int n_beta, int n_det, cons
         {&s->d_sums, 8 * 8},
         {&s->d_pc, (size_t)nw * 12 + 16},
         {&s->d_capcount, (size_t)nw * 8},
+        {&s->d_gsmon, (size_t)nw * 4 * 8},
     };
     for (auto& a : allocs) {
         hipError_t e = a.b->alloc(a.bytes);
@@ -600,7 +601,7 @@ afqmc_status init_system(afqmc_ham ham, int n_alpha, int n_beta, int n_det, cons
     }
     // zero buffers read before first written (theta padding, F one-body row)
     for (DevBuf* b : {&s->d_theta, &s->d_theta_lp, &s->d_lhx, &s->d_exch, &s->d_simp,
-                      &s->d_capcount}) {
+                      &s->d_capcount, &s->d_gsmon}) {
         hipError_t e = hipMemsetAsync(b->p, 0, b->n, st);
         if (e != hipSuccess) return bail(fail(AFQMC_E_DEVICE, hipGetErrorString(e)));
     }
@@ -883,7 +884,7 @@ void afqmc_free_sys(afqmc_sys s) {
                       &s->d_phi, &s->d_phinew, &s->d_theta, &s->d_theta_lp, &s->d_w, &s->d_lnov,
                       &s->d_alive, &s->d_F, &s->d_X, &s->d_simp, &s->d_Apk, &s->d_Af,
                       &s->d_lnd, &s->d_ovl, &s->d_kws, &s->d_exch, &s->d_el, &s->d_sums,
-                      &s->d_pc, &s->d_capcount, &s->d_coef, &s->d_lnd_all, &s->d_F_all,
+                      &s->d_pc, &s->d_capcount, &s->d_gsmon, &s->d_coef, &s->d_lnd_all, &s->d_F_all,
                       &s->d_el_all, &s->d_rw})
         b->release();
     s->xdet.clear();
@@ -956,6 +957,30 @@ afqmc_status afqmc_cap_events(afqmc_sys s, int64_t* count) {
     int64_t n = 0;
     for (int64_t v : c) n += v;
     *count = n;
+    return AFQMC_OK;
+}
+
+afqmc_status afqmc_gs_monitor(afqmc_sys s, double threshold, double* max_ell,
+                              double* max_lndet, int64_t* trips) {
+    afqmc_status r = check_sys(s);
+    if (r != AFQMC_OK) return r;
+    if (!(threshold >= 0.0)) return fail(AFQMC_E_INVALID, "threshold must be >= 0");
+    hipStream_t st = s->ham->stream;
+    std::vector<double> m((size_t)s->nw * 4);
+    HIPCHK(hipStreamSynchronize(st));
+    HIPCHK(hipMemcpy(m.data(), s->d_gsmon.p, m.size() * 8, hipMemcpyDeviceToHost));
+    double me = 0.0, ml = 0.0;
+    int64_t n = 0;
+    for (size_t b = 0; b < m.size(); b += 2) {
+        me = std::max(me, m[b]);
+        ml = std::max(ml, m[b + 1]);
+        n += m[b] > threshold;
+    }
+    if (max_ell) *max_ell = me;
+    if (max_lndet) *max_lndet = ml;
+    if (trips) *trips = n;
+    HIPCHK(hipMemsetAsync(s->d_gsmon.p, 0, s->d_gsmon.n, st));
+    HIPCHK(hipStreamSynchronize(st));
     return AFQMC_OK;
 }
 

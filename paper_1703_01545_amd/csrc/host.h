@@ -182,6 +182,7 @@ struct afqmc_sys_s {
     afq::host::DevBuf d_kws;  // split-K partial sums of the force-bias GEMM
     afq::host::DevBuf d_pc;   // comb workspace: running sums, selection, status
     afq::host::DevBuf d_capcount;  // force-bias cap events per walker (int64)
+    afq::host::DevBuf d_gsmon;     // Gram-Schmidt monitor [w][spin][ell, |ln det R|]
     // Multi-determinant trial (Sec. II.D): determinant 0 uses d_trialT, d_lhx,
     // d_lhx_lp, d_theta, d_theta_lp and d_exch; determinants 1.. their own
     // buffers in xdet.  With n_det > 1 the per-determinant ln dets, force-bias

@@ -258,9 +258,11 @@ hipError_t weights(const double* lnd, const double* s_imp, double* lnov, double*
 // Orthonormalize every spin block of every live walker in place (the QR
 // factor Q with positive diagonal R, as modified Gram-Schmidt gives it):
 // blocks of at most 48 orbitals through the Gram matrix and its Cholesky
-// factor (ws: lu_theta_ws_bytes bytes), larger ones column by column.
+// factor (ws: lu_theta_ws_bytes bytes), larger ones column by column.  mon
+// (or NULL): [w][spin][2] record of the largest loss of orthogonality
+// max_k 1/2 ln(S_kk / D_k) and the largest |ln |det R|| seen by each block.
 hipError_t mgs(double* phi, const uint8_t* live, int nw, int M, int N, int na, int nb, void* ws,
-               hipStream_t s);
+               double* mon, hipStream_t s);
 
 // E_L[w] (complex) from F (f_g and the one-body trace at column n_chol) and
 // the exchange partials.

@@ -814,12 +814,33 @@ __global__ __launch_bounds__(64) void k_gram(const double* __restrict__ phi, d2*
     }
 }
 
+// Loss-of-orthogonality record of one spin block at a Gram-Schmidt step
+// (Sec. II.D): the lanes below n hold ell_k = 1/2 ln(S_kk / D_k), with S =
+// Phi^H Phi = L D L^H (zero for orthogonal columns; the Gram-matrix QR loses
+// about 2 ell / ln 10 decimal digits), and ln R_kk = 1/2 ln D_k.  mon[0]
+// keeps the largest ell and mon[1] the largest |ln |det R|| since the record
+// was cleared; anything non-finite counts as infinite.  One wavefront.
+__device__ __forceinline__ void gs_record(double* mon, double ell, double lnr) {
+    if (!(ell == ell)) ell = INFINITY;
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) {
+        ell = fmax(ell, __shfl_xor(ell, o, 64));
+        lnr += __shfl_xor(lnr, o, 64);
+    }
+    const double ld = (lnr == lnr) ? fabs(lnr) : INFINITY;
+    if ((threadIdx.x & 63) == 0) {
+        mon[0] = fmax(mon[0], ell);
+        mon[1] = fmax(mon[1], ld);
+    }
+}
+
 template <int NC>
 __global__ __launch_bounds__(64, NC <= 40 ? 2 : 1) void k_cholqr(double* phi,
                                                                  const d2* __restrict__ ovl,
                                                                  const uint8_t* __restrict__ live,
                                                                  int M, int N, int na, int nb,
-                                                                 int nmax) {
+                                                                 int nmax,
+                                                                 double* __restrict__ mon) {
     constexpr int SP = NC + 1;
     typedef double __attribute__((ext_vector_type(2))) E2;
     __shared__ __align__(16) E2 S[NC * SP];
@@ -863,6 +884,15 @@ __global__ __launch_bounds__(64, NC <= 40 ? 2 : 1) void k_cholqr(double* phi,
         ai[NC - 1] = -mi;
     }
     __syncthreads();
+    if (mon) {
+        double ell = 0.0, lnr = 0.0;
+        if (lane < n) {
+            const d2 skk = ovl[((long)w * 2 + spin) * nmax * nmax + (long)lane * nmax + lane];
+            ell = 0.5 * log(skk[0] / dv[lane]);
+            lnr = 0.5 * log(dv[lane]);
+        }
+        gs_record(mon + ((long)w * 2 + spin) * 2, ell, lnr);
+    }
     // S[i][k] = D_i^{-1/2} conj(L^{-1}[i][k]): R^{-1} transposed, by rows i
     if (lane < n) {
         const double sc = 1.0 / sqrt(dv[lane]);
@@ -911,7 +941,7 @@ __global__ void k_weights(const double* __restrict__ lnd, const double* __restri
 template <bool STAGE>
 __global__ __launch_bounds__(256) void k_mgs(double* __restrict__ phi,
                                              const uint8_t* __restrict__ live, int M, int N,
-                                             int na, int nb) {
+                                             int na, int nb, double* __restrict__ mon) {
     extern __shared__ double stage_buf[];
     const int w = blockIdx.x, spin = blockIdx.y;
     const int off = spin ? na : 0, n = spin ? nb : na;
@@ -934,6 +964,19 @@ __global__ __launch_bounds__(256) void k_mgs(double* __restrict__ phi,
     }
     __shared__ double red[4];
     __shared__ double proj[2 * 64];
+    __shared__ double s0[256];  // column norms before the sweep (monitor)
+    if (mon) {
+        for (int j = wave; j < n; j += 4) {
+            const double* qr = pr + (long)j * ldp;
+            const double* qi = pi + (long)j * ldp;
+            double a = 0.0;
+            for (int m = lane; m < M; m += 64) a += qr[m] * qr[m] + qi[m] * qi[m];
+            a = wave_sum(a);
+            if (lane == 0) s0[j] = a;
+        }
+        __syncthreads();
+    }
+    double ell = 0.0, lnr = 0.0;  // monitor record, the same in every thread
     for (int j = 0; j < n; ++j) {
         double* qr = pr + (long)j * ldp;
         double* qi = pi + (long)j * ldp;
@@ -942,7 +985,12 @@ __global__ __launch_bounds__(256) void k_mgs(double* __restrict__ phi,
         s = wave_sum(s);
         if (lane == 0) red[wave] = s;
         __syncthreads();
-        const double nrm = sqrt(((red[0] + red[1]) + red[2]) + red[3]);
+        const double dj = ((red[0] + red[1]) + red[2]) + red[3];
+        const double nrm = sqrt(dj);
+        if (mon) {
+            ell = fmax(ell, 0.5 * log(s0[j] / dj));
+            lnr += 0.5 * log(dj);
+        }
         for (int m = tid; m < M; m += 256) {
             qr[m] = qr[m] / nrm;
             qi[m] = qi[m] / nrm;
@@ -982,6 +1030,8 @@ __global__ __launch_bounds__(256) void k_mgs(double* __restrict__ phi,
             gi[e] = pi[e];
         }
     }
+    if (mon && tid < 64) gs_record(mon + ((long)w * 2 + spin) * 2, lane == 0 ? ell : 0.0,
+                                   lane == 0 ? lnr : 0.0);
 }
 
 __global__ void k_local_energy(const double* __restrict__ F, int ldf,
@@ -1226,22 +1276,22 @@ hipError_t weights(const double* lnd, const double* s_imp, double* lnov, double*
 
 template <int NC>
 hipError_t cholqr_nc(double* phi, const uint8_t* live, int nw, int M, int N, int na, int nb,
-                     void* ws, hipStream_t s) {
+                     void* ws, double* mon, hipStream_t s) {
     const dim3 grid(nw, 2), blk(64);
     const int nmax = na > nb ? na : nb;
     hipLaunchKernelGGL((k_gram<(NC + 15) / 16>), grid, blk, 0, s, phi, (d2*)ws, live, M, N, na,
                        nb, nmax);
     hipLaunchKernelGGL((k_cholqr<NC>), grid, blk, 0, s, phi, (const d2*)ws, live, M, N, na, nb,
-                       nmax);
+                       nmax, mon);
     return hipGetLastError();
 }
 
 hipError_t mgs(double* phi, const uint8_t* live, int nw, int M, int N, int na, int nb, void* ws,
-               hipStream_t s) {
+               double* mon, hipStream_t s) {
     if (nw <= 0) return hipSuccess;
     const int nmax = na > nb ? na : nb;
 #define AFQ_QR(NC) \
-    if (nmax <= NC) return cholqr_nc<NC>(phi, live, nw, M, N, na, nb, ws, s);
+    if (nmax <= NC) return cholqr_nc<NC>(phi, live, nw, M, N, na, nb, ws, mon, s);
     AFQ_QR(8)
     AFQ_QR(16)
     AFQ_QR(24)
@@ -1260,9 +1310,11 @@ hipError_t mgs(double* phi, const uint8_t* live, int nw, int M, int N, int na, i
             if (e != hipSuccess) return e;
             attr = true;
         }
-        hipLaunchKernelGGL(k_mgs<true>, dim3(nw, 2), dim3(256), shm, s, phi, live, M, N, na, nb);
+        hipLaunchKernelGGL(k_mgs<true>, dim3(nw, 2), dim3(256), shm, s, phi, live, M, N, na, nb,
+                           mon);
     } else {
-        hipLaunchKernelGGL(k_mgs<false>, dim3(nw, 2), dim3(256), 0, s, phi, live, M, N, na, nb);
+        hipLaunchKernelGGL(k_mgs<false>, dim3(nw, 2), dim3(256), 0, s, phi, live, M, N, na, nb,
+                           mon);
     }
     return hipGetLastError();
 }

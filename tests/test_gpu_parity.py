@@ -330,6 +330,70 @@ def test_exchange_blocks_local_energy_matches_oracle(lib, M, na, nb):
     assert rel(el, ref) < 2e-5
 
 
+def _gs_expected(phi, na, nb):
+    """Per (walker, spin block): ell = max_k 1/2 ln(S_kk / D_k) and
+    ln |det R| = 1/2 sum_k ln D_k from S = Phi^H Phi = C C^H (D_k = |C_kk|^2)."""
+    ell, lnd = [], []
+    for w in range(phi.shape[0]):
+        for sl in (slice(0, na), slice(na, na + nb)):
+            P = phi[w][:, sl]
+            S = P.conj().T @ P
+            D = np.abs(np.diag(np.linalg.cholesky(S))) ** 2
+            ell.append(np.max(0.5 * np.log(np.real(np.diag(S)) / D)))
+            lnd.append(0.5 * np.sum(np.log(D)))
+    return np.array(ell), np.array(lnd)
+
+
+# The Gram-Schmidt monitor against the loss of orthogonality computed from
+# the walkers' own orbitals: steps without orthonormalisation, then one
+# afqmc_orthonormalize; the Gram-matrix factorisation (spin blocks up to 48)
+# and the column-by-column one (52/50 orbitals).
+@pytest.mark.parametrize("M,na,nb", [(12, 4, 3), (64, 52, 50)])
+def test_gs_monitor_matches_the_orbitals(lib, M, na, nb):
+    banner(f"Gram-Schmidt monitor M={M} {na}/{nb}")
+    wl = Workload(M, 2 * M, na, nb, na, nb, 24, 0.02, ham_seed=3)
+    H, (ga, gb) = wl.gpu_systems(lib, ortho_every=0, measure_every=10)
+    ga.gs_monitor()  # clears what the set-up recorded
+    lib.pair_step(ga, gb, 30, seed=2)
+    w = ga.walkers()
+    assert w["alive"].all()
+    ell, lnd = _gs_expected(w["phi"], na, nb)
+    ga.orthonormalize()
+    me, ml, trips = ga.gs_monitor(threshold=float(np.max(ell)) * 0.999)
+    banner(f"  ell {me:.6e} (orbitals {np.max(ell):.6e}), |ln det R| {ml:.6e} "
+           f"(orbitals {np.max(np.abs(lnd)):.6e}), trips {trips}")
+    assert abs(me - np.max(ell)) < 1e-9 * max(1.0, np.max(ell))
+    assert abs(ml - np.max(np.abs(lnd))) < 1e-9 * max(1.0, np.max(np.abs(lnd)))
+    assert trips == int(np.sum(ell > np.max(ell) * 0.999)) and trips >= 1
+    assert ga.gs_monitor() == (0.0, 0.0, 0)  # the record was cleared
+
+
+def test_gs_monitor_trips_without_orthonormalisation(lib):
+    """Free projection keeps every walker; 120 steps at dt = 0.05 without
+    Gram-Schmidt leave the orbitals of most spin blocks more than 9 nepers
+    from orthogonal (the factorisation loses about 8 digits), while every
+    orthonormalisation of a run with Gram-Schmidt every 5 steps finds them
+    close."""
+    banner("Gram-Schmidt monitor trips")
+    wl = Workload(12, 24, 4, 4, 4, 3, 16, 0.05, ham_seed=7)
+    H = lib.Hamiltonian(wl.ham.h, wl.ham.chol, wl.ham.e_core)
+    res = {}
+    for oe in (0, 5):
+        ga, gb = (lib.System(H, na, nb, t, wl.nw, wl.dt, ortho_every=oe, measure_every=10,
+                             mode="free") for t, (na, nb) in zip(wl.trials, wl.spins))
+        ga.gs_monitor()
+        lib.pair_step(ga, gb, 120, seed=5)
+        assert ga.walkers()["alive"].all()
+        if not oe:
+            ga.orthonormalize()
+        # without Gram-Schmidt: the one orthonormalisation at the end; with
+        # it: the 24 periodic ones of the run
+        res[oe] = ga.gs_monitor(threshold=9.0)
+        banner(f"  ortho_every {oe}: ell {res[oe][0]:.3f}, trips {res[oe][2]}")
+    assert res[0][2] >= wl.nw // 2 and res[0][0] > 9.0
+    assert res[5][2] == 0 and res[5][0] < 2.0
+
+
 def test_identical_pair_exact_zero(lib):
     banner("identical pair")
     wl = Workload(20, 40, 4, 4, 4, 4, 32, 0.01, ham_seed=2)
