@@ -260,6 +260,20 @@ def bench_pair(args):
     gb.profile(False)
     alive = (ga.walkers()["alive"].mean(), gb.walkers()["alive"].mean())
     trace = np.concatenate([x for x in (tr_w, tr_t, tr_p) if len(x)])
+    if args.metrics_jsonl:
+        from paper_1703_01545_amd import metrics
+
+        alive_n = (int(ga.walkers()["alive"].sum()), int(gb.walkers()["alive"].sum()))
+        recs = []
+        t = 0
+        for name, tr, n in (("warmup", tr_w, warmup), ("timed", tr_t, steps),
+                            ("profiled", tr_p, profile_steps)):
+            recs += list(metrics.trace_records(tr, t, me, **{"pass": name}))
+            t += n
+        recs.append({"step": t, "alive_A": alive_n[0], "alive_B": alive_n[1],
+                     "n_walkers": cfg.n_walkers,
+                     "walker_steps_per_s": 2 * cfg.n_walkers * steps / elapsed})
+        metrics.write_jsonl(args.metrics_jsonl, recs)
     tuned = [list(lib.autotune(x)) for x in (ga, gb)]  # cached: the shapes the graph used
     phases, roofline = _roofline(prof_a, prof_b, profile_steps, cfg, prec)
     _traffic(roofline, cfg, prec, tuned)
@@ -560,6 +574,9 @@ def make_parser() -> argparse.ArgumentParser:
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="copy a buffer of this size once (device to device) before the timed "
                          "steps: the reference kernel for scaling HBM traffic counters")
+    ap.add_argument("--metrics-jsonl", default=None,
+                    help="pair workload: write every measurement (step, E_A, E_B, dE, pass) and the "
+                         "end-of-run alive counts to this file as JSON lines")
     ap.add_argument("--no-fp64-check", action="store_true",
                     help="skip the FP64 rerun that measures the energy-difference error")
     return ap
