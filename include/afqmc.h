@@ -299,6 +299,23 @@ afqmc_status afqmc_adjoint_backward(afqmc_sys sys, double* dE_dlambda);
  * Synchronises. */
 afqmc_status afqmc_autotune(afqmc_sys sys, int* choice);
 
+/* The autotuner's table on disk, so that a new process need not time the
+ * candidates again.  afqmc_tune_cache_save writes every problem shape tuned
+ * in this process with its choice, tagged with the current device's
+ * architecture and compute-unit count and a format version.
+ * afqmc_tune_cache_load reads such a file, checks the version and that it
+ * was written on a device like the current one, checks every entry (a
+ * choice the tuner could have made for its shape), and only then adds the
+ * entries; shapes already tuned in this process keep their choice.  Any
+ * failed check leaves the table as it was.  Errors: E_INVALID (NULL or
+ * unreadable / unwritable path, another version, another device, a
+ * malformed entry), E_DEVICE (no current device).  afqmc_tune_cache_clear
+ * empties the table (systems keep the shapes already chosen for them; the
+ * next afqmc_autotune of a shape times its candidates again). */
+afqmc_status afqmc_tune_cache_save(const char* path);
+afqmc_status afqmc_tune_cache_load(const char* path);
+afqmc_status afqmc_tune_cache_clear(void);
+
 /* Read back walker state: phi (n_walkers x 2 x N x M: plane 0 = real,
  * plane 1 = imaginary part of orbital column i, N = n_alpha + n_beta),
  * w (n_walkers; free mode n_walkers x 2), log_ovlp (n_walkers x 2:

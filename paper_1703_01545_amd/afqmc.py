@@ -35,7 +35,8 @@ EXPORTS = [
     "afqmc_profile_read", "afqmc_phase_name", "afqmc_selftest_propagate", "afqmc_autotune",
     "afqmc_adjoint_forward", "afqmc_adjoint_backward", "afqmc_pair_step_noalloc",
     "afqmc_population_control", "afqmc_init_from_primary", "afqmc_cap_events",
-    "afqmc_init_walkers_msd", "afqmc_gs_monitor",
+    "afqmc_init_walkers_msd", "afqmc_gs_monitor", "afqmc_tune_cache_save",
+    "afqmc_tune_cache_load", "afqmc_tune_cache_clear",
 ]
 
 
@@ -75,6 +76,9 @@ _lib.afqmc_free_sys.restype = None
 _lib.afqmc_free_ham.argtypes = [_vp]
 _lib.afqmc_free_ham.restype = None
 _lib.afqmc_selftest_gemm.argtypes = [C.c_int, C.c_int, C.c_int, C.c_int, _dp, _dp, _dp]
+_lib.afqmc_tune_cache_save.argtypes = [C.c_char_p]
+_lib.afqmc_tune_cache_load.argtypes = [C.c_char_p]
+_lib.afqmc_tune_cache_clear.argtypes = []
 _lib.afqmc_gs_monitor.argtypes = [_vp, C.c_double, _dp, _dp, C.POINTER(C.c_int64)]
 _lib.afqmc_selftest_gemm_shape.argtypes = [C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int,
                                              _dp, _dp, _dp]
@@ -302,6 +306,22 @@ class System:
             self.free()
         except Exception:
             pass
+
+
+def tune_cache_save(path: str):
+    """Write the launch shapes tuned in this process (tagged with the device)."""
+    _check(_lib.afqmc_tune_cache_save(os.fsencode(path)))
+
+
+def tune_cache_load(path: str):
+    """Add the launch shapes of a cache written on a device like this one;
+    shapes tuned in this process keep their choice."""
+    _check(_lib.afqmc_tune_cache_load(os.fsencode(path)))
+
+
+def tune_cache_clear():
+    """Empty the table of tuned launch shapes (systems keep their choices)."""
+    _check(_lib.afqmc_tune_cache_clear())
 
 
 def pair_step(a: System, b: System, n_steps: int, seed: int = 0, fields=None) -> np.ndarray:

@@ -12,9 +12,13 @@
 // graph advances.
 #include <algorithm>
 #include <array>
+#include <cstdio>
+#include <fstream>
 #include <map>
 #include <memory>
 #include <mutex>
+#include <sstream>
+#include <string>
 
 #include "host.h"
 
@@ -240,6 +244,28 @@ afqmc_status capture(BatchPlan* plan, const std::vector<std::vector<Pair>>& lane
 
 long gcd_l(long x, long y) { return y ? gcd_l(y, x % y) : x; }
 
+constexpr const char* kTuneCacheTag = "afqmc-tune-cache 1";
+
+// The device the tuned shapes belong to: architecture and compute units.
+hipError_t device_tag(std::string* tag) {
+    int dev = 0;
+    hipDeviceProp_t p;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipGetDeviceProperties(&p, dev);
+    if (e != hipSuccess) return e;
+    *tag = std::string(p.gcnArchName) + " cu=" + std::to_string(p.multiProcessorCount);
+    return hipSuccess;
+}
+
+// A cached choice a tuner could have made for its key.
+bool valid_choice(const ShapeKey& k, int v) {
+    if (k[0] == 0 || k[0] == 1) return v >= 1 && v <= 3;
+    if (k[0] == 3)
+        return k[1] > 0 && k[1] <= 256 && propagate_variant_ok(v, (int)k[1], (DType)k[5],
+                                                                (DType)k[6]);
+    return false;
+}
+
 }  // namespace
 
 afqmc_status autotune(afqmc_sys s, hipStream_t st) {
@@ -288,6 +314,62 @@ afqmc_status afqmc_autotune(afqmc_sys s, int* choice) {
         choice[1] = s->tile_fs;
         choice[2] = s->prop_var;
     }
+    return AFQMC_OK;
+}
+
+afqmc_status afqmc_tune_cache_save(const char* path) {
+    if (!path) return fail(AFQMC_E_INVALID, "path is null");
+    std::string tag;
+    if (device_tag(&tag) != hipSuccess) return fail(AFQMC_E_DEVICE, "no device to tag the cache");
+    std::map<ShapeKey, int> copy;
+    {
+        std::lock_guard<std::mutex> lk(g_cache_mu);
+        copy = g_tuned;
+    }
+    FILE* f = std::fopen(path, "w");
+    if (!f) return fail(AFQMC_E_INVALID, std::string("cannot write ") + path);
+    bool ok = std::fprintf(f, "%s\n%s\n", kTuneCacheTag, tag.c_str()) > 0;
+    for (const auto& kv : copy) {
+        for (long x : kv.first) ok = ok && std::fprintf(f, "%ld ", x) > 0;
+        ok = ok && std::fprintf(f, "%d\n", kv.second) > 0;
+    }
+    ok = (std::fclose(f) == 0) && ok;
+    if (!ok) return fail(AFQMC_E_INVALID, std::string("write failed: ") + path);
+    return AFQMC_OK;
+}
+
+afqmc_status afqmc_tune_cache_clear(void) {
+    std::lock_guard<std::mutex> lk(g_cache_mu);
+    g_tuned.clear();
+    return AFQMC_OK;
+}
+
+afqmc_status afqmc_tune_cache_load(const char* path) {
+    if (!path) return fail(AFQMC_E_INVALID, "path is null");
+    std::ifstream in(path);
+    if (!in) return fail(AFQMC_E_INVALID, std::string("cannot read ") + path);
+    std::string head, dev;
+    if (!std::getline(in, head) || head != kTuneCacheTag || !std::getline(in, dev))
+        return fail(AFQMC_E_INVALID, "not a tune cache of this library version");
+    std::string tag;
+    if (device_tag(&tag) != hipSuccess) return fail(AFQMC_E_DEVICE, "no device to check the cache");
+    if (dev != tag) return fail(AFQMC_E_INVALID, "tune cache written on another device: " + dev);
+    std::vector<std::pair<ShapeKey, int>> rows;
+    std::string line;
+    while (std::getline(in, line)) {
+        if (line.empty()) continue;
+        std::istringstream ls(line);
+        ShapeKey k;
+        int v;
+        for (long& x : k)
+            if (!(ls >> x)) return fail(AFQMC_E_INVALID, "malformed tune cache line: " + line);
+        std::string rest;
+        if (!(ls >> v) || (ls >> rest) || !valid_choice(k, v))
+            return fail(AFQMC_E_INVALID, "malformed tune cache line: " + line);
+        rows.emplace_back(k, v);
+    }
+    std::lock_guard<std::mutex> lk(g_cache_mu);
+    for (const auto& kv : rows) g_tuned.emplace(kv.first, kv.second);  // tuned here wins
     return AFQMC_OK;
 }
 

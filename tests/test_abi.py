@@ -44,3 +44,15 @@ def test_product_path_does_not_touch_the_oracle():
             if f.endswith((".py", ".hip", ".h", ".cpp")):
                 text = open(os.path.join(dirpath, f)).read()
                 assert "oracle" not in re.sub(r"(#|//).*", "", text), f
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libafqmc.so not built")
+def test_tune_cache_load_rejects_files_that_are_not_caches(tmp_path):
+    """The format is checked before anything asks for a device."""
+    from paper_1703_01545_amd import afqmc
+    bad = tmp_path / "notes.txt"
+    bad.write_text("not a tune cache\n")
+    for path in (str(tmp_path / "missing"), str(bad)):
+        with pytest.raises(afqmc.AfqmcError) as e:
+            afqmc.tune_cache_load(path)
+        assert e.value.status == afqmc.E_INVALID

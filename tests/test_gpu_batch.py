@@ -139,6 +139,49 @@ def test_unrelated_hamiltonians_from_two_host_threads(lib):
             assert np.array_equal(u, v)
 
 
+def test_tune_cache_carries_choices(lib, tmp_path):
+    """Tune one system and save the table; clear it, change the file's GEMM
+    tiles to other valid tiles and load it: a new system of the same shape
+    gets exactly those tiles (taken from the file, not timed).  A file tagged
+    with another device or holding a choice no tuner could make is refused and
+    leaves the table as it was."""
+    banner("tune cache save / clear / load")
+    wl = Workload(40, 80, 8, 8, 8, 7, 64, 0.01, ham_seed=4)
+    path = str(tmp_path / "tune.txt")
+    H, (a, _) = wl.gpu_systems(lib, precision="bf16x3")
+    c1 = [int(x) for x in lib.autotune(a)]
+    lib.tune_cache_save(path)
+    lines = open(path).read().splitlines()
+    head, rows = lines[:2], [l.split() for l in lines[2:] if l.strip()]
+    planted = {}
+    for r in rows:
+        if r[0] in ("0", "1") and int(r[1]) == 2 * wl.nw:  # this system's GEMMs
+            r[-1] = "2" if r[-1] != "2" else "1"
+            planted[int(r[0])] = int(r[-1])
+    assert set(planted) == {0, 1}, lines
+
+    def write(first, second, body):
+        open(path, "w").write("\n".join([first, second] + [" ".join(r) for r in body]) + "\n")
+
+    lib.tune_cache_clear()
+    write(head[0], "another device", rows)
+    with pytest.raises(lib.AfqmcError) as e:
+        lib.tune_cache_load(path)
+    assert e.value.status == lib.E_INVALID
+    bad = [list(r) for r in rows]
+    bad[0][-1] = "99"
+    write(head[0], head[1], bad)
+    with pytest.raises(lib.AfqmcError) as e:
+        lib.tune_cache_load(path)
+    assert e.value.status == lib.E_INVALID
+    write(head[0], head[1], rows)
+    lib.tune_cache_load(path)
+    H2, (a2, _) = wl.gpu_systems(lib, precision="bf16x3")
+    c2 = [int(x) for x in lib.autotune(a2)]
+    assert c2 == [planted[0], planted[1], c1[2]], (c1, c2)
+    lib.tune_cache_clear()
+
+
 def test_batch_errors(lib):
     banner("batch errors")
     sys_ = _make(lib, "fp64")
