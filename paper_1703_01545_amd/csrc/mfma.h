@@ -51,6 +51,11 @@ __device__ __forceinline__ f4 mma1(float a, float b, f4 c) {
 __device__ __forceinline__ f4 mma8(bf8 a, bf8 b, f4 c) {
     return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
 }
+typedef short s4v __attribute__((ext_vector_type(4)));
+// 16 x 16 x 16 BF16 product: lane l supplies k = 4 (l / 16) .. + 3
+__device__ __forceinline__ f4 mma4(s4v a, s4v b, f4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
+}
 
 // Double held by lane l (wave-uniform result).
 __device__ __forceinline__ double rdlane(double v, int l) {
@@ -254,6 +259,39 @@ struct Core {
     static __device__ __forceinline__ int arow(int j) { return threadIdx.x / TPRA + j * RPA; }
     static __device__ __forceinline__ int brow(int j) { return threadIdx.x / TPRB + j * RPB; }
 
+    // Split BF16, a last K tile whose valid k end at or below 16 (the rest
+    // is zero): the products over its first 16 k only, 16 x 16 x 16 MFMAs.
+    // Every path of run() takes such a tile this way, so all tile shapes
+    // still sum alike.
+    static __device__ __forceinline__ void compute_half(const LT* As, const LT* Bs,
+                                                        accv (&acc)[TM][TN]) {
+        const int lane = threadIdx.x & 63;
+        const int wave = threadIdx.x >> 6;
+        const int wm = wave / WGN, wn = wave % WGN;
+        const int k4 = 4 * (lane >> 4);
+        s4v ah[TM], al[TM], bh[TN], bl[TN];
+#pragma unroll
+        for (int a = 0; a < TM; ++a) {
+            const int i = lds_index<LT, PK>(wm * TM * 16 + a * 16 + (lane & 15), k4);
+            ah[a] = *reinterpret_cast<const s4v*>(&As[i]);
+            al[a] = *reinterpret_cast<const s4v*>(&As[BM * PK + i]);
+        }
+#pragma unroll
+        for (int b = 0; b < TN; ++b) {
+            const int i = lds_index<LT, PK>(wn * TN * 16 + b * 16 + (lane & 15), k4);
+            bh[b] = *reinterpret_cast<const s4v*>(&Bs[i]);
+            bl[b] = *reinterpret_cast<const s4v*>(&Bs[BN * PK + i]);
+        }
+#pragma unroll
+        for (int a = 0; a < TM; ++a)
+#pragma unroll
+            for (int b = 0; b < TN; ++b) {
+                acc[a][b] = mma4(al[a], bh[b], acc[a][b]);
+                acc[a][b] = mma4(ah[a], bl[b], acc[a][b]);
+                acc[a][b] = mma4(ah[a], bh[b], acc[a][b]);
+            }
+    }
+
     // acc += the products of one staged K tile (As, Bs: one buffer)
     static __device__ __forceinline__ void compute(const LT* As, const LT* Bs,
                                                    accv (&acc)[TM][TN]) {
@@ -384,7 +422,8 @@ struct Core {
 
         gload(0, ra, rb);
         sstore(As, Bs, ra, rb);
-        if (DB && PL == 2 && ROWS_VALID && K > 0 && K % BK == 0) {
+        // (operands staged as four-element runs, as FP32 storage gives them)
+        if (DB && PL == 2 && VA % 4 == 0 && VB % 4 == 0 && ROWS_VALID && K > 0 && K % BK == 0) {
             // Split BF16 over whole K tiles: a second staging set, so that each
             // tile is fetched two tiles ahead of its split into LDS (the fetch
             // latency hides behind two tiles of products instead of one).  Tile
@@ -427,7 +466,11 @@ struct Core {
             if (BK < K) gload(BK, ra, rb);
             __syncthreads();
             int cur = 0;
-            for (int k0 = 0; k0 < K; k0 += BK) {
+            // split BF16 with a last tile of at most 16 valid k: that tile
+            // after the loop, with half the products
+            const bool half = PL == 2 && BK == 32 && K > 0 && (K - 1) % BK < 16;
+            const int kend = half ? (K - 1) / BK * BK : K;
+            for (int k0 = 0; k0 < kend; k0 += BK) {
                 compute(As + cur * LDS_A, Bs + cur * LDS_B, acc);
                 if (k0 + BK < K) {
                     sstore(As + (cur ^ 1) * LDS_A, Bs + (cur ^ 1) * LDS_B, ra, rb);
@@ -436,15 +479,29 @@ struct Core {
                 __syncthreads();
                 cur ^= 1;
             }
+            if constexpr (PL == 2 && BK == 32) {
+                if (half) {
+                    compute_half(As + cur * LDS_A, Bs + cur * LDS_B, acc);
+                    __syncthreads();  // callers may reuse the buffers after run()
+                }
+            }
         } else {
             __syncthreads();
-            for (int k0 = 0; k0 < K; k0 += BK) {
+            const bool half = PL == 2 && BK == 32 && K > 0 && (K - 1) % BK < 16;
+            const int kend = half ? (K - 1) / BK * BK : K;
+            for (int k0 = 0; k0 < kend; k0 += BK) {
                 const bool more = k0 + BK < K;
                 if (more) gload(k0 + BK, ra, rb);
                 compute(As, Bs, acc);
                 __syncthreads();
                 if (more) {
                     sstore(As, Bs, ra, rb);
+                    __syncthreads();
+                }
+            }
+            if constexpr (PL == 2 && BK == 32) {
+                if (half) {
+                    compute_half(As, Bs, acc);
                     __syncthreads();
                 }
             }
