@@ -655,19 +655,26 @@ __device__ __forceinline__ void pass_split_rb(__amdgpu_buffer_rsrc_t rb, int M, 
             const bf8 ih = *reinterpret_cast<const bf8*>(s0 + 2 * spl);
             const bf8 il = *reinterpret_cast<const bf8*>(s0 + 3 * spl);
             if constexpr (CX) {
+                // the imaginary products first: their fragments are then
+                // dead, and the negated copies take their registers
+#pragma unroll
+                for (int s = 0; s < MAXB; ++s) {
+                    if (cb[s] >= MB) continue;  // wave-uniform
+                    f4 ai = acc[r][s][1];
+                    ai = mma8(il, bc[s][0], ai);
+                    ai = mma8(ih, bc[s][1], ai);
+                    ai = mma8(ih, bc[s][0], ai);
+                    acc[r][s][1] = ai;
+                }
                 const bf8 nh = neg8(ih), nl = neg8(il);
 #pragma unroll
                 for (int s = 0; s < MAXB; ++s) {
                     if (cb[s] >= MB) continue;  // wave-uniform
-                    f4 ar = acc[r][s][0], ai = acc[r][s][1];
+                    f4 ar = acc[r][s][0];
                     ar = mma8(nl, bc[s][2], ar);
                     ar = mma8(nh, bc[s][3], ar);
                     ar = mma8(nh, bc[s][2], ar);
-                    ai = mma8(il, bc[s][0], ai);
-                    ai = mma8(ih, bc[s][1], ai);
-                    ai = mma8(ih, bc[s][0], ai);
                     acc[r][s][0] = ar;
-                    acc[r][s][1] = ai;
                 }
             } else {
 #pragma unroll
