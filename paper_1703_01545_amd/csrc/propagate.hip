@@ -603,7 +603,8 @@ __global__ __launch_bounds__(64 * NWAVE, 2) void k_propagate_split(
 // accumulator.
 template <int MAXB, int RB, bool CX>
 __device__ __forceinline__ void pass_split_rb(__amdgpu_buffer_rsrc_t rb, int M, int Mp, int MB,
-                                              int nrbv, const bf16_t* Sb, int SPB, const int* cb,
+                                              int rlo, int rhi, const bf16_t* Sb, int SPB,
+                                              const int* cb,
                                               f4 (&acc)[RB][MAXB][2]) {
     constexpr int NP = CX ? 4 : 2;
     const int lane = threadIdx.x & 63;
@@ -630,7 +631,7 @@ __device__ __forceinline__ void pass_split_rb(__amdgpu_buffer_rsrc_t rb, int M, 
                 bc[s][p] = bload8(rb, boff[s] + k0 * 32 + (p & 1) * hl_b + (p >> 1) * pl_b);
 #pragma unroll
         for (int r = 0; r < RB; ++r) {
-            if (r >= nrbv) continue;  // wave-uniform
+            if (r < rlo || r >= rhi) continue;  // wave-uniform
             const bf16_t* s0 = Sb + (r * 16 + li) * SPB + 8 * g + k0;
             // real-part fragments first, then the imaginary ones (fewer live
             // registers; each accumulator sees the same product order)
@@ -694,6 +695,49 @@ __device__ __forceinline__ void pass_split_rb(__amdgpu_buffer_rsrc_t rb, int M, 
     }
 }
 
+// One column block per wave and fewer column blocks than waves: the idle
+// waves take over the upper row blocks of some columns, so that the four
+// SIMDs carry nearly equal numbers of (row block, column block) products
+// (wave w runs on SIMD w mod 4; roles vw are the waves rotated, and with a
+// wave count that is a multiple of 4 the roles vw mod 4 = k share one SIMD).
+// Greedy and wave-uniform: each idle role in turn splits an unsplit column of
+// the most loaded SIMD when that lowers the largest load; the column keeps its
+// lower rs row blocks, the idle role takes the rest.  Every (row block, column
+// block) keeps exactly one owner and the same order of products.
+__device__ __forceinline__ void balance_roles(int nwave, int MB, int nrbv, int vw, int& col,
+                                              int& rlo, int& rhi) {
+    const int moved = nrbv / 2, rs = nrbv - moved;
+    if (moved == 0 || MB >= nwave) return;
+    int load[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) load[k] = nrbv * ((MB - k + 3) / 4);
+    unsigned split = 0;
+    for (int u = MB; u < nwave; ++u) {
+        int h = 0, hl = load[0], lu = load[0];
+#pragma unroll
+        for (int k = 1; k < 4; ++k) {
+            if (load[k] > hl) h = k, hl = load[k];
+            if (k == (u & 3)) lu = load[k];
+        }
+        if (lu + moved >= hl) continue;  // no gain: the role stays idle
+        int c = -1;
+        for (int x = h; x < MB; x += 4)
+            if (!((split >> x) & 1u)) {
+                c = x;
+                break;
+            }
+        if (c < 0) continue;
+        split |= 1u << c;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            if (k == h) load[k] -= moved;
+            if (k == (u & 3)) load[k] += moved;
+        }
+        if (u == vw) col = c, rlo = rs;
+    }
+    if (vw < MB && ((split >> vw) & 1u)) rhi = rs;
+}
+
 // ZREG: the running Taylor sum in registers (else in LDS beside the state).
 template <int NWAVE, int MAXB, int RB, bool ZREG>
 __global__ __launch_bounds__(64 * NWAVE, 1) void k_propagate_split_rb(
@@ -737,6 +781,9 @@ __global__ __launch_bounds__(64 * NWAVE, 1) void k_propagate_split_rb(
     int cb[MAXB];
 #pragma unroll
     for (int s = 0; s < MAXB; ++s) cb[s] = vw + s * NWAVE;
+    // this wave's row blocks [rlo, rhi) of its column blocks
+    int rlo = 0, rhi = nrbv;
+    if constexpr (MAXB == 1 && NWAVE % 4 == 0) balance_roles(NWAVE, MB, nrbv, vw, cb[0], rlo, rhi);
     f4 acc[RB][MAXB][2];
     f4 zr[ZREG ? RB : 1][MAXB][2];
     const long Aplane = split_tile_elems(M);  // fragment-tiled operand planes
@@ -807,30 +854,30 @@ __global__ __launch_bounds__(64 * NWAVE, 1) void k_propagate_split_rb(
                 acc[r][s][0][q] = ok ? (float)xr : 0.0f;
                 acc[r][s][1][q] = ok ? (float)xi : 0.0f;
             }
-            if (r < nrbv && cb[s] < MB) put_b(r, s, acc[r][s][0], acc[r][s][1]);
+            if (r >= rlo && r < rhi && cb[s] < MB) put_b(r, s, acc[r][s][0], acc[r][s][1]);
         }
     __syncthreads();
     // first one-body half: y = x + Q x
-    pass_split_rb<MAXB, RB, false>(rQ, M, Mp, MB, nrbv, Sb, SPB, cb, acc);
+    pass_split_rb<MAXB, RB, false>(rQ, M, Mp, MB, rlo, rhi, Sb, SPB, cb, acc);
     __syncthreads();
 #pragma unroll
     for (int r = 0; r < RB; ++r)
 #pragma unroll
         for (int s = 0; s < MAXB; ++s)
-            if (r < nrbv && cb[s] < MB) {
+            if (r >= rlo && r < rhi && cb[s] < MB) {
                 put_b(r, s, acc[r][s][0], acc[r][s][1]);
                 zacc(r, s, acc[r][s][0], acc[r][s][1], true);
             }
     __syncthreads();
     for (int n = 1; n <= K; ++n) {
-        pass_split_rb<MAXB, RB, true>(rA, M, Mp, MB, nrbv, Sb, SPB, cb, acc);
+        pass_split_rb<MAXB, RB, true>(rA, M, Mp, MB, rlo, rhi, Sb, SPB, cb, acc);
         __syncthreads();
         const float inv = inv_n_f(n);
 #pragma unroll
         for (int r = 0; r < RB; ++r)
 #pragma unroll
             for (int s = 0; s < MAXB; ++s) {
-                if (r >= nrbv || cb[s] >= MB) continue;
+                if (r < rlo || r >= rhi || cb[s] >= MB) continue;
 #pragma unroll
                 for (int q = 0; q < 4; ++q) {
                     acc[r][s][0][q] = acc[r][s][0][q] * inv;
@@ -849,13 +896,13 @@ __global__ __launch_bounds__(64 * NWAVE, 1) void k_propagate_split_rb(
     }
     // second one-body half on the Taylor sum: acc and the BF16 view hold z
     // (with K = 0 both still hold y)
-    pass_split_rb<MAXB, RB, false>(rQ, M, Mp, MB, nrbv, Sb, SPB, cb, acc);
+    pass_split_rb<MAXB, RB, false>(rQ, M, Mp, MB, rlo, rhi, Sb, SPB, cb, acc);
 #pragma unroll
     for (int r = 0; r < RB; ++r)
 #pragma unroll
         for (int s = 0; s < MAXB; ++s) {
             const int col = cb[s] * 16 + li;
-            if (r >= nrbv || cb[s] >= MB || col >= M) continue;
+            if (r < rlo || r >= rhi || cb[s] >= MB || col >= M) continue;
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
                 const int row = r * 16 + acc_row<float>(lane, q);
