@@ -1,10 +1,10 @@
-"""The benchmark's command line, without a GPU: the argument lists the
-round-end run uses must parse, and the step counts actually run must keep
+"""The benchmark's command line, without a GPU: the default argument list
+(one GPU, 20 timed steps, 5 warm-up steps) must parse, and the step counts actually run must keep
 the timed window exact and its start on a Gram-Schmidt/measurement period."""
 import bench
 
 
-def test_driver_argument_list_parses():
+def test_default_argument_list_parses():
     args = bench.make_parser().parse_args(["--gpus", "1", "--steps", "20", "--warmup", "5"])
     assert (args.gpus, args.steps, args.warmup) == (1, 20, 5)
     steps, warmup, prof = bench.plan_counts(args.steps, args.warmup, args.profile_steps, 20)

@@ -1,5 +1,5 @@
 """Repeats of correlated and uncorrelated pairs on the GPU (Sec. II.B): the
-batched repeat driver reproduces each repeat's standalone pair run bit for
+batched repeat runner reproduces each repeat's standalone pair run bit for
 bit, the uncorrelated variant leaves the primary system's energies unchanged,
 and correlating the fields shrinks the standard error of the energy
 difference over repeats."""
@@ -32,7 +32,7 @@ def _setup(lib):
 
 def test_correlated_repeats_equal_standalone_pairs(lib):
     from paper_1703_01545_amd import repeats
-    banner("repeat driver vs standalone pairs")
+    banner("repeat runner vs standalone pairs")
     c, H, sa, sb = _setup(lib)
     kw = dict(ortho_every=5, measure_every=5)
     tr = repeats.correlated_repeats(H, sa, sb, 16, 3, 40, c.dt, seed0=7, **kw)
