@@ -151,9 +151,11 @@ def _traffic(roof, cfg, prec, shapes):
     for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "traffic_*.json"))):
         with open(path) as f:
             t = json.load(f)
-        src = os.path.join(ROOT, t["source"])
-        with open(src, "rb") as f:
-            sha = hashlib.sha256(f.read()).hexdigest()
+        h = hashlib.sha256()
+        for rel in t.get("sources", [t.get("source")]):
+            with open(os.path.join(ROOT, rel), "rb") as f:
+                h.update(f.read())
+        sha = h.hexdigest()
         if (roof["kernel"] == "propagate" and sha == t["source_sha256"] and prec == t["precision"]
                 and cfg.M == t["M"] and cfg.n_walkers == t["n_walkers"]
                 and all(s[2] == t["prop_shape"] for s in shapes)):
