@@ -288,14 +288,16 @@ afqmc_status afqmc_adjoint_forward(afqmc_sys sys, const double* V, uint64_t seed
 afqmc_status afqmc_adjoint_backward(afqmc_sys sys, double* dE_dlambda);
 
 /* Launch-shape autotuner.  Times every candidate launch shape of the
- * force-bias and field-sum GEMMs (64 x 64, 128 x 128 or 256 x 128 tiles) and of the
+ * force-bias and field-sum GEMMs (64 x 64, 128 x 128 or 256 x 128 tiles, the last
+ * over 8 or, for split BF16, 16 wavefronts) and of the
  * fused propagation (waves per workgroup x column blocks per wave, B
  * prefetch or not, orbitals per workgroup) on this system's own buffers and keeps the fastest per
  * problem shape in a process-wide table, so tuning another system of the
  * same shape costs nothing.  All candidates sum in the same order, so tuning
  * never changes a result bit.  The walker state is left unchanged.  choice
  * (optional, host, 3 ints): the chosen force-bias tile and field-sum tile
- * (1: 64 x 64, 2: 128 x 128, 3: 256 x 128) and the propagation shape index.
+ * (1: 64 x 64, 2: 128 x 128, 3: 256 x 128, 4: 256 x 128 over 16 wavefronts)
+ * and the propagation shape index.
  * Synchronises. */
 afqmc_status afqmc_autotune(afqmc_sys sys, int* choice);
 
@@ -366,7 +368,8 @@ afqmc_status afqmc_selftest_gemm(afqmc_prec prec, int m, int n, int k, const dou
  * the operands held in the storage the walker step gives its contractions
  * (FP64 for AFQMC_FP64; FP32 for AFQMC_FP32 and for AFQMC_BF16, which here
  * selects the split-BF16 products) and an FP64 result.  tile: 0 size
- * heuristic, 1 64 x 64, 2 128 x 128, 3 256 x 128 workgroup tiles; ksplit
+ * heuristic, 1 64 x 64, 2 128 x 128, 3 256 x 128 workgroup tiles, 4 256 x 128
+ * over 16 wavefronts (split BF16; the others as 3); ksplit
  * >= 1: K cut into that many ranges whose partial sums are added in range
  * order.  Every tile shape gives the same bits for the same ksplit.  For the
  * tests of the GEMM paths the walker step takes.  Errors: E_INVALID.

@@ -386,7 +386,7 @@ def selftest_gemm(A, B, precision: str = "fp64") -> np.ndarray:
 
 def selftest_gemm_shape(A, B, precision: str, tile: int, ksplit: int = 1) -> np.ndarray:
     """C = A B^T with the workgroup tile (0 heuristic, 1 64x64, 2 128x128,
-    3 256x128) and the number of K ranges fixed; FP32 operand storage for
+    3 256x128, 4 256x128 over 16 wavefronts) and the number of K ranges fixed; FP32 operand storage for
     fp32 and bf16 (split-BF16 products)."""
     A, B = _f64(A), _f64(B)
     m, k = A.shape

@@ -97,7 +97,9 @@ hipError_t pick(const ShapeKey& key, const std::vector<int>& cands, F run, hipSt
 
 hipError_t tune_gemm(int role, Gemm g, DType compute, hipStream_t st, int* out) {
     const ShapeKey key{role, g.m, g.n, g.k, g.ta, g.tb, g.tc, compute};
-    return pick(key, {1, 2, 3},
+    std::vector<int> cands{1, 2, 3};
+    if (compute == DT_SPLIT) cands.push_back(4);
+    return pick(key, cands,
                 [&](int c) {
                     g.tile = c;
                     return gemm(g, compute, st);
@@ -259,7 +261,7 @@ hipError_t device_tag(std::string* tag) {
 
 // A cached choice a tuner could have made for its key.
 bool valid_choice(const ShapeKey& k, int v) {
-    if (k[0] == 0 || k[0] == 1) return v >= 1 && v <= 3;
+    if (k[0] == 0 || k[0] == 1) return v >= 1 && v <= (k[7] == DT_SPLIT ? 4 : 3);
     if (k[0] == 3)
         return k[1] > 0 && k[1] <= 256 && propagate_variant_ok(v, (int)k[1], (DType)k[5],
                                                                 (DType)k[6]);

@@ -1194,7 +1194,7 @@ afqmc_status afqmc_selftest_gemm(afqmc_prec prec, int m, int n, int k, const dou
 
 afqmc_status afqmc_selftest_gemm_shape(afqmc_prec prec, int tile, int ksplit, int m, int n, int k,
                                        const double* A, const double* B, double* C) {
-    if (!A || !B || !C || m <= 0 || n <= 0 || k <= 0 || tile < 0 || tile > 3 || ksplit < 1)
+    if (!A || !B || !C || m <= 0 || n <= 0 || k <= 0 || tile < 0 || tile > 4 || ksplit < 1)
         return fail(AFQMC_E_INVALID, "bad args");
     if (prec != AFQMC_FP64 && prec != AFQMC_FP32 && prec != AFQMC_BF16)
         return fail(AFQMC_E_INVALID, "precision: fp64, fp32 or split bf16");

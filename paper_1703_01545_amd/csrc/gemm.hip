@@ -155,13 +155,26 @@ hipError_t launch_tile(const Gemm& g, hipStream_t s) {
     return hipGetLastError();
 }
 
+// Tile 4: the 256 x 128 tile over 16 wavefronts of 64 x 32 (four per SIMD in
+// about 120 registers instead of two in 233, so more waves cover the barrier
+// and LDS waits); split BF16 only, other types take the 8-wavefront tile.
+template <typename TA, typename TB, typename TC, typename TO, int BK>
+hipError_t launch_tile_256x128_16w(const Gemm& g, hipStream_t s) {
+    if constexpr (std::is_same<TC, Split>::value)
+        return launch_tile<TA, TB, TC, TO, 256, 128, BK, 4, 4>(g, s);
+    else
+        return launch_tile<TA, TB, TC, TO, 256, 128, BK, 4, 2>(g, s);
+}
+
 template <typename TA, typename TB, typename TC, typename TO>
 hipError_t launch_gemm(const Gemm& g, hipStream_t s) {
     const long tiles128 = ((long)(g.m + 127) / 128) * ((g.n + 127) / 128) * g.batch;
     constexpr int BK = Info<TC>::KM == 4 ? 16 : 32;
     const bool big = g.tile ? g.tile == 2 : (g.m >= 96 && g.n >= 96 && tiles128 >= 512);
     hipError_t e;
-    if (g.tile == 3)
+    if (g.tile == 4)
+        e = launch_tile_256x128_16w<TA, TB, TC, TO, BK>(g, s);
+    else if (g.tile == 3)
         e = launch_tile<TA, TB, TC, TO, 256, 128, BK, 4, 2>(g, s);
     else if (big)
         e = launch_tile<TA, TB, TC, TO, 128, 128, BK, 2, 2>(g, s);

@@ -52,7 +52,8 @@ struct Gemm {
     double alpha;
     double beta;
     int m, n, k, batch;
-    int tile;  // 0: size heuristic; 1: 64 x 64 tiles; 2: 128 x 128; 3: 256 x 128
+    int tile;  // 0: size heuristic; 1: 64 x 64 tiles; 2: 128 x 128; 3: 256 x 128;
+               // 4: 256 x 128 over 16 wavefronts (split BF16; else as 3)
     // ksplit > 1: K cut into ksplit ranges of gemm_kchunk(k, ksplit) (the same
     // for every tile shape), partial sums (FP32; FP64 for FP64 compute) into
     // ws[ksplit][m][n] (batch 1), then summed in range order into C

@@ -79,7 +79,7 @@ def test_gemm_tile_shapes_agree(lib, prec, shape, ks):
     B = rng.standard_normal((n, k))
     if prec != "fp64":
         A, B = A.astype(np.float32).astype(np.float64), B.astype(np.float32).astype(np.float64)
-    outs = [lib.selftest_gemm_shape(A, B, prec, tile, ks) for tile in (1, 2, 3)]
+    outs = [lib.selftest_gemm_shape(A, B, prec, tile, ks) for tile in (1, 2, 3, 4)]
     for o in outs[1:]:
         assert np.array_equal(o, outs[0])
     ref = A @ B.T
