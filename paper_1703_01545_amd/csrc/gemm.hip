@@ -155,13 +155,13 @@ hipError_t launch_tile(const Gemm& g, hipStream_t s) {
     return hipGetLastError();
 }
 
-// Tile 4: the 256 x 128 tile over 16 wavefronts of 64 x 32 (four per SIMD in
+// Tile 4: the 256 x 128 tile over 16 wavefronts of 32 x 64 (four per SIMD in
 // about 120 registers instead of two in 233, so more waves cover the barrier
 // and LDS waits); split BF16 only, other types take the 8-wavefront tile.
 template <typename TA, typename TB, typename TC, typename TO, int BK>
 hipError_t launch_tile_256x128_16w(const Gemm& g, hipStream_t s) {
     if constexpr (std::is_same<TC, Split>::value)
-        return launch_tile<TA, TB, TC, TO, 256, 128, BK, 4, 4>(g, s);
+        return launch_tile<TA, TB, TC, TO, 256, 128, BK, 8, 2>(g, s);
     else
         return launch_tile<TA, TB, TC, TO, 256, 128, BK, 4, 2>(g, s);
 }
